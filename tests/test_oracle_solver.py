@@ -1,0 +1,244 @@
+"""Pins of the oracle's Ising / Max-Cut, bSB, selection and greedy pass (Eqs. 4-6).
+
+Exact optima come from exhaustive enumeration (<= 16 vertices), from graphs with
+a textbook optimum (complete bipartite graphs, rings) and from frustration-free
+planted twins; the bSB step is pinned by its J = 0 closed form, a two-spin
+system and the wall invariants; SplitMix64 by its published test vector.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import bruteforce
+
+
+def csr_from_dense(D):
+    D = np.asarray(D, dtype=np.float64)
+    n = D.shape[0]
+    mask = D != 0
+    np.fill_diagonal(mask, False)
+    rows, cols = np.nonzero(mask)
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return oracle.CSR(n, np.cumsum(rp), cols, D[rows, cols])
+
+
+def random_graph(seed, n, density=0.5, integer=True):
+    rng = np.random.default_rng(seed)
+    D = np.zeros((n, n))
+    for a in range(n):
+        for b in range(a + 1, n):
+            if rng.random() < density:
+                v = float(rng.integers(-5, 6)) if integer else rng.normal()
+                D[a, b] = D[b, a] = v
+    return D
+
+
+# ---------------------------------------------------------------- brute force itself
+
+def test_bruteforce_triangle_and_path():
+    # unit antiferromagnetic triangle (A = 1): best cut 2
+    J = -np.ones((3, 3)); np.fill_diagonal(J, 0)
+    best, s = bruteforce.maxcut(J)
+    assert best == 2.0
+    # path of 4 with A = 1: all edges cut
+    J = np.zeros((4, 4))
+    for a in range(3):
+        J[a, a + 1] = J[a + 1, a] = -1
+    assert bruteforce.maxcut(J)[0] == 3.0
+
+
+# ---------------------------------------------------------------- Eqs. (4)-(6)
+
+def test_cut_energy_identity_and_flip_invariance():
+    D = random_graph(3, 30, 0.3, integer=False)
+    g = csr_from_dense(D)
+    rng = np.random.default_rng(0)
+    s = np.where(rng.random((30, 8)) < 0.5, 1, -1).astype(np.int8)
+    comp = np.zeros(30, dtype=np.int32)
+    cut = oracle.cuts(g, comp, 1, s)[:, 0]
+    E = oracle.energy(g, s)
+    A_sum = -D.sum()
+    assert np.allclose(cut, 0.25 * A_sum - 0.5 * E, rtol=0, atol=1e-10)
+    # explicit pair sum: cut = sum_{a<b, s_a != s_b} A_ab
+    for r in range(8):
+        direct = sum(-D[a, b] for a in range(30) for b in range(a + 1, 30) if s[a, r] != s[b, r])
+        assert cut[r] == pytest.approx(direct, abs=1e-10)
+    assert np.array_equal(oracle.cuts(g, comp, 1, -s), oracle.cuts(g, comp, 1, s))
+
+
+@pytest.mark.parametrize("seed,n,integer", [(1, 10, True), (2, 12, True), (3, 14, True),
+                                            (4, 12, False), (5, 14, False), (6, 16, False)])
+def test_bsb_greedy_hits_bruteforce_optimum(seed, n, integer):
+    D = random_graph(seed, n, 0.6, integer)
+    g = csr_from_dense(D)
+    opt, _ = bruteforce.maxcut(D)
+    r = oracle.solve(g, R=64, steps=1000, dt=0.5, seed=seed, integer=integer)
+    assert r["best_cut"] == pytest.approx(opt, abs=1e-9)
+
+
+@pytest.mark.parametrize("m,n", [(3, 4), (5, 5), (7, 9)])
+def test_complete_bipartite_optimum(m, n):
+    N = m + n
+    D = np.zeros((N, N))
+    D[:m, m:] = -1.0
+    D[m:, :m] = -1.0
+    r = oracle.solve(csr_from_dense(D), R=32, steps=800, dt=0.5, seed=1, integer=True)
+    assert r["best_cut"] == m * n
+
+
+@pytest.mark.parametrize("n", [10, 11, 40, 41])
+def test_ring_optimum(n):
+    D = np.zeros((n, n))
+    for a in range(n):
+        b = (a + 1) % n
+        D[a, b] = D[b, a] = -1.0
+    r = oracle.solve(csr_from_dense(D), R=32, steps=1500, dt=0.5, seed=2, integer=True)
+    assert r["best_cut"] == (n if n % 2 == 0 else n - 1)
+
+
+def test_planted_read_twin_optimum():
+    w = synth.read_tiny(error=0.0)
+    g = oracle.build_graph(w, "read_signed")
+    r = oracle.solve(g, R=16, steps=1000, dt=0.5, seed=3, integer=True)
+    # frustration-free: optimum = sum over pairs of max(A_ab, 0), A = -J
+    assert r["best_cut"] == np.maximum(-g.val, 0).sum() / 2
+    # and the planted partition attains it
+    s = np.where(w.origin == 0, 1, -1).astype(np.int8)
+    comp, nc = oracle.components(g)
+    assert oracle.cuts(g, comp, nc, s).sum() == r["best_cut"]
+
+
+# ---------------------------------------------------------------- bSB dynamics
+
+def test_bsb_step_closed_form_zero_coupling():
+    g = csr_from_dense(np.zeros((2, 2)))
+    x = np.array([[0.05, -0.08]], dtype=np.float64).repeat(2, 0).copy()
+    y = np.array([[-0.02, 0.01]], dtype=np.float64).repeat(2, 0).copy()
+    oracle.bsb_run(g, x, y, np.array([0.3]), dt=0.5, c0_=0.7, a0=1.0)
+    # y' = y - (a0 - p) dt x ; x' = x + a0 dt y'
+    assert y[0, 0] == pytest.approx(-0.02 - 0.7 * 0.5 * 0.05, abs=1e-16)
+    assert x[0, 0] == pytest.approx(0.05 + 0.5 * (-0.0375), abs=1e-16)
+    assert x[0, 0] == pytest.approx(0.03125, abs=1e-16)
+    assert y[0, 1] == pytest.approx(0.01 + 0.7 * 0.5 * 0.08, abs=1e-16)
+    assert x[0, 1] == pytest.approx(-0.08 + 0.5 * 0.038, abs=1e-16)
+
+
+def test_bsb_step_coupling_and_wall():
+    D = np.array([[0.0, 2.0], [2.0, 0.0]])
+    g = csr_from_dense(D)
+    x = np.array([[0.9], [0.5]])
+    y = np.array([[0.5], [0.0]])
+    oracle.bsb_run(g, x, y, np.array([1.0]), dt=0.5, c0_=0.25, a0=1.0)
+    # vertex 0: y = 0.5 + (0 + 0.25*2*0.5)*0.5 = 0.625 ; x = 0.9 + 0.3125 > 1 -> wall
+    assert x[0, 0] == 1.0 and y[0, 0] == 0.0
+    # vertex 1: y = 0 + 0.25*2*0.9*0.5 = 0.225 ; x = 0.5 + 0.1125
+    assert y[1, 0] == pytest.approx(0.225, abs=1e-16)
+    assert x[1, 0] == pytest.approx(0.6125, abs=1e-16)
+
+
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_two_spin_alignment(sign):
+    g = csr_from_dense(np.array([[0.0, sign], [sign, 0.0]]))
+    r = oracle.solve(g, R=16, steps=400, dt=0.5, seed=9, greedy_pass=False)
+    s = r["spins"]
+    assert np.all(s[0] == (s[1] if sign > 0 else -s[1]))
+
+
+def test_bsb_wall_invariants_and_resume():
+    w = synth.read_small(21, n_snp=150, n_reads=40, span=(10, 40))
+    g = oracle.build_graph(w, "read_signed")
+    c0 = oracle.c0(g)
+    pump = oracle.pump_linear(300)
+    x, y = oracle.init_state(5, g.n, 8)
+    for k in range(300):
+        x_prev = x.copy()
+        oracle.bsb_run(g, x, y, pump, 0.5, c0, 1.0, k, k + 1)
+        assert np.all(np.abs(x) <= 1.0)
+        clamped = np.abs(x) == 1.0
+        assert np.all(y[clamped] == 0.0)
+    xa, ya = oracle.init_state(5, g.n, 8)
+    oracle.bsb_run(g, xa, ya, pump, 0.5, c0, 1.0, 0, 300)
+    assert np.array_equal(xa, x) and np.array_equal(ya, y)
+    xb, yb = oracle.init_state(5, g.n, 8)
+    oracle.bsb_run(g, xb, yb, pump, 0.5, c0, 1.0, 0, 170)
+    oracle.bsb_run(g, xb, yb, pump, 0.5, c0, 1.0, 170, 300)
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+
+
+def test_c0_complete_graph():
+    n = 9
+    D = -np.ones((n, n)); np.fill_diagonal(D, 0)
+    assert oracle.c0(csr_from_dense(D)) == pytest.approx(0.5 / np.sqrt(n), rel=1e-15)
+
+
+def test_pump_linear_endpoints():
+    p = oracle.pump_linear(5)
+    assert p.tolist() == [0.0, 0.25, 0.5, 0.75, 1.0]
+
+
+def test_splitmix64_published_vector(golden_dir):
+    with open(os.path.join(golden_dir, "splitmix64_vector.json")) as f:
+        ref = json.load(f)
+    got = [oracle.splitmix64(ref["seed"], k) for k in range(len(ref["outputs"]))]
+    assert got == [int(v) for v in ref["outputs"]]
+
+
+def test_init_uses_counter_layout():
+    x, y = oracle.init_state(77, 5, 3)
+    assert np.all(np.abs(x) <= 0.1) and np.all(np.abs(y) <= 0.1)
+    for i in range(5):
+        for r in range(3):
+            c = 2 * (r * 5 + i)
+            ux = (oracle.splitmix64(77, c) >> 11) * 2.0 ** -53
+            uy = (oracle.splitmix64(77, c + 1) >> 11) * 2.0 ** -53
+            assert x[i, r] == 0.2 * ux - 0.1
+            assert y[i, r] == 0.2 * uy - 0.1
+
+
+# ---------------------------------------------------------------- selection, greedy
+
+def test_select_per_component_ties_and_orientation():
+    # components: {0,1,2} -> 0, {3,4} -> 1, vertex 5 isolated
+    comp = np.array([0, 0, 0, 1, 1, -1], dtype=np.int32)
+    s = np.array([[1, -1, 1], [-1, -1, 1], [1, 1, -1], [-1, 1, 1], [1, 1, -1], [-1, 1, -1]],
+                 dtype=np.int8)
+    cut = np.array([[2.0, 1.0], [5.0, 3.0], [5.0, 3.0]])    # [r, c]
+    best, br = oracle.select(comp, 2, s, cut)
+    assert br.tolist() == [1, 1]                 # ties go to the lowest replica
+    # component 0 from replica 1: (-1,-1,1) oriented so vertex 0 is +1
+    assert best[:3].tolist() == [1, 1, -1]
+    assert best[3:5].tolist() == [1, 1]          # (1, 1) from replica 1
+    assert best[5] == 1
+
+
+def test_greedy_monotone_and_one_flip_optimal():
+    for seed in range(5):
+        D = random_graph(100 + seed, 60, 0.15, integer=(seed % 2 == 0))
+        g = csr_from_dense(D)
+        rng = np.random.default_rng(seed)
+        s0 = np.where(rng.random(60) < 0.5, 1, -1).astype(np.int8)
+        comp = np.zeros(60, dtype=np.int32)
+        c_before = oracle.cuts(g, comp, 1, s0).sum()
+        eps = oracle.greedy_eps(g, integer=(seed % 2 == 0))
+        s1, rounds = oracle.greedy(g, s0, eps)
+        c_after = oracle.cuts(g, comp, 1, s1).sum()
+        assert c_after >= c_before
+        # gains of every single flip, computed from the dense matrix
+        A = -D
+        gains = s1 * (A @ s1.astype(np.float64))
+        assert gains.max() <= eps + 1e-12
+        assert rounds >= 0
+
+
+def test_greedy_independent_set_rule_hand():
+    # path 0-1-2 with A = (1, 1) and all spins equal: gains 1, 2, 1.
+    D = np.zeros((3, 3)); D[0, 1] = D[1, 0] = -1; D[1, 2] = D[2, 1] = -1
+    g = csr_from_dense(D)
+    s, rounds = oracle.greedy(g, np.array([1, 1, 1], dtype=np.int8), 0.0)
+    # round 1 flips only the middle vertex (largest gain among neighbours): cut 2 = optimum
+    assert s.tolist() == [1, -1, 1] and rounds == 1
