@@ -1,0 +1,247 @@
+/*
+ * qhap.h -- C ABI of the MI355X (gfx950) haplotype-phasing hot path.
+ *
+ * The paper (QHap) phases diploid haplotypes by posing them as weighted
+ * Max-Cut and solving the Ising form with ballistic simulated bifurcation
+ * (bSB).  This library implements that path on one GPU:
+ *
+ *   qh_build_graph  reads + SNPs  -> coupling matrix J      (Methods, graph construction)
+ *   qh_bsb_solve    J             -> spins, FP64 cuts        (Methods, SB algorithm solution)
+ *   qh_phase        J, spins      -> haplotype 1 per SNP     (Methods, consistency processing /
+ *                                                              SNP-based parity reconstruction)
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns qh_status.  On failure a thread-local message is
+ *    available from qh_last_error(); output buffers are left untouched.
+ *    No C++ exception crosses the ABI.
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary CPU memory.  The caller owns every buffer it passes;
+ *    the library owns everything inside a qh_graph.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is stream-ordered; device outputs are valid once the stream has
+ *    synchronised.  Calls that must read back a count (graph build, the greedy
+ *    pass) synchronise the stream themselves and say so.
+ *  - Spin / momentum state is laid out [n][R] (replica index fastest), FP32.
+ *  - Ising convention (Eqs. 4-6): E(s) = -1/2 s^T J s, A = -J, and
+ *    cut(s) = 1/4 sum_{a,b} A_ab (1 - s_a s_b).
+ */
+#ifndef QHAP_H
+#define QHAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QH_OK = 0,
+    QH_EINVAL = 1,        /* bad argument: null pointer, size, index out of range, bad enum */
+    QH_ENOMEM = 2,        /* device or host allocation failed */
+    QH_EHIP = 3,          /* a HIP runtime call failed (message names it) */
+    QH_EUNSUPPORTED = 4,  /* valid but not implemented combination (e.g. FP8 on a skyline) */
+    QH_ENUMERIC = 5       /* NaN / Inf detected in couplings or final state */
+} qh_status;
+
+/* Graph kinds.
+ *  READ_CONFLICT  vertices = fragments, A_ab = number of shared SNPs whose ternary
+ *                 codes disagree (Eqs. 2-3), J = -A (Eq. 4).
+ *  READ_SIGNED    vertices = fragments, J_ab = sum_j M_aj M_bj (agree minus disagree).
+ *  SNP_LLR        vertices = SNPs, A_uv = w_uv of Eq. 14 (Phred-weighted log-likelihood
+ *                 ratios, Eqs. 9-13, scaled by the per-fragment Pore-C factor alpha),
+ *                 J = -A. Linkage depth k/10: each SNP links to its floor(k(|S_i|-1)/10)
+ *                 nearest downstream SNPs of fragment i.  Observations with Phred <= 3
+ *                 are dropped (the likelihood ratio is undefined or sign-flipped there). */
+typedef enum { QH_READ_CONFLICT = 0, QH_READ_SIGNED = 1, QH_SNP_LLR = 2 } qh_graph_kind;
+
+/* Storage of J for the step kernels.
+ *  DENSE    64x64 tiles; all-zero tiles are not stored.  Read graphs only.
+ *  SKYLINE  per row the contiguous column range [lo_u, hi_u] of linked SNPs (no column
+ *           indices); pairs farther apart than band_limit columns go to a long-range
+ *           CSR (the Pore-C contacts).  SNP graphs only. */
+typedef enum { QH_STORE_DENSE = 0, QH_STORE_SKYLINE = 1 } qh_storage;
+
+/* Stored value type of J for the step kernels (accumulation is always FP32).
+ *  FP8_ROWSCALE: OCP E4M3 codes with one FP32 scale per row, s_i = RNE_f32(max_j|J_ij|/448),
+ *  code = RNE_e4m3(J_ij / s_i) (quotient in FP64, saturating).  Dense storage only. */
+typedef enum { QH_F32 = 0, QH_F16 = 1, QH_BF16 = 2, QH_FP8_ROWSCALE = 3 } qh_dtype;
+
+/* Fragments (reads) in CSR form.  All pointers are device pointers.
+ *  frag_ptr  int64 [n_frag + 1], frag_ptr[0] = 0, non-decreasing.
+ *  snp       int32 [frag_ptr[n_frag]], SNP index in [0, n_snp), strictly ascending
+ *            inside each fragment (index order = genomic order).
+ *  allele    uint8, 0 = reference allele, 1 = alternative allele.
+ *  phred     uint8 base quality (used by SNP_LLR only).
+ *  alpha     float64 [n_frag] per-fragment weight factor (Pore-C down-weighting), or
+ *            NULL for all ones (used by SNP_LLR only).
+ * For read graphs fragment f is vertex f; pass fragments sorted by first SNP so that
+ * J is band-shaped and the dense tiles skip most of the matrix. */
+typedef struct {
+    int64_t n_frag;
+    const int64_t *frag_ptr;
+    const int32_t *snp;
+    const uint8_t *allele;
+    const uint8_t *phred;
+    const double *alpha;
+} qh_reads;
+
+/* SNP set.  init_h1 (device, uint8 [n_snp]) is the allele placed on the initial
+ * haplotype H1 at each SNP (Methods, haplotype initialization); H2 carries the other. */
+typedef struct {
+    int32_t n_snp;
+    const uint8_t *init_h1;
+} qh_snps;
+
+typedef struct {
+    int32_t kind;        /* qh_graph_kind */
+    int32_t storage;     /* qh_storage */
+    int32_t dtype;       /* qh_dtype */
+    int32_t linkage_k;   /* SNP_LLR: 1..10 (10 = every pair inside a fragment) */
+    int32_t band_limit;  /* SKYLINE: max column distance kept in the band; 0 = no limit */
+} qh_graph_opts;
+
+typedef struct qh_graph qh_graph;
+
+typedef struct {
+    int64_t n;               /* vertices */
+    int64_t n_snp;           /* SNPs of the input (haplotype length for qh_phase) */
+    int64_t nnz;             /* nonzero off-diagonal entries of J (both directions) */
+    int64_t n_comp;          /* connected components with >= 2 vertices */
+    int64_t stored_entries;  /* entries the step kernel reads per step and replica */
+    int64_t stored_bytes;    /* bytes of J the step kernel reads per step */
+    int64_t longrange_nnz;   /* entries in the long-range CSR (SKYLINE) */
+    int64_t dense_tiles;     /* stored 64x64 tiles (DENSE) */
+    int64_t device_bytes;    /* device memory owned by the graph */
+    int32_t kind, storage, dtype;
+    int32_t integer_weights; /* 1 when every J_ij is an integer (read graphs) */
+    double c0_auto;          /* 0.5 / sqrt(sum_{i!=j} J_ij^2 / (n - 1)) */
+} qh_graph_info;
+
+/* Builds J from fragments (Methods: read-based Eqs. 1-3, SNP-based Eqs. 9-14).
+ * Computes the FP64 master values, the connected components (single-vertex
+ * components get label -1), the storage copy in `dtype`, and what qh_phase needs.
+ * Synchronises `stream`.  Errors: EINVAL for malformed fragments (index out of range,
+ * non-ascending SNPs, bad enum), EUNSUPPORTED for kind/storage/dtype combinations
+ * not offered, ENOMEM, EHIP. */
+qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_graph_opts *opts,
+                         qh_graph **out, void *stream);
+
+qh_status qh_graph_free(qh_graph *g);
+qh_status qh_graph_get_info(const qh_graph *g, qh_graph_info *out);
+
+/* FP64 master values of rows [row0, row1) as dense rows: out is device
+ * double [(row1 - row0) * n], fully overwritten (zeros where no edge). */
+qh_status qh_graph_export_rows(const qh_graph *g, int64_t row0, int64_t row1, double *out,
+                               void *stream);
+
+/* The values the step kernel multiplies with, dequantized to FP64 (scale * code for
+ * FP8_ROWSCALE), rows [row0, row1) as dense rows; device double [(row1-row0) * n]. */
+qh_status qh_graph_export_stored_rows(const qh_graph *g, int64_t row0, int64_t row1,
+                                      double *out, void *stream);
+
+/* Component label per vertex (device int32 [n]); labels are numbered in the
+ * order of each component's lowest vertex, -1 for single-vertex components. */
+qh_status qh_graph_components(const qh_graph *g, int32_t *comp, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Ballistic simulated bifurcation (Methods, SB algorithm solution; the update
+ * is the published bSB: symplectic Euler, y first):
+ *   y_i <- y_i + [-(a0 - p_k) x_i + c0 (J x)_i] dt
+ *   x_i <- x_i + a0 y_i dt
+ *   |x_i| > 1  =>  x_i <- sgn(x_i), y_i <- 0        (inelastic walls)
+ * for k = step_begin .. step_end-1, all R replicas at once; then s = sgn(x) with
+ * sgn(0) = +1, FP64 cuts per replica and per component from the master values,
+ * the best replica per component (ties -> lowest replica), oriented so that the
+ * component's lowest vertex reads +1, and an optional greedy single-flip pass.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t replicas;    /* R: 16, 32, or a multiple of 64 */
+    int32_t steps;       /* length of the pump schedule (>= 1) */
+    int32_t step_begin;  /* run steps [step_begin, step_end) of the schedule; */
+    int32_t step_end;    /*   step_end = 0 means `steps` (checkpoint / resume) */
+    double dt;           /* time step */
+    double c0;           /* coupling scale; <= 0 selects qh_graph_info.c0_auto */
+    double a0;           /* detuning / mass term; 0 selects 1.0 */
+    const float *pump;   /* device float [steps] schedule p_k, or NULL = p_k = k/(steps-1) */
+    uint64_t seed;       /* SplitMix64 seed for x0, y0 when init = 1 */
+    int32_t init;        /* 1: x0, y0 ~ U(-0.1, 0.1) from the seed (draw k = 2(r n + i) + {0,1});
+                            0: start from the state passed in qh_result.x / .y */
+    int32_t readout;     /* 1: signs, cuts, selection (+ greedy); 0: dynamics only */
+    int32_t greedy;      /* 1: greedy single-flip rounds on the selected spins */
+    int32_t use_graph;   /* 1: replay the step loop from a captured hipGraph (cached per
+                            graph and option set); 0: plain stream launches */
+    int32_t plan;        /* 0 = choose the kernel variant automatically; >0 forces one */
+} qh_bsb_opts;
+
+/* Result buffers (all device, caller-owned; optional ones may be NULL).
+ *  x, y          float [n][R] state.  With init = 0 they supply the starting state.
+ *                On return they hold the state after step_end-1 (if non-NULL).
+ *  best_spins    int8 [n]      selected spins (after greedy when enabled)
+ *  cuts          double [R]    FP64 cut of every replica (sum over components)
+ *  cut_rc        double [R][n_comp] FP64 cut per replica and component (optional)
+ *  best_replica  int32 [n_comp] selected replica per component (optional)
+ *  selected_cut  double [1]    cut of the selected spins before greedy (optional)
+ *  best_cut      double [1]    cut of best_spins
+ *  all_spins     int8 [n][R]   every replica's signs (optional)
+ *  greedy_rounds int32 [1]     rounds that flipped something (optional, host or device: device) */
+typedef struct {
+    float *x;
+    float *y;
+    int8_t *best_spins;
+    double *cuts;
+    double *cut_rc;
+    int32_t *best_replica;
+    double *selected_cut;
+    double *best_cut;
+    int8_t *all_spins;
+    int32_t *greedy_rounds;
+} qh_result;
+
+/* Runs bSB on one graph.  Synchronises the stream only when greedy = 1.
+ * Errors: EINVAL (replicas not 16/32/64k, steps < 1, range outside the schedule,
+ * init = 0 without x/y, readout without best_spins/cuts/best_cut), ENUMERIC when the
+ * final state holds NaN/Inf (checked when readout = 1), ENOMEM, EHIP. */
+qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *res, void *stream);
+
+/* Many independent graphs (phasing blocks) in one persistent launch: every block
+ * runs the same schedule with its own c0 (opts->c0 <= 0: each block's c0_auto).
+ * Results are packed: block b's vertices start at vertex_offset[b] (= sum of the
+ * previous blocks' n) in best_spins / x / y, and its replicas at b * R in cuts.
+ *  best_spins int8 [sum n]; cuts double [n_blocks * R]; best_cut double [n_blocks];
+ *  x, y optional float [sum n * R].  Greedy is applied per block when requested. */
+typedef struct {
+    int8_t *best_spins;
+    double *cuts;
+    double *best_cut;
+    double *selected_cut;
+    float *x;
+    float *y;
+} qh_batched_result;
+
+qh_status qh_bsb_solve_batched(const qh_graph *const *graphs, int32_t n_graphs,
+                               const qh_bsb_opts *opts, qh_batched_result *res, void *stream);
+
+/* Haplotype reconstruction from spins (device int8 [n], +1 = subset S1).
+ * Read graphs: per SNP the vote counts of Eqs. 7-8 and the hierarchical rule of the
+ * paper; h1[j] is the allele of output haplotype 1 (= subset S1), -1 where the SNP is
+ * filtered (no decisive support) or covered only by single-fragment components.
+ * SNP graphs: one parity round (Eqs. 16-17): in each component the smaller subset
+ * S_min (equal sizes: the s = -1 subset) swaps H1/H2; single-vertex components -> -1.
+ * block[j] = component label of the SNP's phase block, -1 when unphased by structure.
+ * h1 device int8 [n_snp], block device int32 [n_snp]. */
+qh_status qh_phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block,
+                   void *stream);
+
+/* Eq. 15: J_uv <- -J_uv for every edge whose endpoints disagree in `spins` (device
+ * int8 [n]); updates the master and the stored copy in place. */
+qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream);
+
+const char *qh_last_error(void);
+const char *qh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QHAP_H */

@@ -262,6 +262,29 @@ def bsb_run(g: CSR, x: np.ndarray, y: np.ndarray, pump: np.ndarray, dt: float, c
     return x, y
 
 
+def bsb_step_dense(J: np.ndarray, x: np.ndarray, y: np.ndarray, p: float, dt: float, c0_: float,
+                   a0: float = 1.0, product_format: Optional[str] = None, walls: bool = True):
+    """One bSB step in FP64 with a dense J, returning (x', y').
+
+    ``product_format`` (None, "f16", "bf16") rounds the x that enters the coupling
+    product J x to that format, which is what the reduced-precision forms multiply;
+    the update itself keeps x and y unrounded.
+    """
+    from . import quant
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    xq = x if product_format is None else quant.round_to(product_format, x)
+    z = np.asarray(J, dtype=np.float64) @ xq
+    y2 = y + (-(a0 - p) * x + c0_ * z) * dt
+    x2 = x + a0 * y2 * dt
+    if not walls:
+        return x2, y2
+    wall = np.abs(x2) > 1.0
+    x2 = np.where(wall, np.where(x2 > 0, 1.0, -1.0), x2)
+    y2 = np.where(wall, 0.0, y2)
+    return x2, y2
+
+
 def signs(x: np.ndarray) -> np.ndarray:
     x = _c(x, np.float64)
     s = np.empty(x.shape, dtype=np.int8)

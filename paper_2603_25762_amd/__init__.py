@@ -1,0 +1,17 @@
+"""Python binding of the gfx950 haplotype-phasing library (``lib/libqhap.so``).
+
+Argument marshalling only: torch tensors serve as device buffers and
+``torch.cuda.current_stream()`` as the HIP stream; every step of the path runs
+in the library's HIP kernels.  The functions mirror the C ABI in
+``include/qhap.h``: :func:`build_graph`, :func:`bsb_solve`,
+:func:`bsb_solve_batched`, :func:`phase`, :func:`flip_crossing`.
+
+Importing this package needs the built library and raises if it is missing;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    QhapError, Graph, build_graph, bsb_solve, bsb_solve_batched, phase, flip_crossing,
+    lib_path, load, version, to_device, KIND, STORAGE, DTYPE, Status,
+)

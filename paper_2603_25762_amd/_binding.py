@@ -1,0 +1,305 @@
+"""ctypes marshalling for ``include/qhap.h``."""
+from __future__ import annotations
+
+import ctypes
+import enum
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "lib", "libqhap.so")
+
+KIND = {"read_conflict": 0, "read_signed": 1, "snp_llr": 2}
+STORAGE = {"dense": 0, "skyline": 1}
+DTYPE = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3}
+
+
+class Status(enum.IntEnum):
+    OK = 0
+    EINVAL = 1
+    ENOMEM = 2
+    EHIP = 3
+    EUNSUPPORTED = 4
+    ENUMERIC = 5
+
+
+class QhapError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{Status(status).name}: {message}")
+        self.status = Status(status)
+
+
+P = ctypes.c_void_p
+
+
+class _Reads(ctypes.Structure):
+    _fields_ = [("n_frag", ctypes.c_int64), ("frag_ptr", P), ("snp", P), ("allele", P),
+                ("phred", P), ("alpha", P)]
+
+
+class _Snps(ctypes.Structure):
+    _fields_ = [("n_snp", ctypes.c_int32), ("init_h1", P)]
+
+
+class _GraphOpts(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("storage", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("linkage_k", ctypes.c_int32), ("band_limit", ctypes.c_int32)]
+
+
+class _GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_snp", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_comp", ctypes.c_int64),
+                ("stored_entries", ctypes.c_int64), ("stored_bytes", ctypes.c_int64),
+                ("longrange_nnz", ctypes.c_int64), ("dense_tiles", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("kind", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("integer_weights", ctypes.c_int32), ("c0_auto", ctypes.c_double)]
+
+
+class _BsbOpts(ctypes.Structure):
+    _fields_ = [("replicas", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("step_begin", ctypes.c_int32), ("step_end", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("c0", ctypes.c_double), ("a0", ctypes.c_double),
+                ("pump", P), ("seed", ctypes.c_uint64), ("init", ctypes.c_int32),
+                ("readout", ctypes.c_int32), ("greedy", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("plan", ctypes.c_int32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("x", P), ("y", P), ("best_spins", P), ("cuts", P), ("cut_rc", P),
+                ("best_replica", P), ("selected_cut", P), ("best_cut", P), ("all_spins", P),
+                ("greedy_rounds", P)]
+
+
+class _BatchedResult(ctypes.Structure):
+    _fields_ = [("best_spins", P), ("cuts", P), ("best_cut", P), ("selected_cut", P),
+                ("x", P), ("y", P)]
+
+
+_lib = None
+
+
+def load():
+    """Load the built library; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(lib_path):
+        raise ImportError(f"HIP library not built: {lib_path} is missing "
+                          "(run __graft_entry__.build())")
+    lib = ctypes.CDLL(lib_path)
+    I = ctypes.c_int
+    sig = {
+        "qh_build_graph": [ctypes.POINTER(_Reads), ctypes.POINTER(_Snps), ctypes.POINTER(_GraphOpts),
+                           ctypes.POINTER(P), P],
+        "qh_graph_free": [P],
+        "qh_graph_get_info": [P, ctypes.POINTER(_GraphInfo)],
+        "qh_graph_export_rows": [P, ctypes.c_int64, ctypes.c_int64, P, P],
+        "qh_graph_export_stored_rows": [P, ctypes.c_int64, ctypes.c_int64, P, P],
+        "qh_graph_components": [P, P, P],
+        "qh_bsb_solve": [P, ctypes.POINTER(_BsbOpts), ctypes.POINTER(_Result), P],
+        "qh_bsb_solve_batched": [P, ctypes.c_int32, ctypes.POINTER(_BsbOpts),
+                                 ctypes.POINTER(_BatchedResult), P],
+        "qh_phase": [P, P, P, P, P],
+        "qh_flip_crossing": [P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = I
+    lib.qh_last_error.restype = ctypes.c_char_p
+    lib.qh_last_error.argtypes = []
+    lib.qh_version.restype = ctypes.c_char_p
+    lib.qh_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().qh_version().decode()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise QhapError(rc, load().qh_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def to_device(a: np.ndarray, device="cuda") -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+class Graph:
+    """Owns a ``qh_graph*``; freed when garbage-collected or by :meth:`free`."""
+
+    def __init__(self, handle: int, keep=()):
+        self._h = ctypes.c_void_p(handle)
+        self._keep = keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> Dict[str, object]:
+        inf = _GraphInfo()
+        _check(load().qh_graph_get_info(self._h, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in _GraphInfo._fields_}
+
+    def export_rows(self, row0: int, row1: int, stored: bool = False) -> torch.Tensor:
+        n = self.info()["n"]
+        out = torch.empty((row1 - row0, n), dtype=torch.float64, device="cuda")
+        fn = load().qh_graph_export_stored_rows if stored else load().qh_graph_export_rows
+        _check(fn(self._h, row0, row1, _ptr(out), _stream()))
+        return out
+
+    def components(self) -> torch.Tensor:
+        n = self.info()["n"]
+        out = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(load().qh_graph_components(self._h, _ptr(out), _stream()))
+        return out
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            torch.cuda.synchronize()
+            _check(load().qh_graph_free(self._h))
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            if self._h is not None and self._h.value and _lib is not None:
+                _lib.qh_graph_free(self._h)
+        except Exception:
+            pass
+
+
+def build_graph(frag_ptr: torch.Tensor, snp: torch.Tensor, allele: torch.Tensor,
+                phred: Optional[torch.Tensor], init_h1: torch.Tensor, *, kind: str = "read_signed",
+                storage: Optional[str] = None, dtype: str = "f32",
+                alpha: Optional[torch.Tensor] = None, linkage_k: int = 10,
+                band_limit: int = 0, stream=None) -> Graph:
+    if storage is None:
+        storage = "skyline" if kind == "snp_llr" else "dense"
+    for t, dt in ((frag_ptr, torch.int64), (snp, torch.int32), (allele, torch.uint8),
+                  (init_h1, torch.uint8)):
+        if t.dtype != dt:
+            raise TypeError(f"expected {dt}, got {t.dtype}")
+    if phred is not None and phred.dtype != torch.uint8:
+        raise TypeError("phred must be uint8")
+    if alpha is not None and alpha.dtype != torch.float64:
+        raise TypeError("alpha must be float64")
+    reads = _Reads(frag_ptr.numel() - 1, _ptr(frag_ptr), _ptr(snp), _ptr(allele), _ptr(phred),
+                   _ptr(alpha))
+    snps = _Snps(init_h1.numel(), _ptr(init_h1))
+    opts = _GraphOpts(KIND[kind], STORAGE[storage], DTYPE[dtype], linkage_k, band_limit)
+    h = ctypes.c_void_p()
+    _check(load().qh_build_graph(ctypes.byref(reads), ctypes.byref(snps), ctypes.byref(opts),
+                                 ctypes.byref(h), _stream(stream)))
+    return Graph(h.value)
+
+
+def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float = 0.0,
+              a0: float = 1.0, pump: Optional[torch.Tensor] = None, seed: int = 0,
+              init: bool = True, x: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None,
+              step_begin: int = 0, step_end: int = 0, readout: bool = True, greedy: bool = True,
+              use_graph: bool = False, all_spins: bool = False, per_component: bool = False,
+              out: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
+    """Runs bSB; returns device tensors (best_spins, cuts, best_cut, selected_cut, ...).
+
+    ``x``/``y`` (float32 [n, R]) give the starting state when ``init`` is False and
+    receive the final state when passed.  ``out`` may supply preallocated result
+    tensors (keys as returned) so that repeated calls allocate nothing.
+    """
+    inf = g.info()
+    n, nc = inf["n"], inf["n_comp"]
+    dev = "cuda"
+    res = {} if out is None else dict(out)
+    keep = {}
+
+    def alloc(key, shape, dtype, zero=False):
+        # buffers never have zero elements, so the library never sees a NULL pointer
+        if key in res:
+            keep[key] = res[key]
+            return
+        full = (torch.zeros if zero else torch.empty)(tuple(max(s, 1) for s in shape), dtype=dtype,
+                                                      device=dev)
+        keep[key] = full
+        res[key] = full[tuple(slice(0, s) for s in shape)]
+
+    if readout:
+        alloc("best_spins", (n,), torch.int8)
+        alloc("cuts", (replicas,), torch.float64)
+        alloc("best_cut", (1,), torch.float64)
+        alloc("selected_cut", (1,), torch.float64)
+        alloc("greedy_rounds", (1,), torch.int32, zero=True)
+        if all_spins:
+            alloc("all_spins", (n, replicas), torch.int8)
+        if per_component:
+            alloc("cut_rc", (replicas, nc), torch.float64)
+            alloc("best_replica", (nc,), torch.int32)
+    if x is not None:
+        res["x"] = x
+    if y is not None:
+        res["y"] = y
+    if pump is not None:
+        res["pump"] = pump
+    opts = _BsbOpts(replicas, steps, step_begin, step_end, dt, c0, a0, _ptr(pump), seed & (2**64 - 1),
+                    int(init), int(readout), int(greedy), int(use_graph), 0)
+    r = _Result(_ptr(x), _ptr(y), _ptr(keep.get("best_spins")), _ptr(keep.get("cuts")),
+                _ptr(keep.get("cut_rc")), _ptr(keep.get("best_replica")), _ptr(keep.get("selected_cut")),
+                _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")))
+    _check(load().qh_bsb_solve(g.handle, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
+    return res
+
+
+def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt: float = 0.5,
+                      c0: float = 0.0, a0: float = 1.0, seed: int = 0, greedy: bool = True,
+                      use_graph: bool = False, plan: int = 0, stream=None) -> Dict[str, torch.Tensor]:
+    ns = [g.info()["n"] for g in graphs]
+    total = int(sum(ns))
+    nb = len(graphs)
+    dev = "cuda"
+    res = dict(best_spins=torch.empty(max(total, 1), dtype=torch.int8, device=dev),
+               cuts=torch.empty(max(nb * replicas, 1), dtype=torch.float64, device=dev),
+               best_cut=torch.empty(max(nb, 1), dtype=torch.float64, device=dev),
+               selected_cut=torch.empty(max(nb, 1), dtype=torch.float64, device=dev))
+    arr = (ctypes.c_void_p * max(nb, 1))(*[g.handle.value for g in graphs])
+    opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
+                    int(use_graph), plan)
+    r = _BatchedResult(_ptr(res["best_spins"]), _ptr(res["cuts"]), _ptr(res["best_cut"]),
+                       _ptr(res["selected_cut"]), None, None)
+    _check(load().qh_bsb_solve_batched(arr, nb, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
+    res["vertex_offset"] = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    return res
+
+
+def phase(g: Graph, spins: torch.Tensor, n_snp: Optional[int] = None, stream=None):
+    """Haplotype 1 allele per SNP (-1 = unphased) and the phase-block label per SNP."""
+    if spins.dtype != torch.int8:
+        raise TypeError("spins must be int8")
+    inf = g.info()
+    if n_snp is None:
+        n_snp = inf["n_snp"]
+    h1 = torch.empty(max(n_snp, 1), dtype=torch.int8, device="cuda")
+    block = torch.empty(max(n_snp, 1), dtype=torch.int32, device="cuda")
+    _check(load().qh_phase(g.handle, _ptr(spins), _ptr(h1), _ptr(block), _stream(stream)))
+    return h1[:n_snp], block[:n_snp]
+
+
+def flip_crossing(g: Graph, spins: torch.Tensor, stream=None):
+    _check(load().qh_flip_crossing(g.handle, _ptr(spins), _stream(stream)))

@@ -1,0 +1,219 @@
+// C ABI entry points: argument validation, error capture, ownership.
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace qh {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void fail(qh_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    throw Failure{st};
+}
+
+void fail_hip(hipError_t e, const char *what, const char *file, int line) {
+    (void)hipGetLastError();
+    qh_status st = (e == hipErrorOutOfMemory) ? QH_ENOMEM : QH_EHIP;
+    snprintf(g_err, sizeof(g_err), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    throw Failure{st};
+}
+
+template <class F>
+static qh_status guarded(F &&f) {
+    try {
+        f();
+        return QH_OK;
+    } catch (const Failure &e) {
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return QH_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return QH_EHIP;
+    }
+}
+
+}  // namespace qh
+
+using namespace qh;
+
+extern "C" {
+
+const char *qh_last_error(void) { return g_err; }
+const char *qh_version(void) { return "qhap-gfx950 0.1.0"; }
+
+qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_graph_opts *opts,
+                         qh_graph **out, void *stream) {
+    return guarded([&] {
+        if (!reads || !snps || !opts || !out) fail(QH_EINVAL, "null argument");
+        if (reads->n_frag < 0) fail(QH_EINVAL, "n_frag < 0");
+        if (snps->n_snp < 0) fail(QH_EINVAL, "n_snp < 0");
+        if (reads->n_frag > 0 && (!reads->frag_ptr || !reads->snp || !reads->allele))
+            fail(QH_EINVAL, "null fragment array");
+        if (snps->n_snp > 0 && !snps->init_h1) fail(QH_EINVAL, "null init_h1");
+        if (opts->kind < QH_READ_CONFLICT || opts->kind > QH_SNP_LLR) fail(QH_EINVAL, "bad kind");
+        if (opts->storage < QH_STORE_DENSE || opts->storage > QH_STORE_SKYLINE)
+            fail(QH_EINVAL, "bad storage");
+        if (opts->dtype < QH_F32 || opts->dtype > QH_FP8_ROWSCALE) fail(QH_EINVAL, "bad dtype");
+        bool read_kind = opts->kind != QH_SNP_LLR;
+        if (read_kind && opts->storage != QH_STORE_DENSE)
+            fail(QH_EUNSUPPORTED, "read graphs use DENSE storage");
+        if (!read_kind && opts->storage != QH_STORE_SKYLINE)
+            fail(QH_EUNSUPPORTED, "SNP graphs use SKYLINE storage");
+        if (!read_kind && opts->dtype == QH_FP8_ROWSCALE)
+            fail(QH_EUNSUPPORTED, "FP8 row scales are offered on dense storage only");
+        if (!read_kind && opts->kind == QH_SNP_LLR && reads->n_frag > 0 && !reads->phred)
+            fail(QH_EINVAL, "SNP graphs need phred");
+        if (!read_kind && (opts->linkage_k < 1 || opts->linkage_k > 10))
+            fail(QH_EINVAL, "linkage_k must be in 1..10");
+        if (opts->band_limit < 0) fail(QH_EINVAL, "band_limit < 0");
+        hipStream_t st = (hipStream_t)stream;
+        std::unique_ptr<qh_graph> g(new qh_graph());
+        QH_HIP(hipGetDevice(&g->device));
+        g->kind = opts->kind;
+        g->storage = opts->storage;
+        g->dtype = opts->dtype;
+        g->n_snp = snps->n_snp;
+        if (read_kind) build_read_graph(g.get(), reads, snps, st);
+        else build_snp_graph(g.get(), reads, snps, opts->linkage_k, opts->band_limit, st);
+        finalize_graph(g.get(), st);
+        QH_HIP(hipStreamSynchronize(st));
+        *out = g.release();
+    });
+}
+
+qh_status qh_graph_free(qh_graph *g) {
+    return guarded([&] {
+        if (!g) return;
+        int cur = 0;
+        const int dev = g->device;
+        QH_HIP(hipGetDevice(&cur));
+        if (cur != dev) QH_HIP(hipSetDevice(dev));
+        QH_HIP(hipDeviceSynchronize());
+        delete g;
+        if (cur != dev) QH_HIP(hipSetDevice(cur));
+    });
+}
+
+qh_status qh_graph_get_info(const qh_graph *g, qh_graph_info *out) {
+    return guarded([&] {
+        if (!g || !out) fail(QH_EINVAL, "null argument");
+        qh_graph_info i{};
+        i.n = g->n;
+        i.n_snp = g->n_snp;
+        i.nnz = g->nnz;
+        i.n_comp = g->n_comp;
+        i.longrange_nnz = g->l_nnz;
+        i.dense_tiles = g->n_tiles;
+        if (g->storage == QH_STORE_DENSE) {
+            i.stored_entries = g->n_tiles * kTileElems;
+            i.stored_bytes = i.stored_entries * dtype_bytes(g->dtype) +
+                             (g->dtype == QH_FP8_ROWSCALE ? g->n * 4 : 0);
+        } else {
+            i.stored_entries = g->s_slots + g->l_nnz;
+            i.stored_bytes = i.stored_entries * dtype_bytes(g->dtype) + g->l_nnz * 4 + g->n * 16;
+        }
+        i.device_bytes = g->device_bytes;
+        i.kind = g->kind;
+        i.storage = g->storage;
+        i.dtype = g->dtype;
+        i.integer_weights = g->integer ? 1 : 0;
+        i.c0_auto = g->c0_auto;
+        *out = i;
+    });
+}
+
+qh_status qh_graph_export_rows(const qh_graph *g, int64_t row0, int64_t row1, double *out,
+                               void *stream) {
+    return guarded([&] {
+        if (!g || !out) fail(QH_EINVAL, "null argument");
+        if (row0 < 0 || row1 < row0 || row1 > g->n) fail(QH_EINVAL, "row range out of bounds");
+        export_master_rows(g, row0, row1, out, (hipStream_t)stream);
+    });
+}
+
+qh_status qh_graph_export_stored_rows(const qh_graph *g, int64_t row0, int64_t row1,
+                                      double *out, void *stream) {
+    return guarded([&] {
+        if (!g || !out) fail(QH_EINVAL, "null argument");
+        if (row0 < 0 || row1 < row0 || row1 > g->n) fail(QH_EINVAL, "row range out of bounds");
+        export_stored_rows(g, row0, row1, out, (hipStream_t)stream);
+    });
+}
+
+qh_status qh_graph_components(const qh_graph *g, int32_t *comp, void *stream) {
+    return guarded([&] {
+        if (!g || !comp) fail(QH_EINVAL, "null argument");
+        if (g->n)
+            QH_HIP(hipMemcpyAsync(comp, g->comp.p, g->n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                  (hipStream_t)stream));
+    });
+}
+
+static void validate_opts(const qh_bsb_opts *o) {
+    if (!o) fail(QH_EINVAL, "null options");
+    int R = o->replicas;
+    if (!(R == 16 || R == 32 || (R >= 64 && R % 64 == 0)) || R > 4096)
+        fail(QH_EINVAL, "replicas must be 16, 32 or a multiple of 64 (<= 4096), got %d", R);
+    if (o->steps < 1) fail(QH_EINVAL, "steps must be >= 1");
+    int end = o->step_end == 0 ? o->steps : o->step_end;
+    if (o->step_begin < 0 || end < o->step_begin || end > o->steps)
+        fail(QH_EINVAL, "step range [%d, %d) outside the schedule of %d steps", o->step_begin, end,
+             o->steps);
+    if (!(o->dt > 0.0)) fail(QH_EINVAL, "dt must be > 0");
+}
+
+qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *res, void *stream) {
+    return guarded([&] {
+        if (!g || !res) fail(QH_EINVAL, "null argument");
+        validate_opts(opts);
+        if (!opts->init && (!res->x || !res->y)) fail(QH_EINVAL, "init = 0 needs x and y");
+        if (opts->readout && (!res->best_spins || !res->cuts || !res->best_cut))
+            fail(QH_EINVAL, "readout needs best_spins, cuts and best_cut");
+        bsb_solve(g, opts, res, (hipStream_t)stream);
+    });
+}
+
+qh_status qh_bsb_solve_batched(const qh_graph *const *graphs, int32_t n_graphs,
+                               const qh_bsb_opts *opts, qh_batched_result *res, void *stream) {
+    return guarded([&] {
+        if (!graphs || !res || n_graphs < 0) fail(QH_EINVAL, "null argument");
+        validate_opts(opts);
+        for (int b = 0; b < n_graphs; ++b)
+            if (!graphs[b]) fail(QH_EINVAL, "null graph %d", b);
+        if (!res->best_spins || !res->cuts || !res->best_cut)
+            fail(QH_EINVAL, "batched solve needs best_spins, cuts and best_cut");
+        bsb_solve_batched(graphs, n_graphs, opts, res, (hipStream_t)stream);
+    });
+}
+
+qh_status qh_phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block,
+                   void *stream) {
+    return guarded([&] {
+        if (!g || !spins || !h1 || !block) fail(QH_EINVAL, "null argument");
+        phase(g, spins, h1, block, (hipStream_t)stream);
+    });
+}
+
+qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream) {
+    return guarded([&] {
+        if (!g || !spins) fail(QH_EINVAL, "null argument");
+        flip_crossing(g, spins, (hipStream_t)stream);
+    });
+}
+
+}  // extern "C"

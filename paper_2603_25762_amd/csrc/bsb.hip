@@ -1,0 +1,724 @@
+// Ballistic simulated bifurcation on gfx950 (Methods, SB algorithm solution).
+//
+// One step, for all R replicas at once:
+//   z = J x                                   (coupling product)
+//   y <- y + [-(a0 - p_k) x + c0 z] dt        (symplectic Euler, y first)
+//   x <- x + a0 y dt
+//   |x| > 1  =>  x <- sgn x, y <- 0           (inelastic walls)
+// The product and the update are fused in one kernel per step; z never
+// reaches memory.  After the last step: s = sgn(x) (sgn 0 = +1), FP64 cuts
+// per replica and component from the master couplings (Eqs. 4-6), the best
+// replica per component, and the greedy single-flip rounds.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "formats.h"
+#include "internal.h"
+
+namespace qh {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// initial state: SplitMix64 (Steele, Lea & Flood 2014), draw k = 2 (r n + i) + {0, 1}
+// ---------------------------------------------------------------------------
+
+__device__ inline uint64_t sm64_draw(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_init(uint64_t seed, int64_t n, int R, float *__restrict__ x, float *__restrict__ y) {
+    int64_t total = n * R;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = t / R, r = t - i * R;
+        uint64_t c = 2ull * ((uint64_t)r * (uint64_t)n + (uint64_t)i);
+        double ux = (double)(sm64_draw(seed, c) >> 11) * 0x1.0p-53;
+        double uy = (double)(sm64_draw(seed, c + 1) >> 11) * 0x1.0p-53;
+        x[t] = (float)(0.2 * ux - 0.1);
+        y[t] = (float)(0.2 * uy - 0.1);
+    }
+}
+
+__global__ void k_pump_linear(int steps, float *__restrict__ p) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < steps; k += gridDim.x * blockDim.x)
+        p[k] = steps > 1 ? (float)((double)k / (double)(steps - 1)) : 0.0f;
+}
+
+// 16-bit product copy of x in the layout [n_pad / 8][R][8]: eight consecutive
+// rows of one replica are contiguous, which is the B-operand register order of
+// v_mfma_f32_16x16x32_{f16,bf16}.
+template <bool BF16>
+__global__ void k_x_to_h(int64_t n, int R, const float *__restrict__ x, uint16_t *__restrict__ h) {
+    int64_t total = n * R;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = t / R, r = t - i * R;
+        float v = x[t];
+        h[((i >> 3) * R + r) * 8 + (i & 7)] = BF16 ? f32_to_bf16_rne(v) : f32_to_f16_rne(v);
+    }
+}
+
+struct StepArgs {
+    float c0, dt, a0;
+    const float *pump;
+    int k;
+};
+
+__device__ inline void bsb_update(float z, float &x, float &y, float coef, const StepArgs &s) {
+    float yn = y + (-coef * x + s.c0 * z) * s.dt;
+    float xn = x + s.a0 * yn * s.dt;
+    if (fabsf(xn) > 1.0f) {
+        xn = xn > 0.0f ? 1.0f : -1.0f;
+        yn = 0.0f;
+    }
+    x = xn;
+    y = yn;
+}
+
+// XCD-aware block index: hardware dispatches workgroup b to XCD b % 8; give each
+// XCD a contiguous range of logical tiles so that neighbouring row tiles (which
+// share columns of x) meet in the same L2.
+__device__ inline int64_t xcd_remap(int64_t bid, int64_t G) {
+    int64_t xcd = bid & 7, q = bid >> 3;
+    int64_t per = G >> 3, rem = G & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + q;
+}
+
+// ---------------------------------------------------------------------------
+// dense tiles, MFMA product (read graphs)
+// ---------------------------------------------------------------------------
+// Workgroup = 4 waves = one 64-row tile x RT replicas.  Wave w owns rows
+// 16w..16w+15 of the tile and NB = RT/16 replica blocks of 16.
+//  DT = QH_F16 / QH_BF16: v_mfma_f32_16x16x32_{f16,bf16}, A = stored tile fragment,
+//       B = 16-bit copy of x.
+//  DT = QH_FP8_ROWSCALE: E4M3 codes expanded exactly to f16 (value * 2^-8) in
+//       registers; the row scale (x 256) multiplies z in the epilogue.
+//  DT = QH_F32: v_mfma_f32_16x16x4f32 on the FP32 tile and FP32 x.
+template <int DT, int NB>
+__global__ __launch_bounds__(256) void k_dense_step(
+    int64_t n, int R, int64_t n_rt, int64_t G, const int32_t *__restrict__ t_ptr,
+    const int32_t *__restrict__ t_col, const uint8_t *__restrict__ t_val, const float *__restrict__ row_scale,
+    const float *x_in, float *x_out, float *__restrict__ y,
+    const uint16_t *__restrict__ h_in, uint16_t *__restrict__ h_out, StepArgs sa) {
+    constexpr int RT = NB * 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t logical = xcd_remap(blockIdx.x, G);
+    const int64_t rt = logical % n_rt;
+    const int64_t r0 = (logical / n_rt) * RT;
+    const int l16 = lane & 15, g4 = lane >> 4;
+
+    float4_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int t_beg = t_ptr[rt], t_end = t_ptr[rt + 1];
+    for (int t = t_beg; t < t_end; ++t) {
+        const int64_t j0 = (int64_t)t_col[t] * kTile;
+        if constexpr (DT == QH_F32) {
+            const float *tile = (const float *)t_val + (int64_t)t * kTileElems;
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) {
+                float4_t a4 = *(const float4_t *)(tile + (((wave * 4 + kq) * 64 + lane) << 2));
+#pragma unroll
+                for (int e4 = 0; e4 < 4; ++e4) {
+                    const int64_t j = j0 + (kq * 4 + e4) * 4 + g4;
+                    const float *xr = x_in + j * R + r0 + l16;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[e4], xr[b * 16], acc[b], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const int frag = wave * 2 + kb;
+                half8_t a;
+                if constexpr (DT == QH_FP8_ROWSCALE) {
+                    const uint8_t *tile = t_val + (int64_t)t * kTileElems;
+                    uint2 c = *(const uint2 *)(tile + ((frag * 64 + lane) << 3));
+                    uint16_t hb[8];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        hb[e] = e4m3_to_f16_bits_scaled((uint8_t)(c.x >> (8 * e)));
+                        hb[4 + e] = e4m3_to_f16_bits_scaled((uint8_t)(c.y >> (8 * e)));
+                    }
+                    __builtin_memcpy(&a, hb, 16);
+                } else {
+                    const uint16_t *tile = (const uint16_t *)t_val + (int64_t)t * kTileElems;
+                    a = *(const half8_t *)(tile + ((frag * 64 + lane) << 3));
+                }
+                const int64_t jg = (j0 + kb * 32) / 8 + g4;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const uint16_t *hp = h_in + (jg * R + r0 + b * 16 + l16) * 8;
+                    if constexpr (DT == QH_BF16) {
+                        bf16x8_t bv = *(const bf16x8_t *)hp;
+                        bf16x8_t av;
+                        __builtin_memcpy(&av, &a, 16);
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
+                    } else {
+                        half8_t bv = *(const half8_t *)hp;
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, bv, acc[b], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+
+    // fused update: lane holds z for rows 4*g4 + q (q = 0..3) and replica l16 of each block
+    const float coef = sa.a0 - sa.pump[sa.k];
+    const int64_t rowbase = rt * kTile + wave * 16 + 4 * g4;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int64_t r = r0 + b * 16 + l16;
+        uint16_t hv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = rowbase + q;
+            hv[q] = 0;
+            if (i < n) {
+                float z = acc[b][q];
+                if constexpr (DT == QH_FP8_ROWSCALE) z *= row_scale[i];
+                const int64_t idx = i * R + r;
+                float xv = x_in[idx], yv = y[idx];
+                bsb_update(z, xv, yv, coef, sa);
+                y[idx] = yv;
+                x_out[idx] = xv;
+                if constexpr (DT == QH_BF16) hv[q] = f32_to_bf16_rne(xv);
+                else if constexpr (DT != QH_F32) hv[q] = f32_to_f16_rne(xv);
+            }
+        }
+        if constexpr (DT != QH_F32) {
+            // rows rowbase..rowbase+3 share one 8-row group: one 8-byte store
+            uint2 pk;
+            pk.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
+            pk.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
+            *(uint2 *)(h_out + ((rowbase >> 3) * R + r) * 8 + (rowbase & 7)) = pk;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// skyline band + long-range CSR (SNP graphs)
+// ---------------------------------------------------------------------------
+
+template <int DT>
+__device__ inline float ld_val(const uint8_t *__restrict__ p, int64_t e) {
+    if constexpr (DT == QH_F32) return ((const float *)p)[e];
+    else if constexpr (DT == QH_F16) return f16_bits_to_f32(((const uint16_t *)p)[e]);
+    else return bf16_bits_to_f32(((const uint16_t *)p)[e]);
+}
+
+// Partial sums of the long-range lists of hub rows, kHubChunk entries each.
+template <int DT, int RT>
+__global__ __launch_bounds__(256) void k_hub_partials(
+    int64_t n_chunks, int R, const int32_t *__restrict__ chunk_row, const int64_t *__restrict__ cbeg,
+    const int64_t *__restrict__ cend, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
+    const float *__restrict__ x_in, float *__restrict__ part) {
+    constexpr int RPW = 64 / RT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sub = lane / RT, rr = lane % RT;
+    const int64_t r = (int64_t)blockIdx.y * RT + rr;
+    for (int64_t c = (int64_t)blockIdx.x * 4 * RPW + wave * RPW + sub; c < n_chunks;
+         c += (int64_t)gridDim.x * 4 * RPW) {
+        float z = 0.f;
+        for (int64_t e = cbeg[c]; e < cend[c]; ++e) z += ld_val<DT>(l_val, e) * x_in[(int64_t)l_col[e] * R + r];
+        part[c * R + r] = z;
+    }
+}
+
+// One wave handles RPW = 64/RT rows x RT replicas; lane = (row slot, replica).
+template <int DT, int RT>
+__global__ __launch_bounds__(256) void k_sky_step(
+    int64_t n, int R, int64_t rows_per_wg, int64_t G, const int64_t *__restrict__ s_off,
+    const int32_t *__restrict__ s_lo, const int32_t *__restrict__ s_len, const uint8_t *__restrict__ s_val,
+    const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
+    const int32_t *__restrict__ hub_of_row, const int32_t *__restrict__ hub_chunk_ptr,
+    const float *__restrict__ hub_part, const float *__restrict__ x_in, float *__restrict__ x_out,
+    float *__restrict__ y, StepArgs sa) {
+    constexpr int RPW = 64 / RT;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sub = lane / RT, rr = lane % RT;
+    const int64_t blk = xcd_remap(blockIdx.x, G);
+    const int64_t row_begin = blk * rows_per_wg;
+    const int64_t row_end = row_begin + rows_per_wg < n ? row_begin + rows_per_wg : n;
+    const int64_t r = (int64_t)blockIdx.y * RT + rr;
+    const float coef = sa.a0 - sa.pump[sa.k];
+    for (int64_t ub = row_begin + wave * RPW; ub < row_end; ub += 4 * RPW) {
+        const int64_t u = ub + sub;
+        if (u >= row_end) continue;
+        const int32_t lo = s_lo[u];
+        const int32_t len = s_len[u];
+        const int64_t off = s_off[u];
+        float z = 0.f;
+        const float *xc = x_in + (int64_t)lo * R + r;
+#pragma unroll 8
+        for (int e = 0; e < len; ++e) z += ld_val<DT>(s_val, off + e) * xc[(int64_t)e * R];
+        if (l_ptr) {
+            const int hub = hub_of_row[u];
+            if (hub < 0) {
+                for (int64_t e = l_ptr[u]; e < l_ptr[u + 1]; ++e)
+                    z += ld_val<DT>(l_val, e) * x_in[(int64_t)l_col[e] * R + r];
+            } else {
+                for (int c = hub_chunk_ptr[hub]; c < hub_chunk_ptr[hub + 1]; ++c) z += hub_part[(int64_t)c * R + r];
+            }
+        }
+        const int64_t idx = u * R + r;
+        float xv = x_in[idx], yv = y[idx];
+        bsb_update(z, xv, yv, coef, sa);
+        y[idx] = yv;
+        x_out[idx] = xv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// readout
+// ---------------------------------------------------------------------------
+
+__global__ void k_signs(int64_t n, int R, const float *__restrict__ x, const float *__restrict__ y,
+                        int8_t *__restrict__ s, int32_t *__restrict__ bad) {
+    int64_t total = n * R;
+    int local_bad = 0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        float v = x[t];
+        if (!isfinite(v) || !isfinite(y[t])) local_bad = 1;
+        s[t] = v >= 0.0f ? 1 : -1;
+    }
+    if (local_bad) atomicOr(bad, 1);
+}
+
+// Chunk partials of cut_{r,c} = 1/4 sum_{a in c} sum_j A_aj (1 - s_a s_j), A = -J.
+__global__ void k_cut_chunks(int64_t n_chunks, int R, const int32_t *__restrict__ chunk_begin,
+                             const int32_t *__restrict__ chunk_end, const int32_t *__restrict__ order,
+                             const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                             const double *__restrict__ val, const int8_t *__restrict__ s,
+                             double *__restrict__ part) {
+    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+        for (int r = threadIdx.x; r < R; r += blockDim.x) {
+            double acc = 0.0;
+            for (int v = chunk_begin[ch]; v < chunk_end[ch]; ++v) {
+                const int64_t a = order[v];
+                const int sa = s[a * R + r];
+                double racc = 0.0;
+                for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
+                    const int sb = s[(int64_t)col[e] * R + r];
+                    racc += -val[e] * (1.0 - (double)(sa * sb));
+                }
+                acc += 0.25 * racc;
+            }
+            part[ch * R + r] = acc;
+        }
+    }
+}
+
+__global__ void k_cut_reduce(int64_t n_comp, int R, const int32_t *__restrict__ comp_chunk_ptr,
+                             const double *__restrict__ part, double *__restrict__ cut_rc) {
+    for (int64_t c = blockIdx.x; c < n_comp; c += gridDim.x)
+        for (int r = threadIdx.x; r < R; r += blockDim.x) {
+            double acc = 0.0;
+            for (int ch = comp_chunk_ptr[c]; ch < comp_chunk_ptr[c + 1]; ++ch) acc += part[(int64_t)ch * R + r];
+            cut_rc[(int64_t)r * n_comp + c] = acc;
+        }
+}
+
+__global__ void k_select(int64_t n_comp, int R, const double *__restrict__ cut_rc, int32_t *__restrict__ best_r) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n_comp;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int br = 0;
+        double bv = cut_rc[c];
+        for (int r = 1; r < R; ++r) {
+            double v = cut_rc[(int64_t)r * n_comp + c];
+            if (v > bv) { bv = v; br = r; }
+        }
+        best_r[c] = br;
+    }
+}
+
+__global__ void k_replica_totals(int64_t n_comp, int R, const double *__restrict__ cut_rc,
+                                 double *__restrict__ cuts) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int64_t c = 0; c < n_comp; ++c) acc += cut_rc[(int64_t)r * n_comp + c];
+        cuts[r] = acc;
+    }
+}
+
+// Deterministic sum of cut_rc[best_r[c]][c] over components (fixed tree).
+__global__ void k_selected_total(int64_t n_comp, const double *__restrict__ cut_rc,
+                                 const int32_t *__restrict__ best_r, double *__restrict__ out) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t c = threadIdx.x; c < n_comp; c += blockDim.x)
+        acc += best_r ? cut_rc[(int64_t)best_r[c] * n_comp + c] : cut_rc[c];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void k_best_spins(int64_t n, int R, const int32_t *__restrict__ comp,
+                             const int32_t *__restrict__ comp_first, const int32_t *__restrict__ best_r,
+                             const int8_t *__restrict__ s, int8_t *__restrict__ best) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        int c = comp[a];
+        if (c < 0) { best[a] = 1; continue; }
+        int rb = best_r[c];
+        int v = s[a * R + rb];
+        int o = s[(int64_t)comp_first[c] * R + rb];
+        best[a] = (int8_t)(v * o);
+    }
+}
+
+// Greedy single-flip rounds: g_a = s_a sum_j A_aj s_j, A = -J.
+__global__ void k_gain(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                       const double *__restrict__ val, const int8_t *__restrict__ s, double *__restrict__ g) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) acc += -val[e] * (double)s[col[e]];
+        g[a] = (double)s[a] * acc;
+    }
+}
+
+// Vertex a flips when g_a > eps and it beats every improving neighbour
+// (larger gain, or equal gain and lower index): the flipped set is independent.
+__global__ void k_pick(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                       const double *__restrict__ g, double eps, int8_t *__restrict__ flag,
+                       int32_t *__restrict__ count) {
+    int local = 0;
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        int8_t f = 0;
+        double ga = g[a];
+        if (ga > eps) {
+            f = 1;
+            for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
+                int64_t j = col[e];
+                double gj = g[j];
+                if (gj > eps && (gj > ga || (gj == ga && j < a))) { f = 0; break; }
+            }
+        }
+        flag[a] = f;
+        local += f;
+    }
+    if (local) atomicAdd(count, local);
+}
+
+__global__ void k_apply_flips(int64_t n, const int8_t *__restrict__ flag, int8_t *__restrict__ s) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
+         a += (int64_t)gridDim.x * blockDim.x)
+        if (flag[a]) s[a] = (int8_t)-s[a];
+}
+
+__global__ void k_copy_state_in(int64_t n, int R, const float *__restrict__ src, float *__restrict__ dst) {
+    int64_t total = n * R;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = src[t];
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+
+static int grid_for(int64_t n, int block = 256, int64_t cap = 65536) {
+    int64_t g = ceil_div(n, block);
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+static SolvePlan &get_plan(const qh_graph *gc, int R, hipStream_t st) {
+    qh_graph *g = const_cast<qh_graph *>(gc);
+    auto it = g->plans.find(R);
+    if (it != g->plans.end()) return *it->second;
+    std::unique_ptr<SolvePlan> p(new SolvePlan());
+    p->R = R;
+    p->n_pad = ceil_div(std::max<int64_t>(g->n, 1), kTile) * kTile;
+    size_t st_elems = (size_t)p->n_pad * R;
+    p->xa.alloc(st_elems);
+    p->xa.zero(st);
+    p->y.alloc(st_elems);
+    p->y.zero(st);
+    bool dense16 = g->storage == QH_STORE_DENSE && g->dtype != QH_F32;
+    if (!dense16) {
+        p->xb.alloc(st_elems);
+        p->xb.zero(st);
+    } else {
+        p->ha.alloc(st_elems);
+        p->ha.zero(st);
+        p->hb.alloc(st_elems);
+        p->hb.zero(st);
+    }
+    p->spins.alloc((size_t)std::max<int64_t>(g->n, 1) * R);
+    p->part.alloc((size_t)std::max<int64_t>(g->n_chunks, 1) * R);
+    p->cut_rc.alloc((size_t)std::max<int64_t>(g->n_comp, 1) * R);
+    p->best_r.alloc(std::max<int64_t>(g->n_comp, 1));
+    p->gain.alloc(std::max<int64_t>(g->n, 1));
+    p->flag.alloc(std::max<int64_t>(g->n, 1));
+    p->counter.alloc(4);
+    p->part1.alloc(std::max<int64_t>(g->n_chunks, 1));
+    p->cut1.alloc(std::max<int64_t>(g->n_comp, 1));
+    if (g->n_hub_chunks) p->hub_part.alloc((size_t)g->n_hub_chunks * R);
+    SolvePlan &ref = *p;
+    g->plans[R] = std::move(p);
+    return ref;
+}
+
+// Launch one step k of the schedule.  `cur` selects the ping-pong half holding x (or h).
+static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int cur, hipStream_t st) {
+    const int R = p.R;
+    const int64_t n = g->n;
+    if (g->storage == QH_STORE_DENSE) {
+        const int RT = R >= 64 ? 64 : R;
+        const int64_t G = g->n_rt * (R / RT);
+        if (G == 0) return;
+        float *xin = cur ? p.xb.p : p.xa.p;
+        float *xout = cur ? p.xa.p : p.xb.p;
+        const uint16_t *hin = cur ? p.hb.p : p.ha.p;
+        uint16_t *hout = cur ? p.ha.p : p.hb.p;
+#define QH_DENSE(DTV, NBV)                                                                                  \
+    hipLaunchKernelGGL((k_dense_step<DTV, NBV>), dim3((unsigned)G), dim3(256), 0, st, n, R, g->n_rt, G,         \
+                       g->t_ptr.p, g->t_col.p, g->t_val.p, g->row_scale.p,                                   \
+                       DTV == QH_F32 ? xin : p.xa.p, DTV == QH_F32 ? xout : p.xa.p, p.y.p, hin, hout, sa)
+#define QH_DENSE_NB(DTV)                      \
+    do {                                      \
+        if (RT == 16) QH_DENSE(DTV, 1);       \
+        else if (RT == 32) QH_DENSE(DTV, 2);  \
+        else QH_DENSE(DTV, 4);                \
+    } while (0)
+        switch (g->dtype) {
+            case QH_F32: QH_DENSE_NB(QH_F32); break;
+            case QH_F16: QH_DENSE_NB(QH_F16); break;
+            case QH_BF16: QH_DENSE_NB(QH_BF16); break;
+            case QH_FP8_ROWSCALE: QH_DENSE_NB(QH_FP8_ROWSCALE); break;
+        }
+#undef QH_DENSE_NB
+#undef QH_DENSE
+        QH_CHECK_LAUNCH();
+        return;
+    }
+    // skyline
+    const int RT = R >= 64 ? 64 : R;
+    const int64_t rows_per_wg = 64;
+    const int64_t nblk = ceil_div(n, rows_per_wg);
+    if (nblk == 0) return;
+    const float *xin = cur ? p.xb.p : p.xa.p;
+    float *xout = cur ? p.xa.p : p.xb.p;
+    const bool lr = g->l_nnz > 0;
+    dim3 grid((unsigned)nblk, (unsigned)(R / RT));
+#define QH_HUB(DTV, RTV)                                                                                        \
+    hipLaunchKernelGGL((k_hub_partials<DTV, RTV>), dim3((unsigned)grid_for(g->n_hub_chunks, 4 * (64 / RTV), 4096), \
+                                                        (unsigned)(R / RTV)),                                       \
+                       dim3(256), 0, st, g->n_hub_chunks, R, g->hub_chunk_row.p, g->hub_chunk_beg.p,           \
+                       g->hub_chunk_end.p, g->l_col.p, g->l_val.p, xin, p.hub_part.p)
+#define QH_SKY(DTV, RTV)                                                                                       \
+    hipLaunchKernelGGL((k_sky_step<DTV, RTV>), grid, dim3(256), 0, st, n, R, rows_per_wg, nblk, g->s_off.p,    \
+                       g->s_lo.p, g->s_len.p, g->s_val.p, lr ? g->l_ptr.p : nullptr, g->l_col.p, g->l_val.p,    \
+                       g->hub_of_row.p, g->hub_chunk_ptr.p, p.hub_part.p, xin, xout, p.y.p, sa)
+#define QH_SKY_RT(DTV)                                                  \
+    do {                                                                \
+        if (RT == 16) { if (g->n_hub_chunks) QH_HUB(DTV, 16); QH_SKY(DTV, 16); } \
+        else if (RT == 32) { if (g->n_hub_chunks) QH_HUB(DTV, 32); QH_SKY(DTV, 32); } \
+        else { if (g->n_hub_chunks) QH_HUB(DTV, 64); QH_SKY(DTV, 64); }  \
+    } while (0)
+    switch (g->dtype) {
+        case QH_F32: QH_SKY_RT(QH_F32); break;
+        case QH_F16: QH_SKY_RT(QH_F16); break;
+        case QH_BF16: QH_SKY_RT(QH_BF16); break;
+        default: fail(QH_EUNSUPPORTED, "dtype not offered on skyline storage");
+    }
+#undef QH_SKY_RT
+#undef QH_SKY
+#undef QH_HUB
+    QH_CHECK_LAUNCH();
+}
+
+static bool x_pingpong(const qh_graph *g) { return !(g->storage == QH_STORE_DENSE && g->dtype != QH_F32); }
+
+// Launch steps [kb, ke); returns the ping-pong half that holds the final state.
+static int run_steps(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, const float *pump, double c0, double a0,
+                     int kb, int ke, hipStream_t st) {
+    StepArgs sa;
+    sa.c0 = (float)c0;
+    sa.dt = (float)o->dt;
+    sa.a0 = (float)a0;
+    sa.pump = pump;
+    int cur = 0;
+    for (int k = kb; k < ke; ++k) {
+        sa.k = k;
+        launch_step(g, p, sa, cur, st);
+        cur ^= 1;
+    }
+    return cur;
+}
+
+void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStream_t st) {
+    int cur_dev = 0;
+    QH_HIP(hipGetDevice(&cur_dev));
+    if (cur_dev != g->device) fail(QH_EINVAL, "graph lives on device %d, current device is %d", g->device, cur_dev);
+    const int R = o->replicas;
+    const int64_t n = g->n;
+    SolvePlan &p = get_plan(g, R, st);
+    const int kb = o->step_begin, ke = o->step_end == 0 ? o->steps : o->step_end;
+    const double c0 = o->c0 > 0.0 ? o->c0 : g->c0_auto;
+    const double a0 = o->a0 > 0.0 ? o->a0 : 1.0;
+    const float *pump = o->pump;
+    if (!pump) {
+        if (p.pump_steps != o->steps) {
+            p.pump_lin.alloc(o->steps);
+            hipLaunchKernelGGL(k_pump_linear, dim3(grid_for(o->steps)), dim3(256), 0, st, o->steps, p.pump_lin.p);
+            QH_CHECK_LAUNCH();
+            p.pump_steps = o->steps;
+        }
+        pump = p.pump_lin.p;
+    }
+    const int64_t nR = n * R;
+    // initial state into xa / y
+    if (o->init) {
+        if (nR) {
+            hipLaunchKernelGGL(k_init, dim3(grid_for(nR)), dim3(256), 0, st, o->seed, n, R, p.xa.p, p.y.p);
+            QH_CHECK_LAUNCH();
+        }
+    } else if (nR) {
+        hipLaunchKernelGGL(k_copy_state_in, dim3(grid_for(nR)), dim3(256), 0, st, n, R, res->x, p.xa.p);
+        hipLaunchKernelGGL(k_copy_state_in, dim3(grid_for(nR)), dim3(256), 0, st, n, R, res->y, p.y.p);
+        QH_CHECK_LAUNCH();
+    }
+    const bool dense16 = !x_pingpong(g);
+    if (dense16 && nR) {
+        if (g->dtype == QH_BF16)
+            hipLaunchKernelGGL(k_x_to_h<true>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p);
+        else
+            hipLaunchKernelGGL(k_x_to_h<false>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p);
+        QH_CHECK_LAUNCH();
+    }
+
+    // the step loop
+    int final_half = 0;
+    if (ke > kb && n > 0) {
+        if (o->use_graph) {
+            auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R);
+            if (!p.exec || p.graph_key != key) {
+                if (p.exec) { (void)hipGraphExecDestroy(p.exec); p.exec = nullptr; }
+                if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }
+                hipStream_t cs;
+                QH_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+                QH_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                try {
+                    run_steps(g, p, o, pump, c0, a0, kb, ke, cs);
+                } catch (...) {
+                    hipGraph_t junk = nullptr;
+                    (void)hipStreamEndCapture(cs, &junk);
+                    if (junk) (void)hipGraphDestroy(junk);
+                    (void)hipStreamDestroy(cs);
+                    throw;
+                }
+                QH_HIP(hipStreamEndCapture(cs, &p.graph));
+                QH_HIP(hipStreamDestroy(cs));
+                QH_HIP(hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0));
+                p.graph_key = key;
+            }
+            QH_HIP(hipGraphLaunch(p.exec, st));
+            final_half = (ke - kb) & 1;
+        } else {
+            final_half = run_steps(g, p, o, pump, c0, a0, kb, ke, st);
+        }
+    }
+    const float *xfin = (!dense16 && final_half) ? p.xb.p : p.xa.p;
+    if (res->x && nR) QH_HIP(hipMemcpyAsync(res->x, xfin, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (res->y && nR) QH_HIP(hipMemcpyAsync(res->y, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (!o->readout) return;
+
+    // signs + NaN watchdog
+    QH_HIP(hipMemsetAsync(p.counter.p, 0, 4 * sizeof(int32_t), st));
+    if (nR) {
+        hipLaunchKernelGGL(k_signs, dim3(grid_for(nR)), dim3(256), 0, st, n, R, xfin, p.y.p, p.spins.p,
+                           p.counter.p + 1);
+        QH_CHECK_LAUNCH();
+    }
+    if (res->all_spins && nR)
+        QH_HIP(hipMemcpyAsync(res->all_spins, p.spins.p, nR, hipMemcpyDeviceToDevice, st));
+    // FP64 cuts per replica and component
+    const int64_t nc = g->n_comp;
+    if (nc) {
+        hipLaunchKernelGGL(k_cut_chunks, dim3((unsigned)std::min<int64_t>(g->n_chunks, 1 << 20)), dim3(256), 0, st,
+                           g->n_chunks, R, g->chunk_begin.p, g->chunk_end.p, g->comp_order.p, g->m_ptr.p,
+                           g->m_col.p, g->m_val.p, p.spins.p, p.part.p);
+        hipLaunchKernelGGL(k_cut_reduce, dim3((unsigned)std::min<int64_t>(nc, 1 << 20)), dim3(256), 0, st, nc, R,
+                           g->comp_chunk_ptr.p, p.part.p, p.cut_rc.p);
+        hipLaunchKernelGGL(k_select, dim3(grid_for(nc)), dim3(256), 0, st, nc, R, p.cut_rc.p, p.best_r.p);
+        QH_CHECK_LAUNCH();
+    }
+    if (nc) {
+        hipLaunchKernelGGL(k_replica_totals, dim3(grid_for(R)), dim3(256), 0, st, nc, R, p.cut_rc.p, res->cuts);
+        hipLaunchKernelGGL(k_selected_total, dim3(1), dim3(256), 0, st, nc, p.cut_rc.p, p.best_r.p,
+                           res->selected_cut ? res->selected_cut : res->best_cut);
+        QH_CHECK_LAUNCH();
+    } else {
+        QH_HIP(hipMemsetAsync(res->cuts, 0, R * sizeof(double), st));
+        QH_HIP(hipMemsetAsync(res->selected_cut ? res->selected_cut : res->best_cut, 0, sizeof(double), st));
+    }
+    if (res->cut_rc && nc)
+        QH_HIP(hipMemcpyAsync(res->cut_rc, p.cut_rc.p, nc * R * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (res->best_replica && nc)
+        QH_HIP(hipMemcpyAsync(res->best_replica, p.best_r.p, nc * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (n) {
+        hipLaunchKernelGGL(k_best_spins, dim3(grid_for(n)), dim3(256), 0, st, n, R, g->comp.p, g->comp_first.p,
+                           p.best_r.p, p.spins.p, res->best_spins);
+        QH_CHECK_LAUNCH();
+    }
+    int32_t rounds = 0;
+    if (o->greedy && n && nc) {
+        for (int it = 0; it < 100000; ++it) {
+            hipLaunchKernelGGL(k_gain, dim3(grid_for(n)), dim3(256), 0, st, n, g->m_ptr.p, g->m_col.p, g->m_val.p,
+                               res->best_spins, p.gain.p);
+            QH_HIP(hipMemsetAsync(p.counter.p, 0, sizeof(int32_t), st));
+            hipLaunchKernelGGL(k_pick, dim3(grid_for(n)), dim3(256), 0, st, n, g->m_ptr.p, g->m_col.p, p.gain.p,
+                               g->greedy_eps, p.flag.p, p.counter.p);
+            QH_CHECK_LAUNCH();
+            int32_t cnt = 0;
+            QH_HIP(hipMemcpyAsync(&cnt, p.counter.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            QH_HIP(hipStreamSynchronize(st));
+            if (cnt == 0) break;
+            hipLaunchKernelGGL(k_apply_flips, dim3(grid_for(n)), dim3(256), 0, st, n, p.flag.p, res->best_spins);
+            QH_CHECK_LAUNCH();
+            ++rounds;
+        }
+    }
+    // cut of the final spins
+    if (nc) {
+        hipLaunchKernelGGL(k_cut_chunks, dim3((unsigned)std::min<int64_t>(g->n_chunks, 1 << 20)), dim3(64), 0, st,
+                           g->n_chunks, 1, g->chunk_begin.p, g->chunk_end.p, g->comp_order.p, g->m_ptr.p,
+                           g->m_col.p, g->m_val.p, res->best_spins, p.part1.p);
+        hipLaunchKernelGGL(k_cut_reduce, dim3((unsigned)std::min<int64_t>(nc, 1 << 20)), dim3(64), 0, st, nc, 1,
+                           g->comp_chunk_ptr.p, p.part1.p, p.cut1.p);
+        hipLaunchKernelGGL(k_selected_total, dim3(1), dim3(256), 0, st, nc, p.cut1.p, (const int32_t *)nullptr,
+                           res->best_cut);
+        QH_CHECK_LAUNCH();
+    } else {
+        QH_HIP(hipMemsetAsync(res->best_cut, 0, sizeof(double), st));
+    }
+    if (res->greedy_rounds)
+        QH_HIP(hipMemcpyAsync(res->greedy_rounds, &rounds, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    int32_t bad = 0;
+    QH_HIP(hipMemcpyAsync(&bad, p.counter.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    QH_HIP(hipStreamSynchronize(st));
+    if (bad) fail(QH_ENUMERIC, "non-finite spin or momentum in the final state");
+}
+
+}  // namespace qh

@@ -1,0 +1,893 @@
+// Graph construction: ternary encoding (Eq. 1), read-graph conflict / signed
+// weights (Eqs. 2-3), SNP-graph log-likelihood weights (Eqs. 9-14), the FP64
+// master CSR, connected components, and the storage copies used by the step
+// kernels (dense MFMA-ordered tiles, skyline band + long-range CSR) in the
+// requested number format.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "formats.h"
+#include "internal.h"
+
+namespace qh {
+
+// ---------------------------------------------------------------------------
+// device kernels
+// ---------------------------------------------------------------------------
+
+// Eq. (1): M = +1 where the observed allele is the one placed on H1, else -1.
+__global__ void k_encode(int64_t nobs, const int32_t *__restrict__ snp,
+                         const uint8_t *__restrict__ allele, const uint8_t *__restrict__ init_h1,
+                         int8_t *__restrict__ M) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nobs;
+         t += (int64_t)gridDim.x * blockDim.x)
+        M[t] = (allele[t] == init_h1[snp[t]]) ? 1 : -1;
+}
+
+__global__ void k_gather_i8(int64_t n, const int64_t *__restrict__ idx, const int8_t *__restrict__ src,
+                            int8_t *__restrict__ dst) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        dst[t] = src[idx[t]];
+}
+
+// Eqs. (2)-(3): every ordered pair of fragments covering SNP column j adds its
+// per-column term.  conflict: 1[M_a M_b = -1] (stored as A); signed: M_a M_b (J).
+__global__ void k_read_pairs(int32_t n_cols, const int64_t *__restrict__ cov_ptr,
+                             const int32_t *__restrict__ cov_frag, const int8_t *__restrict__ cov_M,
+                             int32_t *__restrict__ W, int64_t F, int conflict) {
+    for (int64_t j = blockIdx.x; j < n_cols; j += gridDim.x) {
+        int64_t b = cov_ptr[j], c = cov_ptr[j + 1] - b;
+        for (int64_t t = threadIdx.x; t < c * c; t += blockDim.x) {
+            int64_t p = t / c, q = t - p * c;
+            if (p == q) continue;
+            int prod = (int)cov_M[b + p] * (int)cov_M[b + q];
+            int v = conflict ? (prod == -1 ? 1 : 0) : prod;
+            if (v) atomicAdd(&W[(int64_t)cov_frag[b + p] * F + cov_frag[b + q]], v);
+        }
+    }
+}
+
+// Nonzero count per row of a dense int32 matrix (one wave per row).
+__global__ void k_dense_row_nnz(int64_t F, const int32_t *__restrict__ W, int64_t *__restrict__ cnt) {
+    int lane = threadIdx.x & 63;
+    int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= F) return;
+    int64_t c = 0;
+    for (int64_t col = lane; col < F; col += 64) c += (W[row * F + col] != 0);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if (lane == 0) cnt[row] = c;
+}
+
+// Ordered compaction of the nonzeros of each dense row into the master CSR.
+__global__ void k_dense_row_fill(int64_t F, const int32_t *__restrict__ W, int negate,
+                                 const int64_t *__restrict__ ptr, int32_t *__restrict__ col,
+                                 double *__restrict__ val) {
+    int lane = threadIdx.x & 63;
+    int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= F) return;
+    int64_t out = ptr[row];
+    for (int64_t c0 = 0; c0 < F; c0 += 64) {
+        int64_t c = c0 + lane;
+        int w = c < F ? W[row * F + c] : 0;
+        uint64_t mask = __ballot(w != 0);
+        if (w != 0) {
+            int before = __popcll(mask & ((1ull << lane) - 1ull));
+            col[out + before] = (int32_t)c;
+            val[out + before] = negate ? -(double)w : (double)w;
+        }
+        out += __popcll(mask);
+    }
+}
+
+// Occupancy of each 64x64 tile of a dense matrix.
+__global__ void k_tile_occupancy(int64_t F, int64_t n_rt, const int32_t *__restrict__ W,
+                                 uint8_t *__restrict__ occ) {
+    int64_t rt = blockIdx.y, ct = blockIdx.x;
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int found = 0;
+    for (int e = threadIdx.x; e < kTileElems; e += blockDim.x) {
+        int64_t i = rt * kTile + (e >> 6), j = ct * kTile + (e & 63);
+        if (i < F && j < F && W[i * F + j] != 0) found = 1;
+    }
+    if (found) atomicOr(&any, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) occ[rt * n_rt + ct] = (uint8_t)any;
+}
+
+// Per-row max |J| over the master CSR (one thread per row).
+__global__ void k_row_absmax(int64_t n, const int64_t *__restrict__ ptr,
+                             const double *__restrict__ val, double *__restrict__ out) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        double m = 0.0;
+        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) m = fmax(m, fabs(val[e]));
+        out[r] = m;
+    }
+}
+
+// Per-row sum |J| (greedy tolerance for float weights).
+__global__ void k_row_abssum(int64_t n, const int64_t *__restrict__ ptr,
+                             const double *__restrict__ val, double *__restrict__ out) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        double m = 0.0;
+        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) m += fabs(val[e]);
+        out[r] = m;
+    }
+}
+
+// FP8 row scale s_i = RNE_f32(max_j |J_ij| / 448); the kernels use 256 s_i because the
+// code decode yields code * 2^-8.
+__global__ void k_fp8_scales(int64_t n, const double *__restrict__ rmax, float *__restrict__ scale,
+                             float *__restrict__ scale_dec) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        float s = (float)(rmax[r] / 448.0);
+        scale[r] = s;
+        scale_dec[r] = s * 256.0f;
+    }
+}
+
+// Pack the stored tiles of a dense matrix in MFMA fragment order and number format.
+__global__ void k_pack_tiles(int64_t F, const int32_t *__restrict__ W, int negate,
+                             const int32_t *__restrict__ tile_row, const int32_t *__restrict__ tile_col,
+                             int dtype, const float *__restrict__ scale, uint8_t *__restrict__ out) {
+    int64_t t = blockIdx.x;
+    int64_t rt = tile_row[t], ct = tile_col[t];
+    for (int idx = threadIdx.x; idx < kTileElems; idx += blockDim.x) {
+        int i, j;
+        if (dtype == QH_F32) tile_pos32(idx, i, j);
+        else tile_pos16(idx, i, j);
+        int64_t gi = rt * kTile + i, gj = ct * kTile + j;
+        double v = 0.0;
+        if (gi < F && gj < F) {
+            int w = W[gi * F + gj];
+            v = negate ? -(double)w : (double)w;
+        }
+        int64_t o = t * kTileElems + idx;
+        switch (dtype) {
+            case QH_F32: ((float *)out)[o] = f64_to_f32(v); break;
+            case QH_F16: ((uint16_t *)out)[o] = f64_to_f16_bits(v); break;
+            case QH_BF16: ((uint16_t *)out)[o] = f64_to_bf16_bits(v); break;
+            case QH_FP8_ROWSCALE: {
+                double s = gi < F ? (double)scale[gi] : 0.0;
+                out[o] = s > 0.0 ? f64_to_e4m3_bits(v / s) : (uint8_t)0;
+                break;
+            }
+        }
+    }
+}
+
+// ---- SNP graph (Eqs. 9-14) -------------------------------------------------
+
+// Eqs. (9), (11)-(13) with the per-fragment factor alpha and the 1/(|S_i|-1)
+// normalisation of Eq. (14).  J = -w, so each pair term enters J with a + sign.
+// One thread per kept observation (fragment f, rank a); it handles the pairs
+// (a, b) with a < b <= a + L of its fragment.
+__global__ void k_snp_pairs(int64_t n_kept, const int64_t *__restrict__ kept_obs,
+                            const int32_t *__restrict__ kept_frag, const int64_t *__restrict__ kept_ptr,
+                            const int32_t *__restrict__ snp, const int8_t *__restrict__ M,
+                            const uint8_t *__restrict__ phred, const double *__restrict__ alpha,
+                            const double *__restrict__ qconf, int linkage_k, int32_t band_limit,
+                            const int64_t *__restrict__ s_off, const int32_t *__restrict__ s_lo,
+                            double *__restrict__ s_val64, const int64_t *__restrict__ l_ptr,
+                            const int32_t *__restrict__ l_col, double *__restrict__ l_val64) {
+    for (int64_t kk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; kk < n_kept;
+         kk += (int64_t)gridDim.x * blockDim.x) {
+        int32_t f = kept_frag[kk];
+        int64_t base = kept_ptr[f];
+        int64_t ns = kept_ptr[f + 1] - base;
+        if (ns < 2) continue;
+        int64_t L = (int64_t)linkage_k * (ns - 1) / 10;
+        int64_t a = kk - base;
+        int64_t bmax = a + L < ns - 1 ? a + L : ns - 1;
+        int64_t tu = kept_obs[kk];
+        int32_t u = snp[tu];
+        int Mu = M[tu];
+        double qu = qconf[phred[tu]];
+        double af = alpha ? alpha[f] : 1.0;
+        for (int64_t b = a + 1; b <= bmax; ++b) {
+            int64_t tv = kept_obs[base + b];
+            int32_t v = snp[tv];
+            double qv = qconf[phred[tv]];
+            double p_cis = qu * qv + (1.0 - qu) * (1.0 - qv);
+            double p_trans = qu * (1.0 - qv) + (1.0 - qu) * qv;
+            double sgn = (Mu * (int)M[tv] > 0) ? 1.0 : -1.0;
+            double l = sgn * log10(p_cis / p_trans);
+            double term = af * l / (double)(ns - 1);   // enters J = -w with + sign
+            if (band_limit == 0 || v - u <= band_limit) {
+                unsafeAtomicAdd(&s_val64[s_off[u] + (v - s_lo[u])], term);
+                unsafeAtomicAdd(&s_val64[s_off[v] + (u - s_lo[v])], term);
+            } else {
+                int64_t lo = l_ptr[u], hi = l_ptr[u + 1];
+                while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < v) lo = m + 1; else hi = m; }
+                unsafeAtomicAdd(&l_val64[lo], term);
+                lo = l_ptr[v]; hi = l_ptr[v + 1];
+                while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < u) lo = m + 1; else hi = m; }
+                unsafeAtomicAdd(&l_val64[lo], term);
+            }
+        }
+    }
+}
+
+// Nonzeros per row of skyline + long-range.
+__global__ void k_sky_row_nnz(int64_t n, const int64_t *__restrict__ s_off, const int32_t *__restrict__ s_len,
+                              const double *__restrict__ s_val64, const int64_t *__restrict__ l_ptr,
+                              const double *__restrict__ l_val64, int64_t *__restrict__ cnt) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0;
+        for (int64_t e = 0; e < s_len[u]; ++e) c += (s_val64[s_off[u] + e] != 0.0);
+        if (l_ptr)
+            for (int64_t e = l_ptr[u]; e < l_ptr[u + 1]; ++e) c += (l_val64[e] != 0.0);
+        cnt[u] = c;
+    }
+}
+
+__global__ void k_sky_row_fill(int64_t n, const int64_t *__restrict__ s_off, const int32_t *__restrict__ s_lo,
+                               const int32_t *__restrict__ s_len, const double *__restrict__ s_val64,
+                               const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ l_col,
+                               const double *__restrict__ l_val64, const int64_t *__restrict__ m_ptr,
+                               int32_t *__restrict__ m_col, double *__restrict__ m_val) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        int64_t o = m_ptr[u];
+        int32_t lo = s_lo[u];
+        int64_t le = l_ptr ? l_ptr[u] : 0, lend = l_ptr ? l_ptr[u + 1] : 0;
+        for (; le < lend && l_col[le] < lo; ++le)
+            if (l_val64[le] != 0.0) { m_col[o] = l_col[le]; m_val[o] = l_val64[le]; ++o; }
+        for (int64_t e = 0; e < s_len[u]; ++e) {
+            double v = s_val64[s_off[u] + e];
+            if (v != 0.0) { m_col[o] = lo + (int32_t)e; m_val[o] = v; ++o; }
+        }
+        for (; le < lend; ++le)
+            if (l_val64[le] != 0.0) { m_col[o] = l_col[le]; m_val[o] = l_val64[le]; ++o; }
+    }
+}
+
+// FP64 -> stored number format (elementwise, RNE).
+__global__ void k_quantize(int64_t n, const double *__restrict__ src, int dtype, uint8_t *__restrict__ dst) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        double v = src[t];
+        switch (dtype) {
+            case QH_F32: ((float *)dst)[t] = (float)v; break;
+            case QH_F16: ((uint16_t *)dst)[t] = f64_to_f16_bits(v); break;
+            case QH_BF16: ((uint16_t *)dst)[t] = f64_to_bf16_bits(v); break;
+        }
+    }
+}
+
+// Deterministic partial sums of squares (fixed grid, fixed order per block).
+__global__ void k_sumsq_partial(int64_t n, const double *__restrict__ v, double *__restrict__ part) {
+    __shared__ double sh[256];
+    int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    int64_t b = blockIdx.x * per, e = b + per < n ? b + per : n;
+    double acc = 0.0;
+    for (int64_t t = b + threadIdx.x; t < e; t += blockDim.x) acc += v[t] * v[t];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// ---- export ----------------------------------------------------------------
+
+__global__ void k_export_csr(int64_t r0, int64_t r1, int64_t n, const int64_t *__restrict__ ptr,
+                             const int32_t *__restrict__ col, const double *__restrict__ val,
+                             double *__restrict__ out) {
+    for (int64_t r = r0 + blockIdx.x; r < r1; r += gridDim.x)
+        for (int64_t e = ptr[r] + threadIdx.x; e < ptr[r + 1]; e += blockDim.x)
+            out[(r - r0) * n + col[e]] = val[e];
+}
+
+__global__ void k_export_tiles(int64_t r0, int64_t r1, int64_t n, const int32_t *__restrict__ t_ptr,
+                               const int32_t *__restrict__ t_col, const uint8_t *__restrict__ t_val,
+                               int dtype, const float *__restrict__ scale, double *__restrict__ out) {
+    for (int64_t r = r0 + blockIdx.x; r < r1; r += gridDim.x) {
+        int64_t rt = r / kTile;
+        int i = (int)(r - rt * kTile);
+        for (int64_t t = t_ptr[rt]; t < t_ptr[rt + 1]; ++t) {
+            int64_t ct = t_col[t];
+            for (int j = threadIdx.x; j < kTile; j += blockDim.x) {
+                int64_t c = ct * kTile + j;
+                if (c >= n) continue;
+                int64_t o = t * kTileElems + (dtype == QH_F32 ? tile_idx32(i, j) : tile_idx16(i, j));
+                double v = 0.0;
+                switch (dtype) {
+                    case QH_F32: v = ((const float *)t_val)[o]; break;
+                    case QH_F16: v = f16_bits_to_f32(((const uint16_t *)t_val)[o]); break;
+                    case QH_BF16: v = bf16_bits_to_f32(((const uint16_t *)t_val)[o]); break;
+                    // scale holds 256 s_i; the f16 expansion holds code * 2^-8
+                    case QH_FP8_ROWSCALE:
+                        v = (double)f16_bits_to_f32(e4m3_to_f16_bits_scaled(t_val[o])) * (double)scale[r];
+                        break;
+                }
+                out[(r - r0) * n + c] = v;
+            }
+        }
+    }
+}
+
+__device__ inline double load_stored(const uint8_t *p, int64_t e, int dtype) {
+    switch (dtype) {
+        case QH_F32: return ((const float *)p)[e];
+        case QH_F16: return f16_bits_to_f32(((const uint16_t *)p)[e]);
+        case QH_BF16: return bf16_bits_to_f32(((const uint16_t *)p)[e]);
+    }
+    return 0.0;
+}
+
+__global__ void k_export_sky(int64_t r0, int64_t r1, int64_t n, const int64_t *__restrict__ s_off,
+                             const int32_t *__restrict__ s_lo, const int32_t *__restrict__ s_len,
+                             const uint8_t *__restrict__ s_val, const int64_t *__restrict__ l_ptr,
+                             const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val, int dtype,
+                             double *__restrict__ out) {
+    for (int64_t r = r0 + blockIdx.x; r < r1; r += gridDim.x) {
+        for (int64_t e = threadIdx.x; e < s_len[r]; e += blockDim.x)
+            out[(r - r0) * n + s_lo[r] + e] = load_stored(s_val, s_off[r] + e, dtype);
+        if (l_ptr)
+            for (int64_t e = l_ptr[r] + threadIdx.x; e < l_ptr[r + 1]; e += blockDim.x)
+                out[(r - r0) * n + l_col[e]] = load_stored(l_val, e, dtype);
+    }
+}
+
+// ---- Eq. (15) ---------------------------------------------------------------
+
+__global__ void k_flip_csr(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                           double *__restrict__ val, const int8_t *__restrict__ s) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e)
+            if (s[r] != s[col[e]]) val[e] = -val[e];
+}
+
+__device__ inline void negate_stored(uint8_t *p, int64_t e, int dtype) {
+    if (dtype == QH_F32) ((uint32_t *)p)[e] ^= 0x80000000u;
+    else ((uint16_t *)p)[e] ^= 0x8000u;
+}
+
+__global__ void k_flip_sky(int64_t n, const int64_t *__restrict__ s_off, const int32_t *__restrict__ s_lo,
+                           const int32_t *__restrict__ s_len, uint8_t *__restrict__ s_val,
+                           const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ l_col,
+                           uint8_t *__restrict__ l_val, int dtype, const int8_t *__restrict__ s) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t e = 0; e < s_len[r]; ++e)
+            if (s[r] != s[s_lo[r] + e]) negate_stored(s_val, s_off[r] + e, dtype);
+        if (l_ptr)
+            for (int64_t e = l_ptr[r]; e < l_ptr[r + 1]; ++e)
+                if (s[r] != s[l_col[e]]) negate_stored(l_val, e, dtype);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+
+static int grid_for(int64_t n, int block = 256, int64_t cap = 65536) {
+    int64_t g = ceil_div(n, block);
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+static int32_t uf_find(std::vector<int32_t> &p, int32_t x) {
+    while (p[x] != x) {
+        p[x] = p[p[x]];
+        x = p[x];
+    }
+    return x;
+}
+
+static void uf_union(std::vector<int32_t> &p, int32_t a, int32_t b) {
+    a = uf_find(p, a);
+    b = uf_find(p, b);
+    if (a == b) return;
+    if (a < b) p[b] = a; else p[a] = b;
+}
+
+int64_t label_components(int64_t n, std::vector<int32_t> &parent, std::vector<int32_t> &comp) {
+    std::vector<int32_t> size(n, 0), label(n, -1);
+    for (int64_t i = 0; i < n; ++i) size[uf_find(parent, (int32_t)i)]++;
+    comp.assign(n, -1);
+    int32_t next = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t r = uf_find(parent, (int32_t)i);
+        if (size[r] < 2) continue;
+        if (label[r] < 0) label[r] = next++;
+        comp[i] = label[r];
+    }
+    return next;
+}
+
+static constexpr int kChunkVerts = 32;
+
+void upload_components(qh_graph *g, const std::vector<int32_t> &comp, int64_t n_comp, hipStream_t st) {
+    int64_t n = g->n;
+    g->n_comp = n_comp;
+    g->comp.alloc(n);
+    g->comp.upload(comp.data(), n, st);
+    std::vector<int32_t> first(n_comp, -1);
+    std::vector<int64_t> cnt(n_comp + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        if (comp[i] >= 0) {
+            if (first[comp[i]] < 0) first[comp[i]] = (int32_t)i;
+            cnt[comp[i] + 1]++;
+        }
+    for (int64_t c = 0; c < n_comp; ++c) cnt[c + 1] += cnt[c];
+    std::vector<int32_t> order(cnt[n_comp]);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+        if (comp[i] >= 0) order[fill[comp[i]]++] = (int32_t)i;
+    std::vector<int32_t> ccomp, cbeg, cend, cptr(n_comp + 1, 0);
+    for (int64_t c = 0; c < n_comp; ++c) {
+        cptr[c] = (int32_t)ccomp.size();
+        for (int64_t b = cnt[c]; b < cnt[c + 1]; b += kChunkVerts) {
+            ccomp.push_back((int32_t)c);
+            cbeg.push_back((int32_t)b);
+            cend.push_back((int32_t)std::min<int64_t>(b + kChunkVerts, cnt[c + 1]));
+        }
+    }
+    cptr[n_comp] = (int32_t)ccomp.size();
+    g->n_chunks = (int64_t)ccomp.size();
+    g->comp_first.alloc(n_comp);
+    g->comp_first.upload(first.data(), n_comp, st);
+    g->comp_order.alloc(order.size());
+    g->comp_order.upload(order.data(), order.size(), st);
+    g->chunk_comp.alloc(ccomp.size());
+    g->chunk_comp.upload(ccomp.data(), ccomp.size(), st);
+    g->chunk_begin.alloc(cbeg.size());
+    g->chunk_begin.upload(cbeg.data(), cbeg.size(), st);
+    g->chunk_end.alloc(cend.size());
+    g->chunk_end.upload(cend.data(), cend.size(), st);
+    g->comp_chunk_ptr.alloc(n_comp + 1);
+    g->comp_chunk_ptr.upload(cptr.data(), n_comp + 1, st);
+    QH_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
+}
+
+struct HostFrags {
+    std::vector<int64_t> fp;
+    std::vector<int32_t> snp;
+    std::vector<uint8_t> allele, phred;
+};
+
+static HostFrags fetch_and_validate(const qh_reads *r, int32_t n_snp, bool need_phred, hipStream_t st) {
+    HostFrags h;
+    int64_t F = r->n_frag;
+    h.fp = F > 0 ? download(r->frag_ptr, F + 1, st) : std::vector<int64_t>{0};
+    if (h.fp[0] != 0) fail(QH_EINVAL, "frag_ptr[0] must be 0");
+    for (int64_t f = 0; f < F; ++f)
+        if (h.fp[f + 1] < h.fp[f]) fail(QH_EINVAL, "frag_ptr decreases at fragment %lld", (long long)f);
+    int64_t nobs = h.fp[F];
+    if (nobs > INT32_MAX) fail(QH_EUNSUPPORTED, "more than 2^31 observations");
+    h.snp = download(r->snp, nobs, st);
+    h.allele = download(r->allele, nobs, st);
+    if (need_phred) h.phred = download(r->phred, nobs, st);
+    for (int64_t f = 0; f < F; ++f)
+        for (int64_t t = h.fp[f]; t < h.fp[f + 1]; ++t) {
+            if (h.snp[t] < 0 || h.snp[t] >= n_snp)
+                fail(QH_EINVAL, "fragment %lld: SNP index %d out of range", (long long)f, h.snp[t]);
+            if (t > h.fp[f] && h.snp[t] <= h.snp[t - 1])
+                fail(QH_EINVAL, "fragment %lld: SNP indices not strictly ascending", (long long)f);
+            if (h.allele[t] > 1) fail(QH_EINVAL, "fragment %lld: allele must be 0 or 1", (long long)f);
+        }
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// read graph
+// ---------------------------------------------------------------------------
+
+static void pack_dense_storage(qh_graph *g, const int32_t *W, int negate, hipStream_t st) {
+    int64_t F = g->n;
+    int64_t n_rt = ceil_div(F, kTile);
+    g->n_rt = n_rt;
+    DevBuf<uint8_t> occ(n_rt * n_rt);
+    if (n_rt > 0) {
+        hipLaunchKernelGGL(k_tile_occupancy, dim3((unsigned)n_rt, (unsigned)n_rt), dim3(256), 0, st, F,
+                           n_rt, W, occ.p);
+        QH_CHECK_LAUNCH();
+    }
+    auto occ_h = download(occ.p, n_rt * n_rt, st);
+    std::vector<int32_t> tptr(n_rt + 1, 0), tcol, trow;
+    for (int64_t rt = 0; rt < n_rt; ++rt) {
+        tptr[rt] = (int32_t)tcol.size();
+        for (int64_t ct = 0; ct < n_rt; ++ct)
+            if (occ_h[rt * n_rt + ct]) { tcol.push_back((int32_t)ct); trow.push_back((int32_t)rt); }
+    }
+    tptr[n_rt] = (int32_t)tcol.size();
+    g->n_tiles = (int64_t)tcol.size();
+    g->t_ptr.alloc(n_rt + 1);
+    g->t_ptr.upload(tptr.data(), n_rt + 1, st);
+    g->t_col.alloc(tcol.size());
+    g->t_col.upload(tcol.data(), tcol.size(), st);
+    DevBuf<int32_t> trow_d(trow.size());
+    trow_d.upload(trow.data(), trow.size(), st);
+    g->t_val.alloc((size_t)std::max<int64_t>(g->n_tiles, 1) * kTileElems * dtype_bytes(g->dtype));
+    if (g->dtype == QH_FP8_ROWSCALE) {
+        DevBuf<double> rmax(F);
+        DevBuf<float> scale(F);
+        g->row_scale.alloc(F);
+        if (F) {
+            hipLaunchKernelGGL(k_row_absmax, dim3(grid_for(F)), dim3(256), 0, st, F, g->m_ptr.p, g->m_val.p,
+                               rmax.p);
+            hipLaunchKernelGGL(k_fp8_scales, dim3(grid_for(F)), dim3(256), 0, st, F, rmax.p, scale.p,
+                               g->row_scale.p);
+            QH_CHECK_LAUNCH();
+        }
+        if (g->n_tiles) {
+            hipLaunchKernelGGL(k_pack_tiles, dim3((unsigned)g->n_tiles), dim3(256), 0, st, F, W, negate,
+                               trow_d.p, g->t_col.p, g->dtype, scale.p, g->t_val.p);
+            QH_CHECK_LAUNCH();
+        }
+        QH_HIP(hipStreamSynchronize(st));
+    } else if (g->n_tiles) {
+        hipLaunchKernelGGL(k_pack_tiles, dim3((unsigned)g->n_tiles), dim3(256), 0, st, F, W, negate, trow_d.p,
+                           g->t_col.p, g->dtype, (const float *)nullptr, g->t_val.p);
+        QH_CHECK_LAUNCH();
+        QH_HIP(hipStreamSynchronize(st));
+    }
+}
+
+void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStream_t st) {
+    int64_t F = r->n_frag;
+    int32_t S = s->n_snp;
+    if (F > 46340) fail(QH_EUNSUPPORTED, "dense read graphs are limited to 46340 fragments");
+    g->n = F;
+    g->integer = true;
+    HostFrags h = fetch_and_validate(r, S, false, st);
+    int64_t nobs = h.fp[F];
+
+    // per-SNP coverage lists, fragments ascending
+    std::vector<int64_t> cov_ptr(S + 1, 0), cov_obs(nobs);
+    std::vector<int32_t> cov_frag(nobs);
+    for (int64_t t = 0; t < nobs; ++t) cov_ptr[h.snp[t] + 1]++;
+    for (int32_t j = 0; j < S; ++j) cov_ptr[j + 1] += cov_ptr[j];
+    {
+        std::vector<int64_t> fill(cov_ptr.begin(), cov_ptr.end() - 1);
+        for (int64_t f = 0; f < F; ++f)
+            for (int64_t t = h.fp[f]; t < h.fp[f + 1]; ++t) {
+                int64_t p = fill[h.snp[t]]++;
+                cov_frag[p] = (int32_t)f;
+                cov_obs[p] = t;
+            }
+    }
+    // components: fragments sharing a SNP are linked
+    std::vector<int32_t> parent(F);
+    std::iota(parent.begin(), parent.end(), 0);
+    for (int32_t j = 0; j < S; ++j)
+        for (int64_t p = cov_ptr[j] + 1; p < cov_ptr[j + 1]; ++p) uf_union(parent, cov_frag[p - 1], cov_frag[p]);
+    std::vector<int32_t> comp;
+    int64_t n_comp = label_components(F, parent, comp);
+    upload_components(g, comp, n_comp, st);
+
+    // encode and coverage lists on the device
+    DevBuf<int8_t> M(nobs);
+    if (nobs) {
+        hipLaunchKernelGGL(k_encode, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, r->snp, r->allele,
+                           s->init_h1, M.p);
+        QH_CHECK_LAUNCH();
+    }
+    g->cov_ptr.alloc(S + 1);
+    g->cov_ptr.upload(cov_ptr.data(), S + 1, st);
+    g->cov_frag.alloc(nobs);
+    g->cov_frag.upload(cov_frag.data(), nobs, st);
+    DevBuf<int64_t> cov_obs_d(nobs);
+    cov_obs_d.upload(cov_obs.data(), nobs, st);
+    g->cov_M.alloc(nobs);
+    if (nobs) {
+        hipLaunchKernelGGL(k_gather_i8, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, cov_obs_d.p, M.p,
+                           g->cov_M.p);
+        QH_CHECK_LAUNCH();
+    }
+    g->init_h1.alloc(S);
+    if (S) QH_HIP(hipMemcpyAsync(g->init_h1.p, s->init_h1, S, hipMemcpyDeviceToDevice, st));
+
+    // Eqs. (2)-(3) into a dense int32 matrix
+    int conflict = g->kind == QH_READ_CONFLICT;
+    DevBuf<int32_t> W((size_t)std::max<int64_t>(F * F, 1));
+    W.zero(st);
+    if (S && F) {
+        hipLaunchKernelGGL(k_read_pairs, dim3((unsigned)std::min<int64_t>(S, 1 << 20)), dim3(256), 0, st, S,
+                           g->cov_ptr.p, g->cov_frag.p, g->cov_M.p, W.p, F, conflict);
+        QH_CHECK_LAUNCH();
+    }
+    // master CSR (J = -A for the conflict kind)
+    DevBuf<int64_t> cnt(F);
+    int waves_per_block = 4;
+    if (F) {
+        hipLaunchKernelGGL(k_dense_row_nnz, dim3((unsigned)ceil_div(F, waves_per_block)), dim3(256), 0, st, F,
+                           W.p, cnt.p);
+        QH_CHECK_LAUNCH();
+    }
+    auto cnt_h = download(cnt.p, F, st);
+    std::vector<int64_t> ptr(F + 1, 0);
+    for (int64_t i = 0; i < F; ++i) ptr[i + 1] = ptr[i] + cnt_h[i];
+    g->nnz = ptr[F];
+    g->m_ptr.alloc(F + 1);
+    g->m_ptr.upload(ptr.data(), F + 1, st);
+    g->m_col.alloc(g->nnz);
+    g->m_val.alloc(g->nnz);
+    if (F) {
+        hipLaunchKernelGGL(k_dense_row_fill, dim3((unsigned)ceil_div(F, waves_per_block)), dim3(256), 0, st, F,
+                           W.p, conflict, g->m_ptr.p, g->m_col.p, g->m_val.p);
+        QH_CHECK_LAUNCH();
+    }
+    pack_dense_storage(g, W.p, conflict, st);
+    QH_HIP(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// SNP graph
+// ---------------------------------------------------------------------------
+
+void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linkage_k, int band_limit,
+                     hipStream_t st) {
+    int64_t F = r->n_frag;
+    int32_t n = s->n_snp;
+    g->n = n;
+    g->integer = false;
+    g->band_limit = band_limit;
+    HostFrags h = fetch_and_validate(r, n, true, st);
+    int64_t nobs = h.fp[F];
+
+    // kept observations (Phred > 3), per fragment in SNP order
+    std::vector<int64_t> kept_ptr(F + 1, 0), kept_obs;
+    std::vector<int32_t> kept_frag;
+    kept_obs.reserve(nobs);
+    kept_frag.reserve(nobs);
+    for (int64_t f = 0; f < F; ++f) {
+        kept_ptr[f] = (int64_t)kept_obs.size();
+        for (int64_t t = h.fp[f]; t < h.fp[f + 1]; ++t)
+            if (h.phred[t] > 3) { kept_obs.push_back(t); kept_frag.push_back((int32_t)f); }
+    }
+    kept_ptr[F] = (int64_t)kept_obs.size();
+    int64_t n_kept = kept_ptr[F];
+
+    // structure: components, skyline extents, long-range pair set
+    std::vector<int32_t> parent(n);
+    std::iota(parent.begin(), parent.end(), 0);
+    std::vector<int32_t> lo(n), hi(n);
+    std::iota(lo.begin(), lo.end(), 0);
+    std::iota(hi.begin(), hi.end(), 0);
+    std::vector<uint64_t> lr_keys;
+    for (int64_t f = 0; f < F; ++f) {
+        int64_t base = kept_ptr[f], ns = kept_ptr[f + 1] - base;
+        if (ns < 2) continue;
+        int64_t L = (int64_t)linkage_k * (ns - 1) / 10;
+        if (L < 1) continue;
+        for (int64_t a = 0; a < ns; ++a) {
+            int32_t u = h.snp[kept_obs[base + a]];
+            if (a > 0) uf_union(parent, h.snp[kept_obs[base + a - 1]], u);
+            int64_t bmax = std::min(a + L, ns - 1);
+            for (int64_t b = a + 1; b <= bmax; ++b) {
+                int32_t v = h.snp[kept_obs[base + b]];
+                if (band_limit == 0 || v - u <= band_limit) {
+                    if (v > hi[u]) hi[u] = v;
+                    if (u < lo[v]) lo[v] = u;
+                } else {
+                    lr_keys.push_back((uint64_t)u * (uint64_t)n + (uint64_t)v);
+                    lr_keys.push_back((uint64_t)v * (uint64_t)n + (uint64_t)u);
+                }
+            }
+        }
+    }
+    std::vector<int32_t> comp;
+    int64_t n_comp = label_components(n, parent, comp);
+    upload_components(g, comp, n_comp, st);
+
+    std::vector<int64_t> off(n);
+    std::vector<int32_t> len(n);
+    int64_t slots = 0;
+    for (int32_t u = 0; u < n; ++u) {
+        off[u] = slots;
+        len[u] = hi[u] - lo[u] + 1;
+        slots += len[u];
+    }
+    g->s_slots = slots;
+    std::sort(lr_keys.begin(), lr_keys.end());
+    lr_keys.erase(std::unique(lr_keys.begin(), lr_keys.end()), lr_keys.end());
+    int64_t l_nnz = (int64_t)lr_keys.size();
+    g->l_nnz = l_nnz;
+    std::vector<int64_t> lptr(n + 1, 0);
+    std::vector<int32_t> lcol(l_nnz);
+    for (int64_t e = 0; e < l_nnz; ++e) {
+        lptr[lr_keys[e] / (uint64_t)n + 1]++;
+        lcol[e] = (int32_t)(lr_keys[e] % (uint64_t)n);
+    }
+    for (int32_t u = 0; u < n; ++u) lptr[u + 1] += lptr[u];
+
+    // hub rows: long-range lists longer than the inline limit, split into chunks
+    {
+        std::vector<int32_t> hub_of(n, -1), crow, cptr;
+        std::vector<int64_t> cbeg, cend;
+        int32_t nh = 0;
+        for (int32_t u = 0; u < n; ++u) {
+            int64_t c = lptr[u + 1] - lptr[u];
+            if (c <= kHubInline) continue;
+            hub_of[u] = nh++;
+            cptr.push_back((int32_t)crow.size());
+            for (int64_t b = lptr[u]; b < lptr[u + 1]; b += kHubChunk) {
+                crow.push_back(u);
+                cbeg.push_back(b);
+                cend.push_back(std::min<int64_t>(b + kHubChunk, lptr[u + 1]));
+            }
+        }
+        cptr.push_back((int32_t)crow.size());
+        g->n_hub = nh;
+        g->n_hub_chunks = (int64_t)crow.size();
+        g->hub_of_row.alloc(n);
+        g->hub_of_row.upload(hub_of.data(), n, st);
+        g->hub_chunk_row.alloc(crow.size());
+        g->hub_chunk_row.upload(crow.data(), crow.size(), st);
+        g->hub_chunk_beg.alloc(cbeg.size());
+        g->hub_chunk_beg.upload(cbeg.data(), cbeg.size(), st);
+        g->hub_chunk_end.alloc(cend.size());
+        g->hub_chunk_end.upload(cend.data(), cend.size(), st);
+        g->hub_chunk_ptr.alloc(cptr.size());
+        g->hub_chunk_ptr.upload(cptr.data(), cptr.size(), st);
+        QH_HIP(hipStreamSynchronize(st));
+    }
+
+    // device structure
+    g->s_off.alloc(n);
+    g->s_off.upload(off.data(), n, st);
+    g->s_lo.alloc(n);
+    g->s_lo.upload(lo.data(), n, st);
+    g->s_len.alloc(n);
+    g->s_len.upload(len.data(), n, st);
+    g->l_ptr.alloc(n + 1);
+    g->l_ptr.upload(lptr.data(), n + 1, st);
+    g->l_col.alloc(l_nnz);
+    g->l_col.upload(lcol.data(), l_nnz, st);
+    DevBuf<int64_t> kept_obs_d(n_kept), kept_ptr_d(F + 1);
+    DevBuf<int32_t> kept_frag_d(n_kept);
+    kept_obs_d.upload(kept_obs.data(), n_kept, st);
+    kept_ptr_d.upload(kept_ptr.data(), F + 1, st);
+    kept_frag_d.upload(kept_frag.data(), n_kept, st);
+    // Eq. (9) per integer Phred score
+    double qconf_h[256];
+    for (int q = 0; q < 256; ++q) qconf_h[q] = 1.0 - std::pow(10.0, -(double)q / 10.0);
+    DevBuf<double> qconf(256);
+    qconf.upload(qconf_h, 256, st);
+
+    DevBuf<int8_t> M(nobs);
+    if (nobs) {
+        hipLaunchKernelGGL(k_encode, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, r->snp, r->allele,
+                           s->init_h1, M.p);
+        QH_CHECK_LAUNCH();
+    }
+    g->init_h1.alloc(n);
+    if (n) QH_HIP(hipMemcpyAsync(g->init_h1.p, s->init_h1, n, hipMemcpyDeviceToDevice, st));
+
+    DevBuf<double> s_val64(slots), l_val64(l_nnz);
+    s_val64.zero(st);
+    l_val64.zero(st);
+    if (n_kept) {
+        hipLaunchKernelGGL(k_snp_pairs, dim3(grid_for(n_kept, 256, 1 << 20)), dim3(256), 0, st, n_kept,
+                           kept_obs_d.p, kept_frag_d.p, kept_ptr_d.p, r->snp, M.p, r->phred, r->alpha, qconf.p,
+                           linkage_k, (int32_t)band_limit, g->s_off.p, g->s_lo.p, s_val64.p, g->l_ptr.p,
+                           g->l_col.p, l_val64.p);
+        QH_CHECK_LAUNCH();
+    }
+    // master CSR
+    DevBuf<int64_t> cnt(n);
+    const int64_t *lp = l_nnz ? g->l_ptr.p : nullptr;
+    if (n) {
+        hipLaunchKernelGGL(k_sky_row_nnz, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, g->s_off.p, g->s_len.p,
+                           s_val64.p, lp, l_val64.p, cnt.p);
+        QH_CHECK_LAUNCH();
+    }
+    auto cnt_h = download(cnt.p, n, st);
+    std::vector<int64_t> mptr(n + 1, 0);
+    for (int32_t u = 0; u < n; ++u) mptr[u + 1] = mptr[u] + cnt_h[u];
+    g->nnz = mptr[n];
+    g->m_ptr.alloc(n + 1);
+    g->m_ptr.upload(mptr.data(), n + 1, st);
+    g->m_col.alloc(g->nnz);
+    g->m_val.alloc(g->nnz);
+    if (n) {
+        hipLaunchKernelGGL(k_sky_row_fill, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, g->s_off.p, g->s_lo.p,
+                           g->s_len.p, s_val64.p, lp, g->l_col.p, l_val64.p, g->m_ptr.p, g->m_col.p, g->m_val.p);
+        QH_CHECK_LAUNCH();
+    }
+    // storage copy
+    int eb = dtype_bytes(g->dtype);
+    g->s_val.alloc((size_t)slots * eb);
+    g->l_val.alloc((size_t)std::max<int64_t>(l_nnz, 1) * eb);
+    if (slots) {
+        hipLaunchKernelGGL(k_quantize, dim3(grid_for(slots)), dim3(256), 0, st, slots, s_val64.p, g->dtype,
+                           g->s_val.p);
+        QH_CHECK_LAUNCH();
+    }
+    if (l_nnz) {
+        hipLaunchKernelGGL(k_quantize, dim3(grid_for(l_nnz)), dim3(256), 0, st, l_nnz, l_val64.p, g->dtype,
+                           g->l_val.p);
+        QH_CHECK_LAUNCH();
+    }
+    QH_HIP(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// shared finishing steps
+// ---------------------------------------------------------------------------
+
+void finalize_graph(qh_graph *g, hipStream_t st) {
+    // c0 = 0.5 / (sigma sqrt(n)), sigma^2 = sum J^2 / (n (n - 1))
+    const int parts = 1024;
+    DevBuf<double> part(parts);
+    if (g->nnz) {
+        hipLaunchKernelGGL(k_sumsq_partial, dim3(parts), dim3(256), 0, st, g->nnz, g->m_val.p, part.p);
+        QH_CHECK_LAUNCH();
+        auto ph = download(part.p, parts, st);
+        double ss = 0.0;
+        for (double v : ph) ss += v;
+        if (ss > 0.0 && g->n >= 2) {
+            double sigma = std::sqrt(ss / ((double)g->n * (double)(g->n - 1)));
+            g->c0_auto = 0.5 / (sigma * std::sqrt((double)g->n));
+        }
+    }
+    if (!g->integer && g->n) {
+        DevBuf<double> rs(g->n);
+        hipLaunchKernelGGL(k_row_abssum, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, g->m_ptr.p, g->m_val.p,
+                           rs.p);
+        QH_CHECK_LAUNCH();
+        auto h = download(rs.p, g->n, st);
+        double m = 0.0;
+        for (double v : h) m = std::max(m, v);
+        g->greedy_eps = 1e-12 * m;
+    }
+    g->device_bytes = (int64_t)(g->m_ptr.bytes() + g->m_col.bytes() + g->m_val.bytes() + g->comp.bytes() +
+                                g->comp_order.bytes() + g->t_ptr.bytes() + g->t_col.bytes() + g->t_val.bytes() +
+                                g->row_scale.bytes() + g->s_off.bytes() + g->s_lo.bytes() + g->s_len.bytes() +
+                                g->s_val.bytes() + g->l_ptr.bytes() + g->l_col.bytes() + g->l_val.bytes() +
+                                g->cov_ptr.bytes() + g->cov_frag.bytes() + g->cov_M.bytes() +
+                                g->init_h1.bytes());
+}
+
+void export_master_rows(const qh_graph *g, int64_t r0, int64_t r1, double *out, hipStream_t st) {
+    if (r1 <= r0) return;
+    QH_HIP(hipMemsetAsync(out, 0, (size_t)(r1 - r0) * g->n * sizeof(double), st));
+    hipLaunchKernelGGL(k_export_csr, dim3((unsigned)std::min<int64_t>(r1 - r0, 65536)), dim3(256), 0, st, r0,
+                       r1, g->n, g->m_ptr.p, g->m_col.p, g->m_val.p, out);
+    QH_CHECK_LAUNCH();
+}
+
+void export_stored_rows(const qh_graph *g, int64_t r0, int64_t r1, double *out, hipStream_t st) {
+    if (r1 <= r0) return;
+    QH_HIP(hipMemsetAsync(out, 0, (size_t)(r1 - r0) * g->n * sizeof(double), st));
+    unsigned grid = (unsigned)std::min<int64_t>(r1 - r0, 65536);
+    if (g->storage == QH_STORE_DENSE) {
+        if (!g->n_tiles) return;
+        hipLaunchKernelGGL(k_export_tiles, dim3(grid), dim3(64), 0, st, r0, r1, g->n, g->t_ptr.p, g->t_col.p,
+                           g->t_val.p, g->dtype, g->row_scale.p, out);
+    } else {
+        hipLaunchKernelGGL(k_export_sky, dim3(grid), dim3(64), 0, st, r0, r1, g->n, g->s_off.p, g->s_lo.p,
+                           g->s_len.p, g->s_val.p, g->l_nnz ? g->l_ptr.p : nullptr, g->l_col.p, g->l_val.p,
+                           g->dtype, out);
+    }
+    QH_CHECK_LAUNCH();
+}
+
+void flip_crossing(qh_graph *g, const int8_t *spins, hipStream_t st) {
+    if (g->storage != QH_STORE_SKYLINE) fail(QH_EUNSUPPORTED, "flip_crossing is offered on SNP graphs");
+    if (!g->n) return;
+    hipLaunchKernelGGL(k_flip_csr, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, g->m_ptr.p, g->m_col.p,
+                       g->m_val.p, spins);
+    hipLaunchKernelGGL(k_flip_sky, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, g->s_off.p, g->s_lo.p,
+                       g->s_len.p, g->s_val.p, g->l_nnz ? g->l_ptr.p : nullptr, g->l_col.p, g->l_val.p, g->dtype,
+                       spins);
+    QH_CHECK_LAUNCH();
+    // solve plans hold no copy of J; nothing else to refresh
+}
+
+}  // namespace qh

@@ -1,0 +1,219 @@
+// Internal declarations of the gfx950 phasing library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "qhap.h"
+
+namespace qh {
+
+// Internal failure carried to the ABI boundary, where it becomes a qh_status.
+struct Failure {
+    qh_status st;
+};
+
+void set_error(const char *fmt, ...);
+[[noreturn]] void fail(qh_status st, const char *fmt, ...);
+[[noreturn]] void fail_hip(hipError_t e, const char *what, const char *file, int line);
+
+#define QH_HIP(call)                                                        \
+    do {                                                                    \
+        hipError_t qh_e_ = (call);                                          \
+        if (qh_e_ != hipSuccess) ::qh::fail_hip(qh_e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+#define QH_CHECK_LAUNCH() QH_HIP(hipGetLastError())
+
+// Owning device buffer.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        if (count == 0) count = 1;
+        if (hipMalloc((void **)&p, count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(QH_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+    void upload(const T *host, size_t count, hipStream_t st) {
+        if (count) QH_HIP(hipMemcpyAsync(p, host, count * sizeof(T), hipMemcpyHostToDevice, st));
+    }
+    void zero(hipStream_t st) { if (p) QH_HIP(hipMemsetAsync(p, 0, n * sizeof(T), st)); }
+};
+
+template <class T>
+std::vector<T> download(const T *dev, size_t count, hipStream_t st) {
+    std::vector<T> h(count);
+    if (count) {
+        QH_HIP(hipMemcpyAsync(h.data(), dev, count * sizeof(T), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipStreamSynchronize(st));
+    }
+    return h;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+constexpr int kTile = 64;            // dense tile edge
+constexpr int kTileElems = kTile * kTile;
+
+// Bytes per stored element of each dtype.
+inline int dtype_bytes(int dt) {
+    switch (dt) {
+        case QH_F32: return 4;
+        case QH_F16: case QH_BF16: return 2;
+        case QH_FP8_ROWSCALE: return 1;
+    }
+    return 0;
+}
+
+// Cached state of one solve configuration (scratch buffers + captured graph).
+struct SolvePlan {
+    int R = 0;
+    int64_t n_pad = 0;
+    DevBuf<float> xa, xb, y;        // fp32 state, [n_pad][R]
+    DevBuf<uint16_t> ha, hb;        // 16-bit product copies of x (dense f16/bf16/fp8 paths)
+    DevBuf<float> pump_lin;         // linear schedule for `steps`
+    int pump_steps = 0;
+    DevBuf<int8_t> spins;           // [n][R]
+    DevBuf<double> part;            // [n_chunks][R] cut partials
+    DevBuf<double> cut_rc;          // [R][n_comp]
+    DevBuf<int32_t> best_r;         // [n_comp]
+    DevBuf<double> gain;            // [n]
+    DevBuf<int8_t> flag;            // [n]
+    DevBuf<int32_t> counter;        // small scalars
+    DevBuf<double> part1;           // [n_chunks] partials for one vector
+    DevBuf<double> cut1;            // [n_comp]
+    DevBuf<float> hub_part;         // [n_hub_chunks][R] long-range partial sums of hub rows
+    // captured step loop
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::tuple<int, int, int, double, double, double, const float *, int> graph_key{};
+    ~SolvePlan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+}  // namespace qh
+
+struct qh_graph {
+    int device = 0;
+    int kind = 0, storage = 0, dtype = 0;
+    int64_t n = 0;         // vertices
+    int32_t n_snp = 0;
+    bool integer = false;
+
+    // FP64 master: CSR of the nonzero off-diagonal couplings, columns ascending.
+    qh::DevBuf<int64_t> m_ptr;
+    qh::DevBuf<int32_t> m_col;
+    qh::DevBuf<double> m_val;
+    int64_t nnz = 0;
+
+    // Components (labels in order of lowest vertex, -1 = singleton).
+    qh::DevBuf<int32_t> comp;        // [n]
+    int64_t n_comp = 0;
+    qh::DevBuf<int32_t> comp_first;  // [n_comp] lowest vertex
+    qh::DevBuf<int32_t> comp_order;  // vertices of non-singleton components sorted by (comp, vertex)
+    // reduction chunks over comp_order: (comp, begin, end) per chunk; chunks of a
+    // component are consecutive and in vertex order
+    qh::DevBuf<int32_t> chunk_comp, chunk_begin, chunk_end;
+    int64_t n_chunks = 0;
+    qh::DevBuf<int32_t> comp_chunk_ptr;  // [n_comp + 1]
+
+    // Dense tiles (read graphs).
+    int64_t n_rt = 0;                   // row tiles
+    int64_t n_tiles = 0;
+    qh::DevBuf<int32_t> t_ptr;          // [n_rt + 1]
+    qh::DevBuf<int32_t> t_col;          // [n_tiles] column-tile index
+    qh::DevBuf<uint8_t> t_val;          // [n_tiles][4096] elements in MFMA fragment order
+    qh::DevBuf<float> row_scale;        // FP8: per-row scale (x 256 for the code decode)
+
+    // Skyline band (SNP graphs).
+    qh::DevBuf<int64_t> s_off;          // [n]
+    qh::DevBuf<int32_t> s_lo, s_len;    // [n]
+    qh::DevBuf<uint8_t> s_val;          // slots in dtype
+    int64_t s_slots = 0;
+    int32_t band_limit = 0;
+    // Long-range CSR (pairs farther apart than band_limit).
+    qh::DevBuf<int64_t> l_ptr;          // [n + 1]
+    qh::DevBuf<int32_t> l_col;
+    qh::DevBuf<uint8_t> l_val;          // dtype
+    int64_t l_nnz = 0;
+    // Hub rows: long-range rows longer than kHubInline are summed by chunks.
+    qh::DevBuf<int32_t> hub_of_row;     // [n] hub index or -1
+    qh::DevBuf<int32_t> hub_chunk_row;  // [n_hub_chunks]
+    qh::DevBuf<int64_t> hub_chunk_beg, hub_chunk_end;
+    qh::DevBuf<int32_t> hub_chunk_ptr;  // [n_hub + 1] chunks of each hub, in order
+    int64_t n_hub = 0, n_hub_chunks = 0;
+
+    // Phasing support.
+    qh::DevBuf<uint8_t> init_h1;        // [n_snp]
+    qh::DevBuf<int64_t> cov_ptr;        // read graphs: per-SNP coverage lists
+    qh::DevBuf<int32_t> cov_frag;
+    qh::DevBuf<int8_t> cov_M;
+
+    double c0_auto = 0.0;
+    double greedy_eps = 0.0;
+    int64_t device_bytes = 0;
+
+    std::map<int, std::unique_ptr<qh::SolvePlan>> plans;  // keyed by replicas
+};
+
+namespace qh {
+
+constexpr int kHubInline = 64;      // long-range entries summed inline by the step kernel
+constexpr int kHubChunk = 64;       // entries per hub partial
+
+// graph_build.hip
+void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStream_t st);
+void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linkage_k,
+                     int band_limit, hipStream_t st);
+void finalize_graph(qh_graph *g, hipStream_t st);
+void export_master_rows(const qh_graph *g, int64_t r0, int64_t r1, double *out, hipStream_t st);
+void export_stored_rows(const qh_graph *g, int64_t r0, int64_t r1, double *out, hipStream_t st);
+void flip_crossing(qh_graph *g, const int8_t *spins, hipStream_t st);
+
+// bsb.hip
+void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStream_t st);
+
+// phase.hip
+void phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);
+
+// batched.hip
+void bsb_solve_batched(const qh_graph *const *gs, int n, const qh_bsb_opts *o,
+                       qh_batched_result *res, hipStream_t st);
+
+// host-side components from unions
+int64_t label_components(int64_t n, std::vector<int32_t> &parent, std::vector<int32_t> &comp_out);
+void upload_components(qh_graph *g, const std::vector<int32_t> &comp, int64_t n_comp,
+                       hipStream_t st);
+
+}  // namespace qh

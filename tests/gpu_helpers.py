@@ -1,0 +1,49 @@
+"""Shared helpers of the GPU tests: workloads to device tensors, GPU graphs, bounds."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+import paper_2603_25762_amd as qh
+
+
+def device_reads(w):
+    d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+    return d
+
+
+def gpu_graph(w, kind="read_signed", dtype="f32", linkage_k=10, band_limit=0, with_alpha=True):
+    d = device_reads(w)
+    return qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"],
+                          kind=kind, dtype=dtype, alpha=d["alpha"] if with_alpha else None,
+                          linkage_k=linkage_k, band_limit=band_limit)
+
+
+def oracle_graph(w, kind="read_signed", linkage_k=10):
+    return oracle.build_graph(w, kind, linkage_k)
+
+
+def snp_abs_terms(w, linkage_k=10):
+    """Per-entry sum of |pair terms| of Eq. (14): the oracle graph of the same reads with
+    every allele made concordant with the initial haplotype (all terms then share a sign)."""
+    allele = w.init_h1[w.snp].copy()
+    M = oracle.encode(w.snp, allele, w.init_h1)
+    g = oracle.snp_graph(w.n_snp, w.frag_ptr, w.snp, M, w.phred, w.alpha, linkage_k)
+    return np.abs(g.dense())
+
+
+def step_bounds(J_abs_xabs, x, y, p, dt, c0, a0=1.0, rel=1e-5):
+    """Elementwise tolerance of one FP32 step against the FP64 reference."""
+    S = np.abs(y) + (abs(a0 - p) * np.abs(x) + c0 * J_abs_xabs) * dt
+    tol_y = rel * S
+    tol_x = rel * (np.abs(x) + a0 * dt * S)
+    return tol_x, tol_y
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def cpu(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy()

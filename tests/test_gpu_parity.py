@@ -1,0 +1,484 @@
+"""GPU-vs-oracle parity of the gfx950 library, called through its C ABI.
+
+Every expected value comes from ``oracle/`` (or the paper): graph weights
+(bit-exact for integer kinds, <= 1e-12 of the summed |terms| for the SNP
+log-likelihood weights), stored number formats (bit-exact against the oracle's
+software rounding), one bSB step (<= 1e-5 of the step's own magnitude), the
+FP64 readout (exact for integer weights), phasing (exact), and the final best
+cut of a whole solve (<= 0.1 % below the FP64 oracle, equal switch error).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2603_25762_amd as qh
+import synth
+from oracle import metrics, quant
+from gpu_helpers import cpu, f32, gpu_graph, oracle_graph, snp_abs_terms, step_bounds
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    qh.load()
+    yield
+    torch.cuda.synchronize()
+
+
+FMT = {"f32": None, "f16": "f16", "bf16": "bf16", "fp8": "f16"}
+
+
+def stored_J(J, dtype):
+    if dtype == "f32":
+        return quant.round_to("f32", J)
+    if dtype == "fp8":
+        scale, q = quant.rowscale_e4m3(J)
+        return scale[:, None] * q
+    return quant.round_to(dtype, J)
+
+
+# ----------------------------------------------------------------------------- graphs
+
+READ_CASES = {
+    "tiny": lambda: synth.read_tiny(),
+    "ragged300": lambda: synth.read_small(5, n_snp=400, n_reads=300, span=(10, 60)),
+    "sparse_many_comps": lambda: synth.read_small(6, n_snp=2000, n_reads=130, span=(3, 12)),
+}
+
+
+@pytest.mark.parametrize("kind", ["read_signed", "read_conflict"])
+@pytest.mark.parametrize("case", list(READ_CASES))
+def test_read_graph_bit_exact(kind, case):
+    w = READ_CASES[case]()
+    g = gpu_graph(w, kind)
+    go = oracle_graph(w, kind)
+    info = g.info()
+    assert info["n"] == go.n and info["integer_weights"] == 1
+    assert np.array_equal(cpu(g.export_rows(0, go.n)), go.dense())
+    comp, nc = oracle.components(go)
+    assert info["n_comp"] == nc
+    assert np.array_equal(cpu(g.components()), comp)
+    assert info["nnz"] == go.nnz
+    assert info["c0_auto"] == pytest.approx(oracle.c0(go), rel=1e-15)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])
+def test_dense_stored_values_bit_exact(dtype):
+    w = synth.read_small(9, n_snp=300, n_reads=200, span=(20, 60))
+    g = gpu_graph(w, "read_signed", dtype)
+    J = oracle_graph(w).dense()
+    S = cpu(g.export_rows(0, g.info()["n"], stored=True))
+    assert np.array_equal(S, stored_J(J, dtype))
+    tiles = g.info()["dense_tiles"]
+    assert 0 < tiles <= 4 * 4
+
+
+@pytest.fixture(scope="module")
+def mhc():
+    w = synth.read_mhc()
+    M = oracle.encode(w.snp, w.allele, w.init_h1)
+    W, _ = oracle.read_graph_dense(w.n_snp, w.frag_ptr, w.snp, M, "signed")
+    return w, W
+
+
+def test_read_graph_mhc_scale_sampled_rows(mhc):
+    """Full MHC-scale read graph (8,000 reads): sampled rows, master and FP16 copy."""
+    w, W = mhc
+    g = gpu_graph(w, "read_signed", "f16")
+    n = g.info()["n"]
+    assert n == W.shape[0]
+    rows = sorted(set([0, 1, 63, 64, 65, n // 2, n - 65, n - 64, n - 2, n - 1] +
+                      list(np.random.default_rng(0).integers(0, n, 40))))
+    for r in rows:
+        assert np.array_equal(cpu(g.export_rows(r, r + 1))[0], W[r].astype(np.float64)), r
+        assert np.array_equal(cpu(g.export_rows(r, r + 1, stored=True))[0],
+                              quant.round_to("f16", W[r].astype(np.float64))), r
+    assert g.info()["nnz"] == int(np.count_nonzero(W))
+
+
+SNP_CASES = {
+    "snp2000": dict(make=lambda: synth.snp_small(3, n_snp=2000), k=10, band=0),
+    "snp2000_k5": dict(make=lambda: synth.snp_small(4, n_snp=2000), k=5, band=0),
+    "snp_q_low": dict(make=lambda: synth.snp_small(12, n_snp=800, q=(2, 12)), k=10, band=0),
+    "porec3000": dict(make=lambda: synth.snp_porec(41, n_snp=3000, n_edges=3000, zipf_s=1.0), k=10,
+                      band=100),
+}
+
+
+@pytest.mark.parametrize("case", list(SNP_CASES))
+def test_snp_graph_normwise(case):
+    c = SNP_CASES[case]
+    w = c["make"]()
+    g = gpu_graph(w, "snp_llr", "f32", linkage_k=c["k"], band_limit=c["band"])
+    go = oracle_graph(w, "snp_llr", c["k"])
+    D = cpu(g.export_rows(0, go.n))
+    T = snp_abs_terms(w, c["k"])
+    assert np.all(np.abs(D - go.dense()) <= 1e-12 * T)
+    comp, nc = oracle.components(go)
+    assert g.info()["n_comp"] == nc
+    assert np.array_equal(cpu(g.components()), comp)
+    if c["band"]:
+        assert g.info()["longrange_nnz"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_skyline_stored_values_bit_exact(dtype):
+    w = synth.snp_porec(42, n_snp=1500, n_edges=1500, zipf_s=1.0)
+    g = gpu_graph(w, "snp_llr", dtype, band_limit=100)
+    S = cpu(g.export_rows(0, g.info()["n"], stored=True))
+    J = oracle_graph(w, "snp_llr").dense()
+    tol = 1e-12 * snp_abs_terms(w)
+    lo, hi = quant.round_to(dtype, J - tol), quant.round_to(dtype, J + tol)
+    sure = lo == hi          # the master's last-bit freedom cannot move the rounding
+    assert sure.mean() > 0.999
+    assert np.array_equal(S[sure], lo[sure])
+    assert np.all((S[~sure] == lo[~sure]) | (S[~sure] == hi[~sure]))
+
+
+# ----------------------------------------------------------------------------- one step
+
+def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37):
+    n = J.shape[0]
+    rng = np.random.default_rng(rng_seed)
+    x0 = f32(rng.uniform(-1.0, 1.0, (n, R)))
+    y0 = f32(rng.uniform(-0.6, 0.6, (n, R)))
+    pump = np.linspace(0.0, 1.0, steps).astype(np.float32)
+    c0 = 0.4 / max(1.0, float(np.sqrt((J ** 2).sum() / max(n - 1, 1))))
+    c0 = float(np.float32(c0))
+    p = float(pump[k])
+    dt = 0.5
+    x = torch.tensor(x0, dtype=torch.float32, device="cuda").contiguous()
+    y = torch.tensor(y0, dtype=torch.float32, device="cuda").contiguous()
+    qh.bsb_solve(g, R, steps, dt=dt, c0=c0, pump=torch.tensor(pump, device="cuda"), init=False,
+                 x=x, y=y, step_begin=k, step_end=k + 1, readout=False)
+    xg, yg = cpu(x).astype(np.float64), cpu(y).astype(np.float64)
+    xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False)
+    xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True)
+    xq = x0 if product_format is None else quant.round_to(product_format, x0)
+    tol_x, tol_y = step_bounds(np.abs(J) @ np.abs(xq), x0, y0, p, dt, c0)
+    ambiguous = np.abs(np.abs(xu) - 1.0) <= tol_x
+    ok = ~ambiguous
+    assert ok.mean() > 0.9
+    assert np.all(np.abs(xg - xo)[ok] <= tol_x[ok])
+    assert np.all(np.abs(yg - yo)[ok] <= tol_y[ok])
+    assert np.all(np.abs(xg) <= 1.0)
+    assert np.all(yg[np.abs(xg) == 1.0][~ambiguous[np.abs(xg) == 1.0]] == 0.0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])
+@pytest.mark.parametrize("R", [16, 32, 64, 128])
+def test_dense_one_step(dtype, R):
+    w = synth.read_small(13, n_snp=300, n_reads=150, span=(20, 60))     # 3 row tiles, ragged tail
+    g = gpu_graph(w, "read_signed", dtype)
+    J = stored_J(oracle_graph(w).dense(), dtype)
+    _one_step_case(g, J, dtype, R, 100 + R, FMT[dtype])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("R", [16, 32, 64, 128])
+def test_skyline_one_step(dtype, R):
+    w = synth.snp_small(14, n_snp=1500)
+    g = gpu_graph(w, "snp_llr", dtype)
+    J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
+    _one_step_case(g, J, dtype, R, 200 + R, None)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("R", [32, 64])
+def test_longrange_hub_one_step(dtype, R):
+    w = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
+    g = gpu_graph(w, "snp_llr", dtype, band_limit=100)
+    assert g.info()["longrange_nnz"] > 0
+    J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
+    _one_step_case(g, J, dtype, R, 300 + R, None)
+
+
+def test_mhc_scale_one_step_f16(mhc):
+    """One step at the full MHC-scale shape and the benchmark's launch (R = 256, FP16)."""
+    w, W = mhc
+    g = gpu_graph(w, "read_signed", "f16")
+    _one_step_case(g, W.astype(np.float64), "f16", 256, 7, "f16", steps=2000, k=999)
+
+
+# ----------------------------------------------------------------------------- init, resume, graphs
+
+def test_init_bit_exact():
+    w = synth.read_small(15, n_snp=200, n_reads=70)
+    g = gpu_graph(w)
+    n = g.info()["n"]
+    for R in (16, 64):
+        x = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        y = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        qh.bsb_solve(g, R, 1, seed=12345, init=True, x=x, y=y, step_begin=1, step_end=1, readout=False)
+        xo, yo = oracle.init_state(12345, n, R)
+        assert np.array_equal(cpu(x), xo.astype(np.float32))
+        assert np.array_equal(cpu(y), yo.astype(np.float32))
+
+
+RESUME_CASES = [("read_signed", "f32"), ("read_signed", "f16"), ("read_signed", "fp8"), ("snp_llr", "f32"),
+                ("snp_llr", "bf16")]
+
+
+@pytest.mark.parametrize("kind,dtype", RESUME_CASES)
+def test_resume_and_graph_replay_bit_identical(kind, dtype):
+    w = synth.read_small(16, n_snp=300, n_reads=140) if kind != "snp_llr" else synth.snp_small(16, n_snp=900)
+    g = gpu_graph(w, kind, dtype)
+    n, R, steps = g.info()["n"], 64, 200
+    def run(**kw):
+        x = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        y = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        r = qh.bsb_solve(g, R, steps, seed=5, x=x, y=y, **kw)
+        return x, y, r
+    xa, ya, ra = run()
+    xb, yb, _ = run(step_end=120, readout=False)
+    xb2 = xb.clone(); yb2 = yb.clone()
+    qh.bsb_solve(g, R, steps, init=False, x=xb2, y=yb2, step_begin=120, step_end=200, readout=False)
+    assert torch.equal(xa, xb2) and torch.equal(ya, yb2)
+    # captured step loop, replayed several times with eager work in between
+    for rep in range(3):
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device="cuda").sum()
+        xc, yc, rc = run(use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xc) and torch.equal(ya, yc), rep
+        assert torch.equal(ra["best_spins"], rc["best_spins"]) and torch.equal(ra["best_cut"], rc["best_cut"])
+        del junk
+
+
+# ----------------------------------------------------------------------------- readout
+
+def _readout_case(w, kind, R, seed, exact):
+    g = gpu_graph(w, kind, "f32")
+    go = oracle_graph(w, kind)
+    n = go.n
+    rng = np.random.default_rng(seed)
+    x0 = f32(np.where(rng.random((n, R)) < 0.5, -0.5, 0.5))
+    x0[rng.random((n, R)) < 0.05] = 0.0          # sgn(0) = +1
+    y0 = np.zeros((n, R))
+    x = torch.tensor(x0, dtype=torch.float32, device="cuda")
+    y = torch.tensor(y0, dtype=torch.float32, device="cuda")
+    res = qh.bsb_solve(g, R, 1, init=False, x=x, y=y, step_begin=1, step_end=1, readout=True, greedy=True,
+                       all_spins=True, per_component=True)
+    s = oracle.signs(x0)
+    comp, nc = oracle.components(go)
+    cut = oracle.cuts(go, comp, nc, s)
+    best, br = oracle.select(comp, nc, s, cut)
+    sel = float(sum(cut[br[c], c] for c in range(nc)))
+    gbest, rounds = oracle.greedy(go, best, oracle.greedy_eps(go, exact))
+    final = float(oracle.cuts(go, comp, nc, gbest).sum())
+    assert np.array_equal(cpu(res["all_spins"]), s)
+    if exact:
+        assert np.array_equal(cpu(res["cut_rc"])[:, :nc], cut)
+        assert np.array_equal(cpu(res["cuts"]), cut.sum(axis=1))
+        assert np.array_equal(cpu(res["best_replica"])[:nc], br)
+        assert cpu(res["selected_cut"])[0] == sel
+        assert np.array_equal(cpu(res["best_spins"]), gbest)
+        assert cpu(res["best_cut"])[0] == final
+        assert int(cpu(res["greedy_rounds"])[0]) == rounds
+    else:
+        scale = np.abs(go.val).sum()
+        assert np.allclose(cpu(res["cut_rc"])[:, :nc], cut, rtol=0, atol=1e-12 * scale)
+        assert cpu(res["selected_cut"])[0] == pytest.approx(sel, abs=1e-12 * scale)
+        assert cpu(res["best_cut"])[0] == pytest.approx(final, abs=1e-9 * scale)
+
+
+@pytest.mark.parametrize("R", [16, 64, 256])
+def test_readout_integer_exact(R):
+    _readout_case(synth.read_small(17, n_snp=600, n_reads=250, span=(5, 40)), "read_signed", R, R, True)
+
+
+def test_readout_conflict_many_components():
+    _readout_case(synth.read_small(18, n_snp=3000, n_reads=200, span=(3, 15)), "read_conflict", 32, 3, True)
+
+
+def test_readout_float_weights():
+    _readout_case(synth.snp_small(19, n_snp=1200), "snp_llr", 64, 4, False)
+
+
+# ----------------------------------------------------------------------------- phasing
+
+def test_phase_vote_exact():
+    w = synth.read_small(20, n_snp=500, n_reads=260, span=(5, 50), error=0.08)
+    g = gpu_graph(w)
+    go = oracle_graph(w)
+    comp, nc = oracle.components(go)
+    rng = np.random.default_rng(1)
+    s = np.where(w.origin == 0, 1, -1).astype(np.int8)
+    s[rng.random(s.shape[0]) < 0.2] *= -1
+    h1, blk = qh.phase(g, torch.tensor(s, device="cuda"))
+    M = oracle.encode(w.snp, w.allele, w.init_h1)
+    ho, bo = oracle.phase_vote(w.n_snp, w.frag_ptr, w.snp, M, s, comp, w.init_h1)
+    assert np.array_equal(cpu(h1), ho) and np.array_equal(cpu(blk), bo)
+
+
+def test_phase_parity_exact():
+    w = synth.snp_small(21, n_snp=1500)
+    g = gpu_graph(w, "snp_llr")
+    go = oracle_graph(w, "snp_llr")
+    comp, nc = oracle.components(go)
+    s = np.where(np.random.default_rng(2).random(go.n) < 0.4, 1, -1).astype(np.int8)
+    h1, blk = qh.phase(g, torch.tensor(s, device="cuda"))
+    ho, bo = oracle.phase_parity(comp, nc, s, w.init_h1)
+    assert np.array_equal(cpu(h1), ho) and np.array_equal(cpu(blk), bo)
+
+
+def test_flip_crossing_matches_oracle():
+    w = synth.snp_small(22, n_snp=1000)
+    g = gpu_graph(w, "snp_llr", "f32")
+    go = oracle_graph(w, "snp_llr")
+    s = np.where(np.random.default_rng(3).random(go.n) < 0.5, 1, -1).astype(np.int8)
+    qh.flip_crossing(g, torch.tensor(s, device="cuda"))
+    D = cpu(g.export_rows(0, go.n))
+    Do = oracle.flip_crossing(go, s).dense()
+    assert np.all(np.abs(D - Do) <= 1e-12 * snp_abs_terms(w))
+    S = cpu(g.export_rows(0, go.n, stored=True))
+    assert np.array_equal(S, quant.round_to("f32", D))
+
+
+# ----------------------------------------------------------------------------- whole solves
+
+def _gap(oracle_cut, gpu_cut):
+    return (oracle_cut - gpu_cut) / abs(oracle_cut)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])
+def test_read_tiny_final_cut_and_switch_error(dtype):
+    """Read-based tiny workload: R = 16, 1,000 steps, dt = 0.5, linear pump."""
+    w = synth.read_tiny()
+    g = gpu_graph(w, "read_signed", dtype)
+    go = oracle_graph(w)
+    ro = oracle.solve(go, 16, 1000, 0.5, seed=11, integer=True)
+    rg = qh.bsb_solve(g, 16, 1000, dt=0.5, seed=11)
+    assert _gap(ro["best_cut"], float(cpu(rg["best_cut"])[0])) <= 1e-3
+    M = oracle.encode(w.snp, w.allele, w.init_h1)
+    ho, bo = oracle.phase_vote(w.n_snp, w.frag_ptr, w.snp, M, ro["best"], ro["comp"], w.init_h1)
+    hg, bg = qh.phase(g, rg["best_spins"])
+    assert metrics.switch_error(cpu(hg), w.truth, cpu(bg)) == metrics.switch_error(ho, w.truth, bo)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])
+def test_read_midsize_final_cut(dtype):
+    w = synth.read_mhc(seed=77, n_snp=2400, n_reads=1600, region=800_000)
+    g = gpu_graph(w, "read_signed", dtype)
+    go = oracle_graph(w)
+    ro = oracle.solve(go, 64, 1000, 0.5, seed=3, integer=True)
+    rg = qh.bsb_solve(g, 64, 1000, dt=0.5, seed=3, use_graph=True)
+    assert _gap(ro["best_cut"], float(cpu(rg["best_cut"])[0])) <= 1e-3
+    M = oracle.encode(w.snp, w.allele, w.init_h1)
+    ho, bo = oracle.phase_vote(w.n_snp, w.frag_ptr, w.snp, M, ro["best"], ro["comp"], w.init_h1)
+    hg, bg = qh.phase(g, rg["best_spins"])
+    assert metrics.switch_error(cpu(hg), w.truth, cpu(bg)) <= metrics.switch_error(ho, w.truth, bo)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_snp_final_cut(dtype):
+    w = synth.snp_small(23, n_snp=2000)
+    g = gpu_graph(w, "snp_llr", dtype)
+    go = oracle_graph(w, "snp_llr")
+    ro = oracle.solve(go, 64, 1000, 0.5, seed=4)
+    rg = qh.bsb_solve(g, 64, 1000, dt=0.5, seed=4, use_graph=True)
+    assert _gap(ro["best_cut"], float(cpu(rg["best_cut"])[0])) <= 1e-3
+    comp, nc = oracle.components(go)
+    ho, bo = oracle.phase_parity(comp, nc, ro["best"], w.init_h1)
+    hg, bg = qh.phase(g, rg["best_spins"])
+    assert metrics.switch_error(cpu(hg), w.truth, cpu(bg)) <= metrics.switch_error(ho, w.truth, bo)
+
+
+@pytest.mark.parametrize("n_snp,dtype", [(600, "f16"), (1500, "f32"), (1500, "f16")])
+def test_snp_planted_twin_switch_error_equals_oracle(n_snp, dtype):
+    """Error-free reads: the GPU's switch error equals the FP64 oracle's at the same
+    schedule (on long SNP chains bSB can keep domain walls; both sides then agree)."""
+    w = synth.snp_small(24, n_snp=n_snp, error=0.0)
+    g = gpu_graph(w, "snp_llr", dtype)
+    go = oracle_graph(w, "snp_llr")
+    rg = qh.bsb_solve(g, 32, 600, dt=0.5, seed=1)
+    ro = oracle.solve(go, 32, 600, 0.5, seed=1)
+    comp, nc = oracle.components(go)
+    ho, bo = oracle.phase_parity(comp, nc, ro["best"], w.init_h1)
+    hg, bg = qh.phase(g, rg["best_spins"])
+    se_o = metrics.switch_error(ho, w.truth, bo)
+    assert metrics.switch_error(cpu(hg), w.truth, cpu(bg)) == se_o
+    assert _gap(ro["best_cut"], float(cpu(rg["best_cut"])[0])) <= 1e-3
+
+
+def test_porec_final_cut():
+    w = synth.snp_porec(44, n_snp=2500, n_edges=3000, zipf_s=1.0)
+    g = gpu_graph(w, "snp_llr", "bf16", band_limit=100)
+    go = oracle_graph(w, "snp_llr")
+    ro = oracle.solve(go, 64, 800, 0.5, seed=6)
+    rg = qh.bsb_solve(g, 64, 800, dt=0.5, seed=6)
+    assert _gap(ro["best_cut"], float(cpu(rg["best_cut"])[0])) <= 1e-3
+
+
+def test_batched_matches_single_solves():
+    blocks = [synth.read_small(50 + b, n_snp=200, n_reads=40 + 30 * b) for b in range(3)] + \
+             [synth.snp_small(60 + b, n_snp=150 + 200 * b) for b in range(3)]
+    kinds = ["read_signed"] * 3 + ["snp_llr"] * 3
+    dtypes = ["fp8"] * 3 + ["bf16"] * 3
+    gs = [gpu_graph(w, k, d) for w, k, d in zip(blocks, kinds, dtypes)]
+    rb = qh.bsb_solve_batched(gs, 32, 300, seed=9)
+    off = rb["vertex_offset"]
+    for b, (w, k, g) in enumerate(zip(blocks, kinds, gs)):
+        rs = qh.bsb_solve(g, 32, 300, seed=9)
+        assert torch.equal(rb["best_spins"][off[b]:off[b + 1]], rs["best_spins"]), b
+        assert torch.equal(rb["best_cut"][b:b + 1], rs["best_cut"]), b
+        go = oracle_graph(w, k)
+        ro = oracle.solve(go, 32, 300, 0.5, seed=9, integer=(k != "snp_llr"))
+        assert _gap(ro["best_cut"], float(cpu(rs["best_cut"])[0])) <= 1e-3, b
+
+
+# ----------------------------------------------------------------------------- errors, edges
+
+def test_error_paths():
+    w = synth.read_tiny()
+    g = gpu_graph(w)
+    with pytest.raises(qh.QhapError) as e:
+        qh.bsb_solve(g, 48, 10)
+    assert e.value.status == qh.Status.EINVAL
+    with pytest.raises(qh.QhapError) as e:
+        qh.bsb_solve(g, 16, 10, step_begin=5, step_end=20)
+    assert e.value.status == qh.Status.EINVAL
+    d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+    with pytest.raises(qh.QhapError) as e:     # SNP index beyond n_snp
+        qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"][:100])
+    assert e.value.status == qh.Status.EINVAL
+    with pytest.raises(qh.QhapError) as e:
+        qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="read_signed",
+                       storage="skyline")
+    assert e.value.status == qh.Status.EUNSUPPORTED
+    with pytest.raises(qh.QhapError) as e:
+        qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="snp_llr",
+                       dtype="fp8")
+    assert e.value.status == qh.Status.EUNSUPPORTED
+    bad = d["snp"].clone()
+    bad[5], bad[6] = bad[6].item(), bad[5].item()        # not ascending inside fragment 0
+    with pytest.raises(qh.QhapError) as e:
+        qh.build_graph(d["frag_ptr"], bad, d["allele"], d["phred"], d["init_h1"])
+    assert e.value.status == qh.Status.EINVAL
+    n = g.info()["n"]
+    x = torch.zeros((n, 16), device="cuda")
+    x[3, 2] = float("nan")
+    y = torch.zeros((n, 16), device="cuda")
+    with pytest.raises(qh.QhapError) as e:
+        qh.bsb_solve(g, 16, 1, init=False, x=x, y=y, step_begin=1, step_end=1)
+    assert e.value.status == qh.Status.ENUMERIC
+
+
+def test_degenerate_graphs():
+    # one fragment: no edges, no components; zero fragments
+    for nf in (1, 0):
+        w = synth.read_small(25, n_snp=50, n_reads=max(nf, 1), span=(5, 10))
+        fp = w.frag_ptr[: nf + 1].copy()
+        snp = w.snp[: fp[-1]].copy()
+        d = dict(frag_ptr=qh.to_device(fp), snp=qh.to_device(snp), allele=qh.to_device(w.allele[: fp[-1]].copy()),
+                 phred=qh.to_device(w.phred[: fp[-1]].copy()), init_h1=qh.to_device(w.init_h1))
+        g = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"])
+        inf = g.info()
+        assert inf["n"] == nf and inf["n_comp"] == 0 and inf["nnz"] == 0
+        r = qh.bsb_solve(g, 16, 20)
+        assert float(cpu(r["best_cut"])[0]) == 0.0
+        h1, blk = qh.phase(g, r["best_spins"] if nf else torch.ones(1, dtype=torch.int8, device="cuda"))
+        assert np.all(cpu(h1) == -1)

@@ -242,3 +242,13 @@ def test_greedy_independent_set_rule_hand():
     s, rounds = oracle.greedy(g, np.array([1, 1, 1], dtype=np.int8), 0.0)
     # round 1 flips only the middle vertex (largest gain among neighbours): cut 2 = optimum
     assert s.tolist() == [1, -1, 1] and rounds == 1
+
+
+def test_dense_step_helper_matches_c_step():
+    w = synth.read_small(31, n_snp=100, n_reads=30, span=(10, 30))
+    g = oracle.build_graph(w, "read_signed")
+    x, y = oracle.init_state(3, g.n, 4)
+    x2, y2 = oracle.bsb_step_dense(g.dense(), x, y, 0.37, 0.5, oracle.c0(g), 1.0)
+    pump = np.array([0.0, 0.37])
+    oracle.bsb_run(g, x, y, pump, 0.5, oracle.c0(g), 1.0, 1, 2)
+    assert np.allclose(x2, x, rtol=0, atol=1e-15) and np.allclose(y2, y, rtol=0, atol=1e-15)
