@@ -171,7 +171,10 @@ typedef struct {
     int32_t greedy;      /* 1: greedy single-flip rounds on the selected spins */
     int32_t use_graph;   /* 1: replay the step loop from a captured hipGraph (cached per
                             graph and option set); 0: plain stream launches */
-    int32_t plan;        /* 0 = choose the kernel variant automatically; >0 forces one */
+    int32_t plan;        /* step-loop plan: 0 = autotuned; 1 = one fused kernel per step;
+                            2 = persistent (dense 16/8-bit graphs; XCD-local synchronisation
+                            when the replica groups map onto XCDs); 3 = per-row skyline kernel
+                            (SNP graphs); 4 = persistent with agent-scope synchronisation */
 } qh_bsb_opts;
 
 /* Result buffers (all device, caller-owned; optional ones may be NULL).
@@ -203,6 +206,26 @@ typedef struct {
  * init = 0 without x/y, readout without best_spins/cuts/best_cut), ENUMERIC when the
  * final state holds NaN/Inf (checked when readout = 1), ENOMEM, EHIP. */
 qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *res, void *stream);
+
+/* Step-loop plan chosen for (graph, replicas) by earlier solves.  plan_used: 0 = no solve
+ * yet, 1 = one fused kernel per step, 2 = persistent (all steps in one cooperative
+ * launch, state in registers, J in LDS).  With opts.plan = 0 the first solve of a
+ * (graph, replicas) pair times both plans on scratch state (64 steps each) and keeps the
+ * faster; us_per_step holds those measurements (0 when not measured).  Host output.
+ * The persistent plan synchronises neighbouring workgroups inside one XCD's L2 when each
+ * replica group maps onto one XCD, else with agent-scope release / acquire. */
+typedef struct {
+    int32_t plan_used;
+    int32_t persistent_ok;      /* 1 when the persistent plan fits this graph */
+    int32_t replicas_per_group; /* persistent plan: replicas per independent group */
+    int32_t groups;             /* persistent plan: replica groups */
+    int32_t workgroups_per_group;
+    int32_t lds_bytes;          /* persistent plan: LDS per workgroup */
+    int32_t xcd_local;          /* persistent plan synchronises inside one XCD's L2 */
+    float us_per_step[3];       /* autotuner: [per-step, persistent agent-scope, persistent XCD-local] */
+} qh_plan_info;
+
+qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *out);
 
 /* Many independent graphs (phasing blocks) in one persistent launch: every block
  * runs the same schedule with its own c0 (opts->c0 <= 0: each block's c0_auto).

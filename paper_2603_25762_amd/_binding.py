@@ -73,6 +73,13 @@ class _Result(ctypes.Structure):
                 ("greedy_rounds", P)]
 
 
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("plan_used", ctypes.c_int32), ("persistent_ok", ctypes.c_int32),
+                ("replicas_per_group", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("workgroups_per_group", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("xcd_local", ctypes.c_int32), ("us_per_step", ctypes.c_float * 3)]
+
+
 class _BatchedResult(ctypes.Structure):
     _fields_ = [("best_spins", P), ("cuts", P), ("best_cut", P), ("selected_cut", P),
                 ("x", P), ("y", P)]
@@ -104,6 +111,7 @@ def load():
                                  ctypes.POINTER(_BatchedResult), P],
         "qh_phase": [P, P, P, P, P],
         "qh_flip_crossing": [P, P, P],
+        "qh_solve_plan_info": [P, ctypes.c_int32, ctypes.POINTER(_PlanInfo)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -174,6 +182,14 @@ class Graph:
         _check(load().qh_graph_components(self._h, _ptr(out), _stream()))
         return out
 
+    def plan_info(self, replicas: int) -> Dict[str, object]:
+        """Step-loop plan of earlier solves with this replica count (autotuner report)."""
+        pi = _PlanInfo()
+        _check(load().qh_solve_plan_info(self._h, replicas, ctypes.byref(pi)))
+        d = {name: getattr(pi, name) for name, _ in _PlanInfo._fields_}
+        d["us_per_step"] = list(pi.us_per_step)
+        return d
+
     def free(self):
         if self._h is not None and self._h.value:
             torch.cuda.synchronize()
@@ -218,6 +234,7 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
               init: bool = True, x: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None,
               step_begin: int = 0, step_end: int = 0, readout: bool = True, greedy: bool = True,
               use_graph: bool = False, all_spins: bool = False, per_component: bool = False,
+              plan: int = 0,
               out: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
     """Runs bSB; returns device tensors (best_spins, cuts, best_cut, selected_cut, ...).
 
@@ -259,7 +276,7 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
     if pump is not None:
         res["pump"] = pump
     opts = _BsbOpts(replicas, steps, step_begin, step_end, dt, c0, a0, _ptr(pump), seed & (2**64 - 1),
-                    int(init), int(readout), int(greedy), int(use_graph), 0)
+                    int(init), int(readout), int(greedy), int(use_graph), int(plan))
     r = _Result(_ptr(x), _ptr(y), _ptr(keep.get("best_spins")), _ptr(keep.get("cuts")),
                 _ptr(keep.get("cut_rc")), _ptr(keep.get("best_replica")), _ptr(keep.get("selected_cut")),
                 _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")))

@@ -188,6 +188,13 @@ qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *re
     });
 }
 
+qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *out) {
+    return guarded([&] {
+        if (!g || !out) fail(QH_EINVAL, "null argument");
+        plan_info(g, replicas, out);
+    });
+}
+
 qh_status qh_bsb_solve_batched(const qh_graph *const *graphs, int32_t n_graphs,
                                const qh_bsb_opts *opts, qh_batched_result *res, void *stream) {
     return guarded([&] {

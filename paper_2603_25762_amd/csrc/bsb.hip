@@ -15,6 +15,7 @@
 
 #include "formats.h"
 #include "internal.h"
+#include "persistent.h"
 
 namespace qh {
 
@@ -280,6 +281,61 @@ __global__ __launch_bounds__(256) void k_sky_step(
     }
 }
 
+// Register-tiled band step (R a multiple of 64; lane = replica).  Wave = one band block
+// of kBandRows consecutive rows: it walks the block's union column range once, loads
+// each x row once and applies it to all kBandRows accumulators with one column of the
+// block (kBandRows values, wave-uniform, so they arrive through scalar loads).  The
+// long-range lists of the block's rows follow, then the fused update.
+template <int DT>
+__global__ __launch_bounds__(256) void k_band_step(
+    int64_t n, int R, int64_t n_bblk, int64_t G, const int64_t *__restrict__ bb_off,
+    const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
+    const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
+    const int32_t *__restrict__ hub_of_row, const int32_t *__restrict__ hub_chunk_ptr,
+    const float *__restrict__ hub_part, const float *__restrict__ x_in, float *__restrict__ x_out,
+    float *__restrict__ y, StepArgs sa) {
+    constexpr int RB = kBandRows;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t blk = xcd_remap(blockIdx.x, G) * 4 + wave;
+    if (blk >= n_bblk) return;
+    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
+    const int32_t L = bb_lo[blk], W = bb_w[blk];
+    const int64_t off = bb_off[blk];
+    float z[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) z[i] = 0.f;
+    const float *xc = x_in + (int64_t)L * R + r;
+#pragma unroll 2
+    for (int32_t j = 0; j < W; ++j) {
+        const float xj = xc[(int64_t)j * R];
+        const int64_t e0 = off + (int64_t)j * RB;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) z[i] += ld_val<DT>(bb_val, e0 + i) * xj;
+    }
+    const float coef = sa.a0 - sa.pump[sa.k];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const int64_t u = blk * RB + i;
+        if (u >= n) break;
+        float zi = z[i];
+        if (l_ptr) {
+            const int hub = hub_of_row[u];
+            if (hub < 0) {
+                for (int64_t e = l_ptr[u]; e < l_ptr[u + 1]; ++e)
+                    zi += ld_val<DT>(l_val, e) * x_in[(int64_t)l_col[e] * R + r];
+            } else {
+                for (int c = hub_chunk_ptr[hub]; c < hub_chunk_ptr[hub + 1]; ++c) zi += hub_part[(int64_t)c * R + r];
+            }
+        }
+        const int64_t idx = u * R + r;
+        float xv = x_in[idx], yv = y[idx];
+        bsb_update(zi, xv, yv, coef, sa);
+        y[idx] = yv;
+        x_out[idx] = xv;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // readout
 // ---------------------------------------------------------------------------
@@ -530,10 +586,17 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
     hipLaunchKernelGGL((k_sky_step<DTV, RTV>), grid, dim3(256), 0, st, n, R, rows_per_wg, nblk, g->s_off.p,    \
                        g->s_lo.p, g->s_len.p, g->s_val.p, lr ? g->l_ptr.p : nullptr, g->l_col.p, g->l_val.p,    \
                        g->hub_of_row.p, g->hub_chunk_ptr.p, p.hub_part.p, xin, xout, p.y.p, sa)
+    const bool band = RT == 64 && g->n_bblk > 0 && !p.sky_rows;
+    const int64_t GB = ceil_div(g->n_bblk, 4);
+#define QH_BAND(DTV)                                                                                            \
+    hipLaunchKernelGGL((k_band_step<DTV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, R,      \
+                       g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p, lr ? g->l_ptr.p : nullptr, \
+                       g->l_col.p, g->l_val.p, g->hub_of_row.p, g->hub_chunk_ptr.p, p.hub_part.p, xin, xout, p.y.p, sa)
 #define QH_SKY_RT(DTV)                                                  \
     do {                                                                \
         if (RT == 16) { if (g->n_hub_chunks) QH_HUB(DTV, 16); QH_SKY(DTV, 16); } \
         else if (RT == 32) { if (g->n_hub_chunks) QH_HUB(DTV, 32); QH_SKY(DTV, 32); } \
+        else if (band) { if (g->n_hub_chunks) QH_HUB(DTV, 64); QH_BAND(DTV); } \
         else { if (g->n_hub_chunks) QH_HUB(DTV, 64); QH_SKY(DTV, 64); }  \
     } while (0)
     switch (g->dtype) {
@@ -543,6 +606,7 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
         default: fail(QH_EUNSUPPORTED, "dtype not offered on skyline storage");
     }
 #undef QH_SKY_RT
+#undef QH_BAND
 #undef QH_SKY
 #undef QH_HUB
     QH_CHECK_LAUNCH();
@@ -567,6 +631,107 @@ static int run_steps(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, cons
     return cur;
 }
 
+static void x_to_h(const qh_graph *g, SolvePlan &p, int64_t n, int R, hipStream_t st) {
+    const int64_t nR = n * R;
+    if (!nR) return;
+    if (g->dtype == QH_BF16)
+        hipLaunchKernelGGL(k_x_to_h<true>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p);
+    else
+        hipLaunchKernelGGL(k_x_to_h<false>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p);
+    QH_CHECK_LAUNCH();
+}
+
+// Steps [kb, ke) in one cooperative launch; the state is in p.xa / p.y / p.ha.  `xl`
+// selects the XCD-local synchronisation.  Returns false when a workgroup found itself on
+// an unexpected XCD (the state is then not usable and XCD-local runs are switched off).
+static bool run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, double c0, double dt, double a0,
+                           int kb, int ke, bool xl, hipStream_t st) {
+    PersistPlan &pp = *p.pp;
+    QH_HIP(hipMemsetAsync(pp.flags.p, 0, pp.flags.bytes(), st));
+    PersistArgs pa{};
+    pa.n = g->n;
+    pa.R = p.R;
+    pa.kb = kb;
+    pa.ke = ke;
+    pa.ng = pp.ng;
+    pa.wpg = pp.wpg;
+    pa.wg_rt = pp.wg_rt.p;
+    pa.t_ptr = g->t_ptr.p;
+    pa.t_val = g->t_val.p;
+    pa.row_scale = g->row_scale.p;
+    pa.wg_ct_ptr = pp.wg_ct_ptr.p;
+    pa.wg_ct = pp.wg_ct.p;
+    pa.tile_slot = pp.tile_slot.p;
+    pa.nbr_ptr = pp.nbr_ptr.p;
+    pa.nbr = pp.nbr.p;
+    pa.x = p.xa.p;
+    pa.y = p.y.p;
+    pa.h0 = p.ha.p;
+    pa.h1 = p.hb.p;
+    pa.flags = pp.flags.p;
+    pa.err = pp.flags.p + (int64_t)pp.ng * pp.wpg + 32;
+    pa.c0 = (float)c0;
+    pa.dt = (float)dt;
+    pa.a0 = (float)a0;
+    pa.pump = pump;
+    pa.lds_j_bytes = pp.lds_j_bytes;
+    pa.max_polls = (int64_t)1 << 27;
+    launch_persistent(g, pp, pa, xl, st);
+    int32_t err = 0;
+    QH_HIP(hipMemcpyAsync(&err, pa.err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    QH_HIP(hipStreamSynchronize(st));
+    if (err & 2) {
+        disable_xcd_local();
+        return false;
+    }
+    if (err) fail(QH_EHIP, "persistent bSB kernel: a neighbour wait exceeded its poll limit");
+    return true;
+}
+
+static bool use_xcd_local(const SolvePlan &p) { return p.pp && p.pp->ok && p.pp->xlocal_ok && !xcd_local_disabled(); }
+
+// Autotuner for plan 0 on dense 16/8-bit graphs: time a short run of each candidate on
+// scratch state -- one fused kernel per step, persistent with agent-scope
+// synchronisation, persistent with XCD-local synchronisation -- and keep the fastest.
+// Every candidate computes bit-identical results, so the choice only affects speed.
+static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, const float *pump, double c0,
+                           double a0, hipStream_t st) {
+    const int64_t n = g->n;
+    const int R = p.R;
+    const int nt = std::min(o->steps, 64);
+    hipEvent_t e0, e1;
+    QH_HIP(hipEventCreate(&e0));
+    QH_HIP(hipEventCreate(&e1));
+    float best = 0.0f;
+    int choice = 1;
+    for (int cand : {0, 1, 2}) {   // 0 per-step, 1 persistent agent-scope, 2 persistent XCD-local
+        if (cand >= 1 && !(p.pp && p.pp->ok)) continue;
+        if (cand == 2 && !use_xcd_local(p)) continue;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {   // the first repetition warms caches and code
+            hipLaunchKernelGGL(k_init, dim3(grid_for(n * R)), dim3(256), 0, st, (uint64_t)0x5eed, n, R, p.xa.p,
+                               p.y.p);
+            QH_CHECK_LAUNCH();
+            x_to_h(g, p, n, R, st);
+            QH_HIP(hipEventRecord(e0, st));
+            if (cand == 0) run_steps(g, p, o, pump, c0, a0, 0, nt, st);
+            else ok = run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, cand == 2, st);
+            QH_HIP(hipEventRecord(e1, st));
+            QH_HIP(hipEventSynchronize(e1));
+        }
+        if (!ok) continue;
+        float ms = 0.0f;
+        QH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        p.tuned_us[cand] = ms * 1000.0f / nt;
+        if (cand == 0 || ms < best) { best = ms; choice = cand == 0 ? 1 : 2; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p.tuned_plan = choice;
+    // if the agent-scope persistent run was the faster one, do not use the XCD-local one
+    p.tuned_xl = choice == 2 && p.tuned_us[2] > 0.0f && (p.tuned_us[1] == 0.0f || p.tuned_us[2] <= p.tuned_us[1]);
+}
+
 void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStream_t st) {
     int cur_dev = 0;
     QH_HIP(hipGetDevice(&cur_dev));
@@ -588,29 +753,60 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
         pump = p.pump_lin.p;
     }
     const int64_t nR = n * R;
-    // initial state into xa / y
-    if (o->init) {
-        if (nR) {
-            hipLaunchKernelGGL(k_init, dim3(grid_for(nR)), dim3(256), 0, st, o->seed, n, R, p.xa.p, p.y.p);
-            QH_CHECK_LAUNCH();
-        }
-    } else if (nR) {
-        hipLaunchKernelGGL(k_copy_state_in, dim3(grid_for(nR)), dim3(256), 0, st, n, R, res->x, p.xa.p);
-        hipLaunchKernelGGL(k_copy_state_in, dim3(grid_for(nR)), dim3(256), 0, st, n, R, res->y, p.y.p);
-        QH_CHECK_LAUNCH();
-    }
     const bool dense16 = !x_pingpong(g);
-    if (dense16 && nR) {
-        if (g->dtype == QH_BF16)
-            hipLaunchKernelGGL(k_x_to_h<true>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p);
-        else
-            hipLaunchKernelGGL(k_x_to_h<false>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p);
-        QH_CHECK_LAUNCH();
+    if (p.sky_rows != (o->plan == 3)) {
+        // the captured step loop launches the other skyline kernel: drop it
+        p.sky_rows = o->plan == 3;
+        if (p.exec) { (void)hipGraphExecDestroy(p.exec); p.exec = nullptr; }
+        if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }
     }
 
-    // the step loop
+    // the step loop: the persistent dense plan (plan 2), one fused kernel per step (plan 1,
+    // optionally replayed from a captured hipGraph), or the autotuner's choice (plan 0)
     int final_half = 0;
-    if (ke > kb && n > 0) {
+    bool persistent = false;
+    const bool want_persistent = o->plan == 0 || o->plan == 2 || o->plan == 4;
+    if (dense16 && want_persistent && ke > kb && n > 0) {
+        if (!p.pp_tried) {
+            p.pp = std::make_shared<PersistPlan>();
+            build_persistent_plan(g, R, *p.pp, st);
+            p.pp_tried = true;
+        }
+        persistent = p.pp->ok;
+        if (persistent && o->plan == 0) {
+            if (!p.tuned_plan) autotune_dense(g, p, o, pump, c0, a0, st);
+            persistent = p.tuned_plan == 2;
+        }
+    }
+    if ((o->plan == 2 || o->plan == 4) && !persistent)
+        fail(QH_EUNSUPPORTED, "the persistent plan does not apply to this graph and replica count");
+    // initial state into xa / y (after any tuning, which uses the same buffers)
+    auto load_state = [&]() {
+        if (o->init) {
+            if (nR) {
+                hipLaunchKernelGGL(k_init, dim3(grid_for(nR)), dim3(256), 0, st, o->seed, n, R, p.xa.p, p.y.p);
+                QH_CHECK_LAUNCH();
+            }
+        } else if (nR) {
+            hipLaunchKernelGGL(k_copy_state_in, dim3(grid_for(nR)), dim3(256), 0, st, n, R, res->x, p.xa.p);
+            hipLaunchKernelGGL(k_copy_state_in, dim3(grid_for(nR)), dim3(256), 0, st, n, R, res->y, p.y.p);
+            QH_CHECK_LAUNCH();
+        }
+        if (dense16) x_to_h(g, p, n, R, st);
+    };
+    load_state();
+    if (ke > kb && n > 0) p.last_plan = persistent ? 2 : 1;
+    if (persistent) {
+        bool xl = use_xcd_local(p) && (o->plan == 2 || (o->plan == 0 && p.tuned_xl));
+        p.last_xl = xl;
+        if (!run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, xl, st)) {
+            // a workgroup ran on an unexpected XCD: redo the run with agent-scope synchronisation
+            p.last_xl = false;
+            load_state();
+            if (!run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, false, st))
+                fail(QH_EHIP, "persistent bSB kernel: placement check failed without XCD-local mode");
+        }
+    } else if (ke > kb && n > 0) {
         if (o->use_graph) {
             auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R);
             if (!p.exec || p.graph_key != key) {

@@ -263,6 +263,30 @@ __global__ void k_quantize(int64_t n, const double *__restrict__ src, int dtype,
     }
 }
 
+// Band blocks: element (block b, column offset j, row i) = J[16b + i][bb_lo[b] + j], zero
+// outside the row's skyline range (and on the diagonal, which is zero anyway).
+__global__ void k_pack_band(int64_t n, int64_t n_bblk, const int64_t *__restrict__ s_off,
+                            const int32_t *__restrict__ s_lo, const int32_t *__restrict__ s_len,
+                            const double *__restrict__ s_val64, const int64_t *__restrict__ bb_off,
+                            const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, int dtype,
+                            uint8_t *__restrict__ out) {
+    for (int64_t b = blockIdx.x; b < n_bblk; b += gridDim.x) {
+        const int64_t cnt = (int64_t)bb_w[b] * kBandRows;
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const int64_t j = e / kBandRows, i = e - j * kBandRows;
+            const int64_t u = b * kBandRows + i, c = bb_lo[b] + j;
+            double v = 0.0;
+            if (u < n && c >= s_lo[u] && c < s_lo[u] + s_len[u]) v = s_val64[s_off[u] + (c - s_lo[u])];
+            const int64_t o = bb_off[b] + e;
+            switch (dtype) {
+                case QH_F32: ((float *)out)[o] = (float)v; break;
+                case QH_F16: ((uint16_t *)out)[o] = f64_to_f16_bits(v); break;
+                case QH_BF16: ((uint16_t *)out)[o] = f64_to_bf16_bits(v); break;
+            }
+        }
+    }
+}
+
 // Deterministic partial sums of squares (fixed grid, fixed order per block).
 __global__ void k_sumsq_partial(int64_t n, const double *__restrict__ v, double *__restrict__ part) {
     __shared__ double sh[256];
@@ -366,6 +390,19 @@ __global__ void k_flip_sky(int64_t n, const int64_t *__restrict__ s_off, const i
         if (l_ptr)
             for (int64_t e = l_ptr[r]; e < l_ptr[r + 1]; ++e)
                 if (s[r] != s[l_col[e]]) negate_stored(l_val, e, dtype);
+    }
+}
+
+__global__ void k_flip_band(int64_t n, int64_t n_bblk, const int64_t *__restrict__ bb_off,
+                            const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, uint8_t *__restrict__ val,
+                            int dtype, const int8_t *__restrict__ s) {
+    for (int64_t b = blockIdx.x; b < n_bblk; b += gridDim.x) {
+        const int64_t cnt = (int64_t)bb_w[b] * kBandRows;
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+            const int64_t j = e / kBandRows, i = e - j * kBandRows;
+            const int64_t u = b * kBandRows + i, c = bb_lo[b] + j;
+            if (u < n && s[u] != s[c]) negate_stored(val, bb_off[b] + e, dtype);
+        }
     }
 }
 
@@ -814,6 +851,37 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
                            g->l_val.p);
         QH_CHECK_LAUNCH();
     }
+    // band blocks for the register-tiled step kernel
+    {
+        const int64_t nb = ceil_div(n, kBandRows);
+        std::vector<int32_t> blo(nb), bw(nb);
+        std::vector<int64_t> boff(nb + 1, 0);
+        for (int64_t b = 0; b < nb; ++b) {
+            int32_t L = INT32_MAX, H = -1;
+            for (int64_t u = b * kBandRows; u < std::min<int64_t>(n, (b + 1) * kBandRows); ++u) {
+                L = std::min(L, lo[u]);
+                H = std::max(H, hi[u]);
+            }
+            blo[b] = L;
+            bw[b] = H - L + 1;
+            boff[b + 1] = boff[b] + (int64_t)bw[b] * kBandRows;
+        }
+        g->n_bblk = nb;
+        g->bb_elems = boff[nb];
+        g->bb_off.alloc(nb + 1);
+        g->bb_off.upload(boff.data(), nb + 1, st);
+        g->bb_lo.alloc(nb);
+        g->bb_lo.upload(blo.data(), nb, st);
+        g->bb_w.alloc(nb);
+        g->bb_w.upload(bw.data(), nb, st);
+        g->bb_val.alloc((size_t)std::max<int64_t>(boff[nb], 1) * eb);
+        if (nb) {
+            hipLaunchKernelGGL(k_pack_band, dim3((unsigned)std::min<int64_t>(nb, 1 << 20)), dim3(256), 0, st,
+                               (int64_t)n, nb, g->s_off.p, g->s_lo.p, g->s_len.p, s_val64.p, g->bb_off.p, g->bb_lo.p,
+                               g->bb_w.p, g->dtype, g->bb_val.p);
+            QH_CHECK_LAUNCH();
+        }
+    }
     QH_HIP(hipStreamSynchronize(st));
 }
 
@@ -886,6 +954,9 @@ void flip_crossing(qh_graph *g, const int8_t *spins, hipStream_t st) {
     hipLaunchKernelGGL(k_flip_sky, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, g->s_off.p, g->s_lo.p,
                        g->s_len.p, g->s_val.p, g->l_nnz ? g->l_ptr.p : nullptr, g->l_col.p, g->l_val.p, g->dtype,
                        spins);
+    if (g->n_bblk)
+        hipLaunchKernelGGL(k_flip_band, dim3((unsigned)std::min<int64_t>(g->n_bblk, 1 << 20)), dim3(256), 0, st,
+                           g->n, g->n_bblk, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p, g->dtype, spins);
     QH_CHECK_LAUNCH();
     // solve plans hold no copy of J; nothing else to refresh
 }

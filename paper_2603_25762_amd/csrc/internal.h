@@ -94,8 +94,18 @@ inline int dtype_bytes(int dt) {
     return 0;
 }
 
+struct PersistPlan;
+
 // Cached state of one solve configuration (scratch buffers + captured graph).
 struct SolvePlan {
+    std::shared_ptr<PersistPlan> pp;   // persistent dense plan (null until tried)
+    bool pp_tried = false;
+    int tuned_plan = 0;                // autotuner's choice for plan 0: 1 per-step, 2 persistent
+    int last_plan = 0;                 // plan the last solve ran
+    bool tuned_xl = false;             // autotuner: the XCD-local persistent run was the fastest
+    bool last_xl = false;              // the last persistent run used XCD-local synchronisation
+    bool sky_rows = false;             // SNP graphs: per-row skyline kernel instead of band blocks
+    float tuned_us[3] = {0, 0, 0};     // measured microseconds per step of each candidate
     int R = 0;
     int64_t n_pad = 0;
     DevBuf<float> xa, xb, y;        // fp32 state, [n_pad][R]
@@ -162,6 +172,13 @@ struct qh_graph {
     qh::DevBuf<uint8_t> s_val;          // slots in dtype
     int64_t s_slots = 0;
     int32_t band_limit = 0;
+    // Band blocks of kBandRows consecutive rows: the union column range [bb_lo, bb_lo + bb_w)
+    // of the block's skyline rows, stored column by column with kBandRows row values each
+    // (zero outside a row's own range), in dtype.
+    qh::DevBuf<int64_t> bb_off;         // [n_bblk] element offset of the block
+    qh::DevBuf<int32_t> bb_lo, bb_w;    // [n_bblk]
+    qh::DevBuf<uint8_t> bb_val;
+    int64_t n_bblk = 0, bb_elems = 0;
     // Long-range CSR (pairs farther apart than band_limit).
     qh::DevBuf<int64_t> l_ptr;          // [n + 1]
     qh::DevBuf<int32_t> l_col;
@@ -189,6 +206,7 @@ struct qh_graph {
 
 namespace qh {
 
+constexpr int kBandRows = 16;       // rows per band block (one wave's accumulators)
 constexpr int kHubInline = 64;      // long-range entries summed inline by the step kernel
 constexpr int kHubChunk = 64;       // entries per hub partial
 
@@ -203,6 +221,7 @@ void flip_crossing(qh_graph *g, const int8_t *spins, hipStream_t st);
 
 // bsb.hip
 void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStream_t st);
+void plan_info(const qh_graph *g, int R, qh_plan_info *out);
 
 // phase.hip
 void phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);

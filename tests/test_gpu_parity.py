@@ -140,7 +140,7 @@ def test_skyline_stored_values_bit_exact(dtype):
 
 # ----------------------------------------------------------------------------- one step
 
-def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37):
+def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, plan=0):
     n = J.shape[0]
     rng = np.random.default_rng(rng_seed)
     x0 = f32(rng.uniform(-1.0, 1.0, (n, R)))
@@ -153,7 +153,7 @@ def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37):
     x = torch.tensor(x0, dtype=torch.float32, device="cuda").contiguous()
     y = torch.tensor(y0, dtype=torch.float32, device="cuda").contiguous()
     qh.bsb_solve(g, R, steps, dt=dt, c0=c0, pump=torch.tensor(pump, device="cuda"), init=False,
-                 x=x, y=y, step_begin=k, step_end=k + 1, readout=False)
+                 x=x, y=y, step_begin=k, step_end=k + 1, readout=False, plan=plan)
     xg, yg = cpu(x).astype(np.float64), cpu(y).astype(np.float64)
     xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False)
     xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True)
@@ -168,22 +168,66 @@ def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37):
     assert np.all(yg[np.abs(xg) == 1.0][~ambiguous[np.abs(xg) == 1.0]] == 0.0)
 
 
+@pytest.mark.parametrize("plan", [1, 0])          # 1: one kernel per step; 0: persistent when it applies
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])
 @pytest.mark.parametrize("R", [16, 32, 64, 128])
-def test_dense_one_step(dtype, R):
+def test_dense_one_step(dtype, R, plan):
     w = synth.read_small(13, n_snp=300, n_reads=150, span=(20, 60))     # 3 row tiles, ragged tail
     g = gpu_graph(w, "read_signed", dtype)
     J = stored_J(oracle_graph(w).dense(), dtype)
-    _one_step_case(g, J, dtype, R, 100 + R, FMT[dtype])
+    _one_step_case(g, J, dtype, R, 100 + R, FMT[dtype], plan=plan)
 
 
+@pytest.mark.parametrize("dtype", ["f16", "bf16", "fp8"])
+@pytest.mark.parametrize("R", [16, 64, 256])
+def test_persistent_equals_per_step_bit_exact(dtype, R):
+    """The persistent plan runs the same MFMA sequence and update as the per-step kernel,
+    so 300 steps of both must agree bit for bit (state and readout)."""
+    w = synth.read_mhc(seed=78, n_snp=1500, n_reads=1000, region=500_000)
+    g = gpu_graph(w, "read_signed", dtype)
+    n = g.info()["n"]
+    out = []
+    for plan in (1, 2, 4):       # per-step; persistent (XCD-local when it applies); agent-scope
+        x = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        y = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        r = qh.bsb_solve(g, R, 300, seed=31, x=x, y=y, plan=plan)
+        out.append((x, y, r))
+    xa, ya, ra = out[0]
+    for xb, yb, rb in out[1:]:
+        assert torch.equal(xa, xb) and torch.equal(ya, yb)
+        assert torch.equal(ra["best_spins"], rb["best_spins"]) and torch.equal(ra["best_cut"], rb["best_cut"])
+
+
+@pytest.mark.parametrize("plan", [0, 3])          # 0: band blocks (R % 64 == 0); 3: per-row skyline
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("R", [16, 32, 64, 128])
-def test_skyline_one_step(dtype, R):
+def test_skyline_one_step(dtype, R, plan):
     w = synth.snp_small(14, n_snp=1500)
     g = gpu_graph(w, "snp_llr", dtype)
     J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
-    _one_step_case(g, J, dtype, R, 200 + R, None)
+    _one_step_case(g, J, dtype, R, 200 + R, None, plan=plan)
+
+
+@pytest.mark.parametrize("case", ["snp", "porec"])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_band_kernel_equals_row_kernel_bit_exact(dtype, case):
+    """Band blocks add exact zeros around each row's range in the same ascending column
+    order as the per-row kernel, so 200 steps of both agree bit for bit."""
+    if case == "snp":
+        w, band = synth.snp_small(26, n_snp=1700), 0
+    else:
+        w, band = synth.snp_porec(45, n_snp=2000, n_edges=2500, zipf_s=1.0), 100
+    g = gpu_graph(w, "snp_llr", dtype, band_limit=band)
+    n, R = g.info()["n"], 128
+    out = []
+    for plan in (0, 3):
+        x = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        y = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        r = qh.bsb_solve(g, R, 200, seed=33, x=x, y=y, plan=plan)
+        out.append((x, y, r))
+    (xa, ya, ra), (xb, yb, rb) = out
+    assert torch.equal(xa, xb) and torch.equal(ya, yb)
+    assert torch.equal(ra["best_spins"], rb["best_spins"]) and torch.equal(ra["best_cut"], rb["best_cut"])
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
@@ -196,11 +240,13 @@ def test_longrange_hub_one_step(dtype, R):
     _one_step_case(g, J, dtype, R, 300 + R, None)
 
 
-def test_mhc_scale_one_step_f16(mhc):
-    """One step at the full MHC-scale shape and the benchmark's launch (R = 256, FP16)."""
+@pytest.mark.parametrize("plan", [2, 1])
+def test_mhc_scale_one_step_f16(mhc, plan):
+    """One step at the full MHC-scale shape and the benchmark's launch (R = 256, FP16):
+    plan 2 requires the persistent kernel the benchmark uses, plan 1 the per-step kernel."""
     w, W = mhc
     g = gpu_graph(w, "read_signed", "f16")
-    _one_step_case(g, W.astype(np.float64), "f16", 256, 7, "f16", steps=2000, k=999)
+    _one_step_case(g, W.astype(np.float64), "f16", 256, 7, "f16", steps=2000, k=999, plan=plan)
 
 
 # ----------------------------------------------------------------------------- init, resume, graphs
