@@ -172,9 +172,8 @@ typedef struct {
     int32_t use_graph;   /* 1: replay the step loop from a captured hipGraph (cached per
                             graph and option set); 0: plain stream launches */
     int32_t plan;        /* step-loop plan: 0 = autotuned; 1 = one fused kernel per step;
-                            2 = persistent (dense 16/8-bit graphs; XCD-local synchronisation
-                            when the replica groups map onto XCDs); 3 = per-row skyline kernel
-                            (SNP graphs); 4 = persistent with agent-scope synchronisation */
+                            2 = persistent (dense 16/8-bit graphs only); 3 = per-row skyline
+                            kernel instead of band blocks (SNP graphs) */
 } qh_bsb_opts;
 
 /* Result buffers (all device, caller-owned; optional ones may be NULL).
@@ -212,8 +211,8 @@ qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *re
  * launch, state in registers, J in LDS).  With opts.plan = 0 the first solve of a
  * (graph, replicas) pair times both plans on scratch state (64 steps each) and keeps the
  * faster; us_per_step holds those measurements (0 when not measured).  Host output.
- * The persistent plan synchronises neighbouring workgroups inside one XCD's L2 when each
- * replica group maps onto one XCD, else with agent-scope release / acquire. */
+ * The persistent plan synchronises neighbouring workgroups with agent-scope
+ * release / acquire on per-workgroup step counters. */
 typedef struct {
     int32_t plan_used;
     int32_t persistent_ok;      /* 1 when the persistent plan fits this graph */
@@ -221,8 +220,7 @@ typedef struct {
     int32_t groups;             /* persistent plan: replica groups */
     int32_t workgroups_per_group;
     int32_t lds_bytes;          /* persistent plan: LDS per workgroup */
-    int32_t xcd_local;          /* persistent plan synchronises inside one XCD's L2 */
-    float us_per_step[3];       /* autotuner: [per-step, persistent agent-scope, persistent XCD-local] */
+    float us_per_step[2];       /* autotuner: [per-step plan, persistent plan] */
 } qh_plan_info;
 
 qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *out);

@@ -368,6 +368,54 @@ def flip_crossing(g: CSR, s) -> CSR:
     return CSR(g.n, g.row_ptr, g.col, val)
 
 
+def refine(g: CSR, init_h1: np.ndarray, R: int, steps: int, dt: float = 0.5, seed: int = 0,
+           max_rounds: int = 15, integer: bool = False) -> Dict[str, object]:
+    """Iterative refinement of the SNP-based method (Eqs. 15-17).
+
+    Round t solves the current graph (seed + t).  A component stops when its cut is not
+    positive or its partition puts every vertex on one side; otherwise the vertices of its
+    smaller subset (the s = -1 subset on a tie) add one to their flip counter C and every
+    edge crossing the partition changes sign.  Haplotype 1 is H1 where C is even and H2
+    where C is odd.
+    """
+    comp, nc = components(g)
+    C = np.zeros(g.n, dtype=np.int64)
+    done = np.zeros(nc, dtype=bool)
+    cur = g
+    round_cuts = []
+    rounds = 0
+    for t in range(max_rounds):
+        if done.all():
+            break
+        r = solve(cur, R, steps, dt, seed=seed + t, integer=integer)
+        s = r["best"]
+        cut_c = cuts(cur, comp, nc, s)[0] if nc else np.zeros(0)
+        s_eff = np.ones(g.n, dtype=np.int8)
+        applied = 0.0
+        for c in range(nc):
+            if done[c]:
+                continue
+            members = comp == c
+            sc = s[members]
+            if cut_c[c] <= 0 or np.all(sc == sc[0]):
+                done[c] = True
+                continue
+            plus = int(np.count_nonzero(sc > 0))
+            smin = 1 if plus < sc.shape[0] - plus else -1
+            C[members & (s == smin)] += 1
+            s_eff[members] = s[members]
+            applied += cut_c[c]
+        if not (s_eff < 0).any():
+            break
+        cur = flip_crossing(cur, s_eff)
+        round_cuts.append(applied)
+        rounds += 1
+    h1 = np.where(comp >= 0, np.where(C % 2 == 1, 1 - init_h1.astype(np.int64), init_h1), -1).astype(np.int8)
+    block = np.where(comp >= 0, comp, -1).astype(np.int32)
+    return dict(h1=h1, block=block, flips=C, rounds=rounds, round_cuts=round_cuts, comp=comp,
+                n_comp=nc)
+
+
 # --------------------------------------------------------------------------
 # whole solve, as the library's bsb_solve defines it
 # --------------------------------------------------------------------------

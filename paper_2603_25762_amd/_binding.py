@@ -77,7 +77,7 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("plan_used", ctypes.c_int32), ("persistent_ok", ctypes.c_int32),
                 ("replicas_per_group", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("workgroups_per_group", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("xcd_local", ctypes.c_int32), ("us_per_step", ctypes.c_float * 3)]
+                ("us_per_step", ctypes.c_float * 2)]
 
 
 class _BatchedResult(ctypes.Structure):
@@ -286,7 +286,9 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
 
 def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt: float = 0.5,
                       c0: float = 0.0, a0: float = 1.0, seed: int = 0, greedy: bool = True,
-                      use_graph: bool = False, plan: int = 0, stream=None) -> Dict[str, torch.Tensor]:
+                      use_graph: bool = False, plan: int = 0, return_state: bool = False,
+                      stream=None) -> Dict[str, torch.Tensor]:
+    """All graphs in one launch; per-block results packed at ``vertex_offset`` / ``b * replicas``."""
     ns = [g.info()["n"] for g in graphs]
     total = int(sum(ns))
     nb = len(graphs)
@@ -295,11 +297,14 @@ def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt:
                cuts=torch.empty(max(nb * replicas, 1), dtype=torch.float64, device=dev),
                best_cut=torch.empty(max(nb, 1), dtype=torch.float64, device=dev),
                selected_cut=torch.empty(max(nb, 1), dtype=torch.float64, device=dev))
+    if return_state:
+        res["x"] = torch.empty(max(total * replicas, 1), dtype=torch.float32, device=dev)
+        res["y"] = torch.empty(max(total * replicas, 1), dtype=torch.float32, device=dev)
     arr = (ctypes.c_void_p * max(nb, 1))(*[g.handle.value for g in graphs])
     opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
                     int(use_graph), plan)
     r = _BatchedResult(_ptr(res["best_spins"]), _ptr(res["cuts"]), _ptr(res["best_cut"]),
-                       _ptr(res["selected_cut"]), None, None)
+                       _ptr(res["selected_cut"]), _ptr(res.get("x")), _ptr(res.get("y")))
     _check(load().qh_bsb_solve_batched(arr, nb, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
     res["vertex_offset"] = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
     return res

@@ -1,30 +1,151 @@
-// Many independent phasing blocks (connected components / regions) solved with
-// one schedule.  Each block keeps its own couplings, c0 and readout.
+// Many independent phasing blocks (connected components / regions) solved in one
+// persistent launch.  Every block keeps its own couplings, c0, state and readout; the
+// blocks share the schedule (steps, dt, a0, pump) and the seed.
+//
+// Work placement: whole blocks per workgroup.  Blocks are ordered by estimated bytes
+// streamed per step (largest first) and each goes to the least-loaded worker
+// (longest-processing-time rule), so a few large dense blocks do not serialise behind
+// many small ones.  Inside a workgroup the steps of a block are separated by workgroup
+// barriers only.  The arithmetic and its order are those of the single-graph kernels,
+// so block b's result equals qh_bsb_solve on graph b with the same options, bit for bit.
 #include <algorithm>
+#include <numeric>
+#include <queue>
 #include <vector>
 
 #include "internal.h"
 
 namespace qh {
 
+static double block_cost(const qh_graph *g, int R) {
+    const double eb = dtype_bytes(g->dtype);
+    const double state = (double)g->n * R * 12.0;
+    if (g->storage == QH_STORE_DENSE) return (double)g->n_tiles * kTile * kTile * eb + state;
+    return (double)g->bb_elems * eb + state;
+}
+
 void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, qh_batched_result *res,
                        hipStream_t st) {
     const int R = o->replicas;
+    if (R != 16 && R != 32 && R != 64) fail(QH_EUNSUPPORTED, "batched solves take 16, 32 or 64 replicas");
+    if (!o->init) fail(QH_EINVAL, "batched solves start from the seeded initial state (init = 1)");
+    if (o->step_begin != 0 || (o->step_end != 0 && o->step_end != o->steps))
+        fail(QH_EINVAL, "batched solves run the whole schedule");
+    if (nb == 0) return;
+    int dev = 0;
+    QH_HIP(hipGetDevice(&dev));
+    for (int b = 0; b < nb; ++b) {
+        if (!gs[b]) fail(QH_EINVAL, "graph %d is null", b);
+        if (gs[b]->device != dev) fail(QH_EINVAL, "graph %d lives on device %d, current device is %d", b,
+                                       gs[b]->device, dev);
+        if (gs[b]->storage != QH_STORE_DENSE && gs[b]->l_nnz > 0)
+            fail(QH_EUNSUPPORTED, "graph %d has long-range couplings; solve it on its own", b);
+        if (gs[b]->storage != QH_STORE_DENSE && gs[b]->dtype == QH_FP8_ROWSCALE)
+            fail(QH_EUNSUPPORTED, "graph %d: FP8 applies to dense storage only", b);
+    }
+    {   // every block owns its state buffers: a graph may appear once per batch
+        std::vector<const qh_graph *> seen(gs, gs + nb);
+        std::sort(seen.begin(), seen.end());
+        if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+            fail(QH_EINVAL, "a graph appears twice in one batch");
+    }
+    const double a0 = o->a0 > 0.0 ? o->a0 : 1.0;
+
+    // per-block plans: state buffers and readout scratch of the single-graph solve
+    std::vector<SolvePlan *> plans(nb);
+    for (int b = 0; b < nb; ++b) plans[b] = &solve_plan(gs[b], R, st);
+    const float *pump = o->pump ? o->pump : linear_pump(*plans[0], o->steps, st);
+
+    std::vector<BlockDesc> desc(nb);
+    for (int b = 0; b < nb; ++b) {
+        const qh_graph *g = gs[b];
+        SolvePlan &p = *plans[b];
+        BlockDesc &d = desc[b];
+        d = BlockDesc{};
+        d.kind = g->storage == QH_STORE_DENSE ? 0 : 1;
+        d.dtype = g->dtype;
+        d.n = g->n;
+        d.x = p.xa.p;
+        d.y = p.y.p;
+        d.c0 = (float)(o->c0 > 0.0 ? o->c0 : g->c0_auto);
+        if (d.kind == 0) {
+            d.n_rt = g->n_rt;
+            d.t_ptr = g->t_ptr.p;
+            d.t_col = g->t_col.p;
+            d.t_val = g->t_val.p;
+            d.row_scale = g->row_scale.p;
+            if (g->dtype == QH_F32) d.xs = p.xb.p;
+            else { d.h0 = p.ha.p; d.h1 = p.hb.p; }
+        } else {
+            d.n_bblk = g->n_bblk;
+            d.bb_off = g->bb_off.p;
+            d.bb_lo = g->bb_lo.p;
+            d.bb_w = g->bb_w.p;
+            d.bb_val = g->bb_val.p;
+            d.xs = p.xb.p;
+        }
+    }
+
+    // longest-processing-time placement of blocks on workers
+    int cus = 0;
+    QH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int workers = (int)std::min<int64_t>(nb, (int64_t)std::max(cus, 1) * batched_workers_per_cu(R));
+    std::vector<int> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(nb);
+    for (int b = 0; b < nb; ++b) cost[b] = block_cost(gs[b], R);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    using Load = std::pair<double, int>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int w = 0; w < workers; ++w) heap.push({0.0, w});
+    std::vector<std::vector<int32_t>> lists(workers);
+    for (int b : order) {
+        Load l = heap.top();
+        heap.pop();
+        lists[l.second].push_back(b);
+        heap.push({l.first + cost[b], l.second});
+    }
+    std::vector<int32_t> sptr(workers + 1, 0), sched;
+    sched.reserve(nb);
+    for (int w = 0; w < workers; ++w) {
+        sched.insert(sched.end(), lists[w].begin(), lists[w].end());
+        sptr[w + 1] = (int32_t)sched.size();
+    }
+    DevBuf<BlockDesc> d_desc(nb);
+    DevBuf<int32_t> d_sptr(workers + 1), d_sched(nb);
+    QH_HIP(hipMemcpyAsync(d_desc.p, desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
+    QH_HIP(hipMemcpyAsync(d_sptr.p, sptr.data(), (workers + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    QH_HIP(hipMemcpyAsync(d_sched.p, sched.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (o->steps > 0)
+        launch_batched(R, workers, d_desc.p, d_sptr.p, d_sched.p, o->steps, (float)o->dt, (float)a0, pump, o->seed,
+                       st);
+
+    // per-block readout: FP64 cuts, component selection, optional greedy, cut of the result
     int64_t voff = 0;
     for (int b = 0; b < nb; ++b) {
         const qh_graph *g = gs[b];
+        SolvePlan &p = *plans[b];
+        const int64_t nR = g->n * R;
+        if (res->x && nR)
+            QH_HIP(hipMemcpyAsync(res->x + voff * R, p.xa.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+        if (res->y && nR)
+            QH_HIP(hipMemcpyAsync(res->y + voff * R, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
         qh_result r{};
         r.best_spins = res->best_spins + voff;
         r.cuts = res->cuts + (int64_t)b * R;
         r.best_cut = res->best_cut + b;
         r.selected_cut = res->selected_cut ? res->selected_cut + b : nullptr;
-        r.x = res->x ? res->x + voff * R : nullptr;
-        r.y = res->y ? res->y + voff * R : nullptr;
-        qh_bsb_opts ob = *o;
-        ob.readout = 1;
-        bsb_solve(g, &ob, &r, st);
+        p.last_plan = 1;
+        readout(view_of(g), p, R, p.xa.p, p.y.p, &r, o->greedy != 0, st, false);
         voff += g->n;
     }
+    // one synchronisation for the non-finite checks of every block
+    std::vector<int32_t> bad(nb, 0);
+    for (int b = 0; b < nb; ++b)
+        QH_HIP(hipMemcpyAsync(&bad[b], plans[b]->counter.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    QH_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < nb; ++b)
+        if (bad[b]) fail(QH_ENUMERIC, "non-finite spin or momentum in the final state of block %d", b);
 }
 
 }  // namespace qh

@@ -102,25 +102,15 @@ __device__ inline int64_t xcd_remap(int64_t bid, int64_t G) {
 //  DT = QH_FP8_ROWSCALE: E4M3 codes expanded exactly to f16 (value * 2^-8) in
 //       registers; the row scale (x 256) multiplies z in the epilogue.
 //  DT = QH_F32: v_mfma_f32_16x16x4f32 on the FP32 tile and FP32 x.
+// Product of stored tiles [t_beg, t_end) of one row tile with x, for the 16 rows of this
+// wave and RT = 16 NB replicas starting at r0.  Shared by the per-step and batched kernels.
 template <int DT, int NB>
-__global__ __launch_bounds__(256) void k_dense_step(
-    int64_t n, int R, int64_t n_rt, int64_t G, const int32_t *__restrict__ t_ptr,
-    const int32_t *__restrict__ t_col, const uint8_t *__restrict__ t_val, const float *__restrict__ row_scale,
-    const float *x_in, float *x_out, float *__restrict__ y,
-    const uint16_t *__restrict__ h_in, uint16_t *__restrict__ h_out, StepArgs sa) {
-    constexpr int RT = NB * 16;
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t logical = xcd_remap(blockIdx.x, G);
-    const int64_t rt = logical % n_rt;
-    const int64_t r0 = (logical / n_rt) * RT;
+__device__ inline void dense_product(float4_t (&acc)[NB], int t_beg, int t_end, const int32_t *__restrict__ t_col,
+                                     const uint8_t *__restrict__ t_val, const float *x_in,
+                                     const uint16_t *__restrict__ h_in, int64_t R, int64_t r0, int wave, int lane) {
     const int l16 = lane & 15, g4 = lane >> 4;
-
-    float4_t acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
-
-    const int t_beg = t_ptr[rt], t_end = t_ptr[rt + 1];
     for (int t = t_beg; t < t_end; ++t) {
         const int64_t j0 = (int64_t)t_col[t] * kTile;
         if constexpr (DT == QH_F32) {
@@ -173,10 +163,31 @@ __global__ __launch_bounds__(256) void k_dense_step(
             }
         }
     }
+}
 
-    // fused update: lane holds z for rows 4*g4 + q (q = 0..3) and replica l16 of each block
-    const float coef = sa.a0 - sa.pump[sa.k];
-    const int64_t rowbase = rt * kTile + wave * 16 + 4 * g4;
+// Own state of the lane (rows rowbase..rowbase+3, replicas r0 + 16b + l16).
+template <int NB>
+__device__ inline void dense_load_state(float (&xo)[NB][4], float (&yo)[NB][4], int64_t rowbase, int64_t n,
+                                        const float *x_in, const float *y, int64_t R, int64_t r0, int lane) {
+    const int l16 = lane & 15;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = rowbase + q;
+            const int64_t idx = i * R + r0 + b * 16 + l16;
+            xo[b][q] = i < n ? x_in[idx] : 0.f;
+            yo[b][q] = i < n ? y[idx] : 0.f;
+        }
+}
+
+// Fused update of the lane's rows and the 16-bit copy of the new x.
+template <int DT, int NB>
+__device__ inline void dense_update(const float4_t (&acc)[NB], const float (&xo)[NB][4], const float (&yo)[NB][4],
+                                    int64_t rowbase, int64_t n, int64_t R, int64_t r0, int lane,
+                                    const float *__restrict__ row_scale, float *x_out, float *y,
+                                    uint16_t *__restrict__ h_out, float coef, const StepArgs &sa) {
+    const int l16 = lane & 15;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int64_t r = r0 + b * 16 + l16;
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(256) void k_dense_step(
                 float z = acc[b][q];
                 if constexpr (DT == QH_FP8_ROWSCALE) z *= row_scale[i];
                 const int64_t idx = i * R + r;
-                float xv = x_in[idx], yv = y[idx];
+                float xv = xo[b][q], yv = yo[b][q];
                 bsb_update(z, xv, yv, coef, sa);
                 y[idx] = yv;
                 x_out[idx] = xv;
@@ -205,6 +216,27 @@ __global__ __launch_bounds__(256) void k_dense_step(
             *(uint2 *)(h_out + ((rowbase >> 3) * R + r) * 8 + (rowbase & 7)) = pk;
         }
     }
+}
+
+template <int DT, int NB>
+__global__ __launch_bounds__(256) void k_dense_step(
+    int64_t n, int R, int64_t n_rt, int64_t G, const int32_t *__restrict__ t_ptr,
+    const int32_t *__restrict__ t_col, const uint8_t *__restrict__ t_val, const float *__restrict__ row_scale,
+    const float *x_in, float *x_out, float *__restrict__ y,
+    const uint16_t *__restrict__ h_in, uint16_t *__restrict__ h_out, StepArgs sa) {
+    constexpr int RT = NB * 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t logical = xcd_remap(blockIdx.x, G);
+    const int64_t rt = logical % n_rt;
+    const int64_t r0 = (logical / n_rt) * RT;
+    const int64_t rowbase = rt * kTile + wave * 16 + 4 * (lane >> 4);
+    float xo[NB][4], yo[NB][4];
+    dense_load_state<NB>(xo, yo, rowbase, n, x_in, y, R, r0, lane);   // latency hides under the product
+    float4_t acc[NB];
+    dense_product<DT, NB>(acc, t_ptr[rt], t_ptr[rt + 1], t_col, t_val, x_in, h_in, R, r0, wave, lane);
+    dense_update<DT, NB>(acc, xo, yo, rowbase, n, R, r0, lane, row_scale, x_out, y, h_out,
+                         sa.a0 - sa.pump[sa.k], sa);
 }
 
 // ---------------------------------------------------------------------------
@@ -231,6 +263,7 @@ __global__ __launch_bounds__(256) void k_hub_partials(
     for (int64_t c = (int64_t)blockIdx.x * 4 * RPW + wave * RPW + sub; c < n_chunks;
          c += (int64_t)gridDim.x * 4 * RPW) {
         float z = 0.f;
+#pragma unroll 4
         for (int64_t e = cbeg[c]; e < cend[c]; ++e) z += ld_val<DT>(l_val, e) * x_in[(int64_t)l_col[e] * R + r];
         part[c * R + r] = z;
     }
@@ -286,54 +319,180 @@ __global__ __launch_bounds__(256) void k_sky_step(
 // each x row once and applies it to all kBandRows accumulators with one column of the
 // block (kBandRows values, wave-uniform, so they arrive through scalar loads).  The
 // long-range lists of the block's rows follow, then the fused update.
+// One band block of rows [blk*16, blk*16 + 16) for the lane's replica r (inactive lanes
+// skip every memory access).  Shared by the per-step and batched kernels.
 template <int DT>
-__global__ __launch_bounds__(256) void k_band_step(
-    int64_t n, int R, int64_t n_bblk, int64_t G, const int64_t *__restrict__ bb_off,
-    const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
-    const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
-    const int32_t *__restrict__ hub_of_row, const int32_t *__restrict__ hub_chunk_ptr,
-    const float *__restrict__ hub_part, const float *__restrict__ x_in, float *__restrict__ x_out,
-    float *__restrict__ y, StepArgs sa) {
+__device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_t r, bool active,
+                                       const int64_t *__restrict__ bb_off, const int32_t *__restrict__ bb_lo,
+                                       const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
+                                       const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ hub_of_row,
+                                       const int32_t *__restrict__ hub_chunk_ptr, const float *__restrict__ hub_part,
+                                       const float *x_in, float *x_out, float *y, float coef, const StepArgs &sa) {
     constexpr int RB = kBandRows;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t blk = xcd_remap(blockIdx.x, G) * 4 + wave;
-    if (blk >= n_bblk) return;
-    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
     const int32_t L = bb_lo[blk], W = bb_w[blk];
     const int64_t off = bb_off[blk];
-    float z[RB];
+    float z[RB], xo[RB], yo[RB];
 #pragma unroll
-    for (int i = 0; i < RB; ++i) z[i] = 0.f;
+    for (int i = 0; i < RB; ++i) {
+        z[i] = 0.f;
+        const int64_t u = blk * RB + i;       // own state first: its latency hides under the band loop
+        xo[i] = (active && u < n) ? x_in[u * R + r] : 0.f;
+        yo[i] = (active && u < n) ? y[u * R + r] : 0.f;
+    }
     const float *xc = x_in + (int64_t)L * R + r;
-#pragma unroll 2
+#pragma unroll 4
     for (int32_t j = 0; j < W; ++j) {
-        const float xj = xc[(int64_t)j * R];
+        const float xj = active ? xc[(int64_t)j * R] : 0.f;
         const int64_t e0 = off + (int64_t)j * RB;
 #pragma unroll
         for (int i = 0; i < RB; ++i) z[i] += ld_val<DT>(bb_val, e0 + i) * xj;
     }
-    const float coef = sa.a0 - sa.pump[sa.k];
+    if (!active) return;
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
         const int64_t u = blk * RB + i;
         if (u >= n) break;
         float zi = z[i];
         if (l_ptr) {
-            const int hub = hub_of_row[u];
-            if (hub < 0) {
-                for (int64_t e = l_ptr[u]; e < l_ptr[u + 1]; ++e)
-                    zi += ld_val<DT>(l_val, e) * x_in[(int64_t)l_col[e] * R + r];
-            } else {
+            const int hub = hub_of_row[u];     // every long-range row is summed by chunks
+            if (hub >= 0)
                 for (int c = hub_chunk_ptr[hub]; c < hub_chunk_ptr[hub + 1]; ++c) zi += hub_part[(int64_t)c * R + r];
-            }
         }
         const int64_t idx = u * R + r;
-        float xv = x_in[idx], yv = y[idx];
+        float xv = xo[i], yv = yo[i];
         bsb_update(zi, xv, yv, coef, sa);
         y[idx] = yv;
         x_out[idx] = xv;
     }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_band_step(
+    int64_t n, int R, int64_t n_bblk, int64_t G, const int64_t *__restrict__ bb_off,
+    const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
+    const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ hub_of_row, const int32_t *__restrict__ hub_chunk_ptr,
+    const float *__restrict__ hub_part, const float *__restrict__ x_in, float *__restrict__ x_out,
+    float *__restrict__ y, StepArgs sa) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t blk = xcd_remap(blockIdx.x, G) * 4 + wave;
+    if (blk >= n_bblk) return;
+    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
+    band_block_step<DT>(blk, n, R, r, true, bb_off, bb_lo, bb_w, bb_val, l_ptr, hub_of_row, hub_chunk_ptr, hub_part,
+                        x_in, x_out, y, sa.a0 - sa.pump[sa.k], sa);
+}
+
+// ---------------------------------------------------------------------------
+// batched blocks: one persistent launch, whole blocks per workgroup
+// ---------------------------------------------------------------------------
+
+// Each workgroup runs its scheduled blocks one after another; a block's steps are
+// separated by workgroup barriers only, because no other workgroup touches its state.
+// Dense blocks use the tile product of the per-step kernel (wave w: rows 16w.. of every
+// row tile), SNP blocks the band step; arithmetic and order match the single-graph
+// kernels, so a block's result equals its single-graph solve bit for bit.
+template <int NB>
+__global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ blocks,
+                                                 const int32_t *__restrict__ sched_ptr,
+                                                 const int32_t *__restrict__ sched, int steps, float dt, float a0,
+                                                 const float *__restrict__ pump, uint64_t seed) {
+    constexpr int64_t R = NB * 16;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int k = sched_ptr[blockIdx.x]; k < sched_ptr[blockIdx.x + 1]; ++k) {
+        const BlockDesc B = blocks[sched[k]];
+        const int64_t n = B.n;
+        float *xb = B.x, *yb = B.y;
+        // initial state: the single-graph counter layout with this block's n
+        for (int64_t t = tid; t < n * R; t += 256) {
+            const int64_t i = t / R, r = t - i * R;
+            const uint64_t c = 2ull * ((uint64_t)r * (uint64_t)n + (uint64_t)i);
+            xb[t] = (float)(0.2 * ((double)(sm64_draw(seed, c) >> 11) * 0x1.0p-53) - 0.1);
+            yb[t] = (float)(0.2 * ((double)(sm64_draw(seed, c + 1) >> 11) * 0x1.0p-53) - 0.1);
+        }
+        __syncthreads();
+        const bool dense16 = B.kind == 0 && B.dtype != QH_F32;
+        if (dense16)
+            for (int64_t t = tid; t < n * R; t += 256) {
+                const int64_t i = t / R, r = t - i * R;
+                B.h0[((i >> 3) * R + r) * 8 + (i & 7)] =
+                    B.dtype == QH_BF16 ? f32_to_bf16_rne(xb[t]) : f32_to_f16_rne(xb[t]);
+            }
+        __syncthreads();
+        StepArgs sa{B.c0, dt, a0, pump, 0};
+        float *cur = xb, *oth = B.xs;
+        for (int s = 0; s < steps; ++s) {
+            sa.k = s;
+            const float coef = a0 - pump[s];
+            if (B.kind == 0) {
+                const uint16_t *hin = (s & 1) ? B.h1 : B.h0;
+                uint16_t *hout = (s & 1) ? B.h0 : B.h1;
+                float *xin = dense16 ? xb : cur, *xout = dense16 ? xb : oth;
+                for (int64_t rt = 0; rt < B.n_rt; ++rt) {
+                    const int64_t rowbase = rt * kTile + wave * 16 + 4 * (lane >> 4);
+                    float xo[NB][4], yo[NB][4];
+                    float4_t acc[NB];
+                    dense_load_state<NB>(xo, yo, rowbase, n, xin, yb, R, 0, lane);
+#define QH_BD(DTV)                                                                                              \
+    dense_product<DTV, NB>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, xin, hin, R, 0, wave, lane);  \
+    dense_update<DTV, NB>(acc, xo, yo, rowbase, n, R, 0, lane, B.row_scale, xout, yb, hout, coef, sa)
+                    switch (B.dtype) {
+                        case QH_F32: QH_BD(QH_F32); break;
+                        case QH_F16: QH_BD(QH_F16); break;
+                        case QH_BF16: QH_BD(QH_BF16); break;
+                        default: QH_BD(QH_FP8_ROWSCALE); break;
+                    }
+#undef QH_BD
+                }
+            } else {
+                const bool active = lane < R;
+                for (int64_t bb = wave; bb < B.n_bblk; bb += 4) {
+#define QH_BB(DTV)                                                                                          \
+    band_block_step<DTV>(bb, n, R, lane, active, B.bb_off, B.bb_lo, B.bb_w, B.bb_val, nullptr, nullptr,   \
+                         nullptr, nullptr, cur, oth, yb, coef, sa)
+                    switch (B.dtype) {
+                        case QH_F32: QH_BB(QH_F32); break;
+                        case QH_F16: QH_BB(QH_F16); break;
+                        default: QH_BB(QH_BF16); break;
+                    }
+#undef QH_BB
+                }
+            }
+            __syncthreads();
+            if (!dense16) { float *t = cur; cur = oth; oth = t; }
+        }
+        // the ping-pong paths may end in the scratch half
+        if (!dense16 && cur != xb)
+            for (int64_t t = tid; t < n * R; t += 256) xb[t] = cur[t];
+        __syncthreads();
+    }
+}
+
+void launch_batched(int R, int workers, const BlockDesc *blocks, const int32_t *sched_ptr, const int32_t *sched,
+                    int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st) {
+#define QH_BATCH(NBV)                                                                                          \
+    hipLaunchKernelGGL(k_batched<NBV>, dim3(workers), dim3(256), 0, st, blocks, sched_ptr, sched, steps, dt, a0, \
+                       pump, seed)
+    switch (R) {
+        case 16: QH_BATCH(1); break;
+        case 32: QH_BATCH(2); break;
+        case 64: QH_BATCH(4); break;
+        default: fail(QH_EUNSUPPORTED, "batched solves take 16, 32 or 64 replicas");
+    }
+#undef QH_BATCH
+    QH_CHECK_LAUNCH();
+}
+
+int batched_workers_per_cu(int R) {
+    int occ = 0;
+    hipError_t e = hipSuccess;
+    switch (R) {
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batched<1>, 256, 0); break;
+        case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batched<2>, 256, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_batched<4>, 256, 0); break;
+    }
+    if (e != hipSuccess) { (void)hipGetLastError(); occ = 1; }
+    return std::max(occ, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,13 +612,14 @@ __global__ void k_gain(int64_t n, const int64_t *__restrict__ ptr, const int32_t
 // Vertex a flips when g_a > eps and it beats every improving neighbour
 // (larger gain, or equal gain and lower index): the flipped set is independent.
 __global__ void k_pick(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                       const double *__restrict__ g, double eps, int8_t *__restrict__ flag,
-                       int32_t *__restrict__ count) {
+                       const double *__restrict__ g, double eps_all, const double *__restrict__ eps_v,
+                       int8_t *__restrict__ flag, int32_t *__restrict__ count) {
     int local = 0;
     for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
          a += (int64_t)gridDim.x * blockDim.x) {
         int8_t f = 0;
         double ga = g[a];
+        const double eps = eps_v ? eps_v[a] : eps_all;   // neighbours share a's graph, hence its tolerance
         if (ga > eps) {
             f = 1;
             for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
@@ -498,7 +658,19 @@ static int grid_for(int64_t n, int block = 256, int64_t cap = 65536) {
     return (int)g;
 }
 
-static SolvePlan &get_plan(const qh_graph *gc, int R, hipStream_t st) {
+void alloc_readout_scratch(SolvePlan &p, int64_t n, int64_t n_comp, int64_t n_chunks, int R) {
+    p.spins.alloc((size_t)std::max<int64_t>(n, 1) * R);
+    p.part.alloc((size_t)std::max<int64_t>(n_chunks, 1) * R);
+    p.cut_rc.alloc((size_t)std::max<int64_t>(n_comp, 1) * R);
+    p.best_r.alloc(std::max<int64_t>(n_comp, 1));
+    p.gain.alloc(std::max<int64_t>(n, 1));
+    p.flag.alloc(std::max<int64_t>(n, 1));
+    p.counter.alloc(4);
+    p.part1.alloc(std::max<int64_t>(n_chunks, 1));
+    p.cut1.alloc(std::max<int64_t>(n_comp, 1));
+}
+
+SolvePlan &solve_plan(const qh_graph *gc, int R, hipStream_t st) {
     qh_graph *g = const_cast<qh_graph *>(gc);
     auto it = g->plans.find(R);
     if (it != g->plans.end()) return *it->second;
@@ -520,15 +692,7 @@ static SolvePlan &get_plan(const qh_graph *gc, int R, hipStream_t st) {
         p->hb.alloc(st_elems);
         p->hb.zero(st);
     }
-    p->spins.alloc((size_t)std::max<int64_t>(g->n, 1) * R);
-    p->part.alloc((size_t)std::max<int64_t>(g->n_chunks, 1) * R);
-    p->cut_rc.alloc((size_t)std::max<int64_t>(g->n_comp, 1) * R);
-    p->best_r.alloc(std::max<int64_t>(g->n_comp, 1));
-    p->gain.alloc(std::max<int64_t>(g->n, 1));
-    p->flag.alloc(std::max<int64_t>(g->n, 1));
-    p->counter.alloc(4);
-    p->part1.alloc(std::max<int64_t>(g->n_chunks, 1));
-    p->cut1.alloc(std::max<int64_t>(g->n_comp, 1));
+    alloc_readout_scratch(*p, g->n, g->n_comp, g->n_chunks, R);
     if (g->n_hub_chunks) p->hub_part.alloc((size_t)g->n_hub_chunks * R);
     SolvePlan &ref = *p;
     g->plans[R] = std::move(p);
@@ -591,7 +755,7 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
 #define QH_BAND(DTV)                                                                                            \
     hipLaunchKernelGGL((k_band_step<DTV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, R,      \
                        g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p, lr ? g->l_ptr.p : nullptr, \
-                       g->l_col.p, g->l_val.p, g->hub_of_row.p, g->hub_chunk_ptr.p, p.hub_part.p, xin, xout, p.y.p, sa)
+                       g->hub_of_row.p, g->hub_chunk_ptr.p, p.hub_part.p, xin, xout, p.y.p, sa)
 #define QH_SKY_RT(DTV)                                                  \
     do {                                                                \
         if (RT == 16) { if (g->n_hub_chunks) QH_HUB(DTV, 16); QH_SKY(DTV, 16); } \
@@ -641,11 +805,9 @@ static void x_to_h(const qh_graph *g, SolvePlan &p, int64_t n, int R, hipStream_
     QH_CHECK_LAUNCH();
 }
 
-// Steps [kb, ke) in one cooperative launch; the state is in p.xa / p.y / p.ha.  `xl`
-// selects the XCD-local synchronisation.  Returns false when a workgroup found itself on
-// an unexpected XCD (the state is then not usable and XCD-local runs are switched off).
-static bool run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, double c0, double dt, double a0,
-                           int kb, int ke, bool xl, hipStream_t st) {
+// Steps [kb, ke) in one cooperative launch; the state is in p.xa / p.y / p.ha.
+static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, double c0, double dt, double a0,
+                           int kb, int ke, hipStream_t st) {
     PersistPlan &pp = *p.pp;
     QH_HIP(hipMemsetAsync(pp.flags.p, 0, pp.flags.bytes(), st));
     PersistArgs pa{};
@@ -676,24 +838,16 @@ static bool run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, d
     pa.pump = pump;
     pa.lds_j_bytes = pp.lds_j_bytes;
     pa.max_polls = (int64_t)1 << 27;
-    launch_persistent(g, pp, pa, xl, st);
+    launch_persistent(g, pp, pa, st);
     int32_t err = 0;
     QH_HIP(hipMemcpyAsync(&err, pa.err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     QH_HIP(hipStreamSynchronize(st));
-    if (err & 2) {
-        disable_xcd_local();
-        return false;
-    }
     if (err) fail(QH_EHIP, "persistent bSB kernel: a neighbour wait exceeded its poll limit");
-    return true;
 }
 
-static bool use_xcd_local(const SolvePlan &p) { return p.pp && p.pp->ok && p.pp->xlocal_ok && !xcd_local_disabled(); }
-
 // Autotuner for plan 0 on dense 16/8-bit graphs: time a short run of each candidate on
-// scratch state -- one fused kernel per step, persistent with agent-scope
-// synchronisation, persistent with XCD-local synchronisation -- and keep the fastest.
-// Every candidate computes bit-identical results, so the choice only affects speed.
+// scratch state -- one fused kernel per step, and the persistent launch -- and keep the
+// faster.  Both compute bit-identical results, so the choice only affects speed.
 static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, const float *pump, double c0,
                            double a0, hipStream_t st) {
     const int64_t n = g->n;
@@ -704,32 +858,37 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
     QH_HIP(hipEventCreate(&e1));
     float best = 0.0f;
     int choice = 1;
-    for (int cand : {0, 1, 2}) {   // 0 per-step, 1 persistent agent-scope, 2 persistent XCD-local
-        if (cand >= 1 && !(p.pp && p.pp->ok)) continue;
-        if (cand == 2 && !use_xcd_local(p)) continue;
-        bool ok = true;
-        for (int rep = 0; rep < 2 && ok; ++rep) {   // the first repetition warms caches and code
+    for (int cand : {0, 1}) {   // 0 per-step, 1 persistent
+        if (cand == 1 && !(p.pp && p.pp->ok)) continue;
+        for (int rep = 0; rep < 2; ++rep) {   // the first repetition warms caches and code
             hipLaunchKernelGGL(k_init, dim3(grid_for(n * R)), dim3(256), 0, st, (uint64_t)0x5eed, n, R, p.xa.p,
                                p.y.p);
             QH_CHECK_LAUNCH();
             x_to_h(g, p, n, R, st);
             QH_HIP(hipEventRecord(e0, st));
             if (cand == 0) run_steps(g, p, o, pump, c0, a0, 0, nt, st);
-            else ok = run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, cand == 2, st);
+            else run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, st);
             QH_HIP(hipEventRecord(e1, st));
             QH_HIP(hipEventSynchronize(e1));
         }
-        if (!ok) continue;
         float ms = 0.0f;
         QH_HIP(hipEventElapsedTime(&ms, e0, e1));
         p.tuned_us[cand] = ms * 1000.0f / nt;
-        if (cand == 0 || ms < best) { best = ms; choice = cand == 0 ? 1 : 2; }
+        if (cand == 0 || ms < best) { best = ms; choice = cand + 1; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p.tuned_plan = choice;
-    // if the agent-scope persistent run was the faster one, do not use the XCD-local one
-    p.tuned_xl = choice == 2 && p.tuned_us[2] > 0.0f && (p.tuned_us[1] == 0.0f || p.tuned_us[2] <= p.tuned_us[1]);
+}
+
+const float *linear_pump(SolvePlan &p, int steps, hipStream_t st) {
+    if (p.pump_steps != steps) {
+        p.pump_lin.alloc(steps);
+        hipLaunchKernelGGL(k_pump_linear, dim3(grid_for(steps)), dim3(256), 0, st, steps, p.pump_lin.p);
+        QH_CHECK_LAUNCH();
+        p.pump_steps = steps;
+    }
+    return p.pump_lin.p;
 }
 
 void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStream_t st) {
@@ -738,20 +897,11 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     if (cur_dev != g->device) fail(QH_EINVAL, "graph lives on device %d, current device is %d", g->device, cur_dev);
     const int R = o->replicas;
     const int64_t n = g->n;
-    SolvePlan &p = get_plan(g, R, st);
+    SolvePlan &p = solve_plan(g, R, st);
     const int kb = o->step_begin, ke = o->step_end == 0 ? o->steps : o->step_end;
     const double c0 = o->c0 > 0.0 ? o->c0 : g->c0_auto;
     const double a0 = o->a0 > 0.0 ? o->a0 : 1.0;
-    const float *pump = o->pump;
-    if (!pump) {
-        if (p.pump_steps != o->steps) {
-            p.pump_lin.alloc(o->steps);
-            hipLaunchKernelGGL(k_pump_linear, dim3(grid_for(o->steps)), dim3(256), 0, st, o->steps, p.pump_lin.p);
-            QH_CHECK_LAUNCH();
-            p.pump_steps = o->steps;
-        }
-        pump = p.pump_lin.p;
-    }
+    const float *pump = o->pump ? o->pump : linear_pump(p, o->steps, st);
     const int64_t nR = n * R;
     const bool dense16 = !x_pingpong(g);
     if (p.sky_rows != (o->plan == 3)) {
@@ -765,7 +915,7 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     // optionally replayed from a captured hipGraph), or the autotuner's choice (plan 0)
     int final_half = 0;
     bool persistent = false;
-    const bool want_persistent = o->plan == 0 || o->plan == 2 || o->plan == 4;
+    const bool want_persistent = o->plan == 0 || o->plan == 2;
     if (dense16 && want_persistent && ke > kb && n > 0) {
         if (!p.pp_tried) {
             p.pp = std::make_shared<PersistPlan>();
@@ -778,7 +928,7 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
             persistent = p.tuned_plan == 2;
         }
     }
-    if ((o->plan == 2 || o->plan == 4) && !persistent)
+    if (o->plan == 2 && !persistent)
         fail(QH_EUNSUPPORTED, "the persistent plan does not apply to this graph and replica count");
     // initial state into xa / y (after any tuning, which uses the same buffers)
     auto load_state = [&]() {
@@ -797,15 +947,7 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     load_state();
     if (ke > kb && n > 0) p.last_plan = persistent ? 2 : 1;
     if (persistent) {
-        bool xl = use_xcd_local(p) && (o->plan == 2 || (o->plan == 0 && p.tuned_xl));
-        p.last_xl = xl;
-        if (!run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, xl, st)) {
-            // a workgroup ran on an unexpected XCD: redo the run with agent-scope synchronisation
-            p.last_xl = false;
-            load_state();
-            if (!run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, false, st))
-                fail(QH_EHIP, "persistent bSB kernel: placement check failed without XCD-local mode");
-        }
+        run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, st);
     } else if (ke > kb && n > 0) {
         if (o->use_graph) {
             auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R);
@@ -839,24 +981,51 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     if (res->x && nR) QH_HIP(hipMemcpyAsync(res->x, xfin, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (res->y && nR) QH_HIP(hipMemcpyAsync(res->y, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (!o->readout) return;
+    readout(view_of(g), p, R, xfin, p.y.p, res, o->greedy != 0, st);
+}
+
+ReadoutView view_of(const qh_graph *g) {
+    ReadoutView v;
+    v.n = g->n;
+    v.n_comp = g->n_comp;
+    v.n_chunks = g->n_chunks;
+    v.m_ptr = g->m_ptr.p;
+    v.m_col = g->m_col.p;
+    v.m_val = g->m_val.p;
+    v.comp = g->comp.p;
+    v.comp_first = g->comp_first.p;
+    v.comp_order = g->comp_order.p;
+    v.chunk_begin = g->chunk_begin.p;
+    v.chunk_end = g->chunk_end.p;
+    v.comp_chunk_ptr = g->comp_chunk_ptr.p;
+    v.eps = g->greedy_eps;
+    return v;
+}
+
+// Signs, FP64 cuts per replica and component, per-component selection, greedy rounds and
+// the cut of the final spins, for any graph laid out as a ReadoutView.
+void readout(const ReadoutView &g, SolvePlan &p, int R, const float *xfin, const float *yfin, qh_result *res,
+             bool greedy, hipStream_t st, bool finish) {
+    const int64_t n = g.n;
+    const int64_t nR = n * R;
 
     // signs + NaN watchdog
     QH_HIP(hipMemsetAsync(p.counter.p, 0, 4 * sizeof(int32_t), st));
     if (nR) {
-        hipLaunchKernelGGL(k_signs, dim3(grid_for(nR)), dim3(256), 0, st, n, R, xfin, p.y.p, p.spins.p,
+        hipLaunchKernelGGL(k_signs, dim3(grid_for(nR)), dim3(256), 0, st, n, R, xfin, yfin, p.spins.p,
                            p.counter.p + 1);
         QH_CHECK_LAUNCH();
     }
     if (res->all_spins && nR)
         QH_HIP(hipMemcpyAsync(res->all_spins, p.spins.p, nR, hipMemcpyDeviceToDevice, st));
     // FP64 cuts per replica and component
-    const int64_t nc = g->n_comp;
+    const int64_t nc = g.n_comp;
     if (nc) {
-        hipLaunchKernelGGL(k_cut_chunks, dim3((unsigned)std::min<int64_t>(g->n_chunks, 1 << 20)), dim3(256), 0, st,
-                           g->n_chunks, R, g->chunk_begin.p, g->chunk_end.p, g->comp_order.p, g->m_ptr.p,
-                           g->m_col.p, g->m_val.p, p.spins.p, p.part.p);
+        hipLaunchKernelGGL(k_cut_chunks, dim3((unsigned)std::min<int64_t>(g.n_chunks, 1 << 20)), dim3(256), 0, st,
+                           g.n_chunks, R, g.chunk_begin, g.chunk_end, g.comp_order, g.m_ptr,
+                           g.m_col, g.m_val, p.spins.p, p.part.p);
         hipLaunchKernelGGL(k_cut_reduce, dim3((unsigned)std::min<int64_t>(nc, 1 << 20)), dim3(256), 0, st, nc, R,
-                           g->comp_chunk_ptr.p, p.part.p, p.cut_rc.p);
+                           g.comp_chunk_ptr, p.part.p, p.cut_rc.p);
         hipLaunchKernelGGL(k_select, dim3(grid_for(nc)), dim3(256), 0, st, nc, R, p.cut_rc.p, p.best_r.p);
         QH_CHECK_LAUNCH();
     }
@@ -874,18 +1043,18 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     if (res->best_replica && nc)
         QH_HIP(hipMemcpyAsync(res->best_replica, p.best_r.p, nc * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     if (n) {
-        hipLaunchKernelGGL(k_best_spins, dim3(grid_for(n)), dim3(256), 0, st, n, R, g->comp.p, g->comp_first.p,
+        hipLaunchKernelGGL(k_best_spins, dim3(grid_for(n)), dim3(256), 0, st, n, R, g.comp, g.comp_first,
                            p.best_r.p, p.spins.p, res->best_spins);
         QH_CHECK_LAUNCH();
     }
     int32_t rounds = 0;
-    if (o->greedy && n && nc) {
+    if (greedy && n && nc) {
         for (int it = 0; it < 100000; ++it) {
-            hipLaunchKernelGGL(k_gain, dim3(grid_for(n)), dim3(256), 0, st, n, g->m_ptr.p, g->m_col.p, g->m_val.p,
+            hipLaunchKernelGGL(k_gain, dim3(grid_for(n)), dim3(256), 0, st, n, g.m_ptr, g.m_col, g.m_val,
                                res->best_spins, p.gain.p);
             QH_HIP(hipMemsetAsync(p.counter.p, 0, sizeof(int32_t), st));
-            hipLaunchKernelGGL(k_pick, dim3(grid_for(n)), dim3(256), 0, st, n, g->m_ptr.p, g->m_col.p, p.gain.p,
-                               g->greedy_eps, p.flag.p, p.counter.p);
+            hipLaunchKernelGGL(k_pick, dim3(grid_for(n)), dim3(256), 0, st, n, g.m_ptr, g.m_col, p.gain.p,
+                               g.eps, g.eps_v, p.flag.p, p.counter.p);
             QH_CHECK_LAUNCH();
             int32_t cnt = 0;
             QH_HIP(hipMemcpyAsync(&cnt, p.counter.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -898,11 +1067,11 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     }
     // cut of the final spins
     if (nc) {
-        hipLaunchKernelGGL(k_cut_chunks, dim3((unsigned)std::min<int64_t>(g->n_chunks, 1 << 20)), dim3(64), 0, st,
-                           g->n_chunks, 1, g->chunk_begin.p, g->chunk_end.p, g->comp_order.p, g->m_ptr.p,
-                           g->m_col.p, g->m_val.p, res->best_spins, p.part1.p);
+        hipLaunchKernelGGL(k_cut_chunks, dim3((unsigned)std::min<int64_t>(g.n_chunks, 1 << 20)), dim3(64), 0, st,
+                           g.n_chunks, 1, g.chunk_begin, g.chunk_end, g.comp_order, g.m_ptr,
+                           g.m_col, g.m_val, res->best_spins, p.part1.p);
         hipLaunchKernelGGL(k_cut_reduce, dim3((unsigned)std::min<int64_t>(nc, 1 << 20)), dim3(64), 0, st, nc, 1,
-                           g->comp_chunk_ptr.p, p.part1.p, p.cut1.p);
+                           g.comp_chunk_ptr, p.part1.p, p.cut1.p);
         hipLaunchKernelGGL(k_selected_total, dim3(1), dim3(256), 0, st, nc, p.cut1.p, (const int32_t *)nullptr,
                            res->best_cut);
         QH_CHECK_LAUNCH();
@@ -911,6 +1080,7 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     }
     if (res->greedy_rounds)
         QH_HIP(hipMemcpyAsync(res->greedy_rounds, &rounds, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    if (!finish) return;
     int32_t bad = 0;
     QH_HIP(hipMemcpyAsync(&bad, p.counter.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     QH_HIP(hipStreamSynchronize(st));

@@ -39,14 +39,7 @@ __device__ inline void pbsb_update(float z, float &x, float &y, float coef, floa
     y = yn;
 }
 
-// XL (XCD-local protocol): when every workgroup of a replica group runs on one XCD,
-// producer and consumers share that XCD's L2.  The producer then only needs its stores
-// acknowledged by L2 before it publishes, and a consumer only needs to drop its own L1
-// before reading; no L2 write-back or invalidation is involved.  Workgroup b runs on XCD
-// b % 8 under the hardware's round-robin dispatch; each workgroup checks its XCC id
-// against that and raises error bit 2 on a mismatch, after which the host reruns the
-// solve with agent-scope release / acquire (XL = false), which holds on any placement.
-template <int DT, int NB, int MAXT, bool XL>
+template <int DT, int NB, int MAXT>
 __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     constexpr int RT = NB * 16;
@@ -65,12 +58,6 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
     uint16_t *lds_h = (uint16_t *)(smem + a.lds_j_bytes);
     const int ct_elems = 64 * RT;   // 16-bit elements per staged column tile
 
-    if constexpr (XL) {
-        unsigned xcc;
-        __asm__ volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc));
-        if (tid == 0 && (int)(xcc & 0xF) != (int)(blockIdx.x & 7))
-            __hip_atomic_fetch_or(a.err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
     // J tiles of this workgroup's rows -> LDS (once)
     {
         const int64_t bytes = (int64_t)(jt1 - jt0) * kTileElems * EB;
@@ -117,8 +104,7 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
                 }
             }
             __syncthreads();
-            if constexpr (XL) __asm__ volatile("buffer_inv sc0" ::: "memory");   // drop this CU's L1
-            else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         // 2. stage the column tiles of x (16-bit copy, half s % 2) into LDS
         const uint16_t *hin = (s & 1) ? a.h1 : a.h0;
@@ -217,7 +203,7 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
         __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (tid == 0) {
-            if constexpr (!XL) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(a.flags + (int64_t)grp * a.wpg + w, s + 1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -354,7 +340,6 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
         pp.nbr.alloc(std::max<size_t>(nbrs.size(), 1));
         pp.nbr.upload(nbrs.data(), nbrs.size(), st);
         pp.flags.alloc((size_t)ng * wpg + 64);
-        pp.xlocal_ok = ng % 8 == 0;   // every group's workgroups share b % 8, i.e. one XCD
         QH_HIP(hipStreamSynchronize(st));
         pp.ok = true;
         return true;
@@ -364,8 +349,8 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
 }
 
 template <int DT, int NB>
-static void launch_t(const PersistArgs &args, int grid, int lds, bool xl, hipStream_t st) {
-    auto fn = xl ? k_dense_persistent<DT, NB, kMaxT, true> : k_dense_persistent<DT, NB, kMaxT, false>;
+static void launch_t(const PersistArgs &args, int grid, int lds, hipStream_t st) {
+    auto fn = k_dense_persistent<DT, NB, kMaxT>;
     if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
         (void)hipGetLastError();
     int per_cu = 0;
@@ -381,14 +366,14 @@ static void launch_t(const PersistArgs &args, int grid, int lds, bool xl, hipStr
     QH_HIP(hipLaunchCooperativeKernel((const void *)fn, dim3(grid), dim3(256), kargs, (unsigned)lds, st));
 }
 
-void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, bool xl, hipStream_t st) {
+void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, hipStream_t st) {
     const int grid = pp.ng * pp.wpg;
     const int lds = (int)pp.lds_bytes;
 #define QH_P(DTV)                                                     \
     do {                                                              \
-        if (pp.RT == 16) launch_t<DTV, 1>(args, grid, lds, xl, st);       \
-        else if (pp.RT == 32) launch_t<DTV, 2>(args, grid, lds, xl, st);  \
-        else launch_t<DTV, 4>(args, grid, lds, xl, st);                   \
+        if (pp.RT == 16) launch_t<DTV, 1>(args, grid, lds, st);       \
+        else if (pp.RT == 32) launch_t<DTV, 2>(args, grid, lds, st);  \
+        else launch_t<DTV, 4>(args, grid, lds, st);                   \
     } while (0)
     switch (g->dtype) {
         case QH_F16: QH_P(QH_F16); break;
@@ -402,10 +387,6 @@ void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistAr
 }  // namespace qh
 
 namespace qh {
-
-static bool g_xl_disabled = false;
-bool xcd_local_disabled() { return g_xl_disabled; }
-void disable_xcd_local() { g_xl_disabled = true; }
 
 void plan_info(const qh_graph *g, int R, qh_plan_info *out) {
     qh_plan_info i{};
@@ -422,8 +403,6 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out) {
         }
         i.us_per_step[0] = p.tuned_us[0];
         i.us_per_step[1] = p.tuned_us[1];
-        i.us_per_step[2] = p.tuned_us[2];
-        i.xcd_local = p.last_xl ? 1 : 0;
     }
     *out = i;
 }

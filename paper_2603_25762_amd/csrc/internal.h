@@ -102,10 +102,8 @@ struct SolvePlan {
     bool pp_tried = false;
     int tuned_plan = 0;                // autotuner's choice for plan 0: 1 per-step, 2 persistent
     int last_plan = 0;                 // plan the last solve ran
-    bool tuned_xl = false;             // autotuner: the XCD-local persistent run was the fastest
-    bool last_xl = false;              // the last persistent run used XCD-local synchronisation
     bool sky_rows = false;             // SNP graphs: per-row skyline kernel instead of band blocks
-    float tuned_us[3] = {0, 0, 0};     // measured microseconds per step of each candidate
+    float tuned_us[2] = {0, 0};        // measured microseconds per step: per-step, persistent
     int R = 0;
     int64_t n_pad = 0;
     DevBuf<float> xa, xb, y;        // fp32 state, [n_pad][R]
@@ -184,7 +182,9 @@ struct qh_graph {
     qh::DevBuf<int32_t> l_col;
     qh::DevBuf<uint8_t> l_val;          // dtype
     int64_t l_nnz = 0;
-    // Hub rows: long-range rows longer than kHubInline are summed by chunks.
+    // Long-range rows are summed by chunks of at most kHubChunk entries in a separate
+    // kernel (full parallelism for the gathers, hub rows split); the step kernel adds the
+    // chunk partials of its row in order.
     qh::DevBuf<int32_t> hub_of_row;     // [n] hub index or -1
     qh::DevBuf<int32_t> hub_chunk_row;  // [n_hub_chunks]
     qh::DevBuf<int64_t> hub_chunk_beg, hub_chunk_end;
@@ -207,7 +207,7 @@ struct qh_graph {
 namespace qh {
 
 constexpr int kBandRows = 16;       // rows per band block (one wave's accumulators)
-constexpr int kHubInline = 64;      // long-range entries summed inline by the step kernel
+constexpr int kHubInline = 0;       // long-range rows longer than this are summed by chunks (all of them)
 constexpr int kHubChunk = 64;       // entries per hub partial
 
 // graph_build.hip
@@ -221,10 +221,51 @@ void flip_crossing(qh_graph *g, const int8_t *spins, hipStream_t st);
 
 // bsb.hip
 void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStream_t st);
+
+// What the readout needs of a graph (a single graph, or the block-diagonal union of a batch).
+struct ReadoutView {
+    int64_t n = 0, n_comp = 0, n_chunks = 0;
+    const int64_t *m_ptr = nullptr;
+    const int32_t *m_col = nullptr;
+    const double *m_val = nullptr;
+    const int32_t *comp = nullptr, *comp_first = nullptr, *comp_order = nullptr;
+    const int32_t *chunk_begin = nullptr, *chunk_end = nullptr, *comp_chunk_ptr = nullptr;
+    double eps = 0.0;                  // greedy tolerance
+    const double *eps_v = nullptr;     // per-vertex tolerance (overrides eps when set)
+};
+ReadoutView view_of(const qh_graph *g);
+// finish = false leaves the non-finite check to the caller (p.counter[1] != 0 after a sync)
+void readout(const ReadoutView &g, SolvePlan &p, int R, const float *xfin, const float *yfin, qh_result *res,
+             bool greedy, hipStream_t st, bool finish = true);
+void alloc_readout_scratch(SolvePlan &p, int64_t n, int64_t n_comp, int64_t n_chunks, int R);
 void plan_info(const qh_graph *g, int R, qh_plan_info *out);
 
 // phase.hip
 void phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);
+
+// Device-side descriptor of one block of a batched solve.
+struct BlockDesc {
+    int32_t kind;               // 0 dense tiles, 1 band blocks
+    int32_t dtype;
+    int64_t n;
+    float *x, *y;               // fp32 state [n_pad][R]; x holds the final spins' amplitudes
+    int64_t n_rt;
+    const int32_t *t_ptr, *t_col;
+    const uint8_t *t_val;
+    const float *row_scale;
+    int64_t n_bblk;
+    const int64_t *bb_off;
+    const int32_t *bb_lo, *bb_w;
+    const uint8_t *bb_val;
+    float c0;
+    uint16_t *h0, *h1;          // dense 16/8-bit: product copies [n_pad/8][R][8]
+    float *xs;                  // dense f32 / band: second x buffer [n_pad][R]
+};
+void launch_batched(int R, int workers, const BlockDesc *blocks, const int32_t *sched_ptr, const int32_t *sched,
+                    int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
+int batched_workers_per_cu(int R);
+SolvePlan &solve_plan(const qh_graph *g, int R, hipStream_t st);
+const float *linear_pump(SolvePlan &p, int steps, hipStream_t st);   // p_k = k / (steps - 1)
 
 // batched.hip
 void bsb_solve_batched(const qh_graph *const *gs, int n, const qh_bsb_opts *o,

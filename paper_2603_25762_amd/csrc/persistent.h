@@ -33,12 +33,9 @@ struct PersistPlan {
     int64_t lds_j_bytes = 0, lds_bytes = 0;
     DevBuf<int32_t> wg_rt, wg_ct_ptr, wg_ct, tile_slot, nbr_ptr, nbr;
     DevBuf<int> flags;          // ng * wpg flags followed by the error word
-    bool xlocal_ok = false;     // groups map onto single XCDs: the XCD-local protocol applies
 };
 
 bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_t st);
-void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, bool xl, hipStream_t st);
-bool xcd_local_disabled();   // set once a placement check failed in this process
-void disable_xcd_local();
+void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, hipStream_t st);
 
 }  // namespace qh

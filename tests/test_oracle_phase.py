@@ -162,3 +162,22 @@ def test_rowscale_e4m3_bounds():
     assert np.all(np.abs(q) <= 448.0)
     rel = np.abs(scale[:, None] * q - J) / np.maximum(np.abs(J), 1e-30)
     assert np.all(rel[J != 0] <= 2.0 ** -4 + 1e-6)   # half an ulp at 3 fraction bits
+
+
+def test_refinement_gauge_identity_and_monotone():
+    """Eqs. (15)-(17): the partition implied by the flip counters has, on the original graph,
+    exactly the sum of the per-round cuts; every applied round adds a positive cut; the switch
+    error does not exceed the single-round parity phasing."""
+    w = synth.snp_small(24, n_snp=1500, error=0.0)
+    g = oracle.build_graph(w, "snp_llr")
+    single = oracle.solve(g, 32, 600, 0.5, seed=1)
+    h1s, bs = oracle.phase_parity(single["comp"], single["n_comp"], single["best"], w.init_h1)
+    rr = oracle.refine(g, w.init_h1, 32, 600, 0.5, seed=1, max_rounds=15)
+    S = np.where(rr["flips"] % 2 == 1, -1, 1).astype(np.int8)
+    assert oracle.cuts(g, rr["comp"], rr["n_comp"], S).sum() == pytest.approx(sum(rr["round_cuts"]), rel=1e-12)
+    assert all(c > 0 for c in rr["round_cuts"]) and rr["rounds"] >= 1
+    assert rr["round_cuts"][0] == pytest.approx(single["best_cut"], rel=1e-12)
+    assert metrics.switch_error(rr["h1"], w.truth, rr["block"]) <= metrics.switch_error(h1s, w.truth, bs)
+    # the haplotype of round one alone is the single parity round
+    r1 = oracle.refine(g, w.init_h1, 32, 600, 0.5, seed=1, max_rounds=1)
+    assert np.array_equal(r1["h1"], h1s)
