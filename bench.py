@@ -37,11 +37,59 @@ def parse():
                     help="0 auto (persistent when it applies), 1 one kernel per step, 2 persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of 1 GiB (3 times): the reference kernel that scales "
+                         "the FETCH_SIZE / WRITE_SIZE counters to HBM bytes")
     return ap.parse_args()
+
+
+COPY_BYTES = 1 << 30
+
+
+def calibrate_copy():
+    import torch
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes_read=COPY_BYTES, copy_bytes_written=COPY_BYTES, launches=3)), flush=True)
+
+
+KERNEL_SOURCES = ("paper_2603_25762_amd/csrc/bsb.hip", "paper_2603_25762_amd/csrc/formats.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dense_step_read_mhc_traffic.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
+    there is none or the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic:"):
+            k, _, v = line[len("traffic:"):].strip().partition("=")
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel") != kernel or vals.get("source_sha") != kernel_source_hash():
+        return None
+    return int(float(vals["hbm_bytes_per_launch"]))
 
 
 def main():
     a = parse()
+    if a.calibrate_copy:
+        calibrate_copy()
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {a.gpus} is not offered (replica sharding across GPUs "
               "is a design note, not part of this build)", file=sys.stderr)
@@ -123,32 +171,35 @@ def main():
     tiles = info["dense_tiles"]
     n = info["n"]
     eb = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}[a.dtype]
-    hb = 4 if a.dtype == "f32" else 2                # product copy of x (fp32 x itself on the f32 path)
+    copy = 0 if a.dtype == "f32" else 2 + 2          # 16-bit product copy of x: written once, read once
     if plan == 2:
-        # one launch runs every step: J and the fp32 state cross HBM once, the 16-bit copy of x
-        # is written and read (one column tile per stored tile) every step
+        # one launch runs every step: J and the fp32 state cross HBM once; the 16-bit copy of x
+        # is exchanged every step
         launches_steps = STEPS
         launch_us = loop_ms * 1e3
         flops = 2.0 * tiles * 4096 * R * STEPS
-        bytes_ = tiles * 4096 * eb + n * R * 16 + STEPS * (n * R * 2 + tiles * 64 * R * 2)
+        bytes_ = tiles * 4096 * eb + n * R * 16 + STEPS * n * R * copy
         kernel = f"k_dense_persistent<{a.dtype}>"
     else:
+        # one launch = one step: the stored tiles once, x and y read and written once, the
+        # 16-bit copy written and read once (re-reads of x columns by other row tiles are
+        # cache traffic, not algorithmic)
         launches_steps = 1
         launch_us = step_us
         flops = 2.0 * tiles * 4096 * R               # executed MFMA work of one launch (one step)
-        bytes_ = (tiles * 4096 * eb + tiles * 64 * R * hb + n * R * (4 + 4 + 4 + 4) +
-                  (0 if a.dtype == "f32" else n * R * 2))
+        bytes_ = tiles * 4096 * eb + n * R * 16 + n * R * copy
         kernel = f"k_dense_step<{a.dtype}>"
     ach_tf = flops / (launch_us * 1e-6) / 1e12
     ach_gbs = bytes_ / (launch_us * 1e-6) / 1e9
     frac_m = ach_tf / PEAK_TFLOPS[a.dtype]
     frac_h = ach_gbs / PEAK_HBM_GBS
+    traffic = measured_traffic(kernel) if plan != 2 else None
     if frac_m >= frac_h:
         roof = dict(bound="mfma", achieved=round(ach_tf, 2), peak=PEAK_TFLOPS[a.dtype], unit="TFLOP/s",
-                    frac=round(frac_m, 4), traffic=None)
+                    frac=round(frac_m, 4), traffic=traffic)
     else:
         roof = dict(bound="hbm", achieved=round(ach_gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=round(frac_h, 4), traffic=None)
+                    frac=round(frac_h, 4), traffic=traffic)
     roof.update(kernel=kernel, launch_us=round(launch_us, 3), steps_per_launch=launches_steps,
                 us_per_bsb_step=round(step_us, 3), flop_per_launch=flops, bytes_per_launch=bytes_,
                 mfma_frac=round(frac_m, 4), hbm_frac=round(frac_h, 4))

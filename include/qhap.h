@@ -174,6 +174,9 @@ typedef struct {
     int32_t plan;        /* step-loop plan: 0 = autotuned; 1 = one fused kernel per step;
                             2 = persistent (dense 16/8-bit graphs only); 3 = per-row skyline
                             kernel instead of band blocks (SNP graphs) */
+    int32_t replica_tile; /* dense graphs, per-step plan, R >= 64: replicas per workgroup
+                            (16, 32 or 64); 0 = the autotuner's choice (plan 0) or 64.
+                            Every tile gives bit-identical results. */
 } qh_bsb_opts;
 
 /* Result buffers (all device, caller-owned; optional ones may be NULL).
@@ -209,8 +212,10 @@ qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *re
 /* Step-loop plan chosen for (graph, replicas) by earlier solves.  plan_used: 0 = no solve
  * yet, 1 = one fused kernel per step, 2 = persistent (all steps in one cooperative
  * launch, state in registers, J in LDS).  With opts.plan = 0 the first solve of a
- * (graph, replicas) pair times both plans on scratch state (64 steps each) and keeps the
- * faster; us_per_step holds those measurements (0 when not measured).  Host output.
+ * (graph, replicas) pair times the candidates on scratch state (64 steps each) and keeps
+ * the fastest: the per-step kernel with 64, 32 and 16 replicas per workgroup (dense
+ * graphs, R >= 64) and the persistent plan where it fits; us_per_step holds those
+ * measurements (0 when not measured).  Host output.
  * The persistent plan synchronises neighbouring workgroups with agent-scope
  * release / acquire on per-workgroup step counters. */
 typedef struct {
@@ -220,17 +225,26 @@ typedef struct {
     int32_t groups;             /* persistent plan: replica groups */
     int32_t workgroups_per_group;
     int32_t lds_bytes;          /* persistent plan: LDS per workgroup */
-    float us_per_step[2];       /* autotuner: [per-step plan, persistent plan] */
+    float us_per_step[2];       /* autotuner: [per-step plan (best tile), persistent plan] */
+    int32_t replica_tile;       /* per-step dense plan: replicas per workgroup in use */
 } qh_plan_info;
 
 qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *out);
 
-/* Many independent graphs (phasing blocks) in one persistent launch: every block
- * runs the same schedule with its own c0 (opts->c0 <= 0: each block's c0_auto).
+/* Many independent graphs (phasing blocks) solved together: every block runs the same
+ * schedule (steps, dt, a0, pump, seed) with its own c0 (opts->c0 <= 0: each block's
+ * c0_auto), and block b's results equal qh_bsb_solve on graph b with the same options,
+ * bit for bit.  R must be 16, 32 or 64; init = 1; the whole schedule; no long-range
+ * couplings; each graph at most once per batch.  opts->plan: 1 = one launch per step over
+ * work items of every block (a dense row tile, or four band blocks); 2 = one persistent
+ * launch with whole blocks per workgroup (longest-processing-time placement); 0 = time
+ * both on this batch (8 steps each) and cache the faster for this list of graphs and R.
  * Results are packed: block b's vertices start at vertex_offset[b] (= sum of the
  * previous blocks' n) in best_spins / x / y, and its replicas at b * R in cuts.
  *  best_spins int8 [sum n]; cuts double [n_blocks * R]; best_cut double [n_blocks];
- *  x, y optional float [sum n * R].  Greedy is applied per block when requested. */
+ *  selected_cut double [n_blocks] (optional); x, y optional float [sum n * R];
+ *  plan_used (host output) the plan that ran.  Greedy is applied per block when
+ *  requested.  Synchronises the stream. */
 typedef struct {
     int8_t *best_spins;
     double *cuts;
@@ -238,6 +252,7 @@ typedef struct {
     double *selected_cut;
     float *x;
     float *y;
+    int32_t plan_used;
 } qh_batched_result;
 
 qh_status qh_bsb_solve_batched(const qh_graph *const *graphs, int32_t n_graphs,
@@ -257,6 +272,25 @@ qh_status qh_phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *
 /* Eq. 15: J_uv <- -J_uv for every edge whose endpoints disagree in `spins` (device
  * int8 [n]); updates the master and the stored copy in place. */
 qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream);
+
+/* Iterative refinement of the SNP-based method (Eqs. 15-17), SNP graphs only.  Round t
+ * (t = 0 .. max_rounds-1) runs qh_bsb_solve with opts (seed + t, readout on, whole
+ * schedule) on the current weights.  A component is finished for good when the cut of
+ * its selected spins is not positive or they put all its vertices on one side.  In each
+ * other component the vertices of the smaller subset S_min (the s = -1 subset on a tie)
+ * add one to their flip counter C, and every edge crossing the partition changes sign
+ * (Eq. 15).  The loop ends when every component is finished or after max_rounds.  The
+ * graph's weights are restored exactly before return (also on error).  Outputs:
+ *  h1         device int8 [n_snp]  H1 where C is even, H2 where C is odd; -1 unphased
+ *  block      device int32 [n_snp] component label, -1 for single-vertex components
+ *  flips      device int32 [n]     flip counters C (optional)
+ *  round_cuts host double [max_rounds] cut applied in each round, summed over the
+ *             components that flipped (optional)
+ *  rounds     host int32           rounds that flipped something (optional)
+ * Synchronises the stream.  Errors: EUNSUPPORTED (read graph), EINVAL (max_rounds < 1,
+ * init = 0, options as for qh_bsb_solve), ENUMERIC, ENOMEM, EHIP. */
+qh_status qh_refine(qh_graph *g, const qh_bsb_opts *opts, int32_t max_rounds, int8_t *h1, int32_t *block,
+                    int32_t *flips, double *round_cuts, int32_t *rounds, void *stream);
 
 const char *qh_last_error(void);
 const char *qh_version(void);

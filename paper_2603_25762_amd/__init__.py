@@ -4,7 +4,7 @@ Argument marshalling only: torch tensors serve as device buffers and
 ``torch.cuda.current_stream()`` as the HIP stream; every step of the path runs
 in the library's HIP kernels.  The functions mirror the C ABI in
 ``include/qhap.h``: :func:`build_graph`, :func:`bsb_solve`,
-:func:`bsb_solve_batched`, :func:`phase`, :func:`flip_crossing`.
+:func:`bsb_solve_batched`, :func:`phase`, :func:`flip_crossing`, :func:`refine`.
 
 Importing this package needs the built library and raises if it is missing;
 there is no CPU fallback.
@@ -12,6 +12,6 @@ there is no CPU fallback.
 from __future__ import annotations
 
 from ._binding import (  # noqa: F401
-    QhapError, Graph, build_graph, bsb_solve, bsb_solve_batched, phase, flip_crossing,
+    QhapError, Graph, build_graph, bsb_solve, bsb_solve_batched, phase, flip_crossing, refine,
     lib_path, load, version, to_device, KIND, STORAGE, DTYPE, Status,
 )

@@ -64,7 +64,8 @@ class _BsbOpts(ctypes.Structure):
                 ("dt", ctypes.c_double), ("c0", ctypes.c_double), ("a0", ctypes.c_double),
                 ("pump", P), ("seed", ctypes.c_uint64), ("init", ctypes.c_int32),
                 ("readout", ctypes.c_int32), ("greedy", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("plan", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("plan", ctypes.c_int32),
+                ("replica_tile", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -77,12 +78,12 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("plan_used", ctypes.c_int32), ("persistent_ok", ctypes.c_int32),
                 ("replicas_per_group", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("workgroups_per_group", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
-                ("us_per_step", ctypes.c_float * 2)]
+                ("us_per_step", ctypes.c_float * 2), ("replica_tile", ctypes.c_int32)]
 
 
 class _BatchedResult(ctypes.Structure):
     _fields_ = [("best_spins", P), ("cuts", P), ("best_cut", P), ("selected_cut", P),
-                ("x", P), ("y", P)]
+                ("x", P), ("y", P), ("plan_used", ctypes.c_int32)]
 
 
 _lib = None
@@ -111,6 +112,8 @@ def load():
                                  ctypes.POINTER(_BatchedResult), P],
         "qh_phase": [P, P, P, P, P],
         "qh_flip_crossing": [P, P, P],
+        "qh_refine": [P, ctypes.POINTER(_BsbOpts), ctypes.c_int32, P, P, P, ctypes.POINTER(ctypes.c_double),
+                      ctypes.POINTER(ctypes.c_int32), P],
         "qh_solve_plan_info": [P, ctypes.c_int32, ctypes.POINTER(_PlanInfo)],
     }
     for name, args in sig.items():
@@ -234,7 +237,7 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
               init: bool = True, x: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None,
               step_begin: int = 0, step_end: int = 0, readout: bool = True, greedy: bool = True,
               use_graph: bool = False, all_spins: bool = False, per_component: bool = False,
-              plan: int = 0,
+              plan: int = 0, replica_tile: int = 0,
               out: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
     """Runs bSB; returns device tensors (best_spins, cuts, best_cut, selected_cut, ...).
 
@@ -276,7 +279,7 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
     if pump is not None:
         res["pump"] = pump
     opts = _BsbOpts(replicas, steps, step_begin, step_end, dt, c0, a0, _ptr(pump), seed & (2**64 - 1),
-                    int(init), int(readout), int(greedy), int(use_graph), int(plan))
+                    int(init), int(readout), int(greedy), int(use_graph), int(plan), int(replica_tile))
     r = _Result(_ptr(x), _ptr(y), _ptr(keep.get("best_spins")), _ptr(keep.get("cuts")),
                 _ptr(keep.get("cut_rc")), _ptr(keep.get("best_replica")), _ptr(keep.get("selected_cut")),
                 _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")))
@@ -302,11 +305,12 @@ def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt:
         res["y"] = torch.empty(max(total * replicas, 1), dtype=torch.float32, device=dev)
     arr = (ctypes.c_void_p * max(nb, 1))(*[g.handle.value for g in graphs])
     opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
-                    int(use_graph), plan)
+                    int(use_graph), plan, 0)
     r = _BatchedResult(_ptr(res["best_spins"]), _ptr(res["cuts"]), _ptr(res["best_cut"]),
-                       _ptr(res["selected_cut"]), _ptr(res.get("x")), _ptr(res.get("y")))
+                       _ptr(res["selected_cut"]), _ptr(res.get("x")), _ptr(res.get("y")), 0)
     _check(load().qh_bsb_solve_batched(arr, nb, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
     res["vertex_offset"] = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    res["plan_used"] = r.plan_used
     return res
 
 
@@ -325,3 +329,22 @@ def phase(g: Graph, spins: torch.Tensor, n_snp: Optional[int] = None, stream=Non
 
 def flip_crossing(g: Graph, spins: torch.Tensor, stream=None):
     _check(load().qh_flip_crossing(g.handle, _ptr(spins), _stream(stream)))
+
+
+def refine(g: Graph, replicas: int, steps: int, *, max_rounds: int = 15, dt: float = 0.5, c0: float = 0.0,
+           a0: float = 1.0, seed: int = 0, greedy: bool = True, use_graph: bool = False, plan: int = 0,
+           stream=None) -> Dict[str, object]:
+    """Multi-round SNP refinement: h1, block (device), flips (device), round_cuts, rounds."""
+    inf = g.info()
+    n, n_snp = inf["n"], inf["n_snp"]
+    h1 = torch.empty(max(n_snp, 1), dtype=torch.int8, device="cuda")
+    block = torch.empty(max(n_snp, 1), dtype=torch.int32, device="cuda")
+    flips = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    rc = (ctypes.c_double * max_rounds)()
+    rounds = ctypes.c_int32(0)
+    opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
+                    int(use_graph), plan, 0)
+    _check(load().qh_refine(g.handle, ctypes.byref(opts), max_rounds, _ptr(h1), _ptr(block), _ptr(flips), rc,
+                            ctypes.byref(rounds), _stream(stream)))
+    k = rounds.value
+    return dict(h1=h1[:n_snp], block=block[:n_snp], flips=flips[:n], round_cuts=list(rc[:k]), rounds=k)

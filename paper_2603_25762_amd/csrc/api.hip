@@ -3,6 +3,8 @@
 #include <cstring>
 #include <new>
 
+#include <atomic>
+
 #include "internal.h"
 
 namespace qh {
@@ -83,6 +85,8 @@ qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_gr
         if (opts->band_limit < 0) fail(QH_EINVAL, "band_limit < 0");
         hipStream_t st = (hipStream_t)stream;
         std::unique_ptr<qh_graph> g(new qh_graph());
+        static std::atomic<uint64_t> next_serial{1};
+        g->serial = next_serial.fetch_add(1);
         QH_HIP(hipGetDevice(&g->device));
         g->kind = opts->kind;
         g->storage = opts->storage;
@@ -175,6 +179,9 @@ static void validate_opts(const qh_bsb_opts *o) {
         fail(QH_EINVAL, "step range [%d, %d) outside the schedule of %d steps", o->step_begin, end,
              o->steps);
     if (!(o->dt > 0.0)) fail(QH_EINVAL, "dt must be > 0");
+    const int t = o->replica_tile;
+    if (t != 0 && (!(t == 16 || t == 32 || t == 64) || R < 64))
+        fail(QH_EINVAL, "replica_tile must be 0, or 16, 32 or 64 with R >= 64, got %d", t);
 }
 
 qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *res, void *stream) {
@@ -220,6 +227,15 @@ qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream) {
     return guarded([&] {
         if (!g || !spins) fail(QH_EINVAL, "null argument");
         flip_crossing(g, spins, (hipStream_t)stream);
+    });
+}
+
+qh_status qh_refine(qh_graph *g, const qh_bsb_opts *opts, int32_t max_rounds, int8_t *h1, int32_t *block,
+                    int32_t *flips, double *round_cuts, int32_t *rounds, void *stream) {
+    return guarded([&] {
+        if (!g || !h1 || !block) fail(QH_EINVAL, "null argument");
+        validate_opts(opts);
+        refine(g, opts, max_rounds, h1, block, flips, round_cuts, rounds, (hipStream_t)stream);
     });
 }
 

@@ -1,14 +1,20 @@
-// Many independent phasing blocks (connected components / regions) solved in one
-// persistent launch.  Every block keeps its own couplings, c0, state and readout; the
-// blocks share the schedule (steps, dt, a0, pump) and the seed.
+// Many independent phasing blocks (connected components / regions) solved together.
+// Every block keeps its own couplings, c0, state and readout; the blocks share the
+// schedule (steps, dt, a0, pump) and the seed.  Two plans:
 //
-// Work placement: whole blocks per workgroup.  Blocks are ordered by estimated bytes
-// streamed per step (largest first) and each goes to the least-loaded worker
-// (longest-processing-time rule), so a few large dense blocks do not serialise behind
-// many small ones.  Inside a workgroup the steps of a block are separated by workgroup
-// barriers only.  The arithmetic and its order are those of the single-graph kernels,
-// so block b's result equals qh_bsb_solve on graph b with the same options, bit for bit.
+//  per-step (plan 1): one launch per step over work items of every block (a dense row
+//    tile, or four band blocks), so a large block is spread over many workgroups and the
+//    chip sees tens of thousands of independent items per step;
+//  whole-block (plan 2): one persistent launch, whole blocks per workgroup, placed by the
+//    longest-processing-time rule on estimated bytes per step; the steps of a block are
+//    separated by workgroup barriers only.  Best when every block is small.
+//
+// Plan 0 times both on the batch (a few steps each) and caches the faster for that list of
+// graphs and replica count.  Either way the arithmetic and its order are those of the
+// single-graph kernels, so block b's result equals qh_bsb_solve on graph b, bit for bit.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <queue>
 #include <vector>
@@ -16,6 +22,21 @@
 #include "internal.h"
 
 namespace qh {
+
+static std::mutex g_plan_mu;
+static std::map<std::vector<uint64_t>, int> g_plan_cache;   // (graph serials..., R) -> plan
+
+static int cached_batch_plan(const std::vector<uint64_t> &key) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plan_cache.find(key);
+    return it == g_plan_cache.end() ? 0 : it->second;
+}
+
+static void store_batch_plan(const std::vector<uint64_t> &key, int plan) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plan_cache.size() > 256) g_plan_cache.clear();
+    g_plan_cache[key] = plan;
+}
 
 static double block_cost(const qh_graph *g, int R) {
     const double eb = dtype_bytes(g->dtype);
@@ -31,6 +52,8 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
     if (!o->init) fail(QH_EINVAL, "batched solves start from the seeded initial state (init = 1)");
     if (o->step_begin != 0 || (o->step_end != 0 && o->step_end != o->steps))
         fail(QH_EINVAL, "batched solves run the whole schedule");
+    if (o->plan < 0 || o->plan > 2) fail(QH_EINVAL, "batched plan must be 0, 1 or 2, got %d", o->plan);
+    res->plan_used = 0;
     if (nb == 0) return;
     int dev = 0;
     QH_HIP(hipGetDevice(&dev));
@@ -86,15 +109,30 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         }
     }
 
-    // longest-processing-time placement of blocks on workers
+    std::vector<double> cost(nb);
+    for (int b = 0; b < nb; ++b) cost[b] = block_cost(gs[b], R);
+    std::vector<int> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    DevBuf<BlockDesc> d_desc(nb);
+    QH_HIP(hipMemcpyAsync(d_desc.p, desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
+
+    // per-step plan: work items, largest blocks first, items of a block adjacent
+    std::vector<int2> items;
+    for (int b : order) {
+        const qh_graph *g = gs[b];
+        const int64_t m = g->storage == QH_STORE_DENSE ? g->n_rt : ceil_div(g->n_bblk, 4);
+        for (int64_t i = 0; i < m; ++i) items.push_back(make_int2(b, (int)i));
+    }
+    const int64_t n_items = (int64_t)items.size();
+    DevBuf<int2> d_items(std::max<int64_t>(n_items, 1));
+    if (n_items)
+        QH_HIP(hipMemcpyAsync(d_items.p, items.data(), n_items * sizeof(int2), hipMemcpyHostToDevice, st));
+
+    // whole-block plan: longest-processing-time placement of blocks on workers
     int cus = 0;
     QH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int workers = (int)std::min<int64_t>(nb, (int64_t)std::max(cus, 1) * batched_workers_per_cu(R));
-    std::vector<int> order(nb);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost(nb);
-    for (int b = 0; b < nb; ++b) cost[b] = block_cost(gs[b], R);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
     using Load = std::pair<double, int>;
     std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
     for (int w = 0; w < workers; ++w) heap.push({0.0, w});
@@ -111,14 +149,48 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         sched.insert(sched.end(), lists[w].begin(), lists[w].end());
         sptr[w + 1] = (int32_t)sched.size();
     }
-    DevBuf<BlockDesc> d_desc(nb);
     DevBuf<int32_t> d_sptr(workers + 1), d_sched(nb);
-    QH_HIP(hipMemcpyAsync(d_desc.p, desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
     QH_HIP(hipMemcpyAsync(d_sptr.p, sptr.data(), (workers + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
     QH_HIP(hipMemcpyAsync(d_sched.p, sched.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if (o->steps > 0)
-        launch_batched(R, workers, d_desc.p, d_sptr.p, d_sched.p, o->steps, (float)o->dt, (float)a0, pump, o->seed,
-                       st);
+
+    auto run = [&](int plan, int steps, uint64_t seed) {
+        if (plan == 2) launch_batched(R, workers, d_desc.p, d_sptr.p, d_sched.p, steps, (float)o->dt, (float)a0, pump,
+                                      seed, st);
+        else launch_batched_steps(R, nb, d_desc.p, d_items.p, n_items, steps, (float)o->dt, (float)a0, pump, seed,
+                                  st);
+    };
+    int plan = o->plan == 2 ? 2 : 1;
+    if (o->plan == 0 && o->steps > 0) {
+        std::vector<uint64_t> key(nb + 1);
+        for (int b = 0; b < nb; ++b) key[b] = gs[b]->serial;
+        key[nb] = (uint64_t)R;
+        plan = cached_batch_plan(key);
+        if (!plan) {
+            // time both plans on the real buffers (a few steps each; the state is re-seeded below)
+            const int nt = std::min(o->steps, 8);
+            hipEvent_t e0, e1;
+            QH_HIP(hipEventCreate(&e0));
+            QH_HIP(hipEventCreate(&e1));
+            float ms[2] = {0, 0};
+            for (int c = 0; c < 2; ++c) {
+                run(c + 1, nt, 0x5eed);                         // warm
+                QH_HIP(hipEventRecord(e0, st));
+                run(c + 1, nt, 0x5eed);
+                QH_HIP(hipEventRecord(e1, st));
+                QH_HIP(hipEventSynchronize(e1));
+                QH_HIP(hipEventElapsedTime(&ms[c], e0, e1));
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            plan = ms[1] < ms[0] ? 2 : 1;
+            store_batch_plan(key, plan);
+        }
+    }
+    if (o->steps > 0) run(plan, o->steps, o->seed);
+    res->plan_used = plan;
+    // the per-step plan ping-pongs x like the single-graph solve; the whole-block plan
+    // leaves the final x in the first half
+    const int final_half = plan == 1 ? (o->steps & 1) : 0;
 
     // per-block readout: FP64 cuts, component selection, optional greedy, cut of the result
     int64_t voff = 0;
@@ -126,8 +198,10 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         const qh_graph *g = gs[b];
         SolvePlan &p = *plans[b];
         const int64_t nR = g->n * R;
+        const bool pingpong = !(g->storage == QH_STORE_DENSE && g->dtype != QH_F32);
+        const float *xfin = (pingpong && final_half) ? p.xb.p : p.xa.p;
         if (res->x && nR)
-            QH_HIP(hipMemcpyAsync(res->x + voff * R, p.xa.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+            QH_HIP(hipMemcpyAsync(res->x + voff * R, xfin, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
         if (res->y && nR)
             QH_HIP(hipMemcpyAsync(res->y + voff * R, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
         qh_result r{};
@@ -135,8 +209,7 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         r.cuts = res->cuts + (int64_t)b * R;
         r.best_cut = res->best_cut + b;
         r.selected_cut = res->selected_cut ? res->selected_cut + b : nullptr;
-        p.last_plan = 1;
-        readout(view_of(g), p, R, p.xa.p, p.y.p, &r, o->greedy != 0, st, false);
+        readout(view_of(g), p, R, xfin, p.y.p, &r, o->greedy != 0, st, false);
         voff += g->n;
     }
     // one synchronisation for the non-finite checks of every block

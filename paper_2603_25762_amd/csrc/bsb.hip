@@ -111,9 +111,9 @@ __device__ inline void dense_product(float4_t (&acc)[NB], int t_beg, int t_end, 
     const int l16 = lane & 15, g4 = lane >> 4;
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
-    for (int t = t_beg; t < t_end; ++t) {
-        const int64_t j0 = (int64_t)t_col[t] * kTile;
-        if constexpr (DT == QH_F32) {
+    if constexpr (DT == QH_F32) {
+        for (int t = t_beg; t < t_end; ++t) {
+            const int64_t j0 = (int64_t)t_col[t] * kTile;
             const float *tile = (const float *)t_val + (int64_t)t * kTileElems;
 #pragma unroll
             for (int kq = 0; kq < 4; ++kq) {
@@ -127,39 +127,61 @@ __device__ inline void dense_product(float4_t (&acc)[NB], int t_beg, int t_end, 
                         acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[e4], xr[b * 16], acc[b], 0, 0, 0);
                 }
             }
-        } else {
+        }
+    } else {
+        // U tiles per round: all their loads are issued before the first MFMA of the round
+        // (the scheduling barrier keeps them there), so the latency of the column-index,
+        // tile and x-copy loads is paid once per round.  Slots past t_end reload the last
+        // tile with A = 0, which adds exactly zero; the MFMA order is the tile order, as in
+        // the persistent kernel.
+        constexpr int U = NB >= 4 ? 2 : 4;
+        for (int t = t_beg; t < t_end; t += U) {
+            half8_t a[U][2], bv[U][2][NB];
 #pragma unroll
-            for (int kb = 0; kb < 2; ++kb) {
-                const int frag = wave * 2 + kb;
-                half8_t a;
-                if constexpr (DT == QH_FP8_ROWSCALE) {
-                    const uint8_t *tile = t_val + (int64_t)t * kTileElems;
-                    uint2 c = *(const uint2 *)(tile + ((frag * 64 + lane) << 3));
-                    uint16_t hb[8];
+            for (int u = 0; u < U; ++u) {
+                const int tt = t + u < t_end ? t + u : t_end - 1;
+                const int64_t j0 = (int64_t)t_col[tt] * kTile;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        hb[e] = e4m3_to_f16_bits_scaled((uint8_t)(c.x >> (8 * e)));
-                        hb[4 + e] = e4m3_to_f16_bits_scaled((uint8_t)(c.y >> (8 * e)));
-                    }
-                    __builtin_memcpy(&a, hb, 16);
-                } else {
-                    const uint16_t *tile = (const uint16_t *)t_val + (int64_t)t * kTileElems;
-                    a = *(const half8_t *)(tile + ((frag * 64 + lane) << 3));
-                }
-                const int64_t jg = (j0 + kb * 32) / 8 + g4;
+                for (int kb = 0; kb < 2; ++kb) {
+                    const int frag = wave * 2 + kb;
+                    if constexpr (DT == QH_FP8_ROWSCALE) {
+                        const uint8_t *tile = t_val + (int64_t)tt * kTileElems;
+                        uint2 c = *(const uint2 *)(tile + ((frag * 64 + lane) << 3));
+                        uint16_t hb[8];
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const uint16_t *hp = h_in + (jg * R + r0 + b * 16 + l16) * 8;
-                    if constexpr (DT == QH_BF16) {
-                        bf16x8_t bv = *(const bf16x8_t *)hp;
-                        bf16x8_t av;
-                        __builtin_memcpy(&av, &a, 16);
-                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
+                        for (int e = 0; e < 4; ++e) {
+                            hb[e] = e4m3_to_f16_bits_scaled((uint8_t)(c.x >> (8 * e)));
+                            hb[4 + e] = e4m3_to_f16_bits_scaled((uint8_t)(c.y >> (8 * e)));
+                        }
+                        __builtin_memcpy(&a[u][kb], hb, 16);
                     } else {
-                        half8_t bv = *(const half8_t *)hp;
-                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, bv, acc[b], 0, 0, 0);
+                        const uint16_t *tile = (const uint16_t *)t_val + (int64_t)tt * kTileElems;
+                        a[u][kb] = *(const half8_t *)(tile + ((frag * 64 + lane) << 3));
                     }
+                    if (t + u >= t_end) a[u][kb] = half8_t{};
+                    const int64_t jg = (j0 + kb * 32) / 8 + g4;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        bv[u][kb][b] = *(const half8_t *)(h_in + (jg * R + r0 + b * 16 + l16) * 8);
                 }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        if constexpr (DT == QH_BF16) {
+                            bf16x8_t av, bb;
+                            __builtin_memcpy(&av, &a[u][kb], 16);
+                            __builtin_memcpy(&bb, &bv[u][kb][b], 16);
+                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bb, acc[b], 0, 0, 0);
+                        } else {
+                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[u][kb], bv[u][kb][b], acc[b], 0, 0,
+                                                                            0);
+                        }
+                    }
             }
         }
     }
@@ -250,10 +272,11 @@ __device__ inline float ld_val(const uint8_t *__restrict__ p, int64_t e) {
     else return bf16_bits_to_f32(((const uint16_t *)p)[e]);
 }
 
-// Partial sums of the long-range lists of hub rows, kHubChunk entries each.
+// Partial sums of the long-range lists, one per chunk of at most kHubChunk entries
+// (replica tiles of 16 or 32: several chunks per wave).
 template <int DT, int RT>
 __global__ __launch_bounds__(256) void k_hub_partials(
-    int64_t n_chunks, int R, const int32_t *__restrict__ chunk_row, const int64_t *__restrict__ cbeg,
+    int64_t n_chunks, int R, const int64_t *__restrict__ cbeg,
     const int64_t *__restrict__ cend, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
     const float *__restrict__ x_in, float *__restrict__ part) {
     constexpr int RPW = 64 / RT;
@@ -269,14 +292,66 @@ __global__ __launch_bounds__(256) void k_hub_partials(
     }
 }
 
+// The same partials for replica tiles of 64, one packet (<= 64 entries, whole chunks) per
+// wave: lane j loads entry j's column and value once, then every entry's x row is
+// gathered with the column broadcast from its lane, so the gathers of a packet are
+// independent of one another and of any further index load.  Each chunk is summed in
+// entry order, as in k_hub_partials.
+template <int DT>
+__global__ __launch_bounds__(256) void k_lr_packets(
+    int64_t n_pk, int R, const int32_t *__restrict__ pk_ptr, const int64_t *__restrict__ cbeg,
+    const int64_t *__restrict__ cend, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
+    const float *__restrict__ x_in, float *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
+    for (int64_t p = (int64_t)blockIdx.x * 4 + wave; p < n_pk; p += (int64_t)gridDim.x * 4) {
+        const int32_t c0 = pk_ptr[p], c1 = pk_ptr[p + 1];
+        const int64_t e0 = cbeg[c0];
+        const int32_t cnt = (int32_t)(cend[c1 - 1] - e0);      // <= 64 by construction
+        int32_t my_col = 0, my_end = 0;
+        float my_val = 0.f;
+        if (lane < cnt) {
+            my_col = l_col[e0 + lane];
+            my_val = ld_val<DT>(l_val, e0 + lane);
+        }
+        if (lane < c1 - c0) my_end = (int32_t)(cend[c0 + lane] - e0);   // <= 64 chunks per packet
+        // eight gathers in flight across chunk boundaries; a chunk's sum is flushed when
+        // its last entry has been added
+        int32_t c = c0, ce = __builtin_amdgcn_readlane(my_end, 0);
+        float z = 0.f;
+        for (int32_t j = 0; j < cnt; j += 8) {
+            float xv[8], vv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int32_t jj = j + k < 63 ? j + k : 63;      // lanes past cnt hold column 0
+                vv[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_val), jj));
+                xv[k] = x_in[(int64_t)__builtin_amdgcn_readlane(my_col, jj) * R + r];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (j + k < cnt) {
+                    if (j + k == ce) {
+                        part[(int64_t)c * R + r] = z;
+                        ++c;
+                        ce = __builtin_amdgcn_readlane(my_end, c - c0);
+                        z = 0.f;
+                    }
+                    z += vv[k] * xv[k];
+                }
+            }
+        }
+        part[(int64_t)c * R + r] = z;
+    }
+}
+
 // One wave handles RPW = 64/RT rows x RT replicas; lane = (row slot, replica).
 template <int DT, int RT>
 __global__ __launch_bounds__(256) void k_sky_step(
     int64_t n, int R, int64_t rows_per_wg, int64_t G, const int64_t *__restrict__ s_off,
     const int32_t *__restrict__ s_lo, const int32_t *__restrict__ s_len, const uint8_t *__restrict__ s_val,
-    const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
-    const int32_t *__restrict__ hub_of_row, const int32_t *__restrict__ hub_chunk_ptr,
-    const float *__restrict__ hub_part, const float *__restrict__ x_in, float *__restrict__ x_out,
+    const int32_t *__restrict__ row_chunk_ptr, const float *__restrict__ hub_part,
+    const float *__restrict__ x_in, float *__restrict__ x_out,
     float *__restrict__ y, StepArgs sa) {
     constexpr int RPW = 64 / RT;
     const int lane = threadIdx.x & 63;
@@ -297,15 +372,8 @@ __global__ __launch_bounds__(256) void k_sky_step(
         const float *xc = x_in + (int64_t)lo * R + r;
 #pragma unroll 8
         for (int e = 0; e < len; ++e) z += ld_val<DT>(s_val, off + e) * xc[(int64_t)e * R];
-        if (l_ptr) {
-            const int hub = hub_of_row[u];
-            if (hub < 0) {
-                for (int64_t e = l_ptr[u]; e < l_ptr[u + 1]; ++e)
-                    z += ld_val<DT>(l_val, e) * x_in[(int64_t)l_col[e] * R + r];
-            } else {
-                for (int c = hub_chunk_ptr[hub]; c < hub_chunk_ptr[hub + 1]; ++c) z += hub_part[(int64_t)c * R + r];
-            }
-        }
+        if (row_chunk_ptr)
+            for (int c = row_chunk_ptr[u]; c < row_chunk_ptr[u + 1]; ++c) z += hub_part[(int64_t)c * R + r];
         const int64_t idx = u * R + r;
         float xv = x_in[idx], yv = y[idx];
         bsb_update(z, xv, yv, coef, sa);
@@ -325,8 +393,7 @@ template <int DT>
 __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_t r, bool active,
                                        const int64_t *__restrict__ bb_off, const int32_t *__restrict__ bb_lo,
                                        const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
-                                       const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ hub_of_row,
-                                       const int32_t *__restrict__ hub_chunk_ptr, const float *__restrict__ hub_part,
+                                       const int32_t *__restrict__ row_chunk_ptr, const float *__restrict__ hub_part,
                                        const float *x_in, float *x_out, float *y, float coef, const StepArgs &sa) {
     constexpr int RB = kBandRows;
     const int32_t L = bb_lo[blk], W = bb_w[blk];
@@ -353,11 +420,8 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
         const int64_t u = blk * RB + i;
         if (u >= n) break;
         float zi = z[i];
-        if (l_ptr) {
-            const int hub = hub_of_row[u];     // every long-range row is summed by chunks
-            if (hub >= 0)
-                for (int c = hub_chunk_ptr[hub]; c < hub_chunk_ptr[hub + 1]; ++c) zi += hub_part[(int64_t)c * R + r];
-        }
+        if (row_chunk_ptr)                     // long-range rows: chunk partials, in order
+            for (int c = row_chunk_ptr[u]; c < row_chunk_ptr[u + 1]; ++c) zi += hub_part[(int64_t)c * R + r];
         const int64_t idx = u * R + r;
         float xv = xo[i], yv = yo[i];
         bsb_update(zi, xv, yv, coef, sa);
@@ -370,21 +434,38 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_band_step(
     int64_t n, int R, int64_t n_bblk, int64_t G, const int64_t *__restrict__ bb_off,
     const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
-    const int64_t *__restrict__ l_ptr, const int32_t *__restrict__ hub_of_row, const int32_t *__restrict__ hub_chunk_ptr,
-    const float *__restrict__ hub_part, const float *__restrict__ x_in, float *__restrict__ x_out,
+    const int32_t *__restrict__ row_chunk_ptr, const float *__restrict__ hub_part,
+    const float *__restrict__ x_in, float *__restrict__ x_out,
     float *__restrict__ y, StepArgs sa) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t blk = xcd_remap(blockIdx.x, G) * 4 + wave;
     if (blk >= n_bblk) return;
     const int64_t r = (int64_t)blockIdx.y * 64 + lane;
-    band_block_step<DT>(blk, n, R, r, true, bb_off, bb_lo, bb_w, bb_val, l_ptr, hub_of_row, hub_chunk_ptr, hub_part,
-                        x_in, x_out, y, sa.a0 - sa.pump[sa.k], sa);
+    band_block_step<DT>(blk, n, R, r, true, bb_off, bb_lo, bb_w, bb_val, row_chunk_ptr, hub_part, x_in, x_out, y,
+                        sa.a0 - sa.pump[sa.k], sa);
 }
 
 // ---------------------------------------------------------------------------
 // batched blocks: one persistent launch, whole blocks per workgroup
 // ---------------------------------------------------------------------------
+
+// Initial state of one block by one workgroup: the single-graph counter layout with the
+// block's n, and the 16-bit product copy for dense 16/8-bit blocks.
+template <int64_t R>
+__device__ inline void block_init(const BlockDesc &B, uint64_t seed, int tid) {
+    const int64_t n = B.n;
+    for (int64_t t = tid; t < n * R; t += 256) {
+        const int64_t i = t / R, r = t - i * R;
+        const uint64_t c = 2ull * ((uint64_t)r * (uint64_t)n + (uint64_t)i);
+        const float xv = (float)(0.2 * ((double)(sm64_draw(seed, c) >> 11) * 0x1.0p-53) - 0.1);
+        B.x[t] = xv;
+        B.y[t] = (float)(0.2 * ((double)(sm64_draw(seed, c + 1) >> 11) * 0x1.0p-53) - 0.1);
+        if (B.kind == 0 && B.dtype != QH_F32)
+            B.h0[((i >> 3) * R + r) * 8 + (i & 7)] = B.dtype == QH_BF16 ? f32_to_bf16_rne(xv) : f32_to_f16_rne(xv);
+    }
+    __syncthreads();
+}
 
 // Each workgroup runs its scheduled blocks one after another; a block's steps are
 // separated by workgroup barriers only, because no other workgroup touches its state.
@@ -403,22 +484,8 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
         const BlockDesc B = blocks[sched[k]];
         const int64_t n = B.n;
         float *xb = B.x, *yb = B.y;
-        // initial state: the single-graph counter layout with this block's n
-        for (int64_t t = tid; t < n * R; t += 256) {
-            const int64_t i = t / R, r = t - i * R;
-            const uint64_t c = 2ull * ((uint64_t)r * (uint64_t)n + (uint64_t)i);
-            xb[t] = (float)(0.2 * ((double)(sm64_draw(seed, c) >> 11) * 0x1.0p-53) - 0.1);
-            yb[t] = (float)(0.2 * ((double)(sm64_draw(seed, c + 1) >> 11) * 0x1.0p-53) - 0.1);
-        }
-        __syncthreads();
+        block_init<R>(B, seed, tid);
         const bool dense16 = B.kind == 0 && B.dtype != QH_F32;
-        if (dense16)
-            for (int64_t t = tid; t < n * R; t += 256) {
-                const int64_t i = t / R, r = t - i * R;
-                B.h0[((i >> 3) * R + r) * 8 + (i & 7)] =
-                    B.dtype == QH_BF16 ? f32_to_bf16_rne(xb[t]) : f32_to_f16_rne(xb[t]);
-            }
-        __syncthreads();
         StepArgs sa{B.c0, dt, a0, pump, 0};
         float *cur = xb, *oth = B.xs;
         for (int s = 0; s < steps; ++s) {
@@ -449,7 +516,7 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
                 for (int64_t bb = wave; bb < B.n_bblk; bb += 4) {
 #define QH_BB(DTV)                                                                                          \
     band_block_step<DTV>(bb, n, R, lane, active, B.bb_off, B.bb_lo, B.bb_w, B.bb_val, nullptr, nullptr,   \
-                         nullptr, nullptr, cur, oth, yb, coef, sa)
+                         cur, oth, yb, coef, sa)
                     switch (B.dtype) {
                         case QH_F32: QH_BB(QH_F32); break;
                         case QH_F16: QH_BB(QH_F16); break;
@@ -466,6 +533,85 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
             for (int64_t t = tid; t < n * R; t += 256) xb[t] = cur[t];
         __syncthreads();
     }
+}
+
+// One step of every block in one launch.  Work item = one row tile of a dense block
+// (the k_dense_step workgroup) or four band blocks of an SNP block (one per wave, lanes
+// r < R active); items of one block are adjacent, and the XCD remap keeps them on one
+// XCD.  Ping-pong halves follow the single-graph solve (step k reads half k & 1).
+template <int NB>
+__global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restrict__ blocks,
+                                                      const int2 *__restrict__ items, int64_t n_items, int k,
+                                                      float dt, float a0, const float *__restrict__ pump) {
+    constexpr int64_t R = NB * 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int2 I = items[xcd_remap(blockIdx.x, n_items)];
+    const BlockDesc &B = blocks[I.x];
+    const StepArgs sa{B.c0, dt, a0, pump, k};
+    const float coef = a0 - pump[k];
+    const int cur = k & 1;
+    const int64_t n = B.n;
+    if (B.kind == 0) {
+        const bool d16 = B.dtype != QH_F32;
+        const uint16_t *hin = cur ? B.h1 : B.h0;
+        uint16_t *hout = cur ? B.h0 : B.h1;
+        float *xin = d16 ? B.x : (cur ? B.xs : B.x);
+        float *xout = d16 ? B.x : (cur ? B.x : B.xs);
+        const int64_t rt = I.y;
+        const int64_t rowbase = rt * kTile + wave * 16 + 4 * (lane >> 4);
+        float xo[NB][4], yo[NB][4];
+        float4_t acc[NB];
+        dense_load_state<NB>(xo, yo, rowbase, n, xin, B.y, R, 0, lane);
+#define QH_BS(DTV)                                                                                          \
+    dense_product<DTV, NB>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, xin, hin, R, 0, wave, lane); \
+    dense_update<DTV, NB>(acc, xo, yo, rowbase, n, R, 0, lane, B.row_scale, xout, B.y, hout, coef, sa)
+        switch (B.dtype) {
+            case QH_F32: QH_BS(QH_F32); break;
+            case QH_F16: QH_BS(QH_F16); break;
+            case QH_BF16: QH_BS(QH_BF16); break;
+            default: QH_BS(QH_FP8_ROWSCALE); break;
+        }
+#undef QH_BS
+    } else {
+        const int64_t bb = (int64_t)I.y * 4 + wave;
+        if (bb >= B.n_bblk) return;
+        const float *xin = cur ? B.xs : B.x;
+        float *xout = cur ? B.x : B.xs;
+#define QH_BB(DTV)                                                                                              \
+    band_block_step<DTV>(bb, n, R, lane, lane < R, B.bb_off, B.bb_lo, B.bb_w, B.bb_val, nullptr, nullptr, xin, \
+                         xout, B.y, coef, sa)
+        switch (B.dtype) {
+            case QH_F32: QH_BB(QH_F32); break;
+            case QH_F16: QH_BB(QH_F16); break;
+            default: QH_BB(QH_BF16); break;
+        }
+#undef QH_BB
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_batched_init(const BlockDesc *__restrict__ blocks, uint64_t seed) {
+    block_init<NB * 16>(blocks[blockIdx.x], seed, threadIdx.x);
+}
+
+void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, int64_t n_items, int steps,
+                          float dt, float a0, const float *pump, uint64_t seed, hipStream_t st) {
+#define QH_BSTEPS(NBV)                                                                                        \
+    do {                                                                                                      \
+        hipLaunchKernelGGL(k_batched_init<NBV>, dim3(nb), dim3(256), 0, st, blocks, seed);                   \
+        for (int k = 0; k < steps && n_items; ++k)                                                           \
+            hipLaunchKernelGGL(k_batched_step<NBV>, dim3((unsigned)n_items), dim3(256), 0, st, blocks, items, \
+                               n_items, k, dt, a0, pump);                                                     \
+    } while (0)
+    switch (R) {
+        case 16: QH_BSTEPS(1); break;
+        case 32: QH_BSTEPS(2); break;
+        case 64: QH_BSTEPS(4); break;
+        default: fail(QH_EUNSUPPORTED, "batched solves take 16, 32 or 64 replicas");
+    }
+#undef QH_BSTEPS
+    QH_CHECK_LAUNCH();
 }
 
 void launch_batched(int R, int workers, const BlockDesc *blocks, const int32_t *sched_ptr, const int32_t *sched,
@@ -704,7 +850,7 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
     const int R = p.R;
     const int64_t n = g->n;
     if (g->storage == QH_STORE_DENSE) {
-        const int RT = R >= 64 ? 64 : R;
+        const int RT = R >= 64 ? p.run_rt : R;
         const int64_t G = g->n_rt * (R / RT);
         if (G == 0) return;
         float *xin = cur ? p.xb.p : p.xa.p;
@@ -744,24 +890,28 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
 #define QH_HUB(DTV, RTV)                                                                                        \
     hipLaunchKernelGGL((k_hub_partials<DTV, RTV>), dim3((unsigned)grid_for(g->n_hub_chunks, 4 * (64 / RTV), 4096), \
                                                         (unsigned)(R / RTV)),                                       \
-                       dim3(256), 0, st, g->n_hub_chunks, R, g->hub_chunk_row.p, g->hub_chunk_beg.p,           \
-                       g->hub_chunk_end.p, g->l_col.p, g->l_val.p, xin, p.hub_part.p)
+                       dim3(256), 0, st, g->n_hub_chunks, R, g->hub_chunk_beg.p, g->hub_chunk_end.p, g->l_col.p,   \
+                       g->l_val.p, xin, p.hub_part.p)
+#define QH_PK(DTV)                                                                                              \
+    hipLaunchKernelGGL((k_lr_packets<DTV>), dim3((unsigned)grid_for(g->n_lr_pk, 4, 1 << 20), (unsigned)(R / 64)),  \
+                       dim3(256), 0, st, g->n_lr_pk, R, g->lr_pk_ptr.p, g->hub_chunk_beg.p, g->hub_chunk_end.p,     \
+                       g->l_col.p, g->l_val.p, xin, p.hub_part.p)
 #define QH_SKY(DTV, RTV)                                                                                       \
     hipLaunchKernelGGL((k_sky_step<DTV, RTV>), grid, dim3(256), 0, st, n, R, rows_per_wg, nblk, g->s_off.p,    \
-                       g->s_lo.p, g->s_len.p, g->s_val.p, lr ? g->l_ptr.p : nullptr, g->l_col.p, g->l_val.p,    \
-                       g->hub_of_row.p, g->hub_chunk_ptr.p, p.hub_part.p, xin, xout, p.y.p, sa)
+                       g->s_lo.p, g->s_len.p, g->s_val.p, lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, \
+                       xout, p.y.p, sa)
     const bool band = RT == 64 && g->n_bblk > 0 && !p.sky_rows;
     const int64_t GB = ceil_div(g->n_bblk, 4);
 #define QH_BAND(DTV)                                                                                            \
     hipLaunchKernelGGL((k_band_step<DTV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, R,      \
-                       g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p, lr ? g->l_ptr.p : nullptr, \
-                       g->hub_of_row.p, g->hub_chunk_ptr.p, p.hub_part.p, xin, xout, p.y.p, sa)
+                       g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                          \
+                       lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sa)
 #define QH_SKY_RT(DTV)                                                  \
     do {                                                                \
-        if (RT == 16) { if (g->n_hub_chunks) QH_HUB(DTV, 16); QH_SKY(DTV, 16); } \
-        else if (RT == 32) { if (g->n_hub_chunks) QH_HUB(DTV, 32); QH_SKY(DTV, 32); } \
-        else if (band) { if (g->n_hub_chunks) QH_HUB(DTV, 64); QH_BAND(DTV); } \
-        else { if (g->n_hub_chunks) QH_HUB(DTV, 64); QH_SKY(DTV, 64); }  \
+        if (RT == 16) { if (lr) QH_HUB(DTV, 16); QH_SKY(DTV, 16); }     \
+        else if (RT == 32) { if (lr) QH_HUB(DTV, 32); QH_SKY(DTV, 32); } \
+        else if (band) { if (lr) QH_PK(DTV); QH_BAND(DTV); }            \
+        else { if (lr) QH_PK(DTV); QH_SKY(DTV, 64); }                   \
     } while (0)
     switch (g->dtype) {
         case QH_F32: QH_SKY_RT(QH_F32); break;
@@ -772,6 +922,7 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
 #undef QH_SKY_RT
 #undef QH_BAND
 #undef QH_SKY
+#undef QH_PK
 #undef QH_HUB
     QH_CHECK_LAUNCH();
 }
@@ -853,32 +1004,50 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
     const int64_t n = g->n;
     const int R = p.R;
     const int nt = std::min(o->steps, 64);
+    const bool pers_ok = p.pp && p.pp->ok;
+    std::vector<int> cands;                 // replica tiles of the per-step kernel, then 0 = persistent
+    if (R >= 64) cands = {64, 32, 16};
+    else cands = {R};
+    if (pers_ok) cands.push_back(0);
+    p.tuned_plan = 1;
+    p.tuned_rt = cands[0];
+    p.run_rt = R >= 64 ? 64 : R;
+    if (cands.size() == 1) return;          // nothing to choose
     hipEvent_t e0, e1;
     QH_HIP(hipEventCreate(&e0));
     QH_HIP(hipEventCreate(&e1));
-    float best = 0.0f;
-    int choice = 1;
-    for (int cand : {0, 1}) {   // 0 per-step, 1 persistent
-        if (cand == 1 && !(p.pp && p.pp->ok)) continue;
+    float best = 0.0f, best_step = 0.0f;
+    bool first = true;
+    for (int cand : cands) {
+        if (cand) p.run_rt = cand;
+        float ms = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {   // the first repetition warms caches and code
             hipLaunchKernelGGL(k_init, dim3(grid_for(n * R)), dim3(256), 0, st, (uint64_t)0x5eed, n, R, p.xa.p,
                                p.y.p);
             QH_CHECK_LAUNCH();
-            x_to_h(g, p, n, R, st);
+            if (!x_pingpong(g)) x_to_h(g, p, n, R, st);
             QH_HIP(hipEventRecord(e0, st));
-            if (cand == 0) run_steps(g, p, o, pump, c0, a0, 0, nt, st);
+            if (cand) run_steps(g, p, o, pump, c0, a0, 0, nt, st);
             else run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, st);
             QH_HIP(hipEventRecord(e1, st));
             QH_HIP(hipEventSynchronize(e1));
         }
-        float ms = 0.0f;
         QH_HIP(hipEventElapsedTime(&ms, e0, e1));
-        p.tuned_us[cand] = ms * 1000.0f / nt;
-        if (cand == 0 || ms < best) { best = ms; choice = cand + 1; }
+        if (cand && (best_step == 0.0f || ms < best_step)) {
+            best_step = ms;
+            p.tuned_rt = cand;
+            p.tuned_us[0] = ms * 1000.0f / nt;
+        }
+        if (!cand) p.tuned_us[1] = ms * 1000.0f / nt;
+        if (first || ms < best) {
+            best = ms;
+            p.tuned_plan = cand ? 1 : 2;
+        }
+        first = false;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    p.tuned_plan = choice;
+    p.run_rt = p.tuned_rt;
 }
 
 const float *linear_pump(SolvePlan &p, int steps, hipStream_t st) {
@@ -916,18 +1085,18 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     int final_half = 0;
     bool persistent = false;
     const bool want_persistent = o->plan == 0 || o->plan == 2;
-    if (dense16 && want_persistent && ke > kb && n > 0) {
-        if (!p.pp_tried) {
+    const bool dense = g->storage == QH_STORE_DENSE;
+    if (dense && ke > kb && n > 0) {
+        if (dense16 && want_persistent && !p.pp_tried) {
             p.pp = std::make_shared<PersistPlan>();
             build_persistent_plan(g, R, *p.pp, st);
             p.pp_tried = true;
         }
-        persistent = p.pp->ok;
-        if (persistent && o->plan == 0) {
-            if (!p.tuned_plan) autotune_dense(g, p, o, pump, c0, a0, st);
-            persistent = p.tuned_plan == 2;
-        }
+        if (o->plan == 0 && !p.tuned_plan) autotune_dense(g, p, o, pump, c0, a0, st);
+        if (dense16 && want_persistent && p.pp->ok) persistent = o->plan == 2 || p.tuned_plan == 2;
     }
+    // replica tile of the per-step dense kernel: the caller's, else the tuned one, else 64
+    p.run_rt = R < 64 ? R : o->replica_tile ? o->replica_tile : p.tuned_rt ? p.tuned_rt : 64;
     if (o->plan == 2 && !persistent)
         fail(QH_EUNSUPPORTED, "the persistent plan does not apply to this graph and replica count");
     // initial state into xa / y (after any tuning, which uses the same buffers)
@@ -950,7 +1119,7 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
         run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, st);
     } else if (ke > kb && n > 0) {
         if (o->use_graph) {
-            auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R);
+            auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R, p.run_rt);
             if (!p.exec || p.graph_key != key) {
                 if (p.exec) { (void)hipGraphExecDestroy(p.exec); p.exec = nullptr; }
                 if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }

@@ -403,6 +403,7 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out) {
         }
         i.us_per_step[0] = p.tuned_us[0];
         i.us_per_step[1] = p.tuned_us[1];
+        i.replica_tile = g->storage == QH_STORE_DENSE ? (R >= 64 ? p.run_rt : R) : 0;
     }
     *out = i;
 }

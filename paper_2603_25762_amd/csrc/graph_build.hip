@@ -743,35 +743,37 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
     }
     for (int32_t u = 0; u < n; ++u) lptr[u + 1] += lptr[u];
 
-    // hub rows: long-range lists longer than the inline limit, split into chunks
+    // long-range rows split into chunks of at most kHubChunk entries (chunks tile the
+    // long-range entries in row order); consecutive chunks grouped into packets of at most
+    // 64 entries, one wave each
     {
-        std::vector<int32_t> hub_of(n, -1), crow, cptr;
+        std::vector<int32_t> rptr(n + 1, 0), pk;
         std::vector<int64_t> cbeg, cend;
-        int32_t nh = 0;
+        int64_t pk_entries = 0;
         for (int32_t u = 0; u < n; ++u) {
-            int64_t c = lptr[u + 1] - lptr[u];
-            if (c <= kHubInline) continue;
-            hub_of[u] = nh++;
-            cptr.push_back((int32_t)crow.size());
             for (int64_t b = lptr[u]; b < lptr[u + 1]; b += kHubChunk) {
-                crow.push_back(u);
+                const int64_t e = std::min<int64_t>(b + kHubChunk, lptr[u + 1]);
+                if (pk.empty() || pk_entries + (e - b) > 64) {
+                    pk.push_back((int32_t)cbeg.size());
+                    pk_entries = 0;
+                }
+                pk_entries += e - b;
                 cbeg.push_back(b);
-                cend.push_back(std::min<int64_t>(b + kHubChunk, lptr[u + 1]));
+                cend.push_back(e);
             }
+            rptr[u + 1] = (int32_t)cbeg.size();
         }
-        cptr.push_back((int32_t)crow.size());
-        g->n_hub = nh;
-        g->n_hub_chunks = (int64_t)crow.size();
-        g->hub_of_row.alloc(n);
-        g->hub_of_row.upload(hub_of.data(), n, st);
-        g->hub_chunk_row.alloc(crow.size());
-        g->hub_chunk_row.upload(crow.data(), crow.size(), st);
+        pk.push_back((int32_t)cbeg.size());
+        g->n_hub_chunks = (int64_t)cbeg.size();
+        g->n_lr_pk = (int64_t)pk.size() - 1;
+        g->row_chunk_ptr.alloc(n + 1);
+        g->row_chunk_ptr.upload(rptr.data(), n + 1, st);
         g->hub_chunk_beg.alloc(cbeg.size());
         g->hub_chunk_beg.upload(cbeg.data(), cbeg.size(), st);
         g->hub_chunk_end.alloc(cend.size());
         g->hub_chunk_end.upload(cend.data(), cend.size(), st);
-        g->hub_chunk_ptr.alloc(cptr.size());
-        g->hub_chunk_ptr.upload(cptr.data(), cptr.size(), st);
+        g->lr_pk_ptr.alloc(pk.size());
+        g->lr_pk_ptr.upload(pk.data(), pk.size(), st);
         QH_HIP(hipStreamSynchronize(st));
     }
 

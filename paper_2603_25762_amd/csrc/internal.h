@@ -104,6 +104,8 @@ struct SolvePlan {
     int last_plan = 0;                 // plan the last solve ran
     bool sky_rows = false;             // SNP graphs: per-row skyline kernel instead of band blocks
     float tuned_us[2] = {0, 0};        // measured microseconds per step: per-step, persistent
+    int tuned_rt = 0;                  // autotuner's replica tile for the per-step dense kernel
+    int run_rt = 64;                   // replica tile of the dense step launches (R >= 64)
     int R = 0;
     int64_t n_pad = 0;
     DevBuf<float> xa, xb, y;        // fp32 state, [n_pad][R]
@@ -123,7 +125,7 @@ struct SolvePlan {
     // captured step loop
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::tuple<int, int, int, double, double, double, const float *, int> graph_key{};
+    std::tuple<int, int, int, double, double, double, const float *, int, int> graph_key{};
     ~SolvePlan() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -133,6 +135,7 @@ struct SolvePlan {
 }  // namespace qh
 
 struct qh_graph {
+    uint64_t serial = 0;   // unique per graph in the process (keys cached batch plans)
     int device = 0;
     int kind = 0, storage = 0, dtype = 0;
     int64_t n = 0;         // vertices
@@ -183,13 +186,12 @@ struct qh_graph {
     qh::DevBuf<uint8_t> l_val;          // dtype
     int64_t l_nnz = 0;
     // Long-range rows are summed by chunks of at most kHubChunk entries in a separate
-    // kernel (full parallelism for the gathers, hub rows split); the step kernel adds the
-    // chunk partials of its row in order.
-    qh::DevBuf<int32_t> hub_of_row;     // [n] hub index or -1
-    qh::DevBuf<int32_t> hub_chunk_row;  // [n_hub_chunks]
+    // kernel (full parallelism for the gathers, long rows split); the step kernel adds the
+    // chunk partials of its row in order.  Chunks tile the long-range entries in row order.
+    qh::DevBuf<int32_t> row_chunk_ptr;  // [n + 1] chunks of row u: [ptr[u], ptr[u + 1])
     qh::DevBuf<int64_t> hub_chunk_beg, hub_chunk_end;
-    qh::DevBuf<int32_t> hub_chunk_ptr;  // [n_hub + 1] chunks of each hub, in order
-    int64_t n_hub = 0, n_hub_chunks = 0;
+    qh::DevBuf<int32_t> lr_pk_ptr;      // [n_lr_pk + 1] first chunk of each packet (<= 64 entries)
+    int64_t n_hub_chunks = 0, n_lr_pk = 0;
 
     // Phasing support.
     qh::DevBuf<uint8_t> init_h1;        // [n_snp]
@@ -207,7 +209,6 @@ struct qh_graph {
 namespace qh {
 
 constexpr int kBandRows = 16;       // rows per band block (one wave's accumulators)
-constexpr int kHubInline = 0;       // long-range rows longer than this are summed by chunks (all of them)
 constexpr int kHubChunk = 64;       // entries per hub partial
 
 // graph_build.hip
@@ -242,6 +243,8 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out);
 
 // phase.hip
 void phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);
+void refine(qh_graph *g, const qh_bsb_opts *o, int max_rounds, int8_t *h1, int32_t *block, int32_t *flips,
+            double *round_cuts, int32_t *rounds_out, hipStream_t st);
 
 // Device-side descriptor of one block of a batched solve.
 struct BlockDesc {
@@ -264,6 +267,10 @@ struct BlockDesc {
 void launch_batched(int R, int workers, const BlockDesc *blocks, const int32_t *sched_ptr, const int32_t *sched,
                     int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
 int batched_workers_per_cu(int R);
+// per-step plan: init of every block, then one launch per step over the work items
+// (x = block, y = row tile of a dense block or group of four band blocks)
+void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, int64_t n_items, int steps,
+                          float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
 SolvePlan &solve_plan(const qh_graph *g, int R, hipStream_t st);
 const float *linear_pump(SolvePlan &p, int steps, hipStream_t st);   // p_k = k / (steps - 1)
 

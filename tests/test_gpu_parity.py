@@ -200,6 +200,33 @@ def test_persistent_equals_per_step_bit_exact(dtype, R):
         assert torch.equal(ra["best_spins"], rb["best_spins"]) and torch.equal(ra["best_cut"], rb["best_cut"])
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])
+def test_replica_tiles_bit_exact(dtype):
+    """The per-step dense kernel with 64, 32 or 16 replicas per workgroup computes every
+    replica's product and update identically; the autotuned plan equals them too."""
+    w = synth.read_mhc(seed=79, n_snp=1500, n_reads=900, region=500_000)
+    g = gpu_graph(w, "read_signed", dtype)
+    n, R = g.info()["n"], 128
+    out = []
+    for tile in (64, 32, 16):
+        x = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        y = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        r = qh.bsb_solve(g, R, 200, seed=5, x=x, y=y, plan=1, replica_tile=tile)
+        out.append((x, y, r))
+    x = torch.empty((n, R), dtype=torch.float32, device="cuda")
+    y = torch.empty((n, R), dtype=torch.float32, device="cuda")
+    out.append((x, y, qh.bsb_solve(g, R, 200, seed=5, x=x, y=y, plan=0)))
+    info = g.plan_info(R)
+    assert info["replica_tile"] in (16, 32, 64) and info["us_per_step"][0] > 0
+    xa, ya, ra = out[0]
+    for xb, yb, rb in out[1:]:
+        assert torch.equal(xa, xb) and torch.equal(ya, yb)
+        assert torch.equal(ra["cuts"], rb["cuts"]) and torch.equal(ra["best_spins"], rb["best_spins"])
+    with pytest.raises(qh.QhapError) as e:
+        qh.bsb_solve(g, 32, 10, replica_tile=16)
+    assert e.value.status == qh.Status.EINVAL
+
+
 @pytest.mark.parametrize("plan", [0, 3])          # 0: band blocks (R % 64 == 0); 3: per-row skyline
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("R", [16, 32, 64, 128])
@@ -386,6 +413,49 @@ def test_flip_crossing_matches_oracle():
     assert np.array_equal(S, quant.round_to("f32", D))
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_refine_gauge_identity_restore_and_single_round(dtype):
+    """Eqs. (15)-(17) in the library: the flip counters' partition has, on the original
+    weights (cut by the oracle), exactly the sum of the per-round cuts; the graph is
+    restored bit for bit; one round equals the parity phasing of one solve."""
+    w = synth.snp_small(24, n_snp=1500)
+    g = gpu_graph(w, "snp_llr", dtype)
+    go = oracle_graph(w, "snp_llr")
+    n = go.n
+    master, stored = cpu(g.export_rows(0, n)), cpu(g.export_rows(0, n, stored=True))
+    rr = qh.refine(g, 32, 600, seed=1, max_rounds=15)
+    assert np.array_equal(cpu(g.export_rows(0, n)), master)
+    assert np.array_equal(cpu(g.export_rows(0, n, stored=True)), stored)
+    assert rr["rounds"] >= 1 and all(c > 0 for c in rr["round_cuts"])
+    comp, nc = oracle.components(go)
+    S = np.where(cpu(rr["flips"]) % 2 == 1, -1, 1).astype(np.int8)
+    total = oracle.cuts(go, comp, nc, S).sum()
+    assert total == pytest.approx(sum(rr["round_cuts"]), rel=1e-9)
+    # the oracle's refinement at the same schedule reaches the same total within 0.1 %
+    ro = oracle.refine(go, w.init_h1, 32, 600, 0.5, seed=1, max_rounds=15)
+    assert _gap(sum(ro["round_cuts"]), total) <= 1e-3
+    # one round is the single-round parity phasing of the round-0 solve
+    r1 = qh.refine(g, 32, 600, seed=1, max_rounds=1)
+    rs = qh.bsb_solve(g, 32, 600, seed=1)
+    h1, blk = qh.phase(g, rs["best_spins"])
+    assert torch.equal(r1["h1"], h1) and torch.equal(r1["block"], blk)
+    assert r1["round_cuts"][0] == pytest.approx(float(cpu(rs["best_cut"])[0]), rel=1e-12)
+
+
+def test_refine_planted_twin_and_errors():
+    w = synth.snp_small(8, n_snp=600, error=0.0)
+    g = gpu_graph(w, "snp_llr", "f32")
+    rr = qh.refine(g, 32, 600, seed=5)
+    assert metrics.switch_error(cpu(rr["h1"]), w.truth, cpu(rr["block"])) == 0.0
+    gr = gpu_graph(synth.read_tiny())
+    with pytest.raises(qh.QhapError) as e:
+        qh.refine(gr, 16, 10)
+    assert e.value.status == qh.Status.EUNSUPPORTED
+    with pytest.raises(qh.QhapError) as e:
+        qh.refine(g, 32, 10, max_rounds=0)
+    assert e.value.status == qh.Status.EINVAL
+
+
 # ----------------------------------------------------------------------------- whole solves
 
 def _gap(oracle_cut, gpu_cut):
@@ -461,17 +531,19 @@ def test_porec_final_cut():
     assert _gap(ro["best_cut"], float(cpu(rg["best_cut"])[0])) <= 1e-3
 
 
-@pytest.mark.parametrize("R", [16, 32, 64])
-def test_batched_matches_single_solves(R):
-    """One persistent launch over uneven blocks of every storage and dtype: each block's
-    state, replica cuts, selection and greedy result equal its single-graph solve."""
+@pytest.mark.parametrize("R,plan", [(16, 1), (32, 1), (64, 1), (16, 2), (32, 2), (64, 2), (32, 0)])
+def test_batched_matches_single_solves(R, plan):
+    """Uneven blocks of every storage and dtype, per-step (1), whole-block (2) or autotuned
+    (0) plan: each block's state, replica cuts, selection and greedy result equal its
+    single-graph solve bit for bit."""
     blocks = [synth.read_small(50 + b, n_snp=200, n_reads=40 + 30 * b) for b in range(4)] + \
              [synth.snp_small(60 + b, n_snp=150 + 200 * b) for b in range(3)] + [synth.read_tiny()]
     kinds = ["read_signed"] * 4 + ["snp_llr"] * 3 + ["read_signed"]
     dtypes = ["fp8", "f16", "bf16", "f32", "bf16", "f16", "f32", "f16"]
     gs = [gpu_graph(w, k, d) for w, k, d in zip(blocks, kinds, dtypes)]     # reads dense, SNPs skyline
     steps = 300
-    rb = qh.bsb_solve_batched(gs, R, steps, seed=9, return_state=True)
+    rb = qh.bsb_solve_batched(gs, R, steps, seed=9, return_state=True, plan=plan)
+    assert rb["plan_used"] == plan or (plan == 0 and rb["plan_used"] in (1, 2))
     off = rb["vertex_offset"]
     for b, (w, k, g) in enumerate(zip(blocks, kinds, gs)):
         n = g.info()["n"]
@@ -507,6 +579,9 @@ def test_batched_errors_and_empty_batch():
     assert e.value.status == qh.Status.EUNSUPPORTED
     with pytest.raises(qh.QhapError) as e:
         qh.bsb_solve_batched([g_ok, g_ok], 32, 10)
+    assert e.value.status == qh.Status.EINVAL
+    with pytest.raises(qh.QhapError) as e:
+        qh.bsb_solve_batched([g_ok], 32, 10, plan=3)
     assert e.value.status == qh.Status.EINVAL
     r = qh.bsb_solve_batched([], 32, 10)
     assert r["vertex_offset"].tolist() == [0]
