@@ -31,7 +31,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--dtype", default="f16", choices=["f32", "f16", "bf16", "fp8"])
+    ap.add_argument("--workload", default="read_mhc", choices=["read_mhc", "snp_chrom", "snp_porec", "batched"],
+                    help="read_mhc (default) is the benchmark line; the others profile the SNP and batched paths")
+    ap.add_argument("--dtype", default=None, choices=["f32", "f16", "bf16", "fp8"],
+                    help="default: f16 (read_mhc, snp_chrom), bf16 (snp_porec); batched blocks carry their own")
     ap.add_argument("--graph", type=int, default=1, help="replay the step loop from a hipGraph")
     ap.add_argument("--plan", type=int, default=0,
                     help="0 auto (persistent when it applies), 1 one kernel per step, 2 persistent")
@@ -57,22 +60,26 @@ def calibrate_copy():
     print(json.dumps(dict(copy_bytes_read=COPY_BYTES, copy_bytes_written=COPY_BYTES, launches=3)), flush=True)
 
 
-KERNEL_SOURCES = ("paper_2603_25762_amd/csrc/bsb.hip", "paper_2603_25762_amd/csrc/formats.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dense_step_read_mhc_traffic.md")
 
 
 def kernel_source_hash():
+    """Hash of the dense step kernel's source: the dense-tile section of bsb.hip (from its
+    banner to the skyline banner; the update helper above it included) and formats.h."""
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    src = open(os.path.join(ROOT, "paper_2603_25762_amd", "csrc", "bsb.hip")).read()
+    a = src.index("struct StepArgs")
+    b = src.index("// skyline band + long-range CSR")
+    h.update(src[a:b].encode())
+    h.update(open(os.path.join(ROOT, "paper_2603_25762_amd", "csrc", "formats.h"), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, replica_tile):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when
-    there is none or the kernel sources changed since the counters were taken."""
+    there is none, it covers another replica tile, or the kernel sources changed since the
+    counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -81,6 +88,8 @@ def measured_traffic(kernel):
             k, _, v = line[len("traffic:"):].strip().partition("=")
             vals[k.strip()] = v.strip()
     if vals.get("kernel") != kernel or vals.get("source_sha") != kernel_source_hash():
+        return None
+    if int(vals.get("replica_tile", 0)) != replica_tile:
         return None
     return int(float(vals["hbm_bytes_per_launch"]))
 
@@ -94,6 +103,12 @@ def main():
         print(f"bench.py runs on one GPU; --gpus {a.gpus} is not offered (replica sharding across GPUs "
               "is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if a.workload in ("snp_chrom", "snp_porec"):
+        return bench_snp(a)
+    if a.workload == "batched":
+        return bench_batched(a)
+    if a.dtype is None:
+        a.dtype = "f16"
     import numpy as np
     import torch
 
@@ -193,14 +208,16 @@ def main():
     ach_gbs = bytes_ / (launch_us * 1e-6) / 1e9
     frac_m = ach_tf / PEAK_TFLOPS[a.dtype]
     frac_h = ach_gbs / PEAK_HBM_GBS
-    traffic = measured_traffic(kernel) if plan != 2 else None
+    rtile = (tune or {}).get("replica_tile") or 64
+    traffic = measured_traffic(kernel, rtile) if plan != 2 else None
     if frac_m >= frac_h:
         roof = dict(bound="mfma", achieved=round(ach_tf, 2), peak=PEAK_TFLOPS[a.dtype], unit="TFLOP/s",
                     frac=round(frac_m, 4), traffic=traffic)
     else:
         roof = dict(bound="hbm", achieved=round(ach_gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(frac_h, 4), traffic=traffic)
-    roof.update(kernel=kernel, launch_us=round(launch_us, 3), steps_per_launch=launches_steps,
+    roof.update(kernel=kernel, replica_tile=rtile if plan != 2 else None, launch_us=round(launch_us, 3),
+                steps_per_launch=launches_steps,
                 us_per_bsb_step=round(step_us, 3), flop_per_launch=flops, bytes_per_launch=bytes_,
                 mfma_frac=round(frac_m, 4), hbm_frac=round(frac_h, 4))
 
@@ -224,6 +241,118 @@ def main():
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, R, STEPS, DT, seed, a.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+def _time_loop(fn, reps=1):
+    """HIP-event time (ms) of fn() on torch's current stream, which the library launches on."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_snp(a):
+    """SNP-based chromosome-scale workloads: skyline band (+ long-range CSR for Pore-C)."""
+    import torch
+    import paper_2603_25762_amd as qh
+    import synth
+    porec = a.workload == "snp_porec"
+    dtype = a.dtype or ("bf16" if porec else "f16")
+    R, STEPS, DT, SEED = 64, (4000 if porec else 3000), 0.5, 7
+    band = 128 if porec else 0
+    torch.cuda.set_device(0)
+    w = synth.snp_porec() if porec else synth.snp_chrom()
+    d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+    torch.cuda.synchronize()
+
+    def build():
+        return qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="snp_llr",
+                              dtype=dtype, alpha=d["alpha"], band_limit=band)
+
+    def job():
+        g = build()
+        r = qh.bsb_solve(g, R, STEPS, dt=DT, seed=SEED, use_graph=bool(a.graph))
+        h1, blk = qh.phase(g, r["best_spins"])
+        return g, r, h1, blk
+
+    for _ in range(a.warmup):
+        job()[0].free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [job() for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    g, r, h1, blk = res[-1]
+    for gg, *_ in res[:-1]:
+        gg.free()
+    info = g.info()
+    nnz, n = info["nnz"], info["n"]
+    loop_ms = _time_loop(lambda: qh.bsb_solve(g, R, STEPS, dt=DT, seed=SEED, use_graph=bool(a.graph),
+                                              readout=False))
+    step_us = loop_ms * 1e3 / STEPS
+    # one step: the stored band (no column indices) and the long-range CSR once, x and y read
+    # and written once (gathers of x rows by long-range entries are cache traffic)
+    lr = info["longrange_nnz"]
+    bytes_ = info["stored_bytes"] + n * R * 16
+    ach = bytes_ / (step_us * 1e-6) / 1e9
+    kernel = "k_band_step" + ("+k_lr_packets" if lr else "") + f"<{dtype}>"
+    out = dict(metric=METRIC, value=nnz * R * STEPS / (ms * 1e-3), unit="edge-updates/s", n_gpus=1,
+               steps=a.steps, warmup=a.warmup, ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype=dtype, data="synthetic",
+               config=dict(workload=("snp_porec: snp_chrom plus 600,000 Pore-C contacts (distance ~ d^-1.1, "
+                                     "100 kb-100 Mb, Zipf anchors), band limit 128" if porec else
+                                     "snp_chrom: 250,000 het SNPs, 30x of 20 kb reads, 6% errors, Phred 7-40"),
+                           n=n, nnz=nnz, longrange_nnz=lr, replicas=R, bsb_steps=STEPS, dt=DT,
+                           storage="skyline band blocks" + (" + long-range packets" if lr else ""),
+                           parallelism="single GPU"),
+               roofline=dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                             frac=round(ach / PEAK_HBM_GBS, 4), traffic=None, kernel=kernel,
+                             launch_us=round(step_us, 3), bytes_per_launch=bytes_,
+                             note="per bSB step (all kernels of one step)"))
+    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth))
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(a):
+    """3,000 uneven blocks (dense FP8 read blocks, BF16 SNP blocks), R = 32, 500 steps.
+    Graphs are built before the timed region; one step = one batched solve."""
+    import torch
+    import paper_2603_25762_amd as qh
+    import synth
+    R, STEPS, DT, SEED = 32, 500, 0.5, 11
+    torch.cuda.set_device(0)
+    batch = synth.batched_blocks()
+    gs = []
+    for i, w in enumerate(batch.blocks):
+        d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+        kind = "read_signed" if i % 2 == 0 else "snp_llr"
+        gs.append(qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind=kind,
+                                 dtype=w.solve["dtype"], alpha=d["alpha"] if kind == "snp_llr" else None))
+    torch.cuda.synchronize()
+    nnz = sum(g.info()["nnz"] for g in gs)
+    r = None
+    for _ in range(a.warmup):
+        r = qh.bsb_solve_batched(gs, R, STEPS, dt=DT, seed=SEED, plan=a.plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        r = qh.bsb_solve_batched(gs, R, STEPS, dt=DT, seed=SEED, plan=a.plan)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / a.steps
+    out = dict(metric=METRIC, value=nnz * R * STEPS / (ms * 1e-3), unit="edge-updates/s", n_gpus=1,
+               steps=a.steps, warmup=a.warmup, ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="fp8+bf16", data="synthetic",
+               config=dict(workload="batched: 3,000 blocks, log-uniform 50-5,000 vertices, even blocks dense "
+                                    "FP8 read graphs, odd blocks BF16 SNP graphs",
+                           blocks=len(gs), nnz=nnz, replicas=R, bsb_steps=STEPS, dt=DT,
+                           plan_used=r["plan_used"], parallelism="single GPU"))
     print(json.dumps(out), flush=True)
 
 

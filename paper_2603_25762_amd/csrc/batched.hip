@@ -117,12 +117,23 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
     DevBuf<BlockDesc> d_desc(nb);
     QH_HIP(hipMemcpyAsync(d_desc.p, desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
 
-    // per-step plan: work items, largest blocks first, items of a block adjacent
+    // per-step plan: work items grouped by class (storage x dtype), largest blocks first
+    // within a class, items of a block adjacent
     std::vector<int2> items;
-    for (int b : order) {
-        const qh_graph *g = gs[b];
-        const int64_t m = g->storage == QH_STORE_DENSE ? g->n_rt : ceil_div(g->n_bblk, 4);
-        for (int64_t i = 0; i < m; ++i) items.push_back(make_int2(b, (int)i));
+    int64_t class_ptr[kBatchClasses + 1] = {0};
+    auto class_of = [](const qh_graph *g) {
+        if (g->storage == QH_STORE_DENSE)
+            return g->dtype == QH_F32 ? 0 : g->dtype == QH_F16 ? 1 : g->dtype == QH_BF16 ? 2 : 3;
+        return g->dtype == QH_F32 ? 4 : g->dtype == QH_F16 ? 5 : 6;
+    };
+    for (int c = 0; c < kBatchClasses; ++c) {
+        for (int b : order) {
+            const qh_graph *g = gs[b];
+            if (class_of(g) != c) continue;
+            const int64_t m = g->storage == QH_STORE_DENSE ? g->n_rt : ceil_div(g->n_bblk, 4);
+            for (int64_t i = 0; i < m; ++i) items.push_back(make_int2(b, (int)i));
+        }
+        class_ptr[c + 1] = (int64_t)items.size();
     }
     const int64_t n_items = (int64_t)items.size();
     DevBuf<int2> d_items(std::max<int64_t>(n_items, 1));
@@ -156,8 +167,8 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
     auto run = [&](int plan, int steps, uint64_t seed) {
         if (plan == 2) launch_batched(R, workers, d_desc.p, d_sptr.p, d_sched.p, steps, (float)o->dt, (float)a0, pump,
                                       seed, st);
-        else launch_batched_steps(R, nb, d_desc.p, d_items.p, n_items, steps, (float)o->dt, (float)a0, pump, seed,
-                                  st);
+        else launch_batched_steps(R, nb, d_desc.p, d_items.p, class_ptr, steps, (float)o->dt, (float)a0, pump,
+                                  seed, st);
     };
     int plan = o->plan == 2 ? 2 : 1;
     if (o->plan == 0 && o->steps > 0) {
@@ -192,7 +203,9 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
     // leaves the final x in the first half
     const int final_half = plan == 1 ? (o->steps & 1) : 0;
 
-    // per-block readout: FP64 cuts, component selection, optional greedy, cut of the result
+    // readout of every block in one launch per kernel: FP64 cuts, component selection,
+    // optional greedy, cut of the result
+    std::vector<ReadoutDesc> rd(nb);
     int64_t voff = 0;
     for (int b = 0; b < nb; ++b) {
         const qh_graph *g = gs[b];
@@ -204,21 +217,40 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
             QH_HIP(hipMemcpyAsync(res->x + voff * R, xfin, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
         if (res->y && nR)
             QH_HIP(hipMemcpyAsync(res->y + voff * R, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
-        qh_result r{};
-        r.best_spins = res->best_spins + voff;
-        r.cuts = res->cuts + (int64_t)b * R;
-        r.best_cut = res->best_cut + b;
-        r.selected_cut = res->selected_cut ? res->selected_cut + b : nullptr;
-        readout(view_of(g), p, R, xfin, p.y.p, &r, o->greedy != 0, st, false);
+        const ReadoutView v = view_of(g);
+        ReadoutDesc &d = rd[b];
+        d.n = v.n;
+        d.n_comp = v.n_comp;
+        d.n_chunks = v.n_chunks;
+        d.n_ord = v.n_ord;
+        d.m_ptr = v.m_ptr;
+        d.m_col = v.m_col;
+        d.m_val = v.m_val;
+        d.comp = v.comp;
+        d.comp_first = v.comp_first;
+        d.comp_order = v.comp_order;
+        d.chunk_begin = v.chunk_begin;
+        d.chunk_end = v.chunk_end;
+        d.comp_chunk_ptr = v.comp_chunk_ptr;
+        d.eps = v.eps;
+        d.x = xfin;
+        d.y = p.y.p;
+        d.spins = p.spins.p;
+        d.rowcut = p.rowcut.p;
+        d.part = p.part.p;
+        d.cut_rc = p.cut_rc.p;
+        d.best_r = p.best_r.p;
+        d.gain = p.gain.p;
+        d.flag = p.flag.p;
+        d.part1 = p.part1.p;
+        d.cut1 = p.cut1.p;
+        d.best_spins = res->best_spins + voff;
+        d.cuts = res->cuts + (int64_t)b * R;
+        d.best_cut = res->best_cut + b;
+        d.selected_cut = res->selected_cut ? res->selected_cut + b : nullptr;
         voff += g->n;
     }
-    // one synchronisation for the non-finite checks of every block
-    std::vector<int32_t> bad(nb, 0);
-    for (int b = 0; b < nb; ++b)
-        QH_HIP(hipMemcpyAsync(&bad[b], plans[b]->counter.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    QH_HIP(hipStreamSynchronize(st));
-    for (int b = 0; b < nb; ++b)
-        if (bad[b]) fail(QH_ENUMERIC, "non-finite spin or momentum in the final state of block %d", b);
+    readout_batched(rd, R, o->greedy != 0, st);
 }
 
 }  // namespace qh

@@ -535,11 +535,13 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
     }
 }
 
-// One step of every block in one launch.  Work item = one row tile of a dense block
-// (the k_dense_step workgroup) or four band blocks of an SNP block (one per wave, lanes
-// r < R active); items of one block are adjacent, and the XCD remap keeps them on one
-// XCD.  Ping-pong halves follow the single-graph solve (step k reads half k & 1).
-template <int NB>
+// One step of every block of one class (storage kind x dtype) in one launch.  Work item
+// = one row tile of a dense block (the k_dense_step workgroup) or four band blocks of an
+// SNP block (one per wave, lanes r < R active); items of one block are adjacent, and the
+// XCD remap keeps them on one XCD.  Ping-pong halves follow the single-graph solve (step k
+// reads half k & 1).  One instantiation per class keeps each one's register budget (and
+// occupancy) that of its own path.
+template <int KIND, int DT, int NB>
 __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restrict__ blocks,
                                                       const int2 *__restrict__ items, int64_t n_items, int k,
                                                       float dt, float a0, const float *__restrict__ pump) {
@@ -552,8 +554,8 @@ __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restric
     const float coef = a0 - pump[k];
     const int cur = k & 1;
     const int64_t n = B.n;
-    if (B.kind == 0) {
-        const bool d16 = B.dtype != QH_F32;
+    if constexpr (KIND == 0) {
+        constexpr bool d16 = DT != QH_F32;
         const uint16_t *hin = cur ? B.h1 : B.h0;
         uint16_t *hout = cur ? B.h0 : B.h1;
         float *xin = d16 ? B.x : (cur ? B.xs : B.x);
@@ -563,30 +565,15 @@ __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restric
         float xo[NB][4], yo[NB][4];
         float4_t acc[NB];
         dense_load_state<NB>(xo, yo, rowbase, n, xin, B.y, R, 0, lane);
-#define QH_BS(DTV)                                                                                          \
-    dense_product<DTV, NB>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, xin, hin, R, 0, wave, lane); \
-    dense_update<DTV, NB>(acc, xo, yo, rowbase, n, R, 0, lane, B.row_scale, xout, B.y, hout, coef, sa)
-        switch (B.dtype) {
-            case QH_F32: QH_BS(QH_F32); break;
-            case QH_F16: QH_BS(QH_F16); break;
-            case QH_BF16: QH_BS(QH_BF16); break;
-            default: QH_BS(QH_FP8_ROWSCALE); break;
-        }
-#undef QH_BS
+        dense_product<DT, NB>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, xin, hin, R, 0, wave, lane);
+        dense_update<DT, NB>(acc, xo, yo, rowbase, n, R, 0, lane, B.row_scale, xout, B.y, hout, coef, sa);
     } else {
         const int64_t bb = (int64_t)I.y * 4 + wave;
         if (bb >= B.n_bblk) return;
         const float *xin = cur ? B.xs : B.x;
         float *xout = cur ? B.x : B.xs;
-#define QH_BB(DTV)                                                                                              \
-    band_block_step<DTV>(bb, n, R, lane, lane < R, B.bb_off, B.bb_lo, B.bb_w, B.bb_val, nullptr, nullptr, xin, \
-                         xout, B.y, coef, sa)
-        switch (B.dtype) {
-            case QH_F32: QH_BB(QH_F32); break;
-            case QH_F16: QH_BB(QH_F16); break;
-            default: QH_BB(QH_BF16); break;
-        }
-#undef QH_BB
+        band_block_step<DT>(bb, n, R, lane, lane < R, B.bb_off, B.bb_lo, B.bb_w, B.bb_val, nullptr, nullptr, xin,
+                            xout, B.y, coef, sa);
     }
 }
 
@@ -595,14 +582,36 @@ __global__ __launch_bounds__(256) void k_batched_init(const BlockDesc *__restric
     block_init<NB * 16>(blocks[blockIdx.x], seed, threadIdx.x);
 }
 
-void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, int64_t n_items, int steps,
-                          float dt, float a0, const float *pump, uint64_t seed, hipStream_t st) {
-#define QH_BSTEPS(NBV)                                                                                        \
-    do {                                                                                                      \
-        hipLaunchKernelGGL(k_batched_init<NBV>, dim3(nb), dim3(256), 0, st, blocks, seed);                   \
-        for (int k = 0; k < steps && n_items; ++k)                                                           \
-            hipLaunchKernelGGL(k_batched_step<NBV>, dim3((unsigned)n_items), dim3(256), 0, st, blocks, items, \
-                               n_items, k, dt, a0, pump);                                                     \
+// classes: 0-3 dense F32/F16/BF16/FP8, 4-6 band F32/F16/BF16 (kBatchClasses in total)
+template <int NB>
+static void launch_class(int cls, dim3 grid, hipStream_t st, const BlockDesc *blocks, const int2 *items,
+                         int64_t n_items, int k, float dt, float a0, const float *pump) {
+#define QH_CLS(KD, DTV)                                                                                  \
+    hipLaunchKernelGGL((k_batched_step<KD, DTV, NB>), grid, dim3(256), 0, st, blocks, items, n_items, k, dt, \
+                       a0, pump)
+    switch (cls) {
+        case 0: QH_CLS(0, QH_F32); break;
+        case 1: QH_CLS(0, QH_F16); break;
+        case 2: QH_CLS(0, QH_BF16); break;
+        case 3: QH_CLS(0, QH_FP8_ROWSCALE); break;
+        case 4: QH_CLS(1, QH_F32); break;
+        case 5: QH_CLS(1, QH_F16); break;
+        default: QH_CLS(1, QH_BF16); break;
+    }
+#undef QH_CLS
+}
+
+void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, const int64_t *class_ptr,
+                          int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st) {
+#define QH_BSTEPS(NBV)                                                                                    \
+    do {                                                                                                  \
+        hipLaunchKernelGGL(k_batched_init<NBV>, dim3(nb), dim3(256), 0, st, blocks, seed);               \
+        for (int k = 0; k < steps; ++k)                                                                  \
+            for (int c = 0; c < kBatchClasses; ++c) {                                                    \
+                const int64_t m = class_ptr[c + 1] - class_ptr[c];                                       \
+                if (m) launch_class<NBV>(c, dim3((unsigned)m), st, blocks, items + class_ptr[c], m, k, dt, a0, \
+                                         pump);                                                          \
+            }                                                                                            \
     } while (0)
     switch (R) {
         case 16: QH_BSTEPS(1); break;
@@ -641,151 +650,6 @@ int batched_workers_per_cu(int R) {
     return std::max(occ, 1);
 }
 
-// ---------------------------------------------------------------------------
-// readout
-// ---------------------------------------------------------------------------
-
-__global__ void k_signs(int64_t n, int R, const float *__restrict__ x, const float *__restrict__ y,
-                        int8_t *__restrict__ s, int32_t *__restrict__ bad) {
-    int64_t total = n * R;
-    int local_bad = 0;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        float v = x[t];
-        if (!isfinite(v) || !isfinite(y[t])) local_bad = 1;
-        s[t] = v >= 0.0f ? 1 : -1;
-    }
-    if (local_bad) atomicOr(bad, 1);
-}
-
-// Chunk partials of cut_{r,c} = 1/4 sum_{a in c} sum_j A_aj (1 - s_a s_j), A = -J.
-__global__ void k_cut_chunks(int64_t n_chunks, int R, const int32_t *__restrict__ chunk_begin,
-                             const int32_t *__restrict__ chunk_end, const int32_t *__restrict__ order,
-                             const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                             const double *__restrict__ val, const int8_t *__restrict__ s,
-                             double *__restrict__ part) {
-    for (int64_t ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
-        for (int r = threadIdx.x; r < R; r += blockDim.x) {
-            double acc = 0.0;
-            for (int v = chunk_begin[ch]; v < chunk_end[ch]; ++v) {
-                const int64_t a = order[v];
-                const int sa = s[a * R + r];
-                double racc = 0.0;
-                for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
-                    const int sb = s[(int64_t)col[e] * R + r];
-                    racc += -val[e] * (1.0 - (double)(sa * sb));
-                }
-                acc += 0.25 * racc;
-            }
-            part[ch * R + r] = acc;
-        }
-    }
-}
-
-__global__ void k_cut_reduce(int64_t n_comp, int R, const int32_t *__restrict__ comp_chunk_ptr,
-                             const double *__restrict__ part, double *__restrict__ cut_rc) {
-    for (int64_t c = blockIdx.x; c < n_comp; c += gridDim.x)
-        for (int r = threadIdx.x; r < R; r += blockDim.x) {
-            double acc = 0.0;
-            for (int ch = comp_chunk_ptr[c]; ch < comp_chunk_ptr[c + 1]; ++ch) acc += part[(int64_t)ch * R + r];
-            cut_rc[(int64_t)r * n_comp + c] = acc;
-        }
-}
-
-__global__ void k_select(int64_t n_comp, int R, const double *__restrict__ cut_rc, int32_t *__restrict__ best_r) {
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n_comp;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        int br = 0;
-        double bv = cut_rc[c];
-        for (int r = 1; r < R; ++r) {
-            double v = cut_rc[(int64_t)r * n_comp + c];
-            if (v > bv) { bv = v; br = r; }
-        }
-        best_r[c] = br;
-    }
-}
-
-__global__ void k_replica_totals(int64_t n_comp, int R, const double *__restrict__ cut_rc,
-                                 double *__restrict__ cuts) {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int64_t c = 0; c < n_comp; ++c) acc += cut_rc[(int64_t)r * n_comp + c];
-        cuts[r] = acc;
-    }
-}
-
-// Deterministic sum of cut_rc[best_r[c]][c] over components (fixed tree).
-__global__ void k_selected_total(int64_t n_comp, const double *__restrict__ cut_rc,
-                                 const int32_t *__restrict__ best_r, double *__restrict__ out) {
-    __shared__ double sh[256];
-    double acc = 0.0;
-    for (int64_t c = threadIdx.x; c < n_comp; c += blockDim.x)
-        acc += best_r ? cut_rc[(int64_t)best_r[c] * n_comp + c] : cut_rc[c];
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = sh[0];
-}
-
-__global__ void k_best_spins(int64_t n, int R, const int32_t *__restrict__ comp,
-                             const int32_t *__restrict__ comp_first, const int32_t *__restrict__ best_r,
-                             const int8_t *__restrict__ s, int8_t *__restrict__ best) {
-    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
-         a += (int64_t)gridDim.x * blockDim.x) {
-        int c = comp[a];
-        if (c < 0) { best[a] = 1; continue; }
-        int rb = best_r[c];
-        int v = s[a * R + rb];
-        int o = s[(int64_t)comp_first[c] * R + rb];
-        best[a] = (int8_t)(v * o);
-    }
-}
-
-// Greedy single-flip rounds: g_a = s_a sum_j A_aj s_j, A = -J.
-__global__ void k_gain(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                       const double *__restrict__ val, const int8_t *__restrict__ s, double *__restrict__ g) {
-    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
-         a += (int64_t)gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) acc += -val[e] * (double)s[col[e]];
-        g[a] = (double)s[a] * acc;
-    }
-}
-
-// Vertex a flips when g_a > eps and it beats every improving neighbour
-// (larger gain, or equal gain and lower index): the flipped set is independent.
-__global__ void k_pick(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                       const double *__restrict__ g, double eps_all, const double *__restrict__ eps_v,
-                       int8_t *__restrict__ flag, int32_t *__restrict__ count) {
-    int local = 0;
-    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
-         a += (int64_t)gridDim.x * blockDim.x) {
-        int8_t f = 0;
-        double ga = g[a];
-        const double eps = eps_v ? eps_v[a] : eps_all;   // neighbours share a's graph, hence its tolerance
-        if (ga > eps) {
-            f = 1;
-            for (int64_t e = ptr[a]; e < ptr[a + 1]; ++e) {
-                int64_t j = col[e];
-                double gj = g[j];
-                if (gj > eps && (gj > ga || (gj == ga && j < a))) { f = 0; break; }
-            }
-        }
-        flag[a] = f;
-        local += f;
-    }
-    if (local) atomicAdd(count, local);
-}
-
-__global__ void k_apply_flips(int64_t n, const int8_t *__restrict__ flag, int8_t *__restrict__ s) {
-    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n;
-         a += (int64_t)gridDim.x * blockDim.x)
-        if (flag[a]) s[a] = (int8_t)-s[a];
-}
-
 __global__ void k_copy_state_in(int64_t n, int R, const float *__restrict__ src, float *__restrict__ dst) {
     int64_t total = n * R;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -804,17 +668,6 @@ static int grid_for(int64_t n, int block = 256, int64_t cap = 65536) {
     return (int)g;
 }
 
-void alloc_readout_scratch(SolvePlan &p, int64_t n, int64_t n_comp, int64_t n_chunks, int R) {
-    p.spins.alloc((size_t)std::max<int64_t>(n, 1) * R);
-    p.part.alloc((size_t)std::max<int64_t>(n_chunks, 1) * R);
-    p.cut_rc.alloc((size_t)std::max<int64_t>(n_comp, 1) * R);
-    p.best_r.alloc(std::max<int64_t>(n_comp, 1));
-    p.gain.alloc(std::max<int64_t>(n, 1));
-    p.flag.alloc(std::max<int64_t>(n, 1));
-    p.counter.alloc(4);
-    p.part1.alloc(std::max<int64_t>(n_chunks, 1));
-    p.cut1.alloc(std::max<int64_t>(n_comp, 1));
-}
 
 SolvePlan &solve_plan(const qh_graph *gc, int R, hipStream_t st) {
     qh_graph *g = const_cast<qh_graph *>(gc);
@@ -1153,107 +1006,6 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     readout(view_of(g), p, R, xfin, p.y.p, res, o->greedy != 0, st);
 }
 
-ReadoutView view_of(const qh_graph *g) {
-    ReadoutView v;
-    v.n = g->n;
-    v.n_comp = g->n_comp;
-    v.n_chunks = g->n_chunks;
-    v.m_ptr = g->m_ptr.p;
-    v.m_col = g->m_col.p;
-    v.m_val = g->m_val.p;
-    v.comp = g->comp.p;
-    v.comp_first = g->comp_first.p;
-    v.comp_order = g->comp_order.p;
-    v.chunk_begin = g->chunk_begin.p;
-    v.chunk_end = g->chunk_end.p;
-    v.comp_chunk_ptr = g->comp_chunk_ptr.p;
-    v.eps = g->greedy_eps;
-    return v;
-}
 
-// Signs, FP64 cuts per replica and component, per-component selection, greedy rounds and
-// the cut of the final spins, for any graph laid out as a ReadoutView.
-void readout(const ReadoutView &g, SolvePlan &p, int R, const float *xfin, const float *yfin, qh_result *res,
-             bool greedy, hipStream_t st, bool finish) {
-    const int64_t n = g.n;
-    const int64_t nR = n * R;
-
-    // signs + NaN watchdog
-    QH_HIP(hipMemsetAsync(p.counter.p, 0, 4 * sizeof(int32_t), st));
-    if (nR) {
-        hipLaunchKernelGGL(k_signs, dim3(grid_for(nR)), dim3(256), 0, st, n, R, xfin, yfin, p.spins.p,
-                           p.counter.p + 1);
-        QH_CHECK_LAUNCH();
-    }
-    if (res->all_spins && nR)
-        QH_HIP(hipMemcpyAsync(res->all_spins, p.spins.p, nR, hipMemcpyDeviceToDevice, st));
-    // FP64 cuts per replica and component
-    const int64_t nc = g.n_comp;
-    if (nc) {
-        hipLaunchKernelGGL(k_cut_chunks, dim3((unsigned)std::min<int64_t>(g.n_chunks, 1 << 20)), dim3(256), 0, st,
-                           g.n_chunks, R, g.chunk_begin, g.chunk_end, g.comp_order, g.m_ptr,
-                           g.m_col, g.m_val, p.spins.p, p.part.p);
-        hipLaunchKernelGGL(k_cut_reduce, dim3((unsigned)std::min<int64_t>(nc, 1 << 20)), dim3(256), 0, st, nc, R,
-                           g.comp_chunk_ptr, p.part.p, p.cut_rc.p);
-        hipLaunchKernelGGL(k_select, dim3(grid_for(nc)), dim3(256), 0, st, nc, R, p.cut_rc.p, p.best_r.p);
-        QH_CHECK_LAUNCH();
-    }
-    if (nc) {
-        hipLaunchKernelGGL(k_replica_totals, dim3(grid_for(R)), dim3(256), 0, st, nc, R, p.cut_rc.p, res->cuts);
-        hipLaunchKernelGGL(k_selected_total, dim3(1), dim3(256), 0, st, nc, p.cut_rc.p, p.best_r.p,
-                           res->selected_cut ? res->selected_cut : res->best_cut);
-        QH_CHECK_LAUNCH();
-    } else {
-        QH_HIP(hipMemsetAsync(res->cuts, 0, R * sizeof(double), st));
-        QH_HIP(hipMemsetAsync(res->selected_cut ? res->selected_cut : res->best_cut, 0, sizeof(double), st));
-    }
-    if (res->cut_rc && nc)
-        QH_HIP(hipMemcpyAsync(res->cut_rc, p.cut_rc.p, nc * R * sizeof(double), hipMemcpyDeviceToDevice, st));
-    if (res->best_replica && nc)
-        QH_HIP(hipMemcpyAsync(res->best_replica, p.best_r.p, nc * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-    if (n) {
-        hipLaunchKernelGGL(k_best_spins, dim3(grid_for(n)), dim3(256), 0, st, n, R, g.comp, g.comp_first,
-                           p.best_r.p, p.spins.p, res->best_spins);
-        QH_CHECK_LAUNCH();
-    }
-    int32_t rounds = 0;
-    if (greedy && n && nc) {
-        for (int it = 0; it < 100000; ++it) {
-            hipLaunchKernelGGL(k_gain, dim3(grid_for(n)), dim3(256), 0, st, n, g.m_ptr, g.m_col, g.m_val,
-                               res->best_spins, p.gain.p);
-            QH_HIP(hipMemsetAsync(p.counter.p, 0, sizeof(int32_t), st));
-            hipLaunchKernelGGL(k_pick, dim3(grid_for(n)), dim3(256), 0, st, n, g.m_ptr, g.m_col, p.gain.p,
-                               g.eps, g.eps_v, p.flag.p, p.counter.p);
-            QH_CHECK_LAUNCH();
-            int32_t cnt = 0;
-            QH_HIP(hipMemcpyAsync(&cnt, p.counter.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            QH_HIP(hipStreamSynchronize(st));
-            if (cnt == 0) break;
-            hipLaunchKernelGGL(k_apply_flips, dim3(grid_for(n)), dim3(256), 0, st, n, p.flag.p, res->best_spins);
-            QH_CHECK_LAUNCH();
-            ++rounds;
-        }
-    }
-    // cut of the final spins
-    if (nc) {
-        hipLaunchKernelGGL(k_cut_chunks, dim3((unsigned)std::min<int64_t>(g.n_chunks, 1 << 20)), dim3(64), 0, st,
-                           g.n_chunks, 1, g.chunk_begin, g.chunk_end, g.comp_order, g.m_ptr,
-                           g.m_col, g.m_val, res->best_spins, p.part1.p);
-        hipLaunchKernelGGL(k_cut_reduce, dim3((unsigned)std::min<int64_t>(nc, 1 << 20)), dim3(64), 0, st, nc, 1,
-                           g.comp_chunk_ptr, p.part1.p, p.cut1.p);
-        hipLaunchKernelGGL(k_selected_total, dim3(1), dim3(256), 0, st, nc, p.cut1.p, (const int32_t *)nullptr,
-                           res->best_cut);
-        QH_CHECK_LAUNCH();
-    } else {
-        QH_HIP(hipMemsetAsync(res->best_cut, 0, sizeof(double), st));
-    }
-    if (res->greedy_rounds)
-        QH_HIP(hipMemcpyAsync(res->greedy_rounds, &rounds, sizeof(int32_t), hipMemcpyHostToDevice, st));
-    if (!finish) return;
-    int32_t bad = 0;
-    QH_HIP(hipMemcpyAsync(&bad, p.counter.p + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    QH_HIP(hipStreamSynchronize(st));
-    if (bad) fail(QH_ENUMERIC, "non-finite spin or momentum in the final state");
-}
 
 }  // namespace qh

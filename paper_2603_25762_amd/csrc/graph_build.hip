@@ -8,7 +8,10 @@
 #include <cstring>
 #include <numeric>
 
+#include <rocprim/rocprim.hpp>
+
 #include "formats.h"
+
 #include "internal.h"
 
 namespace qh {
@@ -31,6 +34,101 @@ __global__ void k_gather_i8(int64_t n, const int64_t *__restrict__ idx, const in
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x)
         dst[t] = src[idx[t]];
+}
+
+// ---------------------------------------------------------------------------
+// device structure pass of read graphs: validation, coverage lists, components
+// ---------------------------------------------------------------------------
+
+// Per fragment: frag_ptr non-decreasing, SNP indices in range and strictly ascending,
+// alleles 0/1.  err[k] = lowest offending fragment + 1 for check k (0 when none).
+__global__ void k_validate_frags(int64_t F, const int64_t *__restrict__ fp, const int32_t *__restrict__ snp,
+                                 const uint8_t *__restrict__ allele, int32_t n_snp, int64_t nobs,
+                                 unsigned long long *__restrict__ err) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = fp[f], e = fp[f + 1];
+        const unsigned long long tag = (unsigned long long)f + 1;
+        if (e < b || b < 0 || e > nobs) { atomicMin(&err[0], tag); continue; }
+        for (int64_t t = b; t < e; ++t) {
+            const int32_t j = snp[t];
+            if (j < 0 || j >= n_snp) atomicMin(&err[1], tag);
+            else if (t > b && j <= snp[t - 1]) atomicMin(&err[2], tag);
+            if (allele[t] > 1) atomicMin(&err[3], tag);
+        }
+    }
+}
+
+__global__ void k_obs_frag(int64_t F, const int64_t *__restrict__ fp, int32_t *__restrict__ obs_frag,
+                           int32_t *__restrict__ obs_idx) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t t = fp[f]; t < fp[f + 1]; ++t) {
+            obs_frag[t] = (int32_t)f;
+            obs_idx[t] = (int32_t)t;
+        }
+}
+
+// cov_ptr[j] = first position of SNP j in the SNP-sorted observations (lower bound)
+__global__ void k_cov_ptr(int32_t S, int64_t nobs, const int32_t *__restrict__ sorted_snp,
+                          int64_t *__restrict__ cov_ptr) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j <= S; j += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = nobs;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sorted_snp[mid] < j) lo = mid + 1;
+            else hi = mid;
+        }
+        cov_ptr[j] = lo;
+    }
+}
+
+__global__ void k_cov_fill(int64_t nobs, const int32_t *__restrict__ sorted_obs, const int32_t *__restrict__ obs_frag,
+                           const int8_t *__restrict__ M, int32_t *__restrict__ cov_frag, int8_t *__restrict__ cov_M) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nobs; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t t = sorted_obs[p];
+        cov_frag[p] = obs_frag[t];
+        cov_M[p] = M[t];
+    }
+}
+
+// Union-find with lock-free hooking: a root is hooked under a smaller root by CAS, so the
+// root of every tree is its smallest vertex.  Parent reads bypass stale cache lines.
+__device__ inline int32_t duf_parent(int32_t *p, int32_t x) {
+    return __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int32_t duf_root(int32_t *p, int32_t x) {
+    int32_t y = duf_parent(p, x);
+    while (y != x) {
+        x = y;
+        y = duf_parent(p, x);
+    }
+    return x;
+}
+
+__global__ void k_uf_init(int64_t n, int32_t *__restrict__ p) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+// fragments that share SNP j are linked along its coverage list
+__global__ void k_uf_link(int32_t S, const int64_t *__restrict__ cov_ptr, const int32_t *__restrict__ cov_frag,
+                          int32_t *p) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < S; j += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t q = cov_ptr[j] + 1; q < cov_ptr[j + 1]; ++q) {
+            int32_t a = cov_frag[q - 1], b = cov_frag[q];
+            while (true) {
+                a = duf_root(p, a);
+                b = duf_root(p, b);
+                if (a == b) break;
+                if (a < b) { const int32_t t = a; a = b; b = t; }
+                if (atomicCAS(p + a, a, b) == a) break;   // a was a root and now hangs under b
+            }
+        }
+}
+
+__global__ void k_uf_flatten(int64_t n, int32_t *p) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = duf_root(p, (int32_t)i);
 }
 
 // Eqs. (2)-(3): every ordered pair of fragments covering SNP column j adds its
@@ -478,6 +576,7 @@ void upload_components(qh_graph *g, const std::vector<int32_t> &comp, int64_t n_
     g->n_chunks = (int64_t)ccomp.size();
     g->comp_first.alloc(n_comp);
     g->comp_first.upload(first.data(), n_comp, st);
+    g->n_ord = (int64_t)order.size();
     g->comp_order.alloc(order.size());
     g->comp_order.upload(order.data(), order.size(), st);
     g->chunk_comp.alloc(ccomp.size());
@@ -581,51 +680,76 @@ void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStrea
     if (F > 46340) fail(QH_EUNSUPPORTED, "dense read graphs are limited to 46340 fragments");
     g->n = F;
     g->integer = true;
-    HostFrags h = fetch_and_validate(r, S, false, st);
-    int64_t nobs = h.fp[F];
-
-    // per-SNP coverage lists, fragments ascending
-    std::vector<int64_t> cov_ptr(S + 1, 0), cov_obs(nobs);
-    std::vector<int32_t> cov_frag(nobs);
-    for (int64_t t = 0; t < nobs; ++t) cov_ptr[h.snp[t] + 1]++;
-    for (int32_t j = 0; j < S; ++j) cov_ptr[j + 1] += cov_ptr[j];
-    {
-        std::vector<int64_t> fill(cov_ptr.begin(), cov_ptr.end() - 1);
-        for (int64_t f = 0; f < F; ++f)
-            for (int64_t t = h.fp[f]; t < h.fp[f + 1]; ++t) {
-                int64_t p = fill[h.snp[t]]++;
-                cov_frag[p] = (int32_t)f;
-                cov_obs[p] = t;
-            }
+    // observations and validation on the device (only the error words come back)
+    int64_t nobs = 0;
+    if (F > 0) QH_HIP(hipMemcpyAsync(&nobs, r->frag_ptr + F, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    int64_t fp0 = 0;
+    if (F > 0) QH_HIP(hipMemcpyAsync(&fp0, r->frag_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    QH_HIP(hipStreamSynchronize(st));
+    if (fp0 != 0) fail(QH_EINVAL, "frag_ptr[0] must be 0");
+    if (nobs < 0) fail(QH_EINVAL, "frag_ptr decreases");
+    if (nobs > INT32_MAX) fail(QH_EUNSUPPORTED, "more than 2^31 observations");
+    if (F > 0) {
+        DevBuf<unsigned long long> err(4);
+        QH_HIP(hipMemsetAsync(err.p, 0xFF, 4 * sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_validate_frags, dim3(grid_for(F)), dim3(256), 0, st, F, r->frag_ptr, r->snp, r->allele,
+                           S, nobs, err.p);
+        QH_CHECK_LAUNCH();
+        unsigned long long eh[4];
+        QH_HIP(hipMemcpyAsync(eh, err.p, sizeof(eh), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipStreamSynchronize(st));
+        if (eh[0] != ~0ull) fail(QH_EINVAL, "frag_ptr decreases at fragment %llu", eh[0] - 1);
+        if (eh[1] != ~0ull) fail(QH_EINVAL, "fragment %llu: SNP index out of range", eh[1] - 1);
+        if (eh[2] != ~0ull) fail(QH_EINVAL, "fragment %llu: SNP indices not strictly ascending", eh[2] - 1);
+        if (eh[3] != ~0ull) fail(QH_EINVAL, "fragment %llu: allele must be 0 or 1", eh[3] - 1);
     }
-    // components: fragments sharing a SNP are linked
+
+    // encode, then per-SNP coverage lists (fragments ascending): a stable sort of the
+    // observations by SNP keeps the fragment order inside every list
+    DevBuf<int8_t> M(nobs);
+    g->cov_ptr.alloc(S + 1);
+    g->cov_frag.alloc(nobs);
+    g->cov_M.alloc(nobs);
+    if (nobs) {
+        hipLaunchKernelGGL(k_encode, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, r->snp, r->allele,
+                           s->init_h1, M.p);
+        DevBuf<int32_t> obs_frag(nobs), obs_idx(nobs), keys_out(nobs), vals_out(nobs);
+        hipLaunchKernelGGL(k_obs_frag, dim3(grid_for(F)), dim3(256), 0, st, F, r->frag_ptr, obs_frag.p, obs_idx.p);
+        QH_CHECK_LAUNCH();
+        int bits = 1;
+        while (bits < 31 && (1ll << bits) < (int64_t)S) ++bits;
+        size_t tmp_bytes = 0;
+        QH_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, (const int32_t *)r->snp, keys_out.p,
+                                         (const int32_t *)obs_idx.p, vals_out.p, (size_t)nobs, 0, bits, st));
+        DevBuf<uint8_t> tmp(std::max<size_t>(tmp_bytes, 1));
+        QH_HIP(rocprim::radix_sort_pairs(tmp.p, tmp_bytes, (const int32_t *)r->snp, keys_out.p,
+                                         (const int32_t *)obs_idx.p, vals_out.p, (size_t)nobs, 0, bits, st));
+        hipLaunchKernelGGL(k_cov_ptr, dim3(grid_for(S + 1)), dim3(256), 0, st, S, nobs, keys_out.p, g->cov_ptr.p);
+        hipLaunchKernelGGL(k_cov_fill, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, vals_out.p, obs_frag.p, M.p,
+                           g->cov_frag.p, g->cov_M.p);
+        QH_CHECK_LAUNCH();
+        QH_HIP(hipStreamSynchronize(st));   // sort scratch is released on scope exit
+    } else {
+        g->cov_ptr.zero(st);
+    }
+
+    // components: fragments sharing a SNP are linked (device union-find, root = smallest
+    // fragment, so the labels follow the order of each component's first fragment)
     std::vector<int32_t> parent(F);
-    std::iota(parent.begin(), parent.end(), 0);
-    for (int32_t j = 0; j < S; ++j)
-        for (int64_t p = cov_ptr[j] + 1; p < cov_ptr[j + 1]; ++p) uf_union(parent, cov_frag[p - 1], cov_frag[p]);
+    if (F) {
+        DevBuf<int32_t> par(F);
+        hipLaunchKernelGGL(k_uf_init, dim3(grid_for(F)), dim3(256), 0, st, F, par.p);
+        if (S && nobs)
+            hipLaunchKernelGGL(k_uf_link, dim3(grid_for(S)), dim3(256), 0, st, S, g->cov_ptr.p, g->cov_frag.p, par.p);
+        hipLaunchKernelGGL(k_uf_flatten, dim3(grid_for(F)), dim3(256), 0, st, F, par.p);
+        QH_CHECK_LAUNCH();
+        QH_HIP(hipMemcpyAsync(parent.data(), par.p, F * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipStreamSynchronize(st));
+    }
     std::vector<int32_t> comp;
     int64_t n_comp = label_components(F, parent, comp);
     upload_components(g, comp, n_comp, st);
 
-    // encode and coverage lists on the device
-    DevBuf<int8_t> M(nobs);
-    if (nobs) {
-        hipLaunchKernelGGL(k_encode, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, r->snp, r->allele,
-                           s->init_h1, M.p);
-        QH_CHECK_LAUNCH();
-    }
-    g->cov_ptr.alloc(S + 1);
-    g->cov_ptr.upload(cov_ptr.data(), S + 1, st);
-    g->cov_frag.alloc(nobs);
-    g->cov_frag.upload(cov_frag.data(), nobs, st);
-    DevBuf<int64_t> cov_obs_d(nobs);
-    cov_obs_d.upload(cov_obs.data(), nobs, st);
-    g->cov_M.alloc(nobs);
-    if (nobs) {
-        hipLaunchKernelGGL(k_gather_i8, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, cov_obs_d.p, M.p,
-                           g->cov_M.p);
-        QH_CHECK_LAUNCH();
-    }
     g->init_h1.alloc(S);
     if (S) QH_HIP(hipMemcpyAsync(g->init_h1.p, s->init_h1, S, hipMemcpyDeviceToDevice, st));
 

@@ -114,6 +114,7 @@ struct SolvePlan {
     int pump_steps = 0;
     DevBuf<int8_t> spins;           // [n][R]
     DevBuf<double> part;            // [n_chunks][R] cut partials
+    DevBuf<double> rowcut;          // [n_ord][R] cut row sums (vertices in component order)
     DevBuf<double> cut_rc;          // [R][n_comp]
     DevBuf<int32_t> best_r;         // [n_comp]
     DevBuf<double> gain;            // [n]
@@ -153,6 +154,7 @@ struct qh_graph {
     int64_t n_comp = 0;
     qh::DevBuf<int32_t> comp_first;  // [n_comp] lowest vertex
     qh::DevBuf<int32_t> comp_order;  // vertices of non-singleton components sorted by (comp, vertex)
+    int64_t n_ord = 0;               // length of comp_order
     // reduction chunks over comp_order: (comp, begin, end) per chunk; chunks of a
     // component are consecutive and in vertex order
     qh::DevBuf<int32_t> chunk_comp, chunk_begin, chunk_end;
@@ -225,7 +227,7 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
 
 // What the readout needs of a graph (a single graph, or the block-diagonal union of a batch).
 struct ReadoutView {
-    int64_t n = 0, n_comp = 0, n_chunks = 0;
+    int64_t n = 0, n_comp = 0, n_chunks = 0, n_ord = 0;
     const int64_t *m_ptr = nullptr;
     const int32_t *m_col = nullptr;
     const double *m_val = nullptr;
@@ -239,6 +241,26 @@ ReadoutView view_of(const qh_graph *g);
 void readout(const ReadoutView &g, SolvePlan &p, int R, const float *xfin, const float *yfin, qh_result *res,
              bool greedy, hipStream_t st, bool finish = true);
 void alloc_readout_scratch(SolvePlan &p, int64_t n, int64_t n_comp, int64_t n_chunks, int R);
+
+// One block of a batched readout: its graph view, final state, plan scratch and result slots.
+struct ReadoutDesc {
+    int64_t n, n_comp, n_chunks, n_ord;
+    const int64_t *m_ptr;
+    const int32_t *m_col;
+    const double *m_val;
+    const int32_t *comp, *comp_first, *comp_order, *chunk_begin, *chunk_end, *comp_chunk_ptr;
+    double eps;
+    const float *x, *y;
+    int8_t *spins;
+    double *rowcut, *part, *cut_rc;
+    int32_t *best_r;
+    double *gain;
+    int8_t *flag;
+    double *part1, *cut1;
+    int8_t *best_spins;
+    double *cuts, *best_cut, *selected_cut;
+};
+void readout_batched(const std::vector<ReadoutDesc> &descs, int R, bool greedy, hipStream_t st);
 void plan_info(const qh_graph *g, int R, qh_plan_info *out);
 
 // phase.hip
@@ -267,10 +289,12 @@ struct BlockDesc {
 void launch_batched(int R, int workers, const BlockDesc *blocks, const int32_t *sched_ptr, const int32_t *sched,
                     int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
 int batched_workers_per_cu(int R);
-// per-step plan: init of every block, then one launch per step over the work items
-// (x = block, y = row tile of a dense block or group of four band blocks)
-void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, int64_t n_items, int steps,
-                          float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
+// per-step plan: init of every block, then per step one launch per class over that class's
+// work items (x = block, y = row tile of a dense block or group of four band blocks);
+// class c's items are items[class_ptr[c] .. class_ptr[c + 1])
+constexpr int kBatchClasses = 7;   // dense F32/F16/BF16/FP8, band F32/F16/BF16
+void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, const int64_t *class_ptr,
+                          int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
 SolvePlan &solve_plan(const qh_graph *g, int R, hipStream_t st);
 const float *linear_pump(SolvePlan &p, int steps, hipStream_t st);   // p_k = k / (steps - 1)
 

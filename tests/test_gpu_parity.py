@@ -612,8 +612,19 @@ def test_error_paths():
     assert e.value.status == qh.Status.EUNSUPPORTED
     bad = d["snp"].clone()
     bad[5], bad[6] = bad[6].item(), bad[5].item()        # not ascending inside fragment 0
+    for kind in ("read_signed", "snp_llr"):
+        with pytest.raises(qh.QhapError) as e:
+            qh.build_graph(d["frag_ptr"], bad, d["allele"], d["phred"], d["init_h1"], kind=kind)
+        assert e.value.status == qh.Status.EINVAL
+    al = d["allele"].clone()
+    al[17] = 2                                           # allele outside {0, 1}
     with pytest.raises(qh.QhapError) as e:
-        qh.build_graph(d["frag_ptr"], bad, d["allele"], d["phred"], d["init_h1"])
+        qh.build_graph(d["frag_ptr"], d["snp"], al, d["phred"], d["init_h1"])
+    assert e.value.status == qh.Status.EINVAL
+    fp = d["frag_ptr"].clone()
+    fp[3] = fp[4] + 1                                    # frag_ptr decreases at fragment 3
+    with pytest.raises(qh.QhapError) as e:
+        qh.build_graph(fp, d["snp"], d["allele"], d["phred"], d["init_h1"])
     assert e.value.status == qh.Status.EINVAL
     n = g.info()["n"]
     x = torch.zeros((n, 16), device="cuda")
