@@ -76,7 +76,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, replica_tile):
+def measured_traffic(kernel, replica_tile, depth):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None when
     there is none, it covers another replica tile, or the kernel sources changed since the
     counters were taken."""
@@ -89,7 +89,7 @@ def measured_traffic(kernel, replica_tile):
             vals[k.strip()] = v.strip()
     if vals.get("kernel") != kernel or vals.get("source_sha") != kernel_source_hash():
         return None
-    if int(vals.get("replica_tile", 0)) != replica_tile:
+    if int(vals.get("replica_tile", 0)) != replica_tile or int(vals.get("tiles_in_flight", 2)) != depth:
         return None
     return int(float(vals["hbm_bytes_per_launch"]))
 
@@ -136,11 +136,14 @@ def main():
         tune = g.plan_info(R)
         plan = tune["plan_used"]
         g.free()
+    # the tuned per-step tile and depth, passed explicitly to every job's fresh graph
+    kw = dict(replica_tile=tune["replica_tile"], tiles_in_flight=tune["tiles_in_flight"]) \
+        if tune is not None and plan == 1 else {}
 
     def job():
         g = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"],
                            kind="read_signed", dtype=a.dtype)
-        r = qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan)
+        r = qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan, **kw)
         h1, blk = qh.phase(g, r["best_spins"])
         return g, r, h1, blk
 
@@ -167,17 +170,17 @@ def main():
     # solve-only rate and the dominant kernel (the fused dense step) timed with HIP events on
     # the stream the library launches on (torch's current stream)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan)
+    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan, **kw)
     torch.cuda.synchronize()
     ev0.record()
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan)
+    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan, **kw)
     ev1.record()
     torch.cuda.synchronize()
     solve_ms = ev0.elapsed_time(ev1)
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), readout=False, plan=plan)
+    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), readout=False, plan=plan, **kw)
     torch.cuda.synchronize()
     ev0.record()
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), readout=False, plan=plan)
+    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), readout=False, plan=plan, **kw)
     ev1.record()
     torch.cuda.synchronize()
     loop_ms = ev0.elapsed_time(ev1)
@@ -209,17 +212,19 @@ def main():
     frac_m = ach_tf / PEAK_TFLOPS[a.dtype]
     frac_h = ach_gbs / PEAK_HBM_GBS
     rtile = (tune or {}).get("replica_tile") or 64
-    traffic = measured_traffic(kernel, rtile) if plan != 2 else None
+    depth = (tune or {}).get("tiles_in_flight") or 2
+    traffic = measured_traffic(kernel, rtile, depth) if plan != 2 else None
     if frac_m >= frac_h:
         roof = dict(bound="mfma", achieved=round(ach_tf, 2), peak=PEAK_TFLOPS[a.dtype], unit="TFLOP/s",
                     frac=round(frac_m, 4), traffic=traffic)
     else:
         roof = dict(bound="hbm", achieved=round(ach_gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(frac_h, 4), traffic=traffic)
-    roof.update(kernel=kernel, replica_tile=rtile if plan != 2 else None, launch_us=round(launch_us, 3),
+    roof.update(kernel=kernel, replica_tile=rtile if plan != 2 else None,
+                tiles_in_flight=depth if plan != 2 else None, launch_us=round(launch_us, 3),
                 steps_per_launch=launches_steps,
                 us_per_bsb_step=round(step_us, 3), flop_per_launch=flops, bytes_per_launch=bytes_,
-                mfma_frac=round(frac_m, 4), hbm_frac=round(frac_h, 4))
+                mfma_frac=round(frac_m, 4), hbm_frac=round(frac_h, 4), source_sha=kernel_source_hash())
 
     out = dict(metric=METRIC, value=value, unit="edge-updates/s", n_gpus=1, steps=a.steps,
                warmup=a.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True,
@@ -266,7 +271,7 @@ def bench_snp(a):
     porec = a.workload == "snp_porec"
     dtype = a.dtype or ("bf16" if porec else "f16")
     R, STEPS, DT, SEED = 64, (4000 if porec else 3000), 0.5, 7
-    band = 128 if porec else 0
+    band = 64 if porec else 0     # every read pair stays in the band, every Pore-C contact goes long-range
     torch.cuda.set_device(0)
     w = synth.snp_porec() if porec else synth.snp_chrom()
     d = {k: qh.to_device(v) for k, v in w.arrays().items()}
@@ -307,7 +312,7 @@ def bench_snp(a):
                steps=a.steps, warmup=a.warmup, ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype=dtype, data="synthetic",
                config=dict(workload=("snp_porec: snp_chrom plus 600,000 Pore-C contacts (distance ~ d^-1.1, "
-                                     "100 kb-100 Mb, Zipf anchors), band limit 128" if porec else
+                                     "100 kb-100 Mb, Zipf anchors), band limit 64" if porec else
                                      "snp_chrom: 250,000 het SNPs, 30x of 20 kb reads, 6% errors, Phred 7-40"),
                            n=n, nnz=nnz, longrange_nnz=lr, replicas=R, bsb_steps=STEPS, dt=DT,
                            storage="skyline band blocks" + (" + long-range packets" if lr else ""),

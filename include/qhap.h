@@ -177,6 +177,11 @@ typedef struct {
     int32_t replica_tile; /* dense graphs, per-step plan, R >= 64: replicas per workgroup
                             (16, 32 or 64); 0 = the autotuner's choice (plan 0) or 64.
                             Every tile gives bit-identical results. */
+    int32_t variant;     /* 0: ballistic SB (the coupling takes x_j); 1: discrete SB, the
+                            same update with sgn(x_j) (sgn(0) = +1) in the coupling term */
+    int32_t tiles_in_flight; /* dense per-step plan with 64 replicas per workgroup: stored
+                            tiles whose loads are issued together (2 or 4); 0 = the
+                            autotuner's choice or 2.  Bit-identical either way. */
 } qh_bsb_opts;
 
 /* Result buffers (all device, caller-owned; optional ones may be NULL).
@@ -213,8 +218,9 @@ qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *re
  * yet, 1 = one fused kernel per step, 2 = persistent (all steps in one cooperative
  * launch, state in registers, J in LDS).  With opts.plan = 0 the first solve of a
  * (graph, replicas) pair times the candidates on scratch state (64 steps each) and keeps
- * the fastest: the per-step kernel with 64, 32 and 16 replicas per workgroup (dense
- * graphs, R >= 64) and the persistent plan where it fits; us_per_step holds those
+ * the fastest: the per-step kernel with 64 (two or four tiles in flight), 32 and 16
+ * replicas per workgroup (dense graphs, R >= 64) and the persistent plan where it fits
+ * (every candidate gives bit-identical results); us_per_step holds those
  * measurements (0 when not measured).  Host output.
  * The persistent plan synchronises neighbouring workgroups with agent-scope
  * release / acquire on per-workgroup step counters. */
@@ -227,6 +233,7 @@ typedef struct {
     int32_t lds_bytes;          /* persistent plan: LDS per workgroup */
     float us_per_step[2];       /* autotuner: [per-step plan (best tile), persistent plan] */
     int32_t replica_tile;       /* per-step dense plan: replicas per workgroup in use */
+    int32_t tiles_in_flight;    /* per-step dense plan: stored tiles whose loads are issued together */
 } qh_plan_info;
 
 qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *out);

@@ -63,6 +63,7 @@ def _load():
         "or_splitmix64": (u64, [u64, u64]),
         "or_init": (None, [u64, i64, i32, P, P]),
         "or_bsb_run": (None, [i64, P, P, P, i32, i64, i64, P, dbl, dbl, dbl, P, P]),
+        "or_sb_run": (None, [i64, P, P, P, i32, i64, i64, P, dbl, dbl, dbl, P, P, i32]),
         "or_pump_linear": (None, [i64, P]),
         "or_signs": (None, [i64, P, P]),
         "or_cuts": (None, [i64, P, P, P, P, i64, i32, P, P]),
@@ -249,21 +250,24 @@ def pump_linear(steps: int) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 def bsb_run(g: CSR, x: np.ndarray, y: np.ndarray, pump: np.ndarray, dt: float, c0_: float,
-            a0: float = 1.0, k_begin: int = 0, k_end: Optional[int] = None):
-    """Advance (x, y) in place over steps [k_begin, k_end) of the pump table."""
+            a0: float = 1.0, k_begin: int = 0, k_end: Optional[int] = None, discrete: bool = False):
+    """Advance (x, y) in place over steps [k_begin, k_end) of the pump table.
+
+    ``discrete`` selects the discrete variant (dSB): the coupling uses sgn(x_j)."""
     assert x.dtype == np.float64 and y.dtype == np.float64
     assert x.flags.c_contiguous and y.flags.c_contiguous
     n, R = x.shape
     pump = _c(pump, np.float64)
     if k_end is None:
         k_end = pump.shape[0]
-    _load().or_bsb_run(g.n, _p(g.row_ptr), _p(g.col), _p(g.val), R, k_begin, k_end, _p(pump),
-                       dt, c0_, a0, _p(x), _p(y))
+    _load().or_sb_run(g.n, _p(g.row_ptr), _p(g.col), _p(g.val), R, k_begin, k_end, _p(pump),
+                      dt, c0_, a0, _p(x), _p(y), int(discrete))
     return x, y
 
 
 def bsb_step_dense(J: np.ndarray, x: np.ndarray, y: np.ndarray, p: float, dt: float, c0_: float,
-                   a0: float = 1.0, product_format: Optional[str] = None, walls: bool = True):
+                   a0: float = 1.0, product_format: Optional[str] = None, walls: bool = True,
+                   discrete: bool = False):
     """One bSB step in FP64 with a dense J, returning (x', y').
 
     ``product_format`` (None, "f16", "bf16") rounds the x that enters the coupling
@@ -273,7 +277,10 @@ def bsb_step_dense(J: np.ndarray, x: np.ndarray, y: np.ndarray, p: float, dt: fl
     from . import quant
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
-    xq = x if product_format is None else quant.round_to(product_format, x)
+    if discrete:
+        xq = np.where(x >= 0.0, 1.0, -1.0)       # sgn(x), sgn(0) = +1: exact in every format
+    else:
+        xq = x if product_format is None else quant.round_to(product_format, x)
     z = np.asarray(J, dtype=np.float64) @ xq
     y2 = y + (-(a0 - p) * x + c0_ * z) * dt
     x2 = x + a0 * y2 * dt
@@ -423,7 +430,7 @@ def refine(g: CSR, init_h1: np.ndarray, R: int, steps: int, dt: float = 0.5, see
 def solve(g: CSR, R: int, steps: int, dt: float = 0.5, c0_: Optional[float] = None,
           a0: float = 1.0, seed: int = 0, greedy_pass: bool = True, integer: bool = False,
           x0: Optional[np.ndarray] = None, y0: Optional[np.ndarray] = None,
-          pump: Optional[np.ndarray] = None) -> Dict[str, object]:
+          pump: Optional[np.ndarray] = None, discrete: bool = False) -> Dict[str, object]:
     comp, nc = components(g)
     if c0_ is None or c0_ <= 0:
         c0_ = c0(g)
@@ -434,7 +441,7 @@ def solve(g: CSR, R: int, steps: int, dt: float = 0.5, c0_: Optional[float] = No
         y = np.array(y0, dtype=np.float64, order="C")
     if pump is None:
         pump = pump_linear(steps)
-    bsb_run(g, x, y, pump, dt, c0_, a0)
+    bsb_run(g, x, y, pump, dt, c0_, a0, discrete=discrete)
     s = signs(x)
     cut = cuts(g, comp, nc, s)
     best, best_r = select(comp, nc, s, cut)

@@ -346,11 +346,13 @@ void or_init(uint64_t seed, int64_t n, int R, double *x, double *y) {
 /*   y_i <- y_i + [-(a0 - p_k) x_i + c0 sum_j J_ij x_j] dt                      */
 /*   x_i <- x_i + a0 y_i dt                                                     */
 /*   |x_i| > 1  =>  x_i <- sgn(x_i), y_i <- 0                                   */
-/* for k in [k_begin, k_end), all R replicas side by side.                      */
+/* for k in [k_begin, k_end), all R replicas side by side.  discrete = 1 gives  */
+/* the discrete variant of the same family (dSB): the coupling term uses        */
+/* sgn(x_j) (sgn(0) = +1) in place of x_j; everything else is unchanged.        */
 /* ------------------------------------------------------------------------- */
-void or_bsb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
-                int R, int64_t k_begin, int64_t k_end, const double *pump,
-                double dt, double c0, double a0, double *x, double *y) {
+void or_sb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+               int R, int64_t k_begin, int64_t k_end, const double *pump,
+               double dt, double c0, double a0, double *x, double *y, int discrete) {
     double *xnew = malloc((size_t)(n * R) * sizeof(double));
     double *z = malloc((size_t)(n * R) * sizeof(double));
     for (int64_t k = k_begin; k < k_end; ++k) {
@@ -362,7 +364,10 @@ void or_bsb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const dou
             for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
                 double J = val[e];
                 const double *xj = x + (int64_t)col[e] * R;
-                for (int r = 0; r < R; ++r) zi[r] += J * xj[r];
+                if (discrete)
+                    for (int r = 0; r < R; ++r) zi[r] += J * (xj[r] >= 0.0 ? 1.0 : -1.0);
+                else
+                    for (int r = 0; r < R; ++r) zi[r] += J * xj[r];
             }
             for (int r = 0; r < R; ++r) {
                 double yi = y[i * R + r] + (-(a0 - p) * x[i * R + r] + c0 * zi[r]) * dt;
@@ -375,6 +380,12 @@ void or_bsb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const dou
         memcpy(x, xnew, (size_t)(n * R) * sizeof(double));
     }
     free(xnew); free(z);
+}
+
+void or_bsb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                int R, int64_t k_begin, int64_t k_end, const double *pump,
+                double dt, double c0, double a0, double *x, double *y) {
+    or_sb_run(n, row_ptr, col, val, R, k_begin, k_end, pump, dt, c0, a0, x, y, 0);
 }
 
 /* Linear pump 0 -> 1 with both ends included. */

@@ -91,6 +91,7 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         d.x = p.xa.p;
         d.y = p.y.p;
         d.c0 = (float)(o->c0 > 0.0 ? o->c0 : g->c0_auto);
+        d.discrete = o->variant == 1;
         if (d.kind == 0) {
             d.n_rt = g->n_rt;
             d.t_ptr = g->t_ptr.p;

@@ -55,13 +55,17 @@ __global__ void k_pump_linear(int steps, float *__restrict__ p) {
 // 16-bit product copy of x in the layout [n_pad / 8][R][8]: eight consecutive
 // rows of one replica are contiguous, which is the B-operand register order of
 // v_mfma_f32_16x16x32_{f16,bf16}.
+// value of x_j that enters the coupling product: x_j, or sgn(x_j) (sgn(0) = +1) in the
+// discrete variant; +-1 is exact in every storage format
+__device__ inline float coupling_value(float x, int discrete) { return discrete ? (x >= 0.f ? 1.f : -1.f) : x; }
+
 template <bool BF16>
-__global__ void k_x_to_h(int64_t n, int R, const float *__restrict__ x, uint16_t *__restrict__ h) {
+__global__ void k_x_to_h(int64_t n, int R, const float *__restrict__ x, uint16_t *__restrict__ h, int discrete) {
     int64_t total = n * R;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         int64_t i = t / R, r = t - i * R;
-        float v = x[t];
+        const float v = coupling_value(x[t], discrete);
         h[((i >> 3) * R + r) * 8 + (i & 7)] = BF16 ? f32_to_bf16_rne(v) : f32_to_f16_rne(v);
     }
 }
@@ -70,7 +74,9 @@ struct StepArgs {
     float c0, dt, a0;
     const float *pump;
     int k;
+    int discrete;   // 1: the coupling takes sgn(x_j) (discrete variant), 0: x_j
 };
+
 
 __device__ inline void bsb_update(float z, float &x, float &y, float coef, const StepArgs &s) {
     float yn = y + (-coef * x + s.c0 * z) * s.dt;
@@ -104,10 +110,12 @@ __device__ inline int64_t xcd_remap(int64_t bid, int64_t G) {
 //  DT = QH_F32: v_mfma_f32_16x16x4f32 on the FP32 tile and FP32 x.
 // Product of stored tiles [t_beg, t_end) of one row tile with x, for the 16 rows of this
 // wave and RT = 16 NB replicas starting at r0.  Shared by the per-step and batched kernels.
-template <int DT, int NB>
+// U = stored tiles whose loads are in flight together (16/8-bit paths).
+template <int DT, int NB, int U = (NB >= 4 ? 2 : 4)>
 __device__ inline void dense_product(float4_t (&acc)[NB], int t_beg, int t_end, const int32_t *__restrict__ t_col,
                                      const uint8_t *__restrict__ t_val, const float *x_in,
-                                     const uint16_t *__restrict__ h_in, int64_t R, int64_t r0, int wave, int lane) {
+                                     const uint16_t *__restrict__ h_in, int64_t R, int64_t r0, int wave, int lane,
+                                     int discrete) {
     const int l16 = lane & 15, g4 = lane >> 4;
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
@@ -124,7 +132,8 @@ __device__ inline void dense_product(float4_t (&acc)[NB], int t_beg, int t_end, 
                     const float *xr = x_in + j * R + r0 + l16;
 #pragma unroll
                     for (int b = 0; b < NB; ++b)
-                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[e4], xr[b * 16], acc[b], 0, 0, 0);
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[e4], coupling_value(xr[b * 16], discrete),
+                                                                      acc[b], 0, 0, 0);
                 }
             }
         }
@@ -134,7 +143,6 @@ __device__ inline void dense_product(float4_t (&acc)[NB], int t_beg, int t_end, 
         // tile and x-copy loads is paid once per round.  Slots past t_end reload the last
         // tile with A = 0, which adds exactly zero; the MFMA order is the tile order, as in
         // the persistent kernel.
-        constexpr int U = NB >= 4 ? 2 : 4;
         for (int t = t_beg; t < t_end; t += U) {
             half8_t a[U][2], bv[U][2][NB];
 #pragma unroll
@@ -226,8 +234,8 @@ __device__ inline void dense_update(const float4_t (&acc)[NB], const float (&xo)
                 bsb_update(z, xv, yv, coef, sa);
                 y[idx] = yv;
                 x_out[idx] = xv;
-                if constexpr (DT == QH_BF16) hv[q] = f32_to_bf16_rne(xv);
-                else if constexpr (DT != QH_F32) hv[q] = f32_to_f16_rne(xv);
+                if constexpr (DT == QH_BF16) hv[q] = f32_to_bf16_rne(coupling_value(xv, sa.discrete));
+                else if constexpr (DT != QH_F32) hv[q] = f32_to_f16_rne(coupling_value(xv, sa.discrete));
             }
         }
         if constexpr (DT != QH_F32) {
@@ -240,7 +248,7 @@ __device__ inline void dense_update(const float4_t (&acc)[NB], const float (&xo)
     }
 }
 
-template <int DT, int NB>
+template <int DT, int NB, int U>
 __global__ __launch_bounds__(256) void k_dense_step(
     int64_t n, int R, int64_t n_rt, int64_t G, const int32_t *__restrict__ t_ptr,
     const int32_t *__restrict__ t_col, const uint8_t *__restrict__ t_val, const float *__restrict__ row_scale,
@@ -256,7 +264,7 @@ __global__ __launch_bounds__(256) void k_dense_step(
     float xo[NB][4], yo[NB][4];
     dense_load_state<NB>(xo, yo, rowbase, n, x_in, y, R, r0, lane);   // latency hides under the product
     float4_t acc[NB];
-    dense_product<DT, NB>(acc, t_ptr[rt], t_ptr[rt + 1], t_col, t_val, x_in, h_in, R, r0, wave, lane);
+    dense_product<DT, NB, U>(acc, t_ptr[rt], t_ptr[rt + 1], t_col, t_val, x_in, h_in, R, r0, wave, lane, sa.discrete);
     dense_update<DT, NB>(acc, xo, yo, rowbase, n, R, r0, lane, row_scale, x_out, y, h_out,
                          sa.a0 - sa.pump[sa.k], sa);
 }
@@ -278,7 +286,7 @@ template <int DT, int RT>
 __global__ __launch_bounds__(256) void k_hub_partials(
     int64_t n_chunks, int R, const int64_t *__restrict__ cbeg,
     const int64_t *__restrict__ cend, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
-    const float *__restrict__ x_in, float *__restrict__ part) {
+    const float *__restrict__ x_in, float *__restrict__ part, int discrete) {
     constexpr int RPW = 64 / RT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane / RT, rr = lane % RT;
@@ -287,7 +295,8 @@ __global__ __launch_bounds__(256) void k_hub_partials(
          c += (int64_t)gridDim.x * 4 * RPW) {
         float z = 0.f;
 #pragma unroll 4
-        for (int64_t e = cbeg[c]; e < cend[c]; ++e) z += ld_val<DT>(l_val, e) * x_in[(int64_t)l_col[e] * R + r];
+        for (int64_t e = cbeg[c]; e < cend[c]; ++e)
+            z += ld_val<DT>(l_val, e) * coupling_value(x_in[(int64_t)l_col[e] * R + r], discrete);
         part[c * R + r] = z;
     }
 }
@@ -301,7 +310,7 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_lr_packets(
     int64_t n_pk, int R, const int32_t *__restrict__ pk_ptr, const int64_t *__restrict__ cbeg,
     const int64_t *__restrict__ cend, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
-    const float *__restrict__ x_in, float *__restrict__ part) {
+    const float *__restrict__ x_in, float *__restrict__ part, int discrete) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t r = (int64_t)blockIdx.y * 64 + lane;
@@ -326,7 +335,7 @@ __global__ __launch_bounds__(256) void k_lr_packets(
             for (int k = 0; k < 8; ++k) {
                 const int32_t jj = j + k < 63 ? j + k : 63;      // lanes past cnt hold column 0
                 vv[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_val), jj));
-                xv[k] = x_in[(int64_t)__builtin_amdgcn_readlane(my_col, jj) * R + r];
+                xv[k] = coupling_value(x_in[(int64_t)__builtin_amdgcn_readlane(my_col, jj) * R + r], discrete);
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -371,7 +380,7 @@ __global__ __launch_bounds__(256) void k_sky_step(
         float z = 0.f;
         const float *xc = x_in + (int64_t)lo * R + r;
 #pragma unroll 8
-        for (int e = 0; e < len; ++e) z += ld_val<DT>(s_val, off + e) * xc[(int64_t)e * R];
+        for (int e = 0; e < len; ++e) z += ld_val<DT>(s_val, off + e) * coupling_value(xc[(int64_t)e * R], sa.discrete);
         if (row_chunk_ptr)
             for (int c = row_chunk_ptr[u]; c < row_chunk_ptr[u + 1]; ++c) z += hub_part[(int64_t)c * R + r];
         const int64_t idx = u * R + r;
@@ -399,6 +408,13 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
     const int32_t L = bb_lo[blk], W = bb_w[blk];
     const int64_t off = bb_off[blk];
     float z[RB], xo[RB], yo[RB];
+    // long-range rows: the chunk range of every row (lanes 0..RB load row_chunk_ptr once),
+    // issued first so that the band loop never waits on it
+    int32_t my_cp = 0;
+    if (row_chunk_ptr) {
+        const int lane = threadIdx.x & 63;
+        if (lane <= RB && blk * RB + lane <= n) my_cp = row_chunk_ptr[blk * RB + lane];
+    }
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
         z[i] = 0.f;
@@ -409,19 +425,33 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
     const float *xc = x_in + (int64_t)L * R + r;
 #pragma unroll 4
     for (int32_t j = 0; j < W; ++j) {
-        const float xj = active ? xc[(int64_t)j * R] : 0.f;
+        const float xj = active ? coupling_value(xc[(int64_t)j * R], sa.discrete) : 0.f;
         const int64_t e0 = off + (int64_t)j * RB;
 #pragma unroll
         for (int i = 0; i < RB; ++i) z[i] += ld_val<DT>(bb_val, e0 + i) * xj;
     }
     if (!active) return;
+    // the first chunk partial of every long-range row, all sixteen loads in flight together
+    float p0[RB];
+    if (row_chunk_ptr) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int32_t cb = __builtin_amdgcn_readlane(my_cp, i), ce = __builtin_amdgcn_readlane(my_cp, i + 1);
+            p0[i] = (blk * RB + i < n && cb < ce) ? hub_part[(int64_t)cb * R + r] : 0.f;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
         const int64_t u = blk * RB + i;
         if (u >= n) break;
         float zi = z[i];
-        if (row_chunk_ptr)                     // long-range rows: chunk partials, in order
-            for (int c = row_chunk_ptr[u]; c < row_chunk_ptr[u + 1]; ++c) zi += hub_part[(int64_t)c * R + r];
+        if (row_chunk_ptr) {                   // long-range rows: chunk partials, in order
+            const int32_t cb = __builtin_amdgcn_readlane(my_cp, i), ce = __builtin_amdgcn_readlane(my_cp, i + 1);
+            if (cb < ce) {
+                zi += p0[i];
+                for (int c = cb + 1; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
+            }
+        }
         const int64_t idx = u * R + r;
         float xv = xo[i], yv = yo[i];
         bsb_update(zi, xv, yv, coef, sa);
@@ -461,8 +491,10 @@ __device__ inline void block_init(const BlockDesc &B, uint64_t seed, int tid) {
         const float xv = (float)(0.2 * ((double)(sm64_draw(seed, c) >> 11) * 0x1.0p-53) - 0.1);
         B.x[t] = xv;
         B.y[t] = (float)(0.2 * ((double)(sm64_draw(seed, c + 1) >> 11) * 0x1.0p-53) - 0.1);
-        if (B.kind == 0 && B.dtype != QH_F32)
-            B.h0[((i >> 3) * R + r) * 8 + (i & 7)] = B.dtype == QH_BF16 ? f32_to_bf16_rne(xv) : f32_to_f16_rne(xv);
+        if (B.kind == 0 && B.dtype != QH_F32) {
+            const float cv = coupling_value(xv, B.discrete);
+            B.h0[((i >> 3) * R + r) * 8 + (i & 7)] = B.dtype == QH_BF16 ? f32_to_bf16_rne(cv) : f32_to_f16_rne(cv);
+        }
     }
     __syncthreads();
 }
@@ -486,7 +518,7 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
         float *xb = B.x, *yb = B.y;
         block_init<R>(B, seed, tid);
         const bool dense16 = B.kind == 0 && B.dtype != QH_F32;
-        StepArgs sa{B.c0, dt, a0, pump, 0};
+        StepArgs sa{B.c0, dt, a0, pump, 0, B.discrete};
         float *cur = xb, *oth = B.xs;
         for (int s = 0; s < steps; ++s) {
             sa.k = s;
@@ -501,7 +533,8 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
                     float4_t acc[NB];
                     dense_load_state<NB>(xo, yo, rowbase, n, xin, yb, R, 0, lane);
 #define QH_BD(DTV)                                                                                              \
-    dense_product<DTV, NB>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, xin, hin, R, 0, wave, lane);  \
+    dense_product<DTV, NB>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, xin, hin, R, 0, wave, lane,   \
+                           sa.discrete);                                                                     \
     dense_update<DTV, NB>(acc, xo, yo, rowbase, n, R, 0, lane, B.row_scale, xout, yb, hout, coef, sa)
                     switch (B.dtype) {
                         case QH_F32: QH_BD(QH_F32); break;
@@ -550,7 +583,7 @@ __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restric
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int2 I = items[xcd_remap(blockIdx.x, n_items)];
     const BlockDesc &B = blocks[I.x];
-    const StepArgs sa{B.c0, dt, a0, pump, k};
+    const StepArgs sa{B.c0, dt, a0, pump, k, B.discrete};
     const float coef = a0 - pump[k];
     const int cur = k & 1;
     const int64_t n = B.n;
@@ -565,7 +598,8 @@ __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restric
         float xo[NB][4], yo[NB][4];
         float4_t acc[NB];
         dense_load_state<NB>(xo, yo, rowbase, n, xin, B.y, R, 0, lane);
-        dense_product<DT, NB>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, xin, hin, R, 0, wave, lane);
+        dense_product<DT, NB>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, xin, hin, R, 0, wave, lane,
+                              sa.discrete);
         dense_update<DT, NB>(acc, xo, yo, rowbase, n, R, 0, lane, B.row_scale, xout, B.y, hout, coef, sa);
     } else {
         const int64_t bb = (int64_t)I.y * 4 + wave;
@@ -710,15 +744,16 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
         float *xout = cur ? p.xa.p : p.xb.p;
         const uint16_t *hin = cur ? p.hb.p : p.ha.p;
         uint16_t *hout = cur ? p.ha.p : p.hb.p;
-#define QH_DENSE(DTV, NBV)                                                                                  \
-    hipLaunchKernelGGL((k_dense_step<DTV, NBV>), dim3((unsigned)G), dim3(256), 0, st, n, R, g->n_rt, G,         \
+#define QH_DENSE(DTV, NBV, UV)                                                                              \
+    hipLaunchKernelGGL((k_dense_step<DTV, NBV, UV>), dim3((unsigned)G), dim3(256), 0, st, n, R, g->n_rt, G,     \
                        g->t_ptr.p, g->t_col.p, g->t_val.p, g->row_scale.p,                                   \
                        DTV == QH_F32 ? xin : p.xa.p, DTV == QH_F32 ? xout : p.xa.p, p.y.p, hin, hout, sa)
-#define QH_DENSE_NB(DTV)                      \
-    do {                                      \
-        if (RT == 16) QH_DENSE(DTV, 1);       \
-        else if (RT == 32) QH_DENSE(DTV, 2);  \
-        else QH_DENSE(DTV, 4);                \
+#define QH_DENSE_NB(DTV)                                  \
+    do {                                                  \
+        if (RT == 16) QH_DENSE(DTV, 1, 4);                \
+        else if (RT == 32) QH_DENSE(DTV, 2, 4);           \
+        else if (p.run_depth == 4) QH_DENSE(DTV, 4, 4);   \
+        else QH_DENSE(DTV, 4, 2);                         \
     } while (0)
         switch (g->dtype) {
             case QH_F32: QH_DENSE_NB(QH_F32); break;
@@ -744,11 +779,11 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
     hipLaunchKernelGGL((k_hub_partials<DTV, RTV>), dim3((unsigned)grid_for(g->n_hub_chunks, 4 * (64 / RTV), 4096), \
                                                         (unsigned)(R / RTV)),                                       \
                        dim3(256), 0, st, g->n_hub_chunks, R, g->hub_chunk_beg.p, g->hub_chunk_end.p, g->l_col.p,   \
-                       g->l_val.p, xin, p.hub_part.p)
+                       g->l_val.p, xin, p.hub_part.p, sa.discrete)
 #define QH_PK(DTV)                                                                                              \
     hipLaunchKernelGGL((k_lr_packets<DTV>), dim3((unsigned)grid_for(g->n_lr_pk, 4, 1 << 20), (unsigned)(R / 64)),  \
                        dim3(256), 0, st, g->n_lr_pk, R, g->lr_pk_ptr.p, g->hub_chunk_beg.p, g->hub_chunk_end.p,     \
-                       g->l_col.p, g->l_val.p, xin, p.hub_part.p)
+                       g->l_col.p, g->l_val.p, xin, p.hub_part.p, sa.discrete)
 #define QH_SKY(DTV, RTV)                                                                                       \
     hipLaunchKernelGGL((k_sky_step<DTV, RTV>), grid, dim3(256), 0, st, n, R, rows_per_wg, nblk, g->s_off.p,    \
                        g->s_lo.p, g->s_len.p, g->s_val.p, lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, \
@@ -790,6 +825,7 @@ static int run_steps(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, cons
     sa.dt = (float)o->dt;
     sa.a0 = (float)a0;
     sa.pump = pump;
+    sa.discrete = o->variant == 1;
     int cur = 0;
     for (int k = kb; k < ke; ++k) {
         sa.k = k;
@@ -799,19 +835,19 @@ static int run_steps(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, cons
     return cur;
 }
 
-static void x_to_h(const qh_graph *g, SolvePlan &p, int64_t n, int R, hipStream_t st) {
+static void x_to_h(const qh_graph *g, SolvePlan &p, int64_t n, int R, int discrete, hipStream_t st) {
     const int64_t nR = n * R;
     if (!nR) return;
     if (g->dtype == QH_BF16)
-        hipLaunchKernelGGL(k_x_to_h<true>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p);
+        hipLaunchKernelGGL(k_x_to_h<true>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p, discrete);
     else
-        hipLaunchKernelGGL(k_x_to_h<false>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p);
+        hipLaunchKernelGGL(k_x_to_h<false>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p, discrete);
     QH_CHECK_LAUNCH();
 }
 
 // Steps [kb, ke) in one cooperative launch; the state is in p.xa / p.y / p.ha.
 static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, double c0, double dt, double a0,
-                           int kb, int ke, hipStream_t st) {
+                           int kb, int ke, int discrete, hipStream_t st) {
     PersistPlan &pp = *p.pp;
     QH_HIP(hipMemsetAsync(pp.flags.p, 0, pp.flags.bytes(), st));
     PersistArgs pa{};
@@ -840,6 +876,7 @@ static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, d
     pa.dt = (float)dt;
     pa.a0 = (float)a0;
     pa.pump = pump;
+    pa.discrete = discrete;
     pa.lds_j_bytes = pp.lds_j_bytes;
     pa.max_polls = (int64_t)1 << 27;
     launch_persistent(g, pp, pa, st);
@@ -858,13 +895,17 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
     const int R = p.R;
     const int nt = std::min(o->steps, 64);
     const bool pers_ok = p.pp && p.pp->ok;
-    std::vector<int> cands;                 // replica tiles of the per-step kernel, then 0 = persistent
-    if (R >= 64) cands = {64, 32, 16};
+    // per-step candidates (replica tile, tiles in flight for 64-replica tiles: 64 + depth 4
+    // is coded as 65), then 0 = persistent
+    std::vector<int> cands;
+    if (R >= 64) cands = {64, 65, 32, 16};
     else cands = {R};
     if (pers_ok) cands.push_back(0);
     p.tuned_plan = 1;
     p.tuned_rt = cands[0];
+    p.tuned_depth = 2;
     p.run_rt = R >= 64 ? 64 : R;
+    p.run_depth = 2;
     if (cands.size() == 1) return;          // nothing to choose
     hipEvent_t e0, e1;
     QH_HIP(hipEventCreate(&e0));
@@ -872,23 +913,27 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
     float best = 0.0f, best_step = 0.0f;
     bool first = true;
     for (int cand : cands) {
-        if (cand) p.run_rt = cand;
+        if (cand) {
+            p.run_rt = cand == 65 ? 64 : cand;
+            p.run_depth = cand == 65 ? 4 : 2;
+        }
         float ms = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {   // the first repetition warms caches and code
             hipLaunchKernelGGL(k_init, dim3(grid_for(n * R)), dim3(256), 0, st, (uint64_t)0x5eed, n, R, p.xa.p,
                                p.y.p);
             QH_CHECK_LAUNCH();
-            if (!x_pingpong(g)) x_to_h(g, p, n, R, st);
+            if (!x_pingpong(g)) x_to_h(g, p, n, R, o->variant == 1, st);
             QH_HIP(hipEventRecord(e0, st));
             if (cand) run_steps(g, p, o, pump, c0, a0, 0, nt, st);
-            else run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, st);
+            else run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, o->variant == 1, st);
             QH_HIP(hipEventRecord(e1, st));
             QH_HIP(hipEventSynchronize(e1));
         }
         QH_HIP(hipEventElapsedTime(&ms, e0, e1));
         if (cand && (best_step == 0.0f || ms < best_step)) {
             best_step = ms;
-            p.tuned_rt = cand;
+            p.tuned_rt = p.run_rt;
+            p.tuned_depth = p.run_depth;
             p.tuned_us[0] = ms * 1000.0f / nt;
         }
         if (!cand) p.tuned_us[1] = ms * 1000.0f / nt;
@@ -901,6 +946,7 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p.run_rt = p.tuned_rt;
+    p.run_depth = p.tuned_depth;
 }
 
 const float *linear_pump(SolvePlan &p, int steps, hipStream_t st) {
@@ -950,6 +996,8 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     }
     // replica tile of the per-step dense kernel: the caller's, else the tuned one, else 64
     p.run_rt = R < 64 ? R : o->replica_tile ? o->replica_tile : p.tuned_rt ? p.tuned_rt : 64;
+    p.run_depth = o->tiles_in_flight ? o->tiles_in_flight
+                                     : (!o->replica_tile && p.tuned_rt == p.run_rt) ? p.tuned_depth : 2;
     if (o->plan == 2 && !persistent)
         fail(QH_EUNSUPPORTED, "the persistent plan does not apply to this graph and replica count");
     // initial state into xa / y (after any tuning, which uses the same buffers)
@@ -964,15 +1012,16 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
             hipLaunchKernelGGL(k_copy_state_in, dim3(grid_for(nR)), dim3(256), 0, st, n, R, res->y, p.y.p);
             QH_CHECK_LAUNCH();
         }
-        if (dense16) x_to_h(g, p, n, R, st);
+        if (dense16) x_to_h(g, p, n, R, o->variant == 1, st);
     };
     load_state();
     if (ke > kb && n > 0) p.last_plan = persistent ? 2 : 1;
     if (persistent) {
-        run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, st);
+        run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, o->variant == 1, st);
     } else if (ke > kb && n > 0) {
         if (o->use_graph) {
-            auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R, p.run_rt);
+            auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R,
+                                       (p.run_rt * 8 + p.run_depth) * 2 + (o->variant == 1));
             if (!p.exec || p.graph_key != key) {
                 if (p.exec) { (void)hipGraphExecDestroy(p.exec); p.exec = nullptr; }
                 if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }

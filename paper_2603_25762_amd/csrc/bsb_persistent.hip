@@ -190,8 +190,9 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
                     if constexpr (DT == QH_FP8_ROWSCALE) z *= sc[ti][q];
                     pbsb_update(z, xs[ti][b][q], ys[ti][b][q], coef, a.c0, a.dt, a.a0);
                     const bool live = rowbase + q < a.n;
-                    if constexpr (DT == QH_BF16) hv[q] = live ? f32_to_bf16_rne(xs[ti][b][q]) : 0;
-                    else hv[q] = live ? f32_to_f16_rne(xs[ti][b][q]) : 0;
+                    const float cv = a.discrete ? (xs[ti][b][q] >= 0.f ? 1.f : -1.f) : xs[ti][b][q];
+                    if constexpr (DT == QH_BF16) hv[q] = live ? f32_to_bf16_rne(cv) : 0;
+                    else hv[q] = live ? f32_to_f16_rne(cv) : 0;
                 }
                 uint2 pk;
                 pk.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
@@ -404,6 +405,7 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out) {
         i.us_per_step[0] = p.tuned_us[0];
         i.us_per_step[1] = p.tuned_us[1];
         i.replica_tile = g->storage == QH_STORE_DENSE ? (R >= 64 ? p.run_rt : R) : 0;
+        i.tiles_in_flight = g->storage == QH_STORE_DENSE ? (R >= 64 && p.run_rt == 64 ? p.run_depth : 4) : 0;
     }
     *out = i;
 }

@@ -96,13 +96,17 @@ __device__ inline int32_t duf_parent(int32_t *p, int32_t x) {
     return __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Root with path splitting: every visited non-root is pointed at its grandparent.  Parents
+// only ever point at smaller indices (hooks and splits alike), so every walk ends, and a
+// split never touches a root, so it cannot race with a hook.
 __device__ inline int32_t duf_root(int32_t *p, int32_t x) {
-    int32_t y = duf_parent(p, x);
-    while (y != x) {
+    while (true) {
+        const int32_t y = duf_parent(p, x);
+        if (y == x) return x;
+        const int32_t z = duf_parent(p, y);
+        if (z != y) __hip_atomic_store(p + x, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         x = y;
-        y = duf_parent(p, x);
     }
-    return x;
 }
 
 __global__ void k_uf_init(int64_t n, int32_t *__restrict__ p) {
@@ -129,6 +133,119 @@ __global__ void k_uf_link(int32_t S, const int64_t *__restrict__ cov_ptr, const 
 __global__ void k_uf_flatten(int64_t n, int32_t *p) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = duf_root(p, (int32_t)i);
+}
+
+// ---------------------------------------------------------------------------
+// device structure pass of SNP graphs: kept observations, skyline extents,
+// long-range pair set, components
+// ---------------------------------------------------------------------------
+
+// kept observations (Phred > 3) per fragment; cnt has F + 1 entries (cnt[F] = 0) so that
+// its exclusive scan is the fragment pointer of the kept list
+__global__ void k_kept_count(int64_t F, const int64_t *__restrict__ fp, const uint8_t *__restrict__ phred,
+                             int64_t *__restrict__ cnt) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f <= F; f += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0;
+        if (f < F)
+            for (int64_t t = fp[f]; t < fp[f + 1]; ++t) c += phred[t] > 3;
+        cnt[f] = c;
+    }
+}
+
+__global__ void k_kept_fill(int64_t F, const int64_t *__restrict__ fp, const uint8_t *__restrict__ phred,
+                            const int64_t *__restrict__ kept_ptr, int64_t *__restrict__ kept_obs,
+                            int32_t *__restrict__ kept_frag) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q = kept_ptr[f];
+        for (int64_t t = fp[f]; t < fp[f + 1]; ++t)
+            if (phred[t] > 3) {
+                kept_obs[q] = t;
+                kept_frag[q] = (int32_t)f;
+                ++q;
+            }
+    }
+}
+
+// Per kept observation a of fragment f (SNP u = u_a): the pairs (a, b), a < b <= a + L with
+// L = floor(k (|S_f| - 1) / 10).  In-band pairs (v - u <= band_limit, or no limit) widen
+// the skyline: hi[u] >= the largest in-band v, lo[v] <= u; the others are long-range
+// (counted in pass 0, written as both directed keys u n + v and v n + u in pass 1).
+// Consecutive kept SNPs of a fragment with L >= 1 are linked for the components.
+__global__ void k_snp_structure(int64_t n_kept, const int64_t *__restrict__ kept_obs,
+                                const int32_t *__restrict__ kept_frag, const int64_t *__restrict__ kept_ptr,
+                                const int32_t *__restrict__ snp, int linkage_k, int32_t band_limit, int64_t n,
+                                int32_t *__restrict__ lo, int32_t *__restrict__ hi, int32_t *uf,
+                                unsigned long long *__restrict__ lr_count, uint64_t *__restrict__ lr_keys, int pass) {
+    for (int64_t kk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; kk < n_kept;
+         kk += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t f = kept_frag[kk];
+        const int64_t base = kept_ptr[f], ns = kept_ptr[f + 1] - base;
+        if (ns < 2) continue;
+        const int64_t L = (int64_t)linkage_k * (ns - 1) / 10;
+        if (L < 1) continue;
+        const int64_t a = kk - base;
+        const int32_t u = snp[kept_obs[kk]];
+        const int64_t bmax = a + L < ns - 1 ? a + L : ns - 1;
+        if (pass == 0) {
+            if (a > 0) {      // link to the previous kept SNP of the fragment
+                int32_t x = snp[kept_obs[kk - 1]], y = u;
+                while (true) {
+                    x = duf_root(uf, x);
+                    y = duf_root(uf, y);
+                    if (x == y) break;
+                    if (x < y) { const int32_t t = x; x = y; y = t; }
+                    if (atomicCAS(uf + x, x, y) == x) break;
+                }
+            }
+            int32_t vmax = -1;
+            unsigned long long nlr = 0;
+            for (int64_t b = a + 1; b <= bmax; ++b) {
+                const int32_t v = snp[kept_obs[base + b]];
+                if (band_limit == 0 || v - u <= band_limit) vmax = v;
+                else ++nlr;
+            }
+            if (vmax >= 0) atomicMax(hi + u, vmax);
+            // lo[u]: the smallest partner w < u in band among a' in [a - L, a)
+            const int64_t a0 = a - L > 0 ? a - L : 0;
+            for (int64_t b = a0; b < a; ++b) {
+                const int32_t w = snp[kept_obs[base + b]];
+                if (band_limit == 0 || u - w <= band_limit) { atomicMin(lo + u, w); break; }
+            }
+            if (nlr) atomicAdd(lr_count, nlr);
+        } else {
+            for (int64_t b = a + 1; b <= bmax; ++b) {
+                const int32_t v = snp[kept_obs[base + b]];
+                if (band_limit == 0 || v - u <= band_limit) continue;
+                const unsigned long long at = atomicAdd(lr_count, 2ull);
+                lr_keys[at] = (uint64_t)u * (uint64_t)n + (uint64_t)v;
+                lr_keys[at + 1] = (uint64_t)v * (uint64_t)n + (uint64_t)u;
+            }
+        }
+    }
+}
+
+__global__ void k_iota32(int64_t n, int32_t *__restrict__ p) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+// long-range CSR from the sorted, unique directed keys: l_ptr[u] = first key of row u
+__global__ void k_lr_csr(int64_t n, int64_t l_nnz, const uint64_t *__restrict__ keys, int64_t *__restrict__ l_ptr,
+                         int32_t *__restrict__ l_col) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n || i < l_nnz;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i <= n) {
+            const uint64_t key = (uint64_t)i * (uint64_t)n;
+            int64_t a = 0, b = l_nnz;
+            while (a < b) {
+                const int64_t m = (a + b) >> 1;
+                if (keys[m] < key) a = m + 1;
+                else b = m;
+            }
+            l_ptr[i] = a;
+        }
+        if (i < l_nnz) l_col[i] = (int32_t)(keys[i] % (uint64_t)n);
+    }
 }
 
 // Eqs. (2)-(3): every ordered pair of fragments covering SNP column j adds its
@@ -523,12 +640,6 @@ static int32_t uf_find(std::vector<int32_t> &p, int32_t x) {
     return x;
 }
 
-static void uf_union(std::vector<int32_t> &p, int32_t a, int32_t b) {
-    a = uf_find(p, a);
-    b = uf_find(p, b);
-    if (a == b) return;
-    if (a < b) p[b] = a; else p[a] = b;
-}
 
 int64_t label_components(int64_t n, std::vector<int32_t> &parent, std::vector<int32_t> &comp) {
     std::vector<int32_t> size(n, 0), label(n, -1);
@@ -590,34 +701,6 @@ void upload_components(qh_graph *g, const std::vector<int32_t> &comp, int64_t n_
     QH_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
 }
 
-struct HostFrags {
-    std::vector<int64_t> fp;
-    std::vector<int32_t> snp;
-    std::vector<uint8_t> allele, phred;
-};
-
-static HostFrags fetch_and_validate(const qh_reads *r, int32_t n_snp, bool need_phred, hipStream_t st) {
-    HostFrags h;
-    int64_t F = r->n_frag;
-    h.fp = F > 0 ? download(r->frag_ptr, F + 1, st) : std::vector<int64_t>{0};
-    if (h.fp[0] != 0) fail(QH_EINVAL, "frag_ptr[0] must be 0");
-    for (int64_t f = 0; f < F; ++f)
-        if (h.fp[f + 1] < h.fp[f]) fail(QH_EINVAL, "frag_ptr decreases at fragment %lld", (long long)f);
-    int64_t nobs = h.fp[F];
-    if (nobs > INT32_MAX) fail(QH_EUNSUPPORTED, "more than 2^31 observations");
-    h.snp = download(r->snp, nobs, st);
-    h.allele = download(r->allele, nobs, st);
-    if (need_phred) h.phred = download(r->phred, nobs, st);
-    for (int64_t f = 0; f < F; ++f)
-        for (int64_t t = h.fp[f]; t < h.fp[f + 1]; ++t) {
-            if (h.snp[t] < 0 || h.snp[t] >= n_snp)
-                fail(QH_EINVAL, "fragment %lld: SNP index %d out of range", (long long)f, h.snp[t]);
-            if (t > h.fp[f] && h.snp[t] <= h.snp[t - 1])
-                fail(QH_EINVAL, "fragment %lld: SNP indices not strictly ascending", (long long)f);
-            if (h.allele[t] > 1) fail(QH_EINVAL, "fragment %lld: allele must be 0 or 1", (long long)f);
-        }
-    return h;
-}
 
 // ---------------------------------------------------------------------------
 // read graph
@@ -674,13 +757,10 @@ static void pack_dense_storage(qh_graph *g, const int32_t *W, int negate, hipStr
     }
 }
 
-void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStream_t st) {
-    int64_t F = r->n_frag;
-    int32_t S = s->n_snp;
-    if (F > 46340) fail(QH_EUNSUPPORTED, "dense read graphs are limited to 46340 fragments");
-    g->n = F;
-    g->integer = true;
-    // observations and validation on the device (only the error words come back)
+// Observation count (frag_ptr[F]) and validation of the fragment CSR on the device; only
+// the count and four error words come back to the host.
+static int64_t validate_fragments(const qh_reads *r, int32_t S, hipStream_t st) {
+    const int64_t F = r->n_frag;
     int64_t nobs = 0;
     if (F > 0) QH_HIP(hipMemcpyAsync(&nobs, r->frag_ptr + F, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     int64_t fp0 = 0;
@@ -703,6 +783,17 @@ void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStrea
         if (eh[2] != ~0ull) fail(QH_EINVAL, "fragment %llu: SNP indices not strictly ascending", eh[2] - 1);
         if (eh[3] != ~0ull) fail(QH_EINVAL, "fragment %llu: allele must be 0 or 1", eh[3] - 1);
     }
+
+    return nobs;
+}
+
+void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStream_t st) {
+    int64_t F = r->n_frag;
+    int32_t S = s->n_snp;
+    if (F > 46340) fail(QH_EUNSUPPORTED, "dense read graphs are limited to 46340 fragments");
+    g->n = F;
+    g->integer = true;
+    const int64_t nobs = validate_fragments(r, S, st);
 
     // encode, then per-SNP coverage lists (fragments ascending): a stable sort of the
     // observations by SNP keeps the fragment order inside every list
@@ -798,50 +889,99 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
     g->n = n;
     g->integer = false;
     g->band_limit = band_limit;
-    HostFrags h = fetch_and_validate(r, n, true, st);
-    int64_t nobs = h.fp[F];
+    const int64_t nobs = validate_fragments(r, n, st);
 
     // kept observations (Phred > 3), per fragment in SNP order
-    std::vector<int64_t> kept_ptr(F + 1, 0), kept_obs;
-    std::vector<int32_t> kept_frag;
-    kept_obs.reserve(nobs);
-    kept_frag.reserve(nobs);
-    for (int64_t f = 0; f < F; ++f) {
-        kept_ptr[f] = (int64_t)kept_obs.size();
-        for (int64_t t = h.fp[f]; t < h.fp[f + 1]; ++t)
-            if (h.phred[t] > 3) { kept_obs.push_back(t); kept_frag.push_back((int32_t)f); }
+    DevBuf<int64_t> kept_ptr_d(F + 1);
+    int64_t n_kept = 0;
+    {
+        DevBuf<int64_t> kcnt(F + 1);
+        hipLaunchKernelGGL(k_kept_count, dim3(grid_for(F + 1)), dim3(256), 0, st, F, r->frag_ptr, r->phred, kcnt.p);
+        QH_CHECK_LAUNCH();
+        size_t tb = 0;
+        QH_HIP(rocprim::exclusive_scan(nullptr, tb, kcnt.p, kept_ptr_d.p, (int64_t)0, (size_t)(F + 1),
+                                       rocprim::plus<int64_t>(), st));
+        DevBuf<uint8_t> tmp(std::max<size_t>(tb, 1));
+        QH_HIP(rocprim::exclusive_scan(tmp.p, tb, kcnt.p, kept_ptr_d.p, (int64_t)0, (size_t)(F + 1),
+                                       rocprim::plus<int64_t>(), st));
+        QH_HIP(hipMemcpyAsync(&n_kept, kept_ptr_d.p + F, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipStreamSynchronize(st));
     }
-    kept_ptr[F] = (int64_t)kept_obs.size();
-    int64_t n_kept = kept_ptr[F];
+    DevBuf<int64_t> kept_obs_d(n_kept);
+    DevBuf<int32_t> kept_frag_d(n_kept);
+    if (n_kept) {
+        hipLaunchKernelGGL(k_kept_fill, dim3(grid_for(F)), dim3(256), 0, st, F, r->frag_ptr, r->phred, kept_ptr_d.p,
+                           kept_obs_d.p, kept_frag_d.p);
+        QH_CHECK_LAUNCH();
+    }
 
-    // structure: components, skyline extents, long-range pair set
-    std::vector<int32_t> parent(n);
-    std::iota(parent.begin(), parent.end(), 0);
-    std::vector<int32_t> lo(n), hi(n);
-    std::iota(lo.begin(), lo.end(), 0);
-    std::iota(hi.begin(), hi.end(), 0);
-    std::vector<uint64_t> lr_keys;
-    for (int64_t f = 0; f < F; ++f) {
-        int64_t base = kept_ptr[f], ns = kept_ptr[f + 1] - base;
-        if (ns < 2) continue;
-        int64_t L = (int64_t)linkage_k * (ns - 1) / 10;
-        if (L < 1) continue;
-        for (int64_t a = 0; a < ns; ++a) {
-            int32_t u = h.snp[kept_obs[base + a]];
-            if (a > 0) uf_union(parent, h.snp[kept_obs[base + a - 1]], u);
-            int64_t bmax = std::min(a + L, ns - 1);
-            for (int64_t b = a + 1; b <= bmax; ++b) {
-                int32_t v = h.snp[kept_obs[base + b]];
-                if (band_limit == 0 || v - u <= band_limit) {
-                    if (v > hi[u]) hi[u] = v;
-                    if (u < lo[v]) lo[v] = u;
-                } else {
-                    lr_keys.push_back((uint64_t)u * (uint64_t)n + (uint64_t)v);
-                    lr_keys.push_back((uint64_t)v * (uint64_t)n + (uint64_t)u);
-                }
-            }
+    // structure on the device: skyline extents, components, long-range pair set
+    std::vector<int32_t> lo(n), hi(n), parent(n);
+    int64_t l_nnz = 0;
+    {
+        DevBuf<int32_t> lo_d(n), hi_d(n), uf(n);
+        DevBuf<unsigned long long> lrc(1);
+        lrc.zero(st);
+        if (n) {
+            hipLaunchKernelGGL(k_iota32, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, lo_d.p);
+            hipLaunchKernelGGL(k_iota32, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, hi_d.p);
+            hipLaunchKernelGGL(k_iota32, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, uf.p);
+            QH_CHECK_LAUNCH();
+        }
+        if (n_kept) {
+            hipLaunchKernelGGL(k_snp_structure, dim3(grid_for(n_kept)), dim3(256), 0, st, n_kept, kept_obs_d.p,
+                               kept_frag_d.p, kept_ptr_d.p, r->snp, linkage_k, (int32_t)band_limit, (int64_t)n,
+                               lo_d.p, hi_d.p, uf.p, lrc.p, (uint64_t *)nullptr, 0);
+            QH_CHECK_LAUNCH();
+        }
+        if (n) {
+            hipLaunchKernelGGL(k_uf_flatten, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, uf.p);
+            QH_CHECK_LAUNCH();
+        }
+        unsigned long long n_lr_pairs = 0;
+        QH_HIP(hipMemcpyAsync(&n_lr_pairs, lrc.p, sizeof(n_lr_pairs), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipMemcpyAsync(lo.data(), lo_d.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipMemcpyAsync(hi.data(), hi_d.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipMemcpyAsync(parent.data(), uf.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipStreamSynchronize(st));
+        // long-range keys u n + v of both directions, sorted and unique
+        const int64_t n_dir = 2 * (int64_t)n_lr_pairs;
+        g->l_ptr.alloc(n + 1);
+        if (n_dir) {
+            DevBuf<uint64_t> keys(n_dir), sorted(n_dir), uniq(n_dir);
+            lrc.zero(st);
+            hipLaunchKernelGGL(k_snp_structure, dim3(grid_for(n_kept)), dim3(256), 0, st, n_kept, kept_obs_d.p,
+                               kept_frag_d.p, kept_ptr_d.p, r->snp, linkage_k, (int32_t)band_limit, (int64_t)n,
+                               lo_d.p, hi_d.p, uf.p, lrc.p, keys.p, 1);
+            QH_CHECK_LAUNCH();
+            int bits = 1;
+            while (bits < 64 && ((uint64_t)1 << bits) < (uint64_t)n * (uint64_t)n) ++bits;
+            size_t tb = 0;
+            QH_HIP(rocprim::radix_sort_keys(nullptr, tb, keys.p, sorted.p, (size_t)n_dir, 0, bits, st));
+            DevBuf<uint8_t> tmp(std::max<size_t>(tb, 1));
+            QH_HIP(rocprim::radix_sort_keys(tmp.p, tb, keys.p, sorted.p, (size_t)n_dir, 0, bits, st));
+            DevBuf<size_t> n_unique(1);
+            size_t tu = 0;
+            QH_HIP(rocprim::unique(nullptr, tu, sorted.p, uniq.p, n_unique.p, (size_t)n_dir,
+                                   rocprim::equal_to<uint64_t>(), st));
+            DevBuf<uint8_t> tmp2(std::max<size_t>(tu, 1));
+            QH_HIP(rocprim::unique(tmp2.p, tu, sorted.p, uniq.p, n_unique.p, (size_t)n_dir,
+                                   rocprim::equal_to<uint64_t>(), st));
+            size_t nu = 0;
+            QH_HIP(hipMemcpyAsync(&nu, n_unique.p, sizeof(size_t), hipMemcpyDeviceToHost, st));
+            QH_HIP(hipStreamSynchronize(st));
+            l_nnz = (int64_t)nu;
+            g->l_col.alloc(l_nnz);
+            hipLaunchKernelGGL(k_lr_csr, dim3(grid_for(std::max<int64_t>(n + 1, l_nnz))), dim3(256), 0, st,
+                               (int64_t)n, l_nnz, uniq.p, g->l_ptr.p, g->l_col.p);
+            QH_CHECK_LAUNCH();
+            QH_HIP(hipStreamSynchronize(st));   // sort scratch is released on scope exit
+        } else {
+            g->l_ptr.zero(st);
+            g->l_col.alloc(0);
         }
     }
+    g->l_nnz = l_nnz;
     std::vector<int32_t> comp;
     int64_t n_comp = label_components(n, parent, comp);
     upload_components(g, comp, n_comp, st);
@@ -855,17 +995,8 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
         slots += len[u];
     }
     g->s_slots = slots;
-    std::sort(lr_keys.begin(), lr_keys.end());
-    lr_keys.erase(std::unique(lr_keys.begin(), lr_keys.end()), lr_keys.end());
-    int64_t l_nnz = (int64_t)lr_keys.size();
-    g->l_nnz = l_nnz;
     std::vector<int64_t> lptr(n + 1, 0);
-    std::vector<int32_t> lcol(l_nnz);
-    for (int64_t e = 0; e < l_nnz; ++e) {
-        lptr[lr_keys[e] / (uint64_t)n + 1]++;
-        lcol[e] = (int32_t)(lr_keys[e] % (uint64_t)n);
-    }
-    for (int32_t u = 0; u < n; ++u) lptr[u + 1] += lptr[u];
+    if (l_nnz) lptr = download(g->l_ptr.p, n + 1, st);
 
     // long-range rows split into chunks of at most kHubChunk entries (chunks tile the
     // long-range entries in row order); consecutive chunks grouped into packets of at most
@@ -908,15 +1039,6 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
     g->s_lo.upload(lo.data(), n, st);
     g->s_len.alloc(n);
     g->s_len.upload(len.data(), n, st);
-    g->l_ptr.alloc(n + 1);
-    g->l_ptr.upload(lptr.data(), n + 1, st);
-    g->l_col.alloc(l_nnz);
-    g->l_col.upload(lcol.data(), l_nnz, st);
-    DevBuf<int64_t> kept_obs_d(n_kept), kept_ptr_d(F + 1);
-    DevBuf<int32_t> kept_frag_d(n_kept);
-    kept_obs_d.upload(kept_obs.data(), n_kept, st);
-    kept_ptr_d.upload(kept_ptr.data(), F + 1, st);
-    kept_frag_d.upload(kept_frag.data(), n_kept, st);
     // Eq. (9) per integer Phred score
     double qconf_h[256];
     for (int q = 0; q < 256; ++q) qconf_h[q] = 1.0 - std::pow(10.0, -(double)q / 10.0);

@@ -32,6 +32,10 @@ void set_error(const char *fmt, ...);
 
 #define QH_CHECK_LAUNCH() QH_HIP(hipGetLastError())
 
+// Library device memory (memory.hip): size-classed blocks cached per device.
+void *device_alloc(size_t bytes);   // nullptr when the device is out of memory
+void device_free(void *p);
+
 // Owning device buffer.
 template <class T>
 struct DevBuf {
@@ -48,17 +52,17 @@ struct DevBuf {
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
-        release();
-        if (count == 0) count = 1;
-        if (hipMalloc((void **)&p, count * sizeof(T)) != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            fail(QH_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+        if (p) {   // the old block may still be read by queued work on any stream
+            QH_HIP(hipDeviceSynchronize());
+            release();
         }
+        if (count == 0) count = 1;
+        p = (T *)device_alloc(count * sizeof(T));
+        if (!p) fail(QH_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
         n = count;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        device_free(p);
         p = nullptr;
         n = 0;
     }
@@ -105,7 +109,9 @@ struct SolvePlan {
     bool sky_rows = false;             // SNP graphs: per-row skyline kernel instead of band blocks
     float tuned_us[2] = {0, 0};        // measured microseconds per step: per-step, persistent
     int tuned_rt = 0;                  // autotuner's replica tile for the per-step dense kernel
+    int tuned_depth = 2;               // autotuner's tiles in flight for 64-replica tiles (2 or 4)
     int run_rt = 64;                   // replica tile of the dense step launches (R >= 64)
+    int run_depth = 2;                 // tiles in flight of those launches
     int R = 0;
     int64_t n_pad = 0;
     DevBuf<float> xa, xb, y;        // fp32 state, [n_pad][R]
@@ -283,6 +289,7 @@ struct BlockDesc {
     const int32_t *bb_lo, *bb_w;
     const uint8_t *bb_val;
     float c0;
+    int32_t discrete;           // 1: the coupling takes sgn(x_j)
     uint16_t *h0, *h1;          // dense 16/8-bit: product copies [n_pad/8][R][8]
     float *xs;                  // dense f32 / band: second x buffer [n_pad][R]
 };

@@ -23,6 +23,7 @@ struct PersistArgs {
     int *err;                   // nonzero when a wait gave up
     float c0, dt, a0;
     const float *pump;
+    int discrete;               // 1: the 16-bit copy holds sgn(x) (discrete variant)
     int64_t lds_j_bytes;
     int64_t max_polls;
 };

@@ -140,7 +140,7 @@ def test_skyline_stored_values_bit_exact(dtype):
 
 # ----------------------------------------------------------------------------- one step
 
-def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, plan=0):
+def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, plan=0, discrete=False):
     n = J.shape[0]
     rng = np.random.default_rng(rng_seed)
     x0 = f32(rng.uniform(-1.0, 1.0, (n, R)))
@@ -153,11 +153,14 @@ def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, pl
     x = torch.tensor(x0, dtype=torch.float32, device="cuda").contiguous()
     y = torch.tensor(y0, dtype=torch.float32, device="cuda").contiguous()
     qh.bsb_solve(g, R, steps, dt=dt, c0=c0, pump=torch.tensor(pump, device="cuda"), init=False,
-                 x=x, y=y, step_begin=k, step_end=k + 1, readout=False, plan=plan)
+                 x=x, y=y, step_begin=k, step_end=k + 1, readout=False, plan=plan, discrete=discrete)
     xg, yg = cpu(x).astype(np.float64), cpu(y).astype(np.float64)
-    xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False)
-    xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True)
-    xq = x0 if product_format is None else quant.round_to(product_format, x0)
+    xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False, discrete=discrete)
+    xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True, discrete=discrete)
+    if discrete:
+        xq = np.ones_like(x0)
+    else:
+        xq = x0 if product_format is None else quant.round_to(product_format, x0)
     tol_x, tol_y = step_bounds(np.abs(J) @ np.abs(xq), x0, y0, p, dt, c0)
     ambiguous = np.abs(np.abs(xu) - 1.0) <= tol_x
     ok = ~ambiguous
@@ -178,6 +181,58 @@ def test_dense_one_step(dtype, R, plan):
     g = gpu_graph(w, "read_signed", dtype)
     J = stored_J(oracle_graph(w).dense(), dtype)
     _one_step_case(g, J, dtype, R, 100 + R, FMT[dtype], plan=plan)
+
+
+@pytest.mark.parametrize("plan", [1, 2])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "fp8"])
+@pytest.mark.parametrize("R", [32, 64])
+def test_dense_one_step_discrete(dtype, R, plan):
+    """Discrete variant: the coupling takes sgn(x_j) (sgn(0) = +1), on every dense path."""
+    if plan == 2 and dtype == "f32":
+        pytest.skip("the persistent plan is offered for 16- and 8-bit dense storage")
+    w = synth.read_small(13, n_snp=300, n_reads=150, span=(20, 60))
+    g = gpu_graph(w, "read_signed", dtype)
+    J = stored_J(oracle_graph(w).dense(), dtype)
+    _one_step_case(g, J, dtype, R, 700 + R, None, plan=plan, discrete=True)
+
+
+@pytest.mark.parametrize("plan", [0, 3])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_skyline_one_step_discrete(dtype, plan):
+    w = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
+    g = gpu_graph(w, "snp_llr", dtype, band_limit=100)
+    assert g.info()["longrange_nnz"] > 0
+    J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
+    _one_step_case(g, J, dtype, 64, 800, None, plan=plan, discrete=True)
+
+
+def test_discrete_whole_solves_match_oracle_and_plans():
+    """Discrete variant end to end: cut gap to the oracle's discrete solve, persistent =
+    per-step bit for bit, batched = single bit for bit."""
+    w = synth.read_tiny()
+    g = gpu_graph(w, "read_signed", "f16")
+    ro = oracle.solve(oracle_graph(w), 16, 1000, 0.5, seed=11, integer=True, discrete=True)
+    rs = qh.bsb_solve(g, 16, 1000, seed=11, discrete=True)
+    assert _gap(ro["best_cut"], float(cpu(rs["best_cut"])[0])) <= 1e-3
+    wm = synth.read_mhc(seed=78, n_snp=1500, n_reads=1000, region=500_000)
+    gm = gpu_graph(wm, "read_signed", "f16")
+    n = gm.info()["n"]
+    outs = []
+    for plan in (1, 2):
+        x = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+        y = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+        r = qh.bsb_solve(gm, 64, 300, seed=31, x=x, y=y, plan=plan, discrete=True)
+        outs.append((x, y, r))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    assert torch.equal(outs[0][2]["best_cut"], outs[1][2]["best_cut"])
+    ws = synth.snp_small(61, n_snp=400)
+    gs_ = gpu_graph(ws, "snp_llr", "bf16")
+    rb = qh.bsb_solve_batched([g, gs_], 32, 300, seed=9, discrete=True)
+    for b, gg in enumerate((g, gs_)):
+        r1 = qh.bsb_solve(gg, 32, 300, seed=9, discrete=True, plan=1)
+        assert torch.equal(rb["best_cut"][b:b + 1], r1["best_cut"])
+        lo, hi = int(rb["vertex_offset"][b]), int(rb["vertex_offset"][b + 1])
+        assert torch.equal(rb["best_spins"][lo:hi], r1["best_spins"])
 
 
 @pytest.mark.parametrize("dtype", ["f16", "bf16", "fp8"])
@@ -208,22 +263,26 @@ def test_replica_tiles_bit_exact(dtype):
     g = gpu_graph(w, "read_signed", dtype)
     n, R = g.info()["n"], 128
     out = []
-    for tile in (64, 32, 16):
+    for tile, depth in ((64, 2), (64, 4), (32, 0), (16, 0)):
         x = torch.empty((n, R), dtype=torch.float32, device="cuda")
         y = torch.empty((n, R), dtype=torch.float32, device="cuda")
-        r = qh.bsb_solve(g, R, 200, seed=5, x=x, y=y, plan=1, replica_tile=tile)
+        r = qh.bsb_solve(g, R, 200, seed=5, x=x, y=y, plan=1, replica_tile=tile, tiles_in_flight=depth)
         out.append((x, y, r))
     x = torch.empty((n, R), dtype=torch.float32, device="cuda")
     y = torch.empty((n, R), dtype=torch.float32, device="cuda")
     out.append((x, y, qh.bsb_solve(g, R, 200, seed=5, x=x, y=y, plan=0)))
     info = g.plan_info(R)
     assert info["replica_tile"] in (16, 32, 64) and info["us_per_step"][0] > 0
+    assert info["tiles_in_flight"] in (2, 4)
     xa, ya, ra = out[0]
     for xb, yb, rb in out[1:]:
         assert torch.equal(xa, xb) and torch.equal(ya, yb)
         assert torch.equal(ra["cuts"], rb["cuts"]) and torch.equal(ra["best_spins"], rb["best_spins"])
     with pytest.raises(qh.QhapError) as e:
         qh.bsb_solve(g, 32, 10, replica_tile=16)
+    assert e.value.status == qh.Status.EINVAL
+    with pytest.raises(qh.QhapError) as e:
+        qh.bsb_solve(g, 64, 10, tiles_in_flight=3)
     assert e.value.status == qh.Status.EINVAL
 
 

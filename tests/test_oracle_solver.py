@@ -252,3 +252,45 @@ def test_dense_step_helper_matches_c_step():
     pump = np.array([0.0, 0.37])
     oracle.bsb_run(g, x, y, pump, 0.5, oracle.c0(g), 1.0, 1, 2)
     assert np.allclose(x2, x, rtol=0, atol=1e-15) and np.allclose(y2, y, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- discrete variant (dSB)
+
+def test_dsb_step_by_hand_and_sign_of_zero():
+    """dSB takes sgn(x_j) in the coupling (sgn(0) = +1), the rest of the step unchanged."""
+    D = np.array([[0.0, 2.0, -1.0], [2.0, 0.0, 0.0], [-1.0, 0.0, 0.0]])
+    g = csr_from_dense(D)
+    x = np.array([[0.3], [0.0], [-0.2]])
+    y = np.array([[0.1], [0.0], [0.05]])
+    oracle.bsb_run(g, x, y, np.array([0.4]), dt=0.5, c0_=0.5, a0=1.0, discrete=True)
+    # vertex 0: z = 2 sgn(0) - sgn(-0.2) = 3 ; y = 0.1 + (-0.6*0.3 + 0.5*3)*0.5 = 0.76 ; x = 0.3 + 0.38
+    assert y[0, 0] == pytest.approx(0.76, abs=1e-15) and x[0, 0] == pytest.approx(0.68, abs=1e-15)
+    # vertex 1: z = 2 sgn(0.3) = 2 ; y = 0 + (0 + 0.5*2)*0.5 = 0.5 ; x = 0 + 0.25
+    assert y[1, 0] == pytest.approx(0.5, abs=1e-15) and x[1, 0] == pytest.approx(0.25, abs=1e-15)
+    # vertex 2: z = -sgn(0.3) = -1 ; y = 0.05 + (-0.6*-0.2 - 0.5)*0.5 = -0.14 ; x = -0.2 - 0.07
+    assert y[2, 0] == pytest.approx(-0.14, abs=1e-15) and x[2, 0] == pytest.approx(-0.27, abs=1e-15)
+
+
+def test_dsb_equals_bsb_without_coupling_and_dense_helper():
+    g0 = csr_from_dense(np.zeros((3, 3)))
+    xa, ya = oracle.init_state(4, 3, 8)
+    xb, yb = xa.copy(), ya.copy()
+    pump = oracle.pump_linear(50)
+    oracle.bsb_run(g0, xa, ya, pump, 0.5, 0.3, 1.0)
+    oracle.bsb_run(g0, xb, yb, pump, 0.5, 0.3, 1.0, discrete=True)
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    w = synth.read_small(32, n_snp=100, n_reads=30, span=(10, 30))
+    g = oracle.build_graph(w, "read_signed")
+    x, y = oracle.init_state(3, g.n, 4)
+    x2, y2 = oracle.bsb_step_dense(g.dense(), x, y, 0.37, 0.5, oracle.c0(g), 1.0, discrete=True)
+    oracle.bsb_run(g, x, y, np.array([0.0, 0.37]), 0.5, oracle.c0(g), 1.0, 1, 2, discrete=True)
+    assert np.allclose(x2, x, rtol=0, atol=1e-15) and np.allclose(y2, y, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed,n,integer", [(1, 10, True), (2, 14, True), (5, 14, False)])
+def test_dsb_greedy_hits_bruteforce_optimum(seed, n, integer):
+    D = random_graph(seed, n, 0.6, integer)
+    g = csr_from_dense(D)
+    opt, _ = bruteforce.maxcut(D)
+    r = oracle.solve(g, R=64, steps=1000, dt=0.5, seed=seed, integer=integer, discrete=True)
+    assert r["best_cut"] == pytest.approx(opt, abs=1e-9)
