@@ -171,9 +171,12 @@ typedef struct {
     int32_t greedy;      /* 1: greedy single-flip rounds on the selected spins */
     int32_t use_graph;   /* 1: replay the step loop from a captured hipGraph (cached per
                             graph and option set); 0: plain stream launches */
-    int32_t plan;        /* step-loop plan: 0 = autotuned; 1 = one fused kernel per step;
-                            2 = persistent (dense 16/8-bit graphs only); 3 = per-row skyline
-                            kernel instead of band blocks (SNP graphs) */
+    int32_t plan;        /* step-loop plan: 0 = autotuned; 1 = one fused kernel per step
+                            (the tuned kernel when there is one); 2 = persistent (dense
+                            16/8-bit graphs only).  SNP (skyline) graphs only: 3 = per-row
+                            kernel; 4 = band blocks on FMAs (bit-identical to 3); 5 = band
+                            blocks on MFMAs (four columns summed per MFMA: equal to 3-4 up
+                            to FP32 rounding).  Plan 0 on SNP graphs times 4 and 5 once. */
     int32_t replica_tile; /* dense graphs, per-step plan, R >= 64: replicas per workgroup
                             (16, 32 or 64); 0 = the autotuner's choice (plan 0) or 64.
                             Every tile gives bit-identical results. */
@@ -234,6 +237,8 @@ typedef struct {
     float us_per_step[2];       /* autotuner: [per-step plan (best tile), persistent plan] */
     int32_t replica_tile;       /* per-step dense plan: replicas per workgroup in use */
     int32_t tiles_in_flight;    /* per-step dense plan: stored tiles whose loads are issued together */
+    int32_t skyline_kernel;     /* SNP graphs: step kernel of the last solve: 3 rows, 4 band FMA, 5 band MFMA */
+    float skyline_us[2];        /* SNP autotuner: [band FMA, band MFMA] microseconds per step (0 = not timed) */
 } qh_plan_info;
 
 qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *out);

@@ -80,7 +80,8 @@ class _PlanInfo(ctypes.Structure):
                 ("replicas_per_group", ctypes.c_int32), ("groups", ctypes.c_int32),
                 ("workgroups_per_group", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("us_per_step", ctypes.c_float * 2), ("replica_tile", ctypes.c_int32),
-                ("tiles_in_flight", ctypes.c_int32)]
+                ("tiles_in_flight", ctypes.c_int32), ("skyline_kernel", ctypes.c_int32),
+                ("skyline_us", ctypes.c_float * 2)]
 
 
 class _BatchedResult(ctypes.Structure):
@@ -193,6 +194,7 @@ class Graph:
         _check(load().qh_solve_plan_info(self._h, replicas, ctypes.byref(pi)))
         d = {name: getattr(pi, name) for name, _ in _PlanInfo._fields_}
         d["us_per_step"] = list(pi.us_per_step)
+        d["skyline_us"] = list(pi.skyline_us)
         return d
 
     def free(self):

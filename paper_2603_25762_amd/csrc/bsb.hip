@@ -460,6 +460,92 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
     }
 }
 
+// The same band block on the matrix cores: a band block is a dense 16 x W matrix stored
+// column-major, which is exactly the A-operand order of v_mfma_f32_16x16x4f32 (lane l
+// holds row l % 16 of column l / 16), so four columns arrive with one 64-lane load; x rows
+// L + j .. L + j + 3 of 16 replicas are the B operand.  NB = 16-replica blocks per wave
+// (all 64 lanes busy for any replica count).  Values enter in FP32 (16-bit codes widened
+// exactly); the MFMA sums each group of four columns before adding it, so results match
+// the FMA kernels to FP32 rounding, not bit for bit.  Output: lane l owns rows
+// 4 (l / 16) .. + 3 of the block and replica r0 + 16 b + l % 16.
+template <int DT, int NB>
+__device__ inline void band_block_step_mfma(int64_t blk, int64_t n, int64_t R, int64_t r0,
+                                            const int64_t *__restrict__ bb_off, const int32_t *__restrict__ bb_lo,
+                                            const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
+                                            const int32_t *__restrict__ row_chunk_ptr,
+                                            const float *__restrict__ hub_part, const float *x_in, float *x_out,
+                                            float *y, float coef, const StepArgs &sa) {
+    constexpr int RB = kBandRows;
+    const int lane = threadIdx.x & 63, l16 = lane & 15, g4 = lane >> 4;
+    const int32_t L = bb_lo[blk], W = bb_w[blk];
+    const int64_t off = bb_off[blk];
+    const int64_t rowbase = blk * RB + 4 * g4;
+    int32_t my_cp = 0;
+    if (row_chunk_ptr && lane <= RB && blk * RB + lane <= n) my_cp = row_chunk_ptr[blk * RB + lane];
+    float xo[NB][4], yo[NB][4];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t u = rowbase + q;
+            xo[b][q] = u < n ? x_in[u * R + r0 + b * 16 + l16] : 0.f;
+            yo[b][q] = u < n ? y[u * R + r0 + b * 16 + l16] : 0.f;
+        }
+    float4_t acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
+    // columns j .. j + 15 per round: four MFMA K-steps with their loads in flight together
+    for (int32_t j = 0; j < W; j += 16) {
+        float av[4], bv[4][NB];
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            const int32_t col = j + kq * 4 + g4;
+            const bool in = col < W;
+            av[kq] = in ? ld_val<DT>(bb_val, off + (int64_t)col * RB + l16) : 0.f;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                bv[kq][b] = in ? coupling_value(x_in[(int64_t)(L + col) * R + r0 + b * 16 + l16], sa.discrete) : 0.f;
+        }
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kq], bv[kq][b], acc[b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t u = rowbase + q;
+        // chunk range of row u (row 4 g4 + q of the block): from lanes 4 g4 + q and + 1
+        const int32_t cb = __shfl(my_cp, 4 * g4 + q), ce = __shfl(my_cp, 4 * g4 + q + 1);
+        if (u >= n) continue;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int64_t r = r0 + b * 16 + l16;
+            float zi = acc[b][q];
+            if (row_chunk_ptr)
+                for (int c = cb; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
+            const int64_t idx = u * R + r;
+            float xv = xo[b][q], yv = yo[b][q];
+            bsb_update(zi, xv, yv, coef, sa);
+            y[idx] = yv;
+            x_out[idx] = xv;
+        }
+    }
+}
+
+template <int DT, int NB>
+__global__ __launch_bounds__(256) void k_band_step_mfma(
+    int64_t n, int R, int64_t n_bblk, int64_t G, const int64_t *__restrict__ bb_off,
+    const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
+    const int32_t *__restrict__ row_chunk_ptr, const float *__restrict__ hub_part,
+    const float *__restrict__ x_in, float *__restrict__ x_out, float *__restrict__ y, StepArgs sa) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t blk = xcd_remap(blockIdx.x, G) * 4 + wave;
+    if (blk >= n_bblk) return;
+    band_block_step_mfma<DT, NB>(blk, n, R, (int64_t)blockIdx.y * NB * 16, bb_off, bb_lo, bb_w, bb_val,
+                                 row_chunk_ptr, hub_part, x_in, x_out, y, sa.a0 - sa.pump[sa.k], sa);
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_band_step(
     int64_t n, int R, int64_t n_bblk, int64_t G, const int64_t *__restrict__ bb_off,
@@ -788,18 +874,38 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
     hipLaunchKernelGGL((k_sky_step<DTV, RTV>), grid, dim3(256), 0, st, n, R, rows_per_wg, nblk, g->s_off.p,    \
                        g->s_lo.p, g->s_len.p, g->s_val.p, lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, \
                        xout, p.y.p, sa)
-    const bool band = RT == 64 && g->n_bblk > 0 && !p.sky_rows;
+    // step kernel: band blocks on FMAs (64-replica tiles), band blocks on MFMAs, or per row
+    int sk = p.sky_kernel;
+    if (sk == kSkyBandFma && !(RT == 64 && g->n_bblk > 0)) sk = kSkyRows;
+    if (sk == kSkyBandMfma && g->n_bblk == 0) sk = kSkyRows;
     const int64_t GB = ceil_div(g->n_bblk, 4);
 #define QH_BAND(DTV)                                                                                            \
     hipLaunchKernelGGL((k_band_step<DTV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, R,      \
                        g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                          \
                        lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sa)
+#define QH_BANDM(DTV, NBV)                                                                                      \
+    hipLaunchKernelGGL((k_band_step_mfma<DTV, NBV>), dim3((unsigned)GB, (unsigned)(R / (NBV * 16))), dim3(256), 0, \
+                       st, n, R, g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                \
+                       lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sa)
+#define QH_LR(DTV)                                                      \
+    do {                                                                \
+        if (!lr) break;                                                 \
+        if (RT == 16) QH_HUB(DTV, 16);                                  \
+        else if (RT == 32) QH_HUB(DTV, 32);                             \
+        else QH_PK(DTV);                                                \
+    } while (0)
 #define QH_SKY_RT(DTV)                                                  \
     do {                                                                \
-        if (RT == 16) { if (lr) QH_HUB(DTV, 16); QH_SKY(DTV, 16); }     \
-        else if (RT == 32) { if (lr) QH_HUB(DTV, 32); QH_SKY(DTV, 32); } \
-        else if (band) { if (lr) QH_PK(DTV); QH_BAND(DTV); }            \
-        else { if (lr) QH_PK(DTV); QH_SKY(DTV, 64); }                   \
+        QH_LR(DTV);                                                     \
+        if (sk == kSkyBandMfma) {                                       \
+            if (RT == 16) QH_BANDM(DTV, 1);                             \
+            else if (RT == 32) QH_BANDM(DTV, 2);                        \
+            else QH_BANDM(DTV, 4);                                      \
+        } else if (sk == kSkyBandFma) {                                 \
+            QH_BAND(DTV);                                               \
+        } else if (RT == 16) QH_SKY(DTV, 16);                           \
+        else if (RT == 32) QH_SKY(DTV, 32);                             \
+        else QH_SKY(DTV, 64);                                           \
     } while (0)
     switch (g->dtype) {
         case QH_F32: QH_SKY_RT(QH_F32); break;
@@ -808,6 +914,8 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
         default: fail(QH_EUNSUPPORTED, "dtype not offered on skyline storage");
     }
 #undef QH_SKY_RT
+#undef QH_LR
+#undef QH_BANDM
 #undef QH_BAND
 #undef QH_SKY
 #undef QH_PK
@@ -949,6 +1057,46 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
     p.run_depth = p.tuned_depth;
 }
 
+// SNP graphs: time the two band kernels (64 steps each from a seeded state) and keep the
+// faster; the band FMA kernel needs 64-replica tiles.
+static void autotune_sky(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, const float *pump, double c0,
+                         double a0, hipStream_t st) {
+    const int64_t n = g->n;
+    const int R = p.R;
+    const int nt = std::min(o->steps, 64);
+    std::vector<int> cands;
+    if (R >= 64) cands.push_back(kSkyBandFma);
+    cands.push_back(kSkyBandMfma);
+    p.sky_tuned = true;
+    p.sky_best = cands[0];
+    if (g->n_bblk == 0) { p.sky_best = kSkyRows; return; }
+    hipEvent_t e0, e1;
+    QH_HIP(hipEventCreate(&e0));
+    QH_HIP(hipEventCreate(&e1));
+    float best = 0.0f;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        p.sky_kernel = cands[i];
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {   // the first repetition warms caches and code
+            hipLaunchKernelGGL(k_init, dim3(grid_for(n * R)), dim3(256), 0, st, (uint64_t)0x5eed, n, R, p.xa.p,
+                               p.y.p);
+            QH_CHECK_LAUNCH();
+            QH_HIP(hipEventRecord(e0, st));
+            run_steps(g, p, o, pump, c0, a0, 0, nt, st);
+            QH_HIP(hipEventRecord(e1, st));
+            QH_HIP(hipEventSynchronize(e1));
+        }
+        QH_HIP(hipEventElapsedTime(&ms, e0, e1));
+        p.sky_us[cands[i]] = ms * 1000.0f / nt;
+        if (i == 0 || ms < best) {
+            best = ms;
+            p.sky_best = cands[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
 const float *linear_pump(SolvePlan &p, int steps, hipStream_t st) {
     if (p.pump_steps != steps) {
         p.pump_lin.alloc(steps);
@@ -972,11 +1120,23 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     const float *pump = o->pump ? o->pump : linear_pump(p, o->steps, st);
     const int64_t nR = n * R;
     const bool dense16 = !x_pingpong(g);
-    if (p.sky_rows != (o->plan == 3)) {
-        // the captured step loop launches the other skyline kernel: drop it
-        p.sky_rows = o->plan == 3;
-        if (p.exec) { (void)hipGraphExecDestroy(p.exec); p.exec = nullptr; }
-        if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }
+    const bool dense = g->storage == QH_STORE_DENSE;
+    if (dense && o->plan >= 3) fail(QH_EINVAL, "plans 3-5 choose the step kernel of SNP (skyline) graphs");
+    if (!dense) {
+        // SNP graphs: plan 3 per-row kernel, 4 band blocks on FMAs, 5 band blocks on MFMAs;
+        // plan 0 times the two band kernels on this graph once, plan 1 keeps that choice
+        // (band FMAs when never tuned)
+        int want = o->plan == 3 ? kSkyRows : o->plan == 4 ? kSkyBandFma : o->plan == 5 ? kSkyBandMfma : -1;
+        if (want < 0) {
+            if (o->plan == 0 && !p.sky_tuned && ke > kb && n > 0) autotune_sky(g, p, o, pump, c0, a0, st);
+            want = p.sky_tuned ? p.sky_best : kSkyBandFma;
+        }
+        if (p.sky_kernel != want) {
+            // the captured step loop launches the other kernel: drop it
+            p.sky_kernel = want;
+            if (p.exec) { (void)hipGraphExecDestroy(p.exec); p.exec = nullptr; }
+            if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }
+        }
     }
 
     // the step loop: the persistent dense plan (plan 2), one fused kernel per step (plan 1,
@@ -984,7 +1144,6 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     int final_half = 0;
     bool persistent = false;
     const bool want_persistent = o->plan == 0 || o->plan == 2;
-    const bool dense = g->storage == QH_STORE_DENSE;
     if (dense && ke > kb && n > 0) {
         if (dense16 && want_persistent && !p.pp_tried) {
             p.pp = std::make_shared<PersistPlan>();

@@ -406,6 +406,14 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out) {
         i.us_per_step[1] = p.tuned_us[1];
         i.replica_tile = g->storage == QH_STORE_DENSE ? (R >= 64 ? p.run_rt : R) : 0;
         i.tiles_in_flight = g->storage == QH_STORE_DENSE ? (R >= 64 && p.run_rt == 64 ? p.run_depth : 4) : 0;
+        if (g->storage != QH_STORE_DENSE) {
+            int sk = p.sky_kernel;
+            if (sk == kSkyBandFma && !(R >= 64 && g->n_bblk > 0)) sk = kSkyRows;
+            if (sk == kSkyBandMfma && g->n_bblk == 0) sk = kSkyRows;
+            i.skyline_kernel = sk == kSkyRows ? 3 : sk == kSkyBandFma ? 4 : 5;
+            i.skyline_us[0] = p.sky_us[kSkyBandFma];
+            i.skyline_us[1] = p.sky_us[kSkyBandMfma];
+        }
     }
     *out = i;
 }

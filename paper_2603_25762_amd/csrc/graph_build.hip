@@ -114,20 +114,22 @@ __global__ void k_uf_init(int64_t n, int32_t *__restrict__ p) {
         p[i] = (int32_t)i;
 }
 
-// fragments that share SNP j are linked along its coverage list
-__global__ void k_uf_link(int32_t S, const int64_t *__restrict__ cov_ptr, const int32_t *__restrict__ cov_frag,
+// fragments that share a SNP are linked along its coverage list: one thread per position
+// q of the SNP-sorted observations links cov_frag[q - 1] and cov_frag[q] of the same SNP
+__global__ void k_uf_link(int64_t nobs, const int32_t *__restrict__ sorted_snp, const int32_t *__restrict__ cov_frag,
                           int32_t *p) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < S; j += (int64_t)gridDim.x * blockDim.x)
-        for (int64_t q = cov_ptr[j] + 1; q < cov_ptr[j + 1]; ++q) {
-            int32_t a = cov_frag[q - 1], b = cov_frag[q];
-            while (true) {
-                a = duf_root(p, a);
-                b = duf_root(p, b);
-                if (a == b) break;
-                if (a < b) { const int32_t t = a; a = b; b = t; }
-                if (atomicCAS(p + a, a, b) == a) break;   // a was a root and now hangs under b
-            }
+    for (int64_t q = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nobs;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        if (sorted_snp[q] != sorted_snp[q - 1]) continue;
+        int32_t a = cov_frag[q - 1], b = cov_frag[q];
+        while (true) {
+            a = duf_root(p, a);
+            b = duf_root(p, b);
+            if (a == b) break;
+            if (a < b) { const int32_t t = a; a = b; b = t; }
+            if (atomicCAS(p + a, a, b) == a) break;   // a was a root and now hangs under b
         }
+    }
 }
 
 __global__ void k_uf_flatten(int64_t n, int32_t *p) {
@@ -801,10 +803,12 @@ void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStrea
     g->cov_ptr.alloc(S + 1);
     g->cov_frag.alloc(nobs);
     g->cov_M.alloc(nobs);
+    DevBuf<int32_t> keys_out;   // SNP of every position of the sorted observations
     if (nobs) {
         hipLaunchKernelGGL(k_encode, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, r->snp, r->allele,
                            s->init_h1, M.p);
-        DevBuf<int32_t> obs_frag(nobs), obs_idx(nobs), keys_out(nobs), vals_out(nobs);
+        keys_out.alloc(nobs);
+        DevBuf<int32_t> obs_frag(nobs), obs_idx(nobs), vals_out(nobs);
         hipLaunchKernelGGL(k_obs_frag, dim3(grid_for(F)), dim3(256), 0, st, F, r->frag_ptr, obs_frag.p, obs_idx.p);
         QH_CHECK_LAUNCH();
         int bits = 1;
@@ -830,8 +834,9 @@ void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStrea
     if (F) {
         DevBuf<int32_t> par(F);
         hipLaunchKernelGGL(k_uf_init, dim3(grid_for(F)), dim3(256), 0, st, F, par.p);
-        if (S && nobs)
-            hipLaunchKernelGGL(k_uf_link, dim3(grid_for(S)), dim3(256), 0, st, S, g->cov_ptr.p, g->cov_frag.p, par.p);
+        if (nobs > 1)
+            hipLaunchKernelGGL(k_uf_link, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, keys_out.p, g->cov_frag.p,
+                               par.p);
         hipLaunchKernelGGL(k_uf_flatten, dim3(grid_for(F)), dim3(256), 0, st, F, par.p);
         QH_CHECK_LAUNCH();
         QH_HIP(hipMemcpyAsync(parent.data(), par.p, F * sizeof(int32_t), hipMemcpyDeviceToHost, st));

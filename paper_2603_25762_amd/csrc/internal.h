@@ -106,7 +106,10 @@ struct SolvePlan {
     bool pp_tried = false;
     int tuned_plan = 0;                // autotuner's choice for plan 0: 1 per-step, 2 persistent
     int last_plan = 0;                 // plan the last solve ran
-    bool sky_rows = false;             // SNP graphs: per-row skyline kernel instead of band blocks
+    int sky_kernel = 0;                // SNP graphs: kSkyBandFma, kSkyBandMfma or kSkyRows
+    bool sky_tuned = false;            // the band kernels have been timed on this graph
+    int sky_best = 0;                  // the faster band kernel
+    float sky_us[3] = {0, 0, 0};       // measured microseconds per step of each kernel
     float tuned_us[2] = {0, 0};        // measured microseconds per step: per-step, persistent
     int tuned_rt = 0;                  // autotuner's replica tile for the per-step dense kernel
     int tuned_depth = 2;               // autotuner's tiles in flight for 64-replica tiles (2 or 4)
@@ -217,6 +220,7 @@ struct qh_graph {
 namespace qh {
 
 constexpr int kBandRows = 16;       // rows per band block (one wave's accumulators)
+constexpr int kSkyBandFma = 0, kSkyBandMfma = 1, kSkyRows = 2;   // SNP step kernels
 constexpr int kHubChunk = 64;       // entries per hub partial
 
 // graph_build.hip

@@ -196,7 +196,7 @@ def test_dense_one_step_discrete(dtype, R, plan):
     _one_step_case(g, J, dtype, R, 700 + R, None, plan=plan, discrete=True)
 
 
-@pytest.mark.parametrize("plan", [0, 3])
+@pytest.mark.parametrize("plan", [3, 4, 5])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_skyline_one_step_discrete(dtype, plan):
     w = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
@@ -286,7 +286,7 @@ def test_replica_tiles_bit_exact(dtype):
     assert e.value.status == qh.Status.EINVAL
 
 
-@pytest.mark.parametrize("plan", [0, 3])          # 0: band blocks (R % 64 == 0); 3: per-row skyline
+@pytest.mark.parametrize("plan", [0, 3, 4, 5])   # autotuned; per row; band FMA (R % 64 == 0); band MFMA
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("R", [16, 32, 64, 128])
 def test_skyline_one_step(dtype, R, plan):
@@ -308,7 +308,7 @@ def test_band_kernel_equals_row_kernel_bit_exact(dtype, case):
     g = gpu_graph(w, "snp_llr", dtype, band_limit=band)
     n, R = g.info()["n"], 128
     out = []
-    for plan in (0, 3):
+    for plan in (4, 3):          # band blocks on FMAs; per-row kernel
         x = torch.empty((n, R), dtype=torch.float32, device="cuda")
         y = torch.empty((n, R), dtype=torch.float32, device="cuda")
         r = qh.bsb_solve(g, R, 200, seed=33, x=x, y=y, plan=plan)
@@ -316,6 +316,35 @@ def test_band_kernel_equals_row_kernel_bit_exact(dtype, case):
     (xa, ya, ra), (xb, yb, rb) = out
     assert torch.equal(xa, xb) and torch.equal(ya, yb)
     assert torch.equal(ra["best_spins"], rb["best_spins"]) and torch.equal(ra["best_cut"], rb["best_cut"])
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_band_mfma_whole_solve_and_tuner(dtype):
+    """Band blocks on MFMAs over a whole solve: the final cut tracks the oracle's, the
+    autotuner reports both band kernels, and plans 4 and 5 agree to FP32 rounding."""
+    w = synth.snp_small(27, n_snp=1800)
+    g = gpu_graph(w, "snp_llr", dtype)
+    go = oracle_graph(w, "snp_llr")
+    ro = oracle.solve(go, 64, 600, 0.5, seed=3)
+    r5 = qh.bsb_solve(g, 64, 600, seed=3, plan=5)
+    assert g.plan_info(64)["skyline_kernel"] == 5
+    assert _gap(ro["best_cut"], float(cpu(r5["best_cut"])[0])) <= 1e-3
+    n = g.info()["n"]
+    xs = []
+    for plan in (4, 5):
+        x = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+        y = torch.empty((n, 64), dtype=torch.float32, device="cuda")
+        qh.bsb_solve(g, 64, 3, seed=3, x=x, y=y, plan=plan, readout=False)
+        xs.append(cpu(x))
+    assert np.allclose(xs[0], xs[1], rtol=0, atol=1e-5)
+    g2 = gpu_graph(w, "snp_llr", dtype)
+    qh.bsb_solve(g2, 64, 100, seed=3, plan=0, readout=False)
+    info = g2.plan_info(64)
+    assert info["skyline_kernel"] in (4, 5) and min(info["skyline_us"]) > 0
+    gd = gpu_graph(synth.read_tiny())
+    with pytest.raises(qh.QhapError) as e:      # skyline plans on a dense graph
+        qh.bsb_solve(gd, 16, 10, plan=5)
+    assert e.value.status == qh.Status.EINVAL
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
