@@ -40,6 +40,8 @@ def parse():
                          "every job here builds a fresh graph, so the default launches the steps directly)")
     ap.add_argument("--plan", type=int, default=0,
                     help="0 auto (persistent when it applies), 1 one kernel per step, 2 persistent")
+    ap.add_argument("--persistent-sync", type=int, default=0, choices=[0, 1, 2],
+                    help="persistent plan: 0 tuned, 1 cache-wide fences, 2 device-coherent accesses")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -102,8 +104,8 @@ def main():
         calibrate_copy()
         return
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {a.gpus} is not offered (replica sharding across GPUs "
-              "is a design note, not part of this build)", file=sys.stderr)
+        print(f"bench.py drives one GPU; --gpus {a.gpus} is not offered (sharding replicas across GPUs "
+              "is described in the design notes only)", file=sys.stderr)
         sys.exit(2)
     if a.workload in ("snp_chrom", "snp_porec"):
         return bench_snp(a)
@@ -138,9 +140,15 @@ def main():
         tune = g.plan_info(R)
         plan = tune["plan_used"]
         g.free()
-    # the tuned per-step tile and depth, passed explicitly to every job's fresh graph
-    kw = dict(replica_tile=tune["replica_tile"], tiles_in_flight=tune["tiles_in_flight"]) \
-        if tune is not None and plan == 1 else {}
+    # the tuned per-step tile and depth, or the tuned persistent variant, passed explicitly to
+    # every job's fresh graph
+    kw = {}
+    if tune is not None and plan == 1:
+        kw = dict(replica_tile=tune["replica_tile"], tiles_in_flight=tune["tiles_in_flight"])
+    elif tune is not None and plan == 2:
+        kw = dict(persistent_sync=tune["persistent_sync"])
+    elif plan == 2:
+        kw = dict(persistent_sync=a.persistent_sync)
 
     def job():
         g = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"],
@@ -199,7 +207,7 @@ def main():
         launch_us = loop_ms * 1e3
         flops = 2.0 * tiles * 4096 * R * STEPS
         bytes_ = tiles * 4096 * eb + n * R * 16 + STEPS * n * R * copy
-        kernel = f"k_dense_persistent<{a.dtype}>"
+        kernel = f"k_dense_persistent<{a.dtype}, {'coherent' if kw.get('persistent_sync') == 2 else 'fences'}>"
     else:
         # one launch = one step: the stored tiles once, x and y read and written once, the
         # 16-bit copy written and read once (re-reads of x columns by other row tiles are

@@ -185,6 +185,11 @@ typedef struct {
     int32_t tiles_in_flight; /* dense per-step plan with 64 replicas per workgroup: stored
                             tiles whose loads are issued together (2 or 4); 0 = the
                             autotuner's choice or 2.  Bit-identical either way. */
+    int32_t persistent_sync; /* persistent plan: how the 16-bit copy of x crosses workgroups
+                            each step.  1 = plain accesses with agent-scope release/acquire
+                            fences (L2 write-back / invalidate); 2 = every access of the copy
+                            is device-coherent, no cache-wide fences; 0 = the autotuner's
+                            choice or 1.  Bit-identical either way. */
 } qh_bsb_opts;
 
 /* Result buffers (all device, caller-owned; optional ones may be NULL).
@@ -239,6 +244,8 @@ typedef struct {
     int32_t tiles_in_flight;    /* per-step dense plan: stored tiles whose loads are issued together */
     int32_t skyline_kernel;     /* SNP graphs: step kernel of the last solve: 3 rows, 4 band FMA, 5 band MFMA */
     float skyline_us[2];        /* SNP autotuner: [band FMA, band MFMA] microseconds per step (0 = not timed) */
+    int32_t persistent_sync;    /* persistent plan of the last solve: 1 fences, 2 coherent accesses */
+    float us_persistent_coherent; /* autotuner: persistent plan with coherent accesses (0 = not timed) */
 } qh_plan_info;
 
 qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *out);

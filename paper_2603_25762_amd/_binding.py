@@ -66,7 +66,7 @@ class _BsbOpts(ctypes.Structure):
                 ("readout", ctypes.c_int32), ("greedy", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("plan", ctypes.c_int32),
                 ("replica_tile", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("tiles_in_flight", ctypes.c_int32)]
+                ("tiles_in_flight", ctypes.c_int32), ("persistent_sync", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
@@ -81,7 +81,8 @@ class _PlanInfo(ctypes.Structure):
                 ("workgroups_per_group", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("us_per_step", ctypes.c_float * 2), ("replica_tile", ctypes.c_int32),
                 ("tiles_in_flight", ctypes.c_int32), ("skyline_kernel", ctypes.c_int32),
-                ("skyline_us", ctypes.c_float * 2)]
+                ("skyline_us", ctypes.c_float * 2), ("persistent_sync", ctypes.c_int32),
+                ("us_persistent_coherent", ctypes.c_float)]
 
 
 class _BatchedResult(ctypes.Structure):
@@ -242,6 +243,7 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
               step_begin: int = 0, step_end: int = 0, readout: bool = True, greedy: bool = True,
               use_graph: bool = False, all_spins: bool = False, per_component: bool = False,
               plan: int = 0, replica_tile: int = 0, discrete: bool = False, tiles_in_flight: int = 0,
+              persistent_sync: int = 0,
               out: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
     """Runs bSB; returns device tensors (best_spins, cuts, best_cut, selected_cut, ...).
 
@@ -284,7 +286,7 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
         res["pump"] = pump
     opts = _BsbOpts(replicas, steps, step_begin, step_end, dt, c0, a0, _ptr(pump), seed & (2**64 - 1),
                     int(init), int(readout), int(greedy), int(use_graph), int(plan), int(replica_tile),
-                    int(discrete), int(tiles_in_flight))
+                    int(discrete), int(tiles_in_flight), int(persistent_sync))
     r = _Result(_ptr(x), _ptr(y), _ptr(keep.get("best_spins")), _ptr(keep.get("cuts")),
                 _ptr(keep.get("cut_rc")), _ptr(keep.get("best_replica")), _ptr(keep.get("selected_cut")),
                 _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")))
@@ -310,7 +312,7 @@ def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt:
         res["y"] = torch.empty(max(total * replicas, 1), dtype=torch.float32, device=dev)
     arr = (ctypes.c_void_p * max(nb, 1))(*[g.handle.value for g in graphs])
     opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
-                    int(use_graph), plan, 0, int(discrete), 0)
+                    int(use_graph), plan, 0, int(discrete), 0, 0)
     r = _BatchedResult(_ptr(res["best_spins"]), _ptr(res["cuts"]), _ptr(res["best_cut"]),
                        _ptr(res["selected_cut"]), _ptr(res.get("x")), _ptr(res.get("y")), 0)
     _check(load().qh_bsb_solve_batched(arr, nb, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
@@ -348,7 +350,7 @@ def refine(g: Graph, replicas: int, steps: int, *, max_rounds: int = 15, dt: flo
     rc = (ctypes.c_double * max_rounds)()
     rounds = ctypes.c_int32(0)
     opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
-                    int(use_graph), plan, 0, int(discrete), 0)
+                    int(use_graph), plan, 0, int(discrete), 0, 0)
     _check(load().qh_refine(g.handle, ctypes.byref(opts), max_rounds, _ptr(h1), _ptr(block), _ptr(flips), rc,
                             ctypes.byref(rounds), _stream(stream)))
     k = rounds.value

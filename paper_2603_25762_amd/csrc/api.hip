@@ -181,6 +181,8 @@ static void validate_opts(const qh_bsb_opts *o) {
     if (!(o->dt > 0.0)) fail(QH_EINVAL, "dt must be > 0");
     if (o->plan < 0 || o->plan > 5) fail(QH_EINVAL, "plan must be 0-5, got %d", o->plan);
     if (o->variant != 0 && o->variant != 1) fail(QH_EINVAL, "variant must be 0 (ballistic) or 1 (discrete)");
+    if (o->persistent_sync < 0 || o->persistent_sync > 2)
+        fail(QH_EINVAL, "persistent_sync must be 0, 1 or 2, got %d", o->persistent_sync);
     if (o->tiles_in_flight != 0 && o->tiles_in_flight != 2 && o->tiles_in_flight != 4)
         fail(QH_EINVAL, "tiles_in_flight must be 0, 2 or 4, got %d", o->tiles_in_flight);
     const int t = o->replica_tile;

@@ -391,6 +391,44 @@ __global__ __launch_bounds__(256) void k_sky_step(
     }
 }
 
+// Rows of band block blk for replica r after the band columns: the long-range chunk
+// partials of each row (in chunk order) join the band sum z, then the fused update.
+// my_cp: lanes 0..kBandRows hold row_chunk_ptr of rows blk*kBandRows + lane.
+__device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int64_t r, const float (&z)[kBandRows],
+                                         const float (&xo)[kBandRows], const float (&yo)[kBandRows], int32_t my_cp,
+                                         const int32_t *__restrict__ row_chunk_ptr,
+                                         const float *__restrict__ hub_part, float *x_out, float *y, float coef,
+                                         const StepArgs &sa) {
+    constexpr int RB = kBandRows;
+    // the first chunk partial of every long-range row, all sixteen loads in flight together
+    float p0[RB];
+    if (row_chunk_ptr) {
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int32_t cb = __builtin_amdgcn_readlane(my_cp, i), ce = __builtin_amdgcn_readlane(my_cp, i + 1);
+            p0[i] = (blk * RB + i < n && cb < ce) ? hub_part[(int64_t)cb * R + r] : 0.f;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const int64_t u = blk * RB + i;
+        if (u >= n) break;
+        float zi = z[i];
+        if (row_chunk_ptr) {                   // long-range rows: chunk partials, in order
+            const int32_t cb = __builtin_amdgcn_readlane(my_cp, i), ce = __builtin_amdgcn_readlane(my_cp, i + 1);
+            if (cb < ce) {
+                zi += p0[i];
+                for (int c = cb + 1; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
+            }
+        }
+        const int64_t idx = u * R + r;
+        float xv = xo[i], yv = yo[i];
+        bsb_update(zi, xv, yv, coef, sa);
+        y[idx] = yv;
+        x_out[idx] = xv;
+    }
+}
+
 // Register-tiled band step (R a multiple of 64; lane = replica).  Wave = one band block
 // of kBandRows consecutive rows: it walks the block's union column range once, loads
 // each x row once and applies it to all kBandRows accumulators with one column of the
@@ -431,33 +469,7 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
         for (int i = 0; i < RB; ++i) z[i] += ld_val<DT>(bb_val, e0 + i) * xj;
     }
     if (!active) return;
-    // the first chunk partial of every long-range row, all sixteen loads in flight together
-    float p0[RB];
-    if (row_chunk_ptr) {
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int32_t cb = __builtin_amdgcn_readlane(my_cp, i), ce = __builtin_amdgcn_readlane(my_cp, i + 1);
-            p0[i] = (blk * RB + i < n && cb < ce) ? hub_part[(int64_t)cb * R + r] : 0.f;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < RB; ++i) {
-        const int64_t u = blk * RB + i;
-        if (u >= n) break;
-        float zi = z[i];
-        if (row_chunk_ptr) {                   // long-range rows: chunk partials, in order
-            const int32_t cb = __builtin_amdgcn_readlane(my_cp, i), ce = __builtin_amdgcn_readlane(my_cp, i + 1);
-            if (cb < ce) {
-                zi += p0[i];
-                for (int c = cb + 1; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
-            }
-        }
-        const int64_t idx = u * R + r;
-        float xv = xo[i], yv = yo[i];
-        bsb_update(zi, xv, yv, coef, sa);
-        y[idx] = yv;
-        x_out[idx] = xv;
-    }
+    band_block_finish(blk, n, R, r, z, xo, yo, my_cp, row_chunk_ptr, hub_part, x_out, y, coef, sa);
 }
 
 // The same band block on the matrix cores: a band block is a dense 16 x W matrix stored
@@ -955,7 +967,7 @@ static void x_to_h(const qh_graph *g, SolvePlan &p, int64_t n, int R, int discre
 
 // Steps [kb, ke) in one cooperative launch; the state is in p.xa / p.y / p.ha.
 static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, double c0, double dt, double a0,
-                           int kb, int ke, int discrete, hipStream_t st) {
+                           int kb, int ke, int discrete, int coherent, hipStream_t st) {
     PersistPlan &pp = *p.pp;
     QH_HIP(hipMemsetAsync(pp.flags.p, 0, pp.flags.bytes(), st));
     PersistArgs pa{};
@@ -987,7 +999,7 @@ static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, d
     pa.discrete = discrete;
     pa.lds_j_bytes = pp.lds_j_bytes;
     pa.max_polls = (int64_t)1 << 27;
-    launch_persistent(g, pp, pa, st);
+    launch_persistent(g, pp, pa, coherent, st);
     int32_t err = 0;
     QH_HIP(hipMemcpyAsync(&err, pa.err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     QH_HIP(hipStreamSynchronize(st));
@@ -1008,7 +1020,7 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
     std::vector<int> cands;
     if (R >= 64) cands = {64, 65, 32, 16};
     else cands = {R};
-    if (pers_ok) cands.push_back(0);
+    if (pers_ok) { cands.push_back(0); cands.push_back(-1); }   // persistent: fences; coherent accesses
     p.tuned_plan = 1;
     p.tuned_rt = cands[0];
     p.tuned_depth = 2;
@@ -1021,7 +1033,7 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
     float best = 0.0f, best_step = 0.0f;
     bool first = true;
     for (int cand : cands) {
-        if (cand) {
+        if (cand > 0) {
             p.run_rt = cand == 65 ? 64 : cand;
             p.run_depth = cand == 65 ? 4 : 2;
         }
@@ -1032,22 +1044,24 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
             QH_CHECK_LAUNCH();
             if (!x_pingpong(g)) x_to_h(g, p, n, R, o->variant == 1, st);
             QH_HIP(hipEventRecord(e0, st));
-            if (cand) run_steps(g, p, o, pump, c0, a0, 0, nt, st);
-            else run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, o->variant == 1, st);
+            if (cand > 0) run_steps(g, p, o, pump, c0, a0, 0, nt, st);
+            else run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, o->variant == 1, cand < 0, st);
             QH_HIP(hipEventRecord(e1, st));
             QH_HIP(hipEventSynchronize(e1));
         }
         QH_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (cand && (best_step == 0.0f || ms < best_step)) {
+        if (cand > 0 && (best_step == 0.0f || ms < best_step)) {
             best_step = ms;
             p.tuned_rt = p.run_rt;
             p.tuned_depth = p.run_depth;
             p.tuned_us[0] = ms * 1000.0f / nt;
         }
-        if (!cand) p.tuned_us[1] = ms * 1000.0f / nt;
+        if (cand == 0) p.tuned_us[1] = ms * 1000.0f / nt;
+        if (cand < 0) p.tuned_us_coh = ms * 1000.0f / nt;
         if (first || ms < best) {
             best = ms;
-            p.tuned_plan = cand ? 1 : 2;
+            p.tuned_plan = cand > 0 ? 1 : 2;
+            if (cand <= 0) p.tuned_coh = cand < 0;
         }
         first = false;
     }
@@ -1176,7 +1190,9 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     load_state();
     if (ke > kb && n > 0) p.last_plan = persistent ? 2 : 1;
     if (persistent) {
-        run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, o->variant == 1, st);
+        const int coherent = o->persistent_sync == 2 || (o->persistent_sync == 0 && p.tuned_coh);
+        p.last_coh = coherent;
+        run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, o->variant == 1, coherent, st);
     } else if (ke > kb && n > 0) {
         if (o->use_graph) {
             auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R,

@@ -39,7 +39,15 @@ __device__ inline void pbsb_update(float z, float &x, float &y, float coef, floa
     y = yn;
 }
 
-template <int DT, int NB, int MAXT>
+// COH selects how the 16-bit copy of x crosses workgroups between steps:
+//  COH = 0: plain loads and stores, made visible by an agent-scope release fence before the
+//           step flag (L2 write-back) and an agent-scope acquire fence after the wait (L2
+//           invalidate);
+//  COH = 1: every load and store of the copy is itself an agent-scope (device-coherent)
+//           access, so no cache-wide write-back or invalidate is needed: a workgroup waits
+//           for its own copy stores to complete before it raises its flag, and reads its
+//           neighbours' copies only after seeing their flags.
+template <int DT, int NB, int MAXT, int COH>
 __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     constexpr int RT = NB * 16;
@@ -104,7 +112,7 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
                 }
             }
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         // 2. stage the column tiles of x (16-bit copy, half s % 2) into LDS
         const uint16_t *hin = (s & 1) ? a.h1 : a.h0;
@@ -123,7 +131,15 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
                     if (e < total) {
                         const int c = e / (8 * RT), rem = e - c * 8 * RT;
                         const int jgl = rem / RT, rl = rem - jgl * RT;
-                        v[u] = *(const uint4 *)(hin + (((int64_t)ct_list[c] * 8 + jgl) * R + r0 + rl) * 8);
+                        const uint16_t *src = hin + (((int64_t)ct_list[c] * 8 + jgl) * R + r0 + rl) * 8;
+                        if constexpr (COH) {
+                            uint64_t *q = (uint64_t *)src;
+                            const uint64_t lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            const uint64_t hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            v[u] = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+                        } else {
+                            v[u] = *(const uint4 *)src;
+                        }
                     }
                 }
 #pragma unroll
@@ -197,14 +213,19 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
                 uint2 pk;
                 pk.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
                 pk.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
-                *(uint2 *)(hout + ((rowbase >> 3) * R + r0 + b * 16 + l16) * 8 + (rowbase & 7)) = pk;
+                uint16_t *dst = hout + ((rowbase >> 3) * R + r0 + b * 16 + l16) * 8 + (rowbase & 7);
+                if constexpr (COH)
+                    __hip_atomic_store((uint64_t *)dst, (uint64_t)pk.x | ((uint64_t)pk.y << 32), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                else
+                    *(uint2 *)dst = pk;
             }
         }
         // 4. publish: own stores done, then one agent-scope release per workgroup
         __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (tid == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(a.flags + (int64_t)grp * a.wpg + w, s + 1, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -349,9 +370,9 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
     return false;
 }
 
-template <int DT, int NB>
+template <int DT, int NB, int COH>
 static void launch_t(const PersistArgs &args, int grid, int lds, hipStream_t st) {
-    auto fn = k_dense_persistent<DT, NB, kMaxT>;
+    auto fn = k_dense_persistent<DT, NB, kMaxT, COH>;
     if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
         (void)hipGetLastError();
     int per_cu = 0;
@@ -367,14 +388,20 @@ static void launch_t(const PersistArgs &args, int grid, int lds, hipStream_t st)
     QH_HIP(hipLaunchCooperativeKernel((const void *)fn, dim3(grid), dim3(256), kargs, (unsigned)lds, st));
 }
 
-void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, hipStream_t st) {
+void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, int coherent,
+                       hipStream_t st) {
     const int grid = pp.ng * pp.wpg;
     const int lds = (int)pp.lds_bytes;
+#define QH_PC(DTV, NBV)                                                  \
+    do {                                                                 \
+        if (coherent) launch_t<DTV, NBV, 1>(args, grid, lds, st);        \
+        else launch_t<DTV, NBV, 0>(args, grid, lds, st);                 \
+    } while (0)
 #define QH_P(DTV)                                                     \
     do {                                                              \
-        if (pp.RT == 16) launch_t<DTV, 1>(args, grid, lds, st);       \
-        else if (pp.RT == 32) launch_t<DTV, 2>(args, grid, lds, st);  \
-        else launch_t<DTV, 4>(args, grid, lds, st);                   \
+        if (pp.RT == 16) QH_PC(DTV, 1);                               \
+        else if (pp.RT == 32) QH_PC(DTV, 2);                          \
+        else QH_PC(DTV, 4);                                           \
     } while (0)
     switch (g->dtype) {
         case QH_F16: QH_P(QH_F16); break;
@@ -383,6 +410,7 @@ void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistAr
         default: fail(QH_EUNSUPPORTED, "persistent plan needs a 16- or 8-bit dense graph");
     }
 #undef QH_P
+#undef QH_PC
 }
 
 }  // namespace qh
@@ -406,6 +434,8 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out) {
         i.us_per_step[1] = p.tuned_us[1];
         i.replica_tile = g->storage == QH_STORE_DENSE ? (R >= 64 ? p.run_rt : R) : 0;
         i.tiles_in_flight = g->storage == QH_STORE_DENSE ? (R >= 64 && p.run_rt == 64 ? p.run_depth : 4) : 0;
+        i.persistent_sync = p.last_plan == 2 ? 1 + p.last_coh : 0;
+        i.us_persistent_coherent = p.tuned_us_coh;
         if (g->storage != QH_STORE_DENSE) {
             int sk = p.sky_kernel;
             if (sk == kSkyBandFma && !(R >= 64 && g->n_bblk > 0)) sk = kSkyRows;

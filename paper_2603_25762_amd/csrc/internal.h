@@ -110,7 +110,10 @@ struct SolvePlan {
     bool sky_tuned = false;            // the band kernels have been timed on this graph
     int sky_best = 0;                  // the faster band kernel
     float sky_us[3] = {0, 0, 0};       // measured microseconds per step of each kernel
-    float tuned_us[2] = {0, 0};        // measured microseconds per step: per-step, persistent
+    float tuned_us[2] = {0, 0};        // measured microseconds per step: per-step, persistent (fences)
+    float tuned_us_coh = 0;            // persistent with device-coherent accesses
+    bool tuned_coh = false;            // the autotuner's persistent variant is the coherent one
+    int last_coh = 0;                  // variant of the last persistent run
     int tuned_rt = 0;                  // autotuner's replica tile for the per-step dense kernel
     int tuned_depth = 2;               // autotuner's tiles in flight for 64-replica tiles (2 or 4)
     int run_rt = 64;                   // replica tile of the dense step launches (R >= 64)

@@ -37,6 +37,9 @@ struct PersistPlan {
 };
 
 bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_t st);
-void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, hipStream_t st);
+// coherent = 1 selects the variant whose copy-of-x traffic uses device-coherent accesses
+// instead of cache-wide fences (both give identical results)
+void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, int coherent,
+                       hipStream_t st);
 
 }  // namespace qh

@@ -218,13 +218,14 @@ def test_discrete_whole_solves_match_oracle_and_plans():
     gm = gpu_graph(wm, "read_signed", "f16")
     n = gm.info()["n"]
     outs = []
-    for plan in (1, 2):
+    for plan, sync in ((1, 0), (2, 1), (2, 2)):
         x = torch.empty((n, 64), dtype=torch.float32, device="cuda")
         y = torch.empty((n, 64), dtype=torch.float32, device="cuda")
-        r = qh.bsb_solve(gm, 64, 300, seed=31, x=x, y=y, plan=plan, discrete=True)
+        r = qh.bsb_solve(gm, 64, 300, seed=31, x=x, y=y, plan=plan, discrete=True, persistent_sync=sync)
         outs.append((x, y, r))
-    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
-    assert torch.equal(outs[0][2]["best_cut"], outs[1][2]["best_cut"])
+    for o in outs[1:]:
+        assert torch.equal(outs[0][0], o[0]) and torch.equal(outs[0][1], o[1])
+        assert torch.equal(outs[0][2]["best_cut"], o[2]["best_cut"])
     ws = synth.snp_small(61, n_snp=400)
     gs_ = gpu_graph(ws, "snp_llr", "bf16")
     rb = qh.bsb_solve_batched([g, gs_], 32, 300, seed=9, discrete=True)
@@ -239,15 +240,20 @@ def test_discrete_whole_solves_match_oracle_and_plans():
 @pytest.mark.parametrize("R", [16, 64, 256])
 def test_persistent_equals_per_step_bit_exact(dtype, R):
     """The persistent plan runs the same MFMA sequence and update as the per-step kernel,
-    so 300 steps of both must agree bit for bit (state and readout)."""
+    so 300 steps of both must agree bit for bit (state and readout), with either way of
+    passing x between workgroups (cache-wide fences, device-coherent accesses)."""
     w = synth.read_mhc(seed=78, n_snp=1500, n_reads=1000, region=500_000)
     g = gpu_graph(w, "read_signed", dtype)
     n = g.info()["n"]
     out = []
-    for plan in (1, 2):          # one fused kernel per step; persistent
+    # one fused kernel per step; persistent with fences; persistent with coherent accesses
+    for plan, sync in ((1, 0), (2, 1), (2, 2)):
         x = torch.empty((n, R), dtype=torch.float32, device="cuda")
         y = torch.empty((n, R), dtype=torch.float32, device="cuda")
-        r = qh.bsb_solve(g, R, 300, seed=31, x=x, y=y, plan=plan)
+        r = qh.bsb_solve(g, R, 300, seed=31, x=x, y=y, plan=plan, persistent_sync=sync)
+        if plan == 2:
+            info = g.plan_info(R)
+            assert info["plan_used"] == 2 and info["persistent_sync"] == sync
         out.append((x, y, r))
     xa, ya, ra = out[0]
     for xb, yb, rb in out[1:]:
@@ -283,6 +289,9 @@ def test_replica_tiles_bit_exact(dtype):
     assert e.value.status == qh.Status.EINVAL
     with pytest.raises(qh.QhapError) as e:
         qh.bsb_solve(g, 64, 10, tiles_in_flight=3)
+    assert e.value.status == qh.Status.EINVAL
+    with pytest.raises(qh.QhapError) as e:
+        qh.bsb_solve(g, 64, 10, persistent_sync=3)
     assert e.value.status == qh.Status.EINVAL
 
 
