@@ -64,38 +64,52 @@ def calibrate_copy():
     print(json.dumps(dict(copy_bytes_read=COPY_BYTES, copy_bytes_written=COPY_BYTES, launches=3)), flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_dense_step_read_mhc_traffic.md")
-
-
-def kernel_source_hash():
-    """Hash of the dense step kernel's source: the dense-tile section of bsb.hip (from its
-    banner to the skyline banner; the update helper above it included) and formats.h."""
+def kernel_source_hash(kernel="k_dense_step"):
+    """Hash of a step kernel's source.  k_dense_step: the dense-tile section of bsb.hip
+    (from StepArgs to the skyline banner, the update helpers included); k_dense_persistent:
+    bsb_persistent.hip; k_band_step: the update helpers and the skyline section of bsb.hip.
+    formats.h (the number formats) is part of every hash."""
     import hashlib
     h = hashlib.sha256()
-    src = open(os.path.join(ROOT, "paper_2603_25762_amd", "csrc", "bsb.hip")).read()
-    a = src.index("struct StepArgs")
-    b = src.index("// skyline band + long-range CSR")
-    h.update(src[a:b].encode())
-    h.update(open(os.path.join(ROOT, "paper_2603_25762_amd", "csrc", "formats.h"), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2603_25762_amd", "csrc")
+    if kernel.startswith("k_dense_persistent"):
+        h.update(open(os.path.join(csrc, "bsb_persistent.hip"), "rb").read())
+    elif kernel.startswith("k_band_step"):
+        src = open(os.path.join(csrc, "bsb.hip")).read()
+        a = src.index("struct StepArgs")
+        b = src.index("struct StepArgs") + src[a:].index("// ------", 1)
+        h.update(src[a:b].encode())                      # StepArgs and the update helpers
+        a = src.index("// skyline band + long-range CSR")
+        b = src.index("// batched blocks:")
+        h.update(src[a:b].encode())                      # the skyline / band kernels
+    else:
+        src = open(os.path.join(csrc, "bsb.hip")).read()
+        a = src.index("struct StepArgs")
+        b = src.index("// skyline band + long-range CSR")
+        h.update(src[a:b].encode())
+    h.update(open(os.path.join(csrc, "formats.h"), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, replica_tile, depth):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None when
-    there is none, it covers another replica tile, or the kernel sources changed since the
-    counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    vals = {}
-    for line in open(TRAFFIC_FILE):
-        if line.startswith("traffic:"):
-            k, _, v = line[len("traffic:"):].strip().partition("=")
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel") != kernel or vals.get("source_sha") != kernel_source_hash():
-        return None
-    if int(vals.get("replica_tile", 0)) != replica_tile or int(vals.get("tiles_in_flight", 2)) != depth:
-        return None
-    return int(float(vals["hbm_bytes_per_launch"]))
+def measured_traffic(kernel, replica_tile=None, depth=None):
+    """HBM bytes per launch of `kernel` from the committed counter summaries
+    (profiles/*_traffic.md), or None when none covers this kernel and configuration or the
+    kernel's source changed since the counters were taken."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        vals = {}
+        for line in open(path):
+            if line.startswith("traffic:"):
+                k, _, v = line[len("traffic:"):].strip().partition("=")
+                vals[k.strip()] = v.strip()
+        if vals.get("kernel") != kernel or vals.get("source_sha") != kernel_source_hash(kernel):
+            continue
+        if replica_tile is not None and int(vals.get("replica_tile", 0)) != replica_tile:
+            continue
+        if depth is not None and int(vals.get("tiles_in_flight", 2)) != depth:
+            continue
+        return int(float(vals["hbm_bytes_per_launch"]))
+    return None
 
 
 def main():
@@ -223,7 +237,7 @@ def main():
     frac_h = ach_gbs / PEAK_HBM_GBS
     rtile = (tune or {}).get("replica_tile") or 64
     depth = (tune or {}).get("tiles_in_flight") or 2
-    traffic = measured_traffic(kernel, rtile, depth) if plan != 2 else None
+    traffic = measured_traffic(kernel, rtile, depth) if plan != 2 else measured_traffic(kernel)
     if frac_m >= frac_h:
         roof = dict(bound="mfma", achieved=round(ach_tf, 2), peak=PEAK_TFLOPS[a.dtype], unit="TFLOP/s",
                     frac=round(frac_m, 4), traffic=traffic)
@@ -234,7 +248,7 @@ def main():
                 tiles_in_flight=depth if plan != 2 else None, launch_us=round(launch_us, 3),
                 steps_per_launch=launches_steps,
                 us_per_bsb_step=round(step_us, 3), flop_per_launch=flops, bytes_per_launch=bytes_,
-                mfma_frac=round(frac_m, 4), hbm_frac=round(frac_h, 4), source_sha=kernel_source_hash())
+                mfma_frac=round(frac_m, 4), hbm_frac=round(frac_h, 4), source_sha=kernel_source_hash(kernel))
 
     out = dict(metric=METRIC, value=value, unit="edge-updates/s", n_gpus=1, steps=a.steps,
                warmup=a.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True,
@@ -336,7 +350,9 @@ def bench_snp(a):
                            storage="skyline band blocks" + (" + long-range packets" if lr else ""),
                            parallelism="single GPU"),
                roofline=dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                             frac=round(ach / PEAK_HBM_GBS, 4), traffic=None, kernel=kernel,
+                             frac=round(ach / PEAK_HBM_GBS, 4),
+                             traffic=None if lr else measured_traffic(kernel), kernel=kernel,
+                             source_sha=kernel_source_hash(kernel),
                              launch_us=round(step_us, 3), bytes_per_launch=bytes_,
                              note="per bSB step (all kernels of one step)"),
                autotune=tune)

@@ -79,14 +79,11 @@ struct StepArgs {
 
 
 __device__ inline void bsb_update(float z, float &x, float &y, float coef, const StepArgs &s) {
-    float yn = y + (-coef * x + s.c0 * z) * s.dt;
-    float xn = x + s.a0 * yn * s.dt;
-    if (fabsf(xn) > 1.0f) {
-        xn = xn > 0.0f ? 1.0f : -1.0f;
-        yn = 0.0f;
-    }
-    x = xn;
-    y = yn;
+    const float yn = y + (-coef * x + s.c0 * z) * s.dt;
+    const float xn = x + s.a0 * yn * s.dt;
+    // walls: past |x| = 1, x = sgn(x) (the median of -1, xn, 1) and y = 0
+    y = fabsf(xn) > 1.0f ? 0.0f : yn;
+    x = __builtin_amdgcn_fmed3f(xn, -1.0f, 1.0f);
 }
 
 // XCD-aware block index: hardware dispatches workgroup b to XCD b % 8; give each
@@ -155,13 +152,7 @@ __device__ inline void dense_product(float4_t (&acc)[NB], int t_beg, int t_end, 
                     if constexpr (DT == QH_FP8_ROWSCALE) {
                         const uint8_t *tile = t_val + (int64_t)tt * kTileElems;
                         uint2 c = *(const uint2 *)(tile + ((frag * 64 + lane) << 3));
-                        uint16_t hb[8];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            hb[e] = e4m3_to_f16_bits_scaled((uint8_t)(c.x >> (8 * e)));
-                            hb[4 + e] = e4m3_to_f16_bits_scaled((uint8_t)(c.y >> (8 * e)));
-                        }
-                        __builtin_memcpy(&a[u][kb], hb, 16);
+                        a[u][kb] = e4m3x8_to_f16_scaled(c);
                     } else {
                         const uint16_t *tile = (const uint16_t *)t_val + (int64_t)tt * kTileElems;
                         a[u][kb] = *(const half8_t *)(tile + ((frag * 64 + lane) << 3));
@@ -391,6 +382,31 @@ __global__ __launch_bounds__(256) void k_sky_step(
     }
 }
 
+// One column of a band block (kBandRows values) through the scalar cache: the address is
+// wave-uniform, so the values arrive in SGPRs and feed the FMAs directly.
+template <int DT>
+__device__ inline void band_column(const uint8_t *bb_val, int64_t e0, float (&v)[kBandRows]) {
+    typedef const __attribute__((address_space(4))) uint32_t cu32;
+    if constexpr (DT == QH_F32) {
+        cu32 *q = (cu32 *)(bb_val + e0 * 4);
+#pragma unroll
+        for (int i = 0; i < kBandRows; ++i) v[i] = __uint_as_float(q[i]);
+    } else {
+        cu32 *q = (cu32 *)(bb_val + e0 * 2);
+#pragma unroll
+        for (int i = 0; i < kBandRows / 2; ++i) {
+            const uint32_t w = q[i];
+            if constexpr (DT == QH_F16) {
+                v[2 * i] = f16_bits_to_f32((uint16_t)w);
+                v[2 * i + 1] = f16_bits_to_f32((uint16_t)(w >> 16));
+            } else {
+                v[2 * i] = __uint_as_float(w << 16);
+                v[2 * i + 1] = __uint_as_float(w & 0xffff0000u);
+            }
+        }
+    }
+}
+
 // Rows of band block blk for replica r after the band columns: the long-range chunk
 // partials of each row (in chunk order) join the band sum z, then the fused update.
 // my_cp: lanes 0..kBandRows hold row_chunk_ptr of rows blk*kBandRows + lane.
@@ -443,8 +459,10 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
                                        const int32_t *__restrict__ row_chunk_ptr, const float *__restrict__ hub_part,
                                        const float *x_in, float *x_out, float *y, float coef, const StepArgs &sa) {
     constexpr int RB = kBandRows;
-    const int32_t L = bb_lo[blk], W = bb_w[blk];
-    const int64_t off = bb_off[blk];
+    // blk is wave-uniform, so are the block's extents: keep them (and the band loop) scalar
+    const int32_t L = __builtin_amdgcn_readfirstlane(bb_lo[blk]), W = __builtin_amdgcn_readfirstlane(bb_w[blk]);
+    const int64_t off = (int64_t)__builtin_amdgcn_readfirstlane((int32_t)bb_off[blk]) |
+                        ((int64_t)__builtin_amdgcn_readfirstlane((int32_t)(bb_off[blk] >> 32)) << 32);
     float z[RB], xo[RB], yo[RB];
     // long-range rows: the chunk range of every row (lanes 0..RB load row_chunk_ptr once),
     // issued first so that the band loop never waits on it
@@ -460,13 +478,21 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
         xo[i] = (active && u < n) ? x_in[u * R + r] : 0.f;
         yo[i] = (active && u < n) ? y[u * R + r] : 0.f;
     }
-    const float *xc = x_in + (int64_t)L * R + r;
+    // inactive lanes read replica 0 of the same rows (always in bounds) and weigh it by 0:
+    // no divergent branch around the loads (|x| <= 1, so the product is an exact 0)
+    // (x is device memory: global loads, so that the wait for the scalar band values does
+    // not also wait for them, as it would for flat loads)
+    typedef const __attribute__((address_space(1))) float gfloat;
+    gfloat *xc = (gfloat *)(x_in + (int64_t)L * R + (active ? r : 0));
+    const float live = active ? 1.f : 0.f;
 #pragma unroll 4
     for (int32_t j = 0; j < W; ++j) {
-        const float xj = active ? coupling_value(xc[(int64_t)j * R], sa.discrete) : 0.f;
+        const float xj = coupling_value(xc[(int64_t)j * R], sa.discrete) * live;
         const int64_t e0 = off + (int64_t)j * RB;
+        float val[RB];
+        band_column<DT>(bb_val, e0, val);
 #pragma unroll
-        for (int i = 0; i < RB; ++i) z[i] += ld_val<DT>(bb_val, e0 + i) * xj;
+        for (int i = 0; i < RB; ++i) z[i] += val[i] * xj;
     }
     if (!active) return;
     band_block_finish(blk, n, R, r, z, xo, yo, my_cp, row_chunk_ptr, hub_part, x_out, y, coef, sa);
@@ -965,11 +991,20 @@ static void x_to_h(const qh_graph *g, SolvePlan &p, int64_t n, int R, int discre
     QH_CHECK_LAUNCH();
 }
 
+// Clears the persistent plan's step flags and error word (a kernel rather than a memset,
+// so that a caller capturing the stream into a graph records no memset node).
+__global__ void k_zero_i32(int64_t n, int *__restrict__ p) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 // Steps [kb, ke) in one cooperative launch; the state is in p.xa / p.y / p.ha.
 static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, double c0, double dt, double a0,
                            int kb, int ke, int discrete, int coherent, hipStream_t st) {
     PersistPlan &pp = *p.pp;
-    QH_HIP(hipMemsetAsync(pp.flags.p, 0, pp.flags.bytes(), st));
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for((int64_t)pp.flags.n)), dim3(256), 0, st, (int64_t)pp.flags.n,
+                       pp.flags.p);
+    QH_CHECK_LAUNCH();
     PersistArgs pa{};
     pa.n = g->n;
     pa.R = p.R;
@@ -998,6 +1033,9 @@ static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, d
     pa.pump = pump;
     pa.discrete = discrete;
     pa.lds_j_bytes = pp.lds_j_bytes;
+    pa.lds_tab_off = pp.lds_tab_off;
+    pa.max_wg_tiles = pp.max_wg_tiles;
+    pa.max_ct = pp.max_ct;
     pa.max_polls = (int64_t)1 << 27;
     launch_persistent(g, pp, pa, coherent, st);
     int32_t err = 0;

@@ -29,14 +29,11 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline void pbsb_update(float z, float &x, float &y, float coef, float c0, float dt, float a0) {
-    float yn = y + (-coef * x + c0 * z) * dt;
-    float xn = x + a0 * yn * dt;
-    if (fabsf(xn) > 1.0f) {
-        xn = xn > 0.0f ? 1.0f : -1.0f;
-        yn = 0.0f;
-    }
-    x = xn;
-    y = yn;
+    const float yn = y + (-coef * x + c0 * z) * dt;
+    const float xn = x + a0 * yn * dt;
+    // walls: past |x| = 1, x = sgn(x) (the median of -1, xn, 1) and y = 0
+    y = fabsf(xn) > 1.0f ? 0.0f : yn;
+    x = __builtin_amdgcn_fmed3f(xn, -1.0f, 1.0f);
 }
 
 // COH selects how the 16-bit copy of x crosses workgroups between steps:
@@ -52,6 +49,9 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     constexpr int RT = NB * 16;
     constexpr int EB = (DT == QH_FP8_ROWSCALE) ? 1 : 2;
+    // 16-byte staging loads per thread in flight together (fewer where the state of more
+    // row tiles occupies the registers)
+    constexpr int kStageBatch = MAXT <= 2 ? 16 : (MAXT <= 4 ? 12 : 4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, g4 = lane >> 4;
     const int grp = blockIdx.x % a.ng, w = blockIdx.x / a.ng;
@@ -64,7 +64,31 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
     const int *ct_list = a.wg_ct + a.wg_ct_ptr[w];
     uint8_t *lds_j = smem;
     uint16_t *lds_h = (uint16_t *)(smem + a.lds_j_bytes);
+    int32_t *lds_slot = (int32_t *)(smem + a.lds_tab_off);   // staging slot of each own stored tile
+    int32_t *lds_xct = lds_slot + a.max_wg_tiles;             // column tiles staged from memory ...
+    int32_t *lds_xslot = lds_xct + a.max_ct;                  // ... and their staging slots
     const int ct_elems = 64 * RT;   // 16-bit elements per staged column tile
+    for (int i = tid; i < jt1 - jt0; i += 256) lds_slot[i] = a.tile_slot[jt0 + i];
+    // Column tiles that are this workgroup's own row tiles reach LDS straight from the
+    // registers that hold their x; the others (the neighbours' rows) are staged from memory.
+    int own_slot[MAXT];
+#pragma unroll
+    for (int ti = 0; ti < MAXT; ++ti) own_slot[ti] = -1;
+    int n_ext = 0;
+    for (int c = 0; c < n_ct; ++c) {          // wave-uniform walk over a short list
+        const int ct = ct_list[c];
+        if (ct >= rt_b && ct < rt_e) {
+#pragma unroll
+            for (int ti = 0; ti < MAXT; ++ti)
+                if (ct == rt_b + ti) own_slot[ti] = c;
+        } else {
+            if (tid == 0) {
+                lds_xct[n_ext] = ct;
+                lds_xslot[n_ext] = c;
+            }
+            ++n_ext;
+        }
+    }
 
     // J tiles of this workgroup's rows -> LDS (once)
     {
@@ -90,7 +114,60 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
             }
         }
     }
+    // 16-bit copy of the lane's four rows of (row tile ti, replica block b), as the other
+    // workgroups receive it (rows past n hold 0)
+    auto pack_copy = [&](int ti, int b) -> uint2 {
+        const int64_t rowbase = (int64_t)(rt_b + ti) * kTile + wave * 16 + 4 * g4;
+        uint16_t hv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool live = rowbase + q < a.n;
+            const float cv = a.discrete ? (xs[ti][b][q] >= 0.f ? 1.f : -1.f) : xs[ti][b][q];
+            if constexpr (DT == QH_BF16) hv[q] = live ? f32_to_bf16_rne(cv) : 0;
+            else hv[q] = live ? f32_to_f16_rne(cv) : 0;
+        }
+        return make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16), (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
+    };
+    // the packed copy of the own rows is kept for the LDS write where registers allow (up to
+    // four row tiles) and packed again from x otherwise
+    constexpr bool kKeepPk = MAXT <= 4;
+    uint2 pkw[kKeepPk ? MAXT : 1][NB];
+    // own rows -> their staging slots (rows 4 g4 .. 4 g4 + 3 of the wave's 16)
+    auto write_own = [&]() {
+        const int lr = wave * 16 + 4 * g4;
+#pragma unroll
+        for (int ti = 0; ti < MAXT; ++ti) {
+            if (ti >= T || own_slot[ti] < 0) continue;
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                *(uint2 *)(lds_h + (int64_t)own_slot[ti] * ct_elems + ((lr >> 3) * RT + b * 16 + l16) * 8 + (lr & 7)) =
+                    kKeepPk ? pkw[kKeepPk ? ti : 0][b] : pack_copy(ti, b);
+        }
+    };
+    if constexpr (kKeepPk) {
+#pragma unroll
+        for (int ti = 0; ti < MAXT; ++ti)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) pkw[ti][b] = ti < T ? pack_copy(ti, b) : make_uint2(0, 0);
+    }
+    write_own();
     __syncthreads();
+    // The staging pattern is the same every step.  A column tile is 8 row groups of 8 rows;
+    // each group holds RT replicas x 8 values contiguously (one 16-byte piece).  The pieces of
+    // the first batch keep their source offsets and LDS destinations (in pieces) in registers.
+    const int total = n_ext * 8 * RT;
+    uint32_t soff[kStageBatch], doff[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+        const int e = u * 256 + tid;
+        soff[u] = doff[u] = 0;
+        if (e < total) {
+            const int k = e / (8 * RT), rem = e - k * 8 * RT;
+            const int jgl = rem / RT, rl = rem - jgl * RT;
+            soff[u] = (uint32_t)(((int64_t)lds_xct[k] * 8 + jgl) * R + r0 + rl);
+            doff[u] = (uint32_t)(lds_xslot[k] * 8 * RT + rem);
+        }
+    }
 
     const int *flags = a.flags + (int64_t)grp * a.wpg;
     const int nbr_b = a.nbr_ptr[w], n_nbr = a.nbr_ptr[w + 1] - nbr_b;
@@ -118,20 +195,24 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
         const uint16_t *hin = (s & 1) ? a.h1 : a.h0;
         uint16_t *hout = (s & 1) ? a.h0 : a.h1;
         {
-            // a column tile is 8 row groups of 8 rows; each group holds RT replicas x 8 values
-            // contiguously.  Issue a batch of 16-byte loads before any LDS store so that one
-            // round trip to memory covers the whole batch.
-            constexpr int kBatch = 8;
-            const int total = n_ct * 8 * RT;
-            for (int base = 0; base < total; base += 256 * kBatch) {
-                uint4 v[kBatch];
+            // Every 16-byte load of a batch is issued before the first LDS store, so that one
+            // round trip to memory covers the batch (kStageBatch x 4 KB; later batches, for
+            // longer column-tile lists, take their sources from the LDS copy of the list).
+            for (int base = 0; base < total; base += 256 * kStageBatch) {
+                uint4 v[kStageBatch];
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
+                for (int u = 0; u < kStageBatch; ++u) {
                     const int e = base + u * 256 + tid;
                     if (e < total) {
-                        const int c = e / (8 * RT), rem = e - c * 8 * RT;
-                        const int jgl = rem / RT, rl = rem - jgl * RT;
-                        const uint16_t *src = hin + (((int64_t)ct_list[c] * 8 + jgl) * R + r0 + rl) * 8;
+                        uint32_t off;
+                        if (base == 0) {
+                            off = soff[u];
+                        } else {
+                            const int k = e / (8 * RT), rem = e - k * 8 * RT;
+                            const int jgl = rem / RT, rl = rem - jgl * RT;
+                            off = (uint32_t)(((int64_t)lds_xct[k] * 8 + jgl) * R + r0 + rl);
+                        }
+                        const uint16_t *src = hin + (int64_t)off * 8;
                         if constexpr (COH) {
                             uint64_t *q = (uint64_t *)src;
                             const uint64_t lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -143,9 +224,13 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
+                for (int u = 0; u < kStageBatch; ++u) {
                     const int e = base + u * 256 + tid;
-                    if (e < total) *(uint4 *)(lds_h + (int64_t)e * 8) = v[u];
+                    if (e < total) {
+                        const int k = e / (8 * RT);
+                        const uint32_t d = base == 0 ? doff[u] : (uint32_t)(lds_xslot[k] * 8 * RT + e - k * 8 * RT);
+                        *(uint4 *)(lds_h + (int64_t)d * 8) = v[u];
+                    }
                 }
             }
         }
@@ -160,59 +245,64 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
             float4_t acc[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
-            for (int t = a.t_ptr[rt]; t < a.t_ptr[rt + 1]; ++t) {
-                const int slot = a.tile_slot[t];
+            const int tb = a.t_ptr[rt], te = a.t_ptr[rt + 1];
+            // A fragments (J) and B fragments (x copy) of one stored tile, for both K halves
+            half8_t af[2][2], bf[2][2][NB];
+            auto load_frags = [&](int t, half8_t (&A)[2], half8_t (&Bv)[2][NB]) {
+                const int slot = lds_slot[t - jt0];
                 const uint8_t *jt = lds_j + (int64_t)(t - jt0) * kTileElems * EB;
                 const uint16_t *ht = lds_h + (int64_t)slot * ct_elems;
 #pragma unroll
                 for (int kb = 0; kb < 2; ++kb) {
                     const int frag = wave * 2 + kb;
-                    half8_t av;
                     if constexpr (DT == QH_FP8_ROWSCALE) {
                         uint2 c = *(const uint2 *)(jt + ((frag * 64 + lane) << 3));
-                        uint16_t hb[8];
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            hb[e] = e4m3_to_f16_bits_scaled((uint8_t)(c.x >> (8 * e)));
-                            hb[4 + e] = e4m3_to_f16_bits_scaled((uint8_t)(c.y >> (8 * e)));
-                        }
-                        __builtin_memcpy(&av, hb, 16);
+                        A[kb] = e4m3x8_to_f16_scaled(c);
                     } else {
-                        av = *(const half8_t *)((const uint16_t *)jt + ((frag * 64 + lane) << 3));
+                        A[kb] = *(const half8_t *)((const uint16_t *)jt + ((frag * 64 + lane) << 3));
                     }
                     const int jgl = kb * 4 + g4;
 #pragma unroll
+                    for (int b = 0; b < NB; ++b)
+                        Bv[kb][b] = *(const half8_t *)(ht + (jgl * RT + b * 16 + l16) * 8);
+                }
+            };
+            auto mfmas = [&](const half8_t (&A)[2], const half8_t (&Bv)[2][NB]) {
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        const uint16_t *hp = ht + (jgl * RT + b * 16 + l16) * 8;
                         if constexpr (DT == QH_BF16) {
-                            bf16x8_t bv = *(const bf16x8_t *)hp;
-                            bf16x8_t aw;
-                            __builtin_memcpy(&aw, &av, 16);
-                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bv, acc[b], 0, 0, 0);
+                            bf16x8_t aw, bw;
+                            __builtin_memcpy(&aw, &A[kb], 16);
+                            __builtin_memcpy(&bw, &Bv[kb][b], 16);
+                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bw, acc[b], 0, 0, 0);
                         } else {
-                            half8_t bv = *(const half8_t *)hp;
-                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, acc[b], 0, 0, 0);
+                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[kb], Bv[kb][b], acc[b], 0, 0, 0);
                         }
                     }
+            };
+            // two tiles per iteration, each one's fragments loaded before the other's MFMAs
+            if (tb < te) load_frags(tb, af[0], bf[0]);
+            for (int t = tb; t < te; t += 2) {
+                if (t + 1 < te) load_frags(t + 1, af[1], bf[1]);
+                mfmas(af[0], bf[0]);
+                if (t + 1 < te) {
+                    if (t + 2 < te) load_frags(t + 2, af[0], bf[0]);
+                    mfmas(af[1], bf[1]);
                 }
             }
             const int64_t rowbase = (int64_t)rt * kTile + wave * 16 + 4 * g4;
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                uint16_t hv[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     float z = acc[b][q];
                     if constexpr (DT == QH_FP8_ROWSCALE) z *= sc[ti][q];
                     pbsb_update(z, xs[ti][b][q], ys[ti][b][q], coef, a.c0, a.dt, a.a0);
-                    const bool live = rowbase + q < a.n;
-                    const float cv = a.discrete ? (xs[ti][b][q] >= 0.f ? 1.f : -1.f) : xs[ti][b][q];
-                    if constexpr (DT == QH_BF16) hv[q] = live ? f32_to_bf16_rne(cv) : 0;
-                    else hv[q] = live ? f32_to_f16_rne(cv) : 0;
                 }
-                uint2 pk;
-                pk.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
-                pk.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
+                const uint2 pk = pack_copy(ti, b);
+                if constexpr (kKeepPk) pkw[kKeepPk ? ti : 0][b] = pk;
                 uint16_t *dst = hout + ((rowbase >> 3) * R + r0 + b * 16 + l16) * 8 + (rowbase & 7);
                 if constexpr (COH)
                     __hip_atomic_store((uint64_t *)dst, (uint64_t)pk.x | ((uint64_t)pk.y << 32), __ATOMIC_RELAXED,
@@ -221,9 +311,11 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
                     *(uint2 *)dst = pk;
             }
         }
-        // 4. publish: own stores done, then one agent-scope release per workgroup
+        // 4. publish: own stores done, then one agent-scope release per workgroup.  Every wave
+        // is past this step's product here, so the own column tiles can take the new x.
         __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
+        write_own();
         if (tid == 0) {
             if constexpr (!COH) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(a.flags + (int64_t)grp * a.wpg + w, s + 1, __ATOMIC_RELAXED,
@@ -252,7 +344,7 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
 // host side
 // ---------------------------------------------------------------------------
 
-static constexpr int kMaxT = 8;
+static constexpr int kMaxT = 8;     // row tiles per workgroup (kernels for 2, 4 and 8)
 static constexpr int64_t kLdsLimit = 160 * 1024;
 
 // Replica-group widths to try, most groups first (more workgroups, fewer row tiles each).
@@ -279,6 +371,7 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
     QH_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
     if (!coop) return false;
     const int64_t n_rt = g->n_rt;
+    if (n_rt * 8 * (int64_t)R >= ((int64_t)1 << 32)) return false;   // 16-byte piece offsets are 32-bit
     auto tptr = download(g->t_ptr.p, n_rt + 1, st);
     auto tcol = download(g->t_col.p, g->n_tiles, st);
     const int eb = dtype_bytes(g->dtype);
@@ -317,7 +410,8 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
         for (int w = 0; w < wpg; ++w)
             for (int32_t rt = wg_rt[w]; rt < wg_rt[w + 1]; ++rt) owner[rt] = w;
         std::vector<int32_t> ct_ptr(wpg + 1, 0), cts, slot(g->n_tiles), nbr_ptr(wpg + 1, 0), nbrs;
-        int64_t lds_max_j = 0, lds_max_h = 0;
+        int64_t lds_max_j = 0, lds_max_h = 0, max_tiles = 0, max_ct = 0;
+        int max_t = 0;
         for (int w = 0; w < wpg && ok; ++w) {
             std::vector<int32_t> u;
             for (int32_t t = tptr[wg_rt[w]]; t < tptr[wg_rt[w + 1]]; ++t) u.push_back(tcol[t]);
@@ -336,19 +430,27 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
             nbr_ptr[w] = (int32_t)nbrs.size();
             nbrs.insert(nbrs.end(), nb.begin(), nb.end());
             int64_t jb = (int64_t)(tptr[wg_rt[w + 1]] - tptr[wg_rt[w]]) * kTileElems * eb;
+            max_tiles = std::max<int64_t>(max_tiles, tptr[wg_rt[w + 1]] - tptr[wg_rt[w]]);
+            max_ct = std::max<int64_t>(max_ct, (int64_t)u.size());
+            max_t = std::max(max_t, wg_rt[w + 1] - wg_rt[w]);
             lds_max_j = std::max(lds_max_j, jb);
             lds_max_h = std::max(lds_max_h, (int64_t)u.size() * ct_bytes);
         }
         ct_ptr[wpg] = (int32_t)cts.size();
         nbr_ptr[wpg] = (int32_t)nbrs.size();
         lds_max_j = ceil_div(lds_max_j, 16) * 16;
-        if (!ok || lds_max_j + lds_max_h > kLdsLimit) continue;
+        const int64_t lds_tab = ceil_div((max_tiles + 2 * max_ct) * 4, 16) * 16;   // slot and column-tile tables
+        if (!ok || lds_max_j + lds_max_h + lds_tab > kLdsLimit) continue;
         // upload
         pp.RT = RT;
         pp.ng = ng;
         pp.wpg = wpg;
         pp.lds_j_bytes = lds_max_j;
-        pp.lds_bytes = lds_max_j + lds_max_h;
+        pp.lds_tab_off = lds_max_j + lds_max_h;
+        pp.lds_bytes = lds_max_j + lds_max_h + lds_tab;
+        pp.max_wg_tiles = (int32_t)max_tiles;
+        pp.max_ct = (int32_t)max_ct;
+        pp.max_t = max_t;
         pp.wg_rt.alloc(wpg + 1);
         pp.wg_rt.upload(wg_rt.data(), wpg + 1, st);
         pp.wg_ct_ptr.alloc(wpg + 1);
@@ -370,9 +472,9 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
     return false;
 }
 
-template <int DT, int NB, int COH>
+template <int DT, int NB, int MAXT, int COH>
 static void launch_t(const PersistArgs &args, int grid, int lds, hipStream_t st) {
-    auto fn = k_dense_persistent<DT, NB, kMaxT, COH>;
+    auto fn = k_dense_persistent<DT, NB, MAXT, COH>;
     if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
         (void)hipGetLastError();
     int per_cu = 0;
@@ -392,10 +494,16 @@ void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistAr
                        hipStream_t st) {
     const int grid = pp.ng * pp.wpg;
     const int lds = (int)pp.lds_bytes;
+#define QH_PM(DTV, NBV, COHV)                                                   \
+    do {                                                                        \
+        if (pp.max_t <= 2) launch_t<DTV, NBV, 2, COHV>(args, grid, lds, st);    \
+        else if (pp.max_t <= 4) launch_t<DTV, NBV, 4, COHV>(args, grid, lds, st); \
+        else launch_t<DTV, NBV, kMaxT, COHV>(args, grid, lds, st);              \
+    } while (0)
 #define QH_PC(DTV, NBV)                                                  \
     do {                                                                 \
-        if (coherent) launch_t<DTV, NBV, 1>(args, grid, lds, st);        \
-        else launch_t<DTV, NBV, 0>(args, grid, lds, st);                 \
+        if (coherent) QH_PM(DTV, NBV, 1);                                \
+        else QH_PM(DTV, NBV, 0);                                         \
     } while (0)
 #define QH_P(DTV)                                                     \
     do {                                                              \
@@ -411,6 +519,7 @@ void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistAr
     }
 #undef QH_P
 #undef QH_PC
+#undef QH_PM
 }
 
 }  // namespace qh

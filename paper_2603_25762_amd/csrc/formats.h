@@ -78,6 +78,25 @@ __host__ __device__ inline uint16_t e4m3_to_f16_bits_scaled(uint8_t c) {
     return (uint16_t)(((uint16_t)(c & 0x80) << 8) | ((uint16_t)(c & 0x7F) << 7));
 }
 
+// Eight E4M3 codes (c.x bytes 0-3, then c.y bytes 0-3) -> eight binary16 values holding
+// (code value) * 2^-8, in that order, by the hardware conversion: the same bits as
+// e4m3_to_f16_bits_scaled for every finite code (the scaled values are exact in binary16).
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+__device__ inline f16x8_t e4m3x8_to_f16_scaled(uint2 c) {
+    const auto p0 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(c.x, 0.00390625f, false);
+    const auto p1 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(c.x, 0.00390625f, true);
+    const auto p2 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(c.y, 0.00390625f, false);
+    const auto p3 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(c.y, 0.00390625f, true);
+    uint32_t w[4];
+    __builtin_memcpy(&w[0], &p0, 4);
+    __builtin_memcpy(&w[1], &p1, 4);
+    __builtin_memcpy(&w[2], &p2, 4);
+    __builtin_memcpy(&w[3], &p3, 4);
+    f16x8_t r;
+    __builtin_memcpy(&r, w, 16);
+    return r;
+}
+
 __host__ __device__ inline double e4m3_bits_to_f64(uint8_t c) {
     return (double)f16_bits_to_f32(e4m3_to_f16_bits_scaled(c)) * 256.0;
 }

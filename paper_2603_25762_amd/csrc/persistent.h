@@ -25,13 +25,19 @@ struct PersistArgs {
     const float *pump;
     int discrete;               // 1: the 16-bit copy holds sgn(x) (discrete variant)
     int64_t lds_j_bytes;
+    int64_t lds_tab_off;        // LDS offset of the tables: slots of the own stored tiles [max_wg_tiles],
+                                // then the column tiles staged from memory and their slots [max_ct] each
+    int32_t max_wg_tiles;       // most stored tiles of one workgroup
+    int32_t max_ct;             // most column tiles of one workgroup
     int64_t max_polls;
 };
 
 struct PersistPlan {
     bool ok = false;
     int RT = 0, ng = 0, wpg = 0;
-    int64_t lds_j_bytes = 0, lds_bytes = 0;
+    int max_t = 0;              // most row tiles of one workgroup (selects the kernel's register budget)
+    int32_t max_wg_tiles = 0, max_ct = 0;
+    int64_t lds_j_bytes = 0, lds_tab_off = 0, lds_bytes = 0;
     DevBuf<int32_t> wg_rt, wg_ct_ptr, wg_ct, tile_slot, nbr_ptr, nbr;
     DevBuf<int> flags;          // ng * wpg flags followed by the error word
 };
