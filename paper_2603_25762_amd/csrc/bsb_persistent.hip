@@ -60,6 +60,11 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
     const int rt_b = a.wg_rt[w], rt_e = a.wg_rt[w + 1];
     const int T = rt_e - rt_b;
     const int jt0 = a.t_ptr[rt_b], jt1 = a.t_ptr[rt_e];
+    // stored-tile range of each own row tile, read once (wave-uniform, kept in SGPRs)
+    int tile_b[MAXT + 1];
+#pragma unroll
+    for (int ti = 0; ti <= MAXT; ++ti)
+        tile_b[ti] = __builtin_amdgcn_readfirstlane(ti <= T ? a.t_ptr[rt_b + ti] : jt1);
     const int n_ct = a.wg_ct_ptr[w + 1] - a.wg_ct_ptr[w];
     const int *ct_list = a.wg_ct + a.wg_ct_ptr[w];
     uint8_t *lds_j = smem;
@@ -245,11 +250,17 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
             float4_t acc[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) acc[b] = float4_t{0.f, 0.f, 0.f, 0.f};
-            const int tb = a.t_ptr[rt], te = a.t_ptr[rt + 1];
+            const int tb = tile_b[ti], te = tile_b[ti + 1];
             // A fragments (J) and B fragments (x copy) of one stored tile, for both K halves
             half8_t af[2][2], bf[2][2][NB];
-            auto load_frags = [&](int t, half8_t (&A)[2], half8_t (&Bv)[2][NB]) {
-                const int slot = lds_slot[t - jt0];
+            // staging slot of tile t (clamped into the row tile's range): read two tiles
+            // ahead, so that waiting for it never waits for the fragment loads issued since
+            auto slot_of = [&](int t) { return lds_slot[min(t, te - 1) - jt0]; };
+            // fragments of tile t; a slot past the row tile's last tile reloads that tile with
+            // A = 0, which adds exactly zero, so that the loop below has no branches (the
+            // accumulators then stay in place across iterations)
+            auto load_frags = [&](int t, int slot, half8_t (&A)[2], half8_t (&Bv)[2][NB]) {
+                t = min(t, te - 1);
                 const uint8_t *jt = lds_j + (int64_t)(t - jt0) * kTileElems * EB;
                 const uint16_t *ht = lds_h + (int64_t)slot * ct_elems;
 #pragma unroll
@@ -267,29 +278,40 @@ __global__ __launch_bounds__(256, 1) void k_dense_persistent(PersistArgs a) {
                         Bv[kb][b] = *(const half8_t *)(ht + (jgl * RT + b * 16 + l16) * 8);
                 }
             };
-            auto mfmas = [&](const half8_t (&A)[2], const half8_t (&Bv)[2][NB]) {
+            // (pad: the slot is past the row tile's last tile, A = 0; applied here, where the
+            // MFMAs wait for the fragments anyway)
+            auto mfmas = [&](const half8_t (&A)[2], const half8_t (&Bv)[2][NB], bool pad) {
 #pragma unroll
-                for (int kb = 0; kb < 2; ++kb)
+                for (int kb = 0; kb < 2; ++kb) {
+                    const half8_t ak = pad ? half8_t{} : A[kb];
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         if constexpr (DT == QH_BF16) {
                             bf16x8_t aw, bw;
-                            __builtin_memcpy(&aw, &A[kb], 16);
+                            __builtin_memcpy(&aw, &ak, 16);
                             __builtin_memcpy(&bw, &Bv[kb][b], 16);
                             acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bw, acc[b], 0, 0, 0);
                         } else {
-                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[kb], Bv[kb][b], acc[b], 0, 0, 0);
+                            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ak, Bv[kb][b], acc[b], 0, 0, 0);
                         }
                     }
+                }
             };
             // two tiles per iteration, each one's fragments loaded before the other's MFMAs
-            if (tb < te) load_frags(tb, af[0], bf[0]);
-            for (int t = tb; t < te; t += 2) {
-                if (t + 1 < te) load_frags(t + 1, af[1], bf[1]);
-                mfmas(af[0], bf[0]);
-                if (t + 1 < te) {
-                    if (t + 2 < te) load_frags(t + 2, af[0], bf[0]);
-                    mfmas(af[1], bf[1]);
+            if (tb < te) {
+                int sl_next = slot_of(tb + 1);
+                load_frags(tb, slot_of(tb), af[0], bf[0]);
+                for (int t = tb; t < te; t += 2) {
+                    const int sl2 = slot_of(t + 2), sl3 = slot_of(t + 3);
+                    load_frags(t + 1, sl_next, af[1], bf[1]);
+                    __builtin_amdgcn_sched_barrier(0);   // keep the next tile's loads ahead of these MFMAs
+                    mfmas(af[0], bf[0], false);
+                    __builtin_amdgcn_sched_barrier(0);
+                    load_frags(t + 2, sl2, af[0], bf[0]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    mfmas(af[1], bf[1], t + 1 >= te);
+                    __builtin_amdgcn_sched_barrier(0);
+                    sl_next = sl3;
                 }
             }
             const int64_t rowbase = (int64_t)rt * kTile + wave * 16 + 4 * g4;
