@@ -221,7 +221,8 @@ def main():
         launch_us = loop_ms * 1e3
         flops = 2.0 * tiles * 4096 * R * STEPS
         bytes_ = tiles * 4096 * eb + n * R * 16 + STEPS * n * R * copy
-        kernel = f"k_dense_persistent<{a.dtype}, {'coherent' if kw.get('persistent_sync') == 2 else 'fences'}>"
+        sync_name = {1: "fences", 2: "coherent"}.get(kw.get("persistent_sync"), "fences")
+        kernel = f"k_dense_persistent<{a.dtype}, {sync_name}>"
     else:
         # one launch = one step: the stored tiles once, x and y read and written once, the
         # 16-bit copy written and read once (re-reads of x columns by other row tiles are

@@ -116,6 +116,9 @@ typedef struct {
     int32_t kind, storage, dtype;
     int32_t integer_weights; /* 1 when every J_ij is an integer (read graphs) */
     double c0_auto;          /* 0.5 / sqrt(sum_{i!=j} J_ij^2 / (n - 1)) */
+    int32_t band_dtype;      /* SKYLINE: encoding of the band blocks the step kernel reads: the
+                                graph's dtype, or QH_F16 for a BF16 graph whose band values are
+                                all exactly representable in binary16 (same values) */
 } qh_graph_info;
 
 /* Builds J from fragments (Methods: read-based Eqs. 1-3, SNP-based Eqs. 9-14).

@@ -55,7 +55,8 @@ class _GraphInfo(ctypes.Structure):
                 ("longrange_nnz", ctypes.c_int64), ("dense_tiles", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("kind", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("integer_weights", ctypes.c_int32), ("c0_auto", ctypes.c_double)]
+                ("integer_weights", ctypes.c_int32), ("c0_auto", ctypes.c_double),
+                ("band_dtype", ctypes.c_int32)]
 
 
 class _BsbOpts(ctypes.Structure):

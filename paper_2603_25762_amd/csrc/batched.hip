@@ -86,7 +86,8 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         BlockDesc &d = desc[b];
         d = BlockDesc{};
         d.kind = g->storage == QH_STORE_DENSE ? 0 : 1;
-        d.dtype = g->dtype;
+        d.dtype = g->storage == QH_STORE_DENSE ? g->dtype : g->bb_dtype;
+        d.bscale = g->storage == QH_STORE_DENSE ? 1.0f : g->bb_scale;
         d.n = g->n;
         d.x = p.xa.p;
         d.y = p.y.p;
@@ -125,7 +126,7 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
     auto class_of = [](const qh_graph *g) {
         if (g->storage == QH_STORE_DENSE)
             return g->dtype == QH_F32 ? 0 : g->dtype == QH_F16 ? 1 : g->dtype == QH_BF16 ? 2 : 3;
-        return g->dtype == QH_F32 ? 4 : g->dtype == QH_F16 ? 5 : 6;
+        return g->bb_dtype == QH_F32 ? 4 : g->bb_dtype == QH_F16 ? 5 : 6;
     };
     for (int c = 0; c < kBatchClasses; ++c) {
         for (int b : order) {

@@ -75,6 +75,7 @@ struct StepArgs {
     const float *pump;
     int k;
     int discrete;   // 1: the coupling takes sgn(x_j) (discrete variant), 0: x_j
+    float bscale;   // band blocks: power of two undoing the scale of their binary16 encoding (1: none)
 };
 
 
@@ -434,7 +435,16 @@ __device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int6
             const int32_t cb = __builtin_amdgcn_readlane(my_cp, i), ce = __builtin_amdgcn_readlane(my_cp, i + 1);
             if (cb < ce) {
                 zi += p0[i];
-                for (int c = cb + 1; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
+                // hub rows have many chunks: eight loads in flight at a time, added in order
+                int c = cb + 1;
+                for (; c + 8 <= ce; c += 8) {
+                    float v[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) v[k] = hub_part[(int64_t)(c + k) * R + r];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) zi += v[k];
+                }
+                for (; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
             }
         }
         const int64_t idx = u * R + r;
@@ -495,6 +505,8 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
         for (int i = 0; i < RB; ++i) z[i] += val[i] * xj;
     }
     if (!active) return;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) z[i] *= sa.bscale;   // exact: a power of two
     band_block_finish(blk, n, R, r, z, xo, yo, my_cp, row_chunk_ptr, hub_part, x_out, y, coef, sa);
 }
 
@@ -559,7 +571,7 @@ __device__ inline void band_block_step_mfma(int64_t blk, int64_t n, int64_t R, i
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int64_t r = r0 + b * 16 + l16;
-            float zi = acc[b][q];
+            float zi = acc[b][q] * sa.bscale;
             if (row_chunk_ptr)
                 for (int c = cb; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
             const int64_t idx = u * R + r;
@@ -642,7 +654,7 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
         float *xb = B.x, *yb = B.y;
         block_init<R>(B, seed, tid);
         const bool dense16 = B.kind == 0 && B.dtype != QH_F32;
-        StepArgs sa{B.c0, dt, a0, pump, 0, B.discrete};
+        StepArgs sa{B.c0, dt, a0, pump, 0, B.discrete, B.bscale};
         float *cur = xb, *oth = B.xs;
         for (int s = 0; s < steps; ++s) {
             sa.k = s;
@@ -707,7 +719,7 @@ __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restric
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int2 I = items[xcd_remap(blockIdx.x, n_items)];
     const BlockDesc &B = blocks[I.x];
-    const StepArgs sa{B.c0, dt, a0, pump, k, B.discrete};
+    const StepArgs sa{B.c0, dt, a0, pump, k, B.discrete, B.bscale};
     const float coef = a0 - pump[k];
     const int cur = k & 1;
     const int64_t n = B.n;
@@ -936,11 +948,18 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
     do {                                                                \
         QH_LR(DTV);                                                     \
         if (sk == kSkyBandMfma) {                                       \
-            if (RT == 16) QH_BANDM(DTV, 1);                             \
-            else if (RT == 32) QH_BANDM(DTV, 2);                        \
-            else QH_BANDM(DTV, 4);                                      \
+            if (g->bb_dtype == QH_F16) {                                \
+                if (RT == 16) QH_BANDM(QH_F16, 1);                      \
+                else if (RT == 32) QH_BANDM(QH_F16, 2);                 \
+                else QH_BANDM(QH_F16, 4);                               \
+            } else {                                                    \
+                if (RT == 16) QH_BANDM(DTV, 1);                         \
+                else if (RT == 32) QH_BANDM(DTV, 2);                    \
+                else QH_BANDM(DTV, 4);                                  \
+            }                                                           \
         } else if (sk == kSkyBandFma) {                                 \
-            QH_BAND(DTV);                                               \
+            if (g->bb_dtype == QH_F16) QH_BAND(QH_F16);                 \
+            else QH_BAND(DTV);                                          \
         } else if (RT == 16) QH_SKY(DTV, 16);                           \
         else if (RT == 32) QH_SKY(DTV, 32);                             \
         else QH_SKY(DTV, 64);                                           \
@@ -972,6 +991,7 @@ static int run_steps(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, cons
     sa.a0 = (float)a0;
     sa.pump = pump;
     sa.discrete = o->variant == 1;
+    sa.bscale = g->bb_scale;
     int cur = 0;
     for (int k = kb; k < ke; ++k) {
         sa.k = k;

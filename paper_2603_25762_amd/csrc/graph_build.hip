@@ -482,6 +482,29 @@ __global__ void k_quantize(int64_t n, const double *__restrict__ src, int dtype,
 
 // Band blocks: element (block b, column offset j, row i) = J[16b + i][bb_lo[b] + j], zero
 // outside the row's skyline range (and on the diagonal, which is zero anyway).
+// Exponent range of nonzero BF16 band values: ext[0] = largest biased exponent, ext[1] =
+// smallest (a BF16 subnormal counts as exponent 0, which no scale can bring into range).
+__global__ void k_band_exp_range(int64_t m, const uint16_t *__restrict__ v, int32_t *__restrict__ ext) {
+    int32_t hi = -1, lo = 1 << 30;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const uint16_t b = v[e] & 0x7fff;
+        if (!b) continue;
+        const int32_t ex = b >> 7;
+        hi = max(hi, ex);
+        lo = min(lo, ex);
+    }
+    if (hi >= 0) {
+        atomicMax(&ext[0], hi);
+        atomicMin(&ext[1], lo);
+    }
+}
+
+// BF16 band values -> binary16 of value * 2^shift, exact when the exponent range allows it.
+__global__ void k_band_bf16_to_f16(int64_t m, uint16_t *__restrict__ v, int shift) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        v[e] = f32_to_f16_rne(ldexpf(bf16_bits_to_f32(v[e]), shift));
+}
+
 __global__ void k_pack_band(int64_t n, int64_t n_bblk, const int64_t *__restrict__ s_off,
                             const int32_t *__restrict__ s_lo, const int32_t *__restrict__ s_len,
                             const double *__restrict__ s_val64, const int64_t *__restrict__ bb_off,
@@ -1128,11 +1151,37 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
         g->bb_w.alloc(nb);
         g->bb_w.upload(bw.data(), nb, st);
         g->bb_val.alloc((size_t)std::max<int64_t>(boff[nb], 1) * eb);
+        g->bb_dtype = g->dtype;
         if (nb) {
             hipLaunchKernelGGL(k_pack_band, dim3((unsigned)std::min<int64_t>(nb, 1 << 20)), dim3(256), 0, st,
                                (int64_t)n, nb, g->s_off.p, g->s_lo.p, g->s_len.p, s_val64.p, g->bb_off.p, g->bb_lo.p,
                                g->bb_w.p, g->dtype, g->bb_val.p);
             QH_CHECK_LAUNCH();
+            if (g->dtype == QH_BF16) {
+                // a BF16 value 1.m x 2^E (7 fraction bits) is exact in binary16 after scaling by
+                // 2^s when E + s <= 15 and E - 7 + s >= -24: one s serves every value when the
+                // exponents span at most 32 binades; take the largest such s
+                const int32_t init[2] = {-1, 1 << 30};
+                DevBuf<int32_t> ext(2);
+                ext.upload(init, 2, st);
+                hipLaunchKernelGGL(k_band_exp_range, dim3(grid_for(boff[nb])), dim3(256), 0, st, boff[nb],
+                                   (const uint16_t *)g->bb_val.p, ext.p);
+                QH_CHECK_LAUNCH();
+                int32_t hl[2];
+                QH_HIP(hipMemcpyAsync(hl, ext.p, sizeof(hl), hipMemcpyDeviceToHost, st));
+                QH_HIP(hipStreamSynchronize(st));
+                const int e_max = hl[0] - 127, e_min = hl[1] - 127;
+                if (hl[0] < 0) {
+                    g->bb_dtype = QH_F16;          // all zeros
+                } else if (hl[1] > 0 && e_max - e_min <= 32 && e_max >= -45 && e_max <= 75) {
+                    const int shift = 15 - e_max;       // |shift| <= 60: the scale stays a normal float
+                    hipLaunchKernelGGL(k_band_bf16_to_f16, dim3(grid_for(boff[nb])), dim3(256), 0, st, boff[nb],
+                                       (uint16_t *)g->bb_val.p, shift);
+                    QH_CHECK_LAUNCH();
+                    g->bb_dtype = QH_F16;
+                    g->bb_scale = std::ldexp(1.0f, -shift);
+                }
+            }
         }
     }
     QH_HIP(hipStreamSynchronize(st));
@@ -1209,7 +1258,7 @@ void flip_crossing(qh_graph *g, const int8_t *spins, hipStream_t st) {
                        spins);
     if (g->n_bblk)
         hipLaunchKernelGGL(k_flip_band, dim3((unsigned)std::min<int64_t>(g->n_bblk, 1 << 20)), dim3(256), 0, st,
-                           g->n, g->n_bblk, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p, g->dtype, spins);
+                           g->n, g->n_bblk, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p, g->bb_dtype, spins);
     QH_CHECK_LAUNCH();
     // solve plans hold no copy of J; nothing else to refresh
 }

@@ -194,6 +194,12 @@ struct qh_graph {
     qh::DevBuf<int32_t> bb_lo, bb_w;    // [n_bblk]
     qh::DevBuf<uint8_t> bb_val;
     int64_t n_bblk = 0, bb_elems = 0;
+    // Encoding of bb_val: the graph's dtype, except that the BF16 band values of a graph are
+    // stored as binary16 holding value * 2^s when one power of two brings all of them into
+    // binary16 exactly (cheaper to expand); the band kernels multiply their sums by
+    // bb_scale = 2^-s, which restores the BF16 products bit for bit.
+    int bb_dtype = 0;
+    float bb_scale = 1.0f;
     // Long-range CSR (pairs farther apart than band_limit).
     qh::DevBuf<int64_t> l_ptr;          // [n + 1]
     qh::DevBuf<int32_t> l_col;
@@ -296,6 +302,7 @@ struct BlockDesc {
     const int32_t *bb_lo, *bb_w;
     const uint8_t *bb_val;
     float c0;
+    float bscale;               // band blocks: scale undoing their binary16 encoding (1: none)
     int32_t discrete;           // 1: the coupling takes sgn(x_j)
     uint16_t *h0, *h1;          // dense 16/8-bit: product copies [n_pad/8][R][8]
     float *xs;                  // dense f32 / band: second x buffer [n_pad][R]

@@ -305,16 +305,29 @@ def test_skyline_one_step(dtype, R, plan):
     _one_step_case(g, J, dtype, R, 200 + R, None, plan=plan)
 
 
-@pytest.mark.parametrize("case", ["snp", "porec"])
+@pytest.mark.parametrize("case", ["snp", "porec", "snp_large", "porec_wide"])
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 def test_band_kernel_equals_row_kernel_bit_exact(dtype, case):
     """Band blocks add exact zeros around each row's range in the same ascending column
-    order as the per-row kernel, so 200 steps of both agree bit for bit."""
-    if case == "snp":
+    order as the per-row kernel, so 200 steps of both agree bit for bit.  BF16 band values
+    are stored as binary16 of value x 2^s when one power of two makes all of them exact
+    there (the kernels multiply the band sums by 2^-s), else as BF16: "snp_large" scales every
+    fragment weight by 1e5 (past the binary16 range, still one scale), "porec_wide" shrinks
+    the Pore-C contacts by 1e-12 and keeps them in the band (more than 32 binades apart)."""
+    if case in ("snp", "snp_large"):
         w, band = synth.snp_small(26, n_snp=1700), 0
+        if case == "snp_large":
+            if dtype == "f16":
+                pytest.skip("weights past the binary16 range")
+            w.alpha = w.alpha * 1e5
+    elif case == "porec_wide":
+        w, band = synth.snp_porec(45, n_snp=2000, n_edges=2500, zipf_s=1.0), 0
+        w.alpha = np.where(w.alpha < 1.0, w.alpha * 1e-12, w.alpha)
     else:
         w, band = synth.snp_porec(45, n_snp=2000, n_edges=2500, zipf_s=1.0), 100
     g = gpu_graph(w, "snp_llr", dtype, band_limit=band)
+    want_band = {"f32": 0, "f16": 1, "bf16": 2 if case == "porec_wide" else 1}[dtype]
+    assert g.info()["band_dtype"] == want_band
     n, R = g.info()["n"], 128
     out = []
     for plan in (4, 3):          # band blocks on FMAs; per-row kernel
