@@ -92,11 +92,11 @@ def kernel_source_hash(kernel="k_dense_step"):
 
 
 def measured_traffic(kernel, replica_tile=None, depth=None):
-    """HBM bytes per launch of `kernel` from the committed counter summaries
-    (profiles/*_traffic.md), or None when none covers this kernel and configuration or the
-    kernel's source changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` from the committed counter summaries (the
+    `traffic:` lines of profiles/*.md), or None when none covers this kernel and
+    configuration or the kernel's source changed since the counters were taken."""
     import glob
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         vals = {}
         for line in open(path):
             if line.startswith("traffic:"):
