@@ -493,7 +493,13 @@ __global__ void k_band_exp_range(int64_t m, const uint16_t *__restrict__ v, int3
         hi = max(hi, ex);
         lo = min(lo, ex);
     }
-    if (hi >= 0) {
+    // wave-wide max / min first: one pair of atomics per wave
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        hi = max(hi, __shfl_xor(hi, d));
+        lo = min(lo, __shfl_xor(lo, d));
+    }
+    if ((threadIdx.x & 63) == 0 && hi >= 0) {
         atomicMax(&ext[0], hi);
         atomicMin(&ext[1], lo);
     }
