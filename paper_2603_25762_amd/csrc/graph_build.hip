@@ -468,10 +468,13 @@ __global__ void k_sky_row_fill(int64_t n, const int64_t *__restrict__ s_off, con
 }
 
 // FP64 -> stored number format (elementwise, RNE).
-__global__ void k_quantize(int64_t n, const double *__restrict__ src, int dtype, uint8_t *__restrict__ dst) {
+// flush: magnitudes below it store as 0 (BF16 SNP storage, see the caller); 0 = none
+__global__ void k_quantize(int64_t n, const double *__restrict__ src, int dtype, uint8_t *__restrict__ dst,
+                           double flush) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
         double v = src[t];
+        if (fabs(v) < flush) v = 0.0;
         switch (dtype) {
             case QH_F32: ((float *)dst)[t] = (float)v; break;
             case QH_F16: ((uint16_t *)dst)[t] = f64_to_f16_bits(v); break;
@@ -482,6 +485,22 @@ __global__ void k_quantize(int64_t n, const double *__restrict__ src, int dtype,
 
 // Band blocks: element (block b, column offset j, row i) = J[16b + i][bb_lo[b] + j], zero
 // outside the row's skyline range (and on the diagonal, which is zero anyway).
+// Largest |value| of an FP64 array, as the bits of a non-negative double (which order like
+// the values), reduced over the wave before one atomic.
+__global__ void k_absmax_bits(int64_t m, const double *__restrict__ v, unsigned long long *__restrict__ out) {
+    unsigned long long hi = 0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(v[e]));
+        hi = b > hi ? b : hi;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(hi, d);
+        hi = o > hi ? o : hi;
+    }
+    if ((threadIdx.x & 63) == 0 && hi) atomicMax(out, hi);
+}
+
 // Exponent range of nonzero BF16 band values: ext[0] = largest biased exponent, ext[1] =
 // smallest (a BF16 subnormal counts as exponent 0, which no scale can bring into range).
 __global__ void k_band_exp_range(int64_t m, const uint16_t *__restrict__ v, int32_t *__restrict__ ext) {
@@ -515,7 +534,7 @@ __global__ void k_pack_band(int64_t n, int64_t n_bblk, const int64_t *__restrict
                             const int32_t *__restrict__ s_lo, const int32_t *__restrict__ s_len,
                             const double *__restrict__ s_val64, const int64_t *__restrict__ bb_off,
                             const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, int dtype,
-                            uint8_t *__restrict__ out) {
+                            uint8_t *__restrict__ out, double flush) {
     for (int64_t b = blockIdx.x; b < n_bblk; b += gridDim.x) {
         const int64_t cnt = (int64_t)bb_w[b] * kBandRows;
         for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
@@ -523,6 +542,7 @@ __global__ void k_pack_band(int64_t n, int64_t n_bblk, const int64_t *__restrict
             const int64_t u = b * kBandRows + i, c = bb_lo[b] + j;
             double v = 0.0;
             if (u < n && c >= s_lo[u] && c < s_lo[u] + s_len[u]) v = s_val64[s_off[u] + (c - s_lo[u])];
+            if (fabs(v) < flush) v = 0.0;
             const int64_t o = bb_off[b] + e;
             switch (dtype) {
                 case QH_F32: ((float *)out)[o] = (float)v; break;
@@ -1119,18 +1139,42 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
                            g->s_len.p, s_val64.p, lp, g->l_col.p, l_val64.p, g->m_ptr.p, g->m_col.p, g->m_val.p);
         QH_CHECK_LAUNCH();
     }
-    // storage copy
+    // storage copy.  BF16 storage flushes magnitudes below 2^(E - 31), E the exponent of the
+    // largest |weight|, to zero: such entries are FP64 rounding residue of Eq. 14 sums whose
+    // terms cancel (or weights 2^-31 of the largest and below), and without them every BF16
+    // value fits one scaled binary16 encoding of the band (32 binades).
     int eb = dtype_bytes(g->dtype);
+    double flush = 0.0;
+    if (g->dtype == QH_BF16 && (slots || l_nnz)) {
+        DevBuf<unsigned long long> mx(1);
+        mx.zero(st);
+        if (slots)
+            hipLaunchKernelGGL(k_absmax_bits, dim3(grid_for(slots)), dim3(256), 0, st, slots, s_val64.p, mx.p);
+        if (l_nnz)
+            hipLaunchKernelGGL(k_absmax_bits, dim3(grid_for(l_nnz)), dim3(256), 0, st, l_nnz, l_val64.p, mx.p);
+        QH_CHECK_LAUNCH();
+        unsigned long long bits = 0;
+        QH_HIP(hipMemcpyAsync(&bits, mx.p, sizeof(bits), hipMemcpyDeviceToHost, st));
+        QH_HIP(hipStreamSynchronize(st));
+        double wmax;
+        std::memcpy(&wmax, &bits, sizeof(wmax));
+        if (wmax > 0.0) {
+            int ex = 0;
+            std::frexp(wmax, &ex);                 // wmax = f * 2^ex, f in [0.5, 1)
+            flush = std::ldexp(1.0, ex - 1 - 31);
+        }
+    }
+    g->snp_flush = flush;
     g->s_val.alloc((size_t)slots * eb);
     g->l_val.alloc((size_t)std::max<int64_t>(l_nnz, 1) * eb);
     if (slots) {
         hipLaunchKernelGGL(k_quantize, dim3(grid_for(slots)), dim3(256), 0, st, slots, s_val64.p, g->dtype,
-                           g->s_val.p);
+                           g->s_val.p, flush);
         QH_CHECK_LAUNCH();
     }
     if (l_nnz) {
         hipLaunchKernelGGL(k_quantize, dim3(grid_for(l_nnz)), dim3(256), 0, st, l_nnz, l_val64.p, g->dtype,
-                           g->l_val.p);
+                           g->l_val.p, flush);
         QH_CHECK_LAUNCH();
     }
     // band blocks for the register-tiled step kernel
@@ -1161,7 +1205,7 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
         if (nb) {
             hipLaunchKernelGGL(k_pack_band, dim3((unsigned)std::min<int64_t>(nb, 1 << 20)), dim3(256), 0, st,
                                (int64_t)n, nb, g->s_off.p, g->s_lo.p, g->s_len.p, s_val64.p, g->bb_off.p, g->bb_lo.p,
-                               g->bb_w.p, g->dtype, g->bb_val.p);
+                               g->bb_w.p, g->dtype, g->bb_val.p, flush);
             QH_CHECK_LAUNCH();
             if (g->dtype == QH_BF16) {
                 // a BF16 value 1.m x 2^E (7 fraction bits) is exact in binary16 after scaling by

@@ -200,6 +200,7 @@ struct qh_graph {
     // bb_scale = 2^-s, which restores the BF16 products bit for bit.
     int bb_dtype = 0;
     float bb_scale = 1.0f;
+    double snp_flush = 0.0;             // BF16 SNP storage: magnitudes below this are stored as 0
     // Long-range CSR (pairs farther apart than band_limit).
     qh::DevBuf<int64_t> l_ptr;          // [n + 1]
     qh::DevBuf<int32_t> l_col;

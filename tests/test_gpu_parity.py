@@ -132,6 +132,15 @@ def test_skyline_stored_values_bit_exact(dtype):
     J = oracle_graph(w, "snp_llr").dense()
     tol = 1e-12 * snp_abs_terms(w)
     lo, hi = quant.round_to(dtype, J - tol), quant.round_to(dtype, J + tol)
+    if dtype == "bf16":
+        # BF16 storage flushes magnitudes below 2^(E - 31), E = exponent of the largest weight
+        thr = 2.0 ** (np.floor(np.log2(np.abs(J).max())) - 31)
+        lo = np.where(np.abs(J) + tol < thr, 0.0, lo)
+        hi = np.where(np.abs(J) - tol < thr, np.where(np.abs(J) + tol < thr, 0.0, hi), hi)
+        maybe = (np.abs(J) - tol < thr) & (np.abs(J) + tol >= thr)
+        assert np.all(np.where(maybe, (S == 0) | (S == lo) | (S == hi), True))
+        lo = np.where(maybe, S, lo)
+        hi = np.where(maybe, S, hi)
     sure = lo == hi          # the master's last-bit freedom cannot move the rounding
     assert sure.mean() > 0.999
     assert np.array_equal(S[sure], lo[sure])
@@ -305,28 +314,34 @@ def test_skyline_one_step(dtype, R, plan):
     _one_step_case(g, J, dtype, R, 200 + R, None, plan=plan)
 
 
-@pytest.mark.parametrize("case", ["snp", "porec", "snp_large", "porec_wide"])
+@pytest.mark.parametrize("case", ["snp", "porec", "snp_large", "porec_wide", "snp_tiny"])
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 def test_band_kernel_equals_row_kernel_bit_exact(dtype, case):
     """Band blocks add exact zeros around each row's range in the same ascending column
     order as the per-row kernel, so 200 steps of both agree bit for bit.  BF16 band values
     are stored as binary16 of value x 2^s when one power of two makes all of them exact
-    there (the kernels multiply the band sums by 2^-s), else as BF16: "snp_large" scales every
-    fragment weight by 1e5 (past the binary16 range, still one scale), "porec_wide" shrinks
-    the Pore-C contacts by 1e-12 and keeps them in the band (more than 32 binades apart)."""
-    if case in ("snp", "snp_large"):
+    there (the kernels multiply the band sums by 2^-s; BF16 storage flushes magnitudes 2^31
+    below the largest, so this always holds unless the scale leaves the float range), else
+    as BF16: "snp_large" scales every fragment weight by 1e5 (past the binary16 range),
+    "porec_wide" shrinks the Pore-C contacts in the band by 1e-12 (flushed), "snp_tiny"
+    scales every weight by 1e-35 (the scale would be 2^128: the band stays BF16)."""
+    if case in ("snp", "snp_large", "snp_tiny"):
         w, band = synth.snp_small(26, n_snp=1700), 0
         if case == "snp_large":
             if dtype == "f16":
                 pytest.skip("weights past the binary16 range")
             w.alpha = w.alpha * 1e5
+        if case == "snp_tiny":
+            if dtype == "f16":
+                pytest.skip("weights below the binary16 range")
+            w.alpha = w.alpha * 1e-35
     elif case == "porec_wide":
         w, band = synth.snp_porec(45, n_snp=2000, n_edges=2500, zipf_s=1.0), 0
         w.alpha = np.where(w.alpha < 1.0, w.alpha * 1e-12, w.alpha)
     else:
         w, band = synth.snp_porec(45, n_snp=2000, n_edges=2500, zipf_s=1.0), 100
     g = gpu_graph(w, "snp_llr", dtype, band_limit=band)
-    want_band = {"f32": 0, "f16": 1, "bf16": 2 if case == "porec_wide" else 1}[dtype]
+    want_band = {"f32": 0, "f16": 1, "bf16": 2 if case == "snp_tiny" else 1}[dtype]
     assert g.info()["band_dtype"] == want_band
     n, R = g.info()["n"], 128
     out = []
