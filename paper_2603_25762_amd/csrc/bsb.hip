@@ -298,6 +298,7 @@ __global__ __launch_bounds__(256) void k_hub_partials(
 // gathered with the column broadcast from its lane, so the gathers of a packet are
 // independent of one another and of any further index load.  Each chunk is summed in
 // entry order, as in k_hub_partials.
+constexpr int kLrInFlight = 32;    // x-row gathers a wave keeps in flight (a packet has at most 64)
 template <int DT>
 __global__ __launch_bounds__(256) void k_lr_packets(
     int64_t n_pk, int R, const int32_t *__restrict__ pk_ptr, const int64_t *__restrict__ cbeg,
@@ -317,20 +318,20 @@ __global__ __launch_bounds__(256) void k_lr_packets(
             my_val = ld_val<DT>(l_val, e0 + lane);
         }
         if (lane < c1 - c0) my_end = (int32_t)(cend[c0 + lane] - e0);   // <= 64 chunks per packet
-        // eight gathers in flight across chunk boundaries; a chunk's sum is flushed when
+        // kLrInFlight gathers in flight across chunk boundaries; a chunk's sum is flushed when
         // its last entry has been added
         int32_t c = c0, ce = __builtin_amdgcn_readlane(my_end, 0);
         float z = 0.f;
-        for (int32_t j = 0; j < cnt; j += 8) {
-            float xv[8], vv[8];
+        for (int32_t j = 0; j < cnt; j += kLrInFlight) {
+            float xv[kLrInFlight], vv[kLrInFlight];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < kLrInFlight; ++k) {
                 const int32_t jj = j + k < 63 ? j + k : 63;      // lanes past cnt hold column 0
                 vv[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_val), jj));
                 xv[k] = coupling_value(x_in[(int64_t)__builtin_amdgcn_readlane(my_col, jj) * R + r], discrete);
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < kLrInFlight; ++k) {
                 if (j + k < cnt) {
                     if (j + k == ce) {
                         part[(int64_t)c * R + r] = z;
@@ -411,6 +412,9 @@ __device__ inline void band_column(const uint8_t *bb_val, int64_t e0, float (&v)
 // Rows of band block blk for replica r after the band columns: the long-range chunk
 // partials of each row (in chunk order) join the band sum z, then the fused update.
 // my_cp: lanes 0..kBandRows hold row_chunk_ptr of rows blk*kBandRows + lane.
+// NT: the state goes out with non-temporal stores (graphs with long-range rows, where it
+// leaves the L2 to the long-range gathers; measured on the Pore-C workload).
+template <bool NT>
 __device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int64_t r, const float (&z)[kBandRows],
                                          const float (&xo)[kBandRows], const float (&yo)[kBandRows], int32_t my_cp,
                                          const int32_t *__restrict__ row_chunk_ptr,
@@ -450,8 +454,13 @@ __device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int6
         const int64_t idx = u * R + r;
         float xv = xo[i], yv = yo[i];
         bsb_update(zi, xv, yv, coef, sa);
-        y[idx] = yv;
-        x_out[idx] = xv;
+        if constexpr (NT) {
+            __builtin_nontemporal_store(yv, &y[idx]);
+            __builtin_nontemporal_store(xv, &x_out[idx]);
+        } else {
+            y[idx] = yv;
+            x_out[idx] = xv;
+        }
     }
 }
 
@@ -462,7 +471,7 @@ __device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int6
 // long-range lists of the block's rows follow, then the fused update.
 // One band block of rows [blk*16, blk*16 + 16) for the lane's replica r (inactive lanes
 // skip every memory access).  Shared by the per-step and batched kernels.
-template <int DT>
+template <int DT, bool NT = false>
 __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_t r, bool active,
                                        const int64_t *__restrict__ bb_off, const int32_t *__restrict__ bb_lo,
                                        const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
@@ -486,7 +495,8 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
         z[i] = 0.f;
         const int64_t u = blk * RB + i;       // own state first: its latency hides under the band loop
         xo[i] = (active && u < n) ? x_in[u * R + r] : 0.f;
-        yo[i] = (active && u < n) ? y[u * R + r] : 0.f;
+        if constexpr (NT) yo[i] = (active && u < n) ? __builtin_nontemporal_load(&y[u * R + r]) : 0.f;
+        else yo[i] = (active && u < n) ? y[u * R + r] : 0.f;
     }
     // inactive lanes read replica 0 of the same rows (always in bounds) and weigh it by 0:
     // no divergent branch around the loads (|x| <= 1, so the product is an exact 0)
@@ -507,7 +517,7 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
     if (!active) return;
 #pragma unroll
     for (int i = 0; i < RB; ++i) z[i] *= sa.bscale;   // exact: a power of two
-    band_block_finish(blk, n, R, r, z, xo, yo, my_cp, row_chunk_ptr, hub_part, x_out, y, coef, sa);
+    band_block_finish<NT>(blk, n, R, r, z, xo, yo, my_cp, row_chunk_ptr, hub_part, x_out, y, coef, sa);
 }
 
 // The same band block on the matrix cores: a band block is a dense 16 x W matrix stored
@@ -596,7 +606,7 @@ __global__ __launch_bounds__(256) void k_band_step_mfma(
                                  row_chunk_ptr, hub_part, x_in, x_out, y, sa.a0 - sa.pump[sa.k], sa);
 }
 
-template <int DT>
+template <int DT, bool NT>
 __global__ __launch_bounds__(256) void k_band_step(
     int64_t n, int R, int64_t n_bblk, int64_t G, const int64_t *__restrict__ bb_off,
     const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
@@ -608,8 +618,8 @@ __global__ __launch_bounds__(256) void k_band_step(
     const int64_t blk = xcd_remap(blockIdx.x, G) * 4 + wave;
     if (blk >= n_bblk) return;
     const int64_t r = (int64_t)blockIdx.y * 64 + lane;
-    band_block_step<DT>(blk, n, R, r, true, bb_off, bb_lo, bb_w, bb_val, row_chunk_ptr, hub_part, x_in, x_out, y,
-                        sa.a0 - sa.pump[sa.k], sa);
+    band_block_step<DT, NT>(blk, n, R, r, true, bb_off, bb_lo, bb_w, bb_val, row_chunk_ptr, hub_part, x_in, x_out,
+                            y, sa.a0 - sa.pump[sa.k], sa);
 }
 
 // ---------------------------------------------------------------------------
@@ -929,10 +939,15 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
     if (sk == kSkyBandFma && !(RT == 64 && g->n_bblk > 0)) sk = kSkyRows;
     if (sk == kSkyBandMfma && g->n_bblk == 0) sk = kSkyRows;
     const int64_t GB = ceil_div(g->n_bblk, 4);
-#define QH_BAND(DTV)                                                                                            \
-    hipLaunchKernelGGL((k_band_step<DTV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, R,      \
+#define QH_BAND_NT(DTV, NTV)                                                                                    \
+    hipLaunchKernelGGL((k_band_step<DTV, NTV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, R, \
                        g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                          \
                        lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sa)
+#define QH_BAND(DTV)                                                    \
+    do {                                                                \
+        if (lr) QH_BAND_NT(DTV, true);                                  \
+        else QH_BAND_NT(DTV, false);                                    \
+    } while (0)
 #define QH_BANDM(DTV, NBV)                                                                                      \
     hipLaunchKernelGGL((k_band_step_mfma<DTV, NBV>), dim3((unsigned)GB, (unsigned)(R / (NBV * 16))), dim3(256), 0, \
                        st, n, R, g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                \
@@ -974,6 +989,7 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
 #undef QH_LR
 #undef QH_BANDM
 #undef QH_BAND
+#undef QH_BAND_NT
 #undef QH_SKY
 #undef QH_PK
 #undef QH_HUB
