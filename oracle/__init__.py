@@ -63,7 +63,7 @@ def _load():
         "or_splitmix64": (u64, [u64, u64]),
         "or_init": (None, [u64, i64, i32, P, P]),
         "or_bsb_run": (None, [i64, P, P, P, i32, i64, i64, P, dbl, dbl, dbl, P, P]),
-        "or_sb_run": (None, [i64, P, P, P, i32, i64, i64, P, dbl, dbl, dbl, P, P, i32]),
+        "or_sb_run": (None, [i64, P, P, P, i32, i64, i64, P, dbl, dbl, dbl, P, P, i32, P]),
         "or_pump_linear": (None, [i64, P]),
         "or_signs": (None, [i64, P, P]),
         "or_cuts": (None, [i64, P, P, P, P, i64, i32, P, P]),
@@ -250,24 +250,28 @@ def pump_linear(steps: int) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 def bsb_run(g: CSR, x: np.ndarray, y: np.ndarray, pump: np.ndarray, dt: float, c0_: float,
-            a0: float = 1.0, k_begin: int = 0, k_end: Optional[int] = None, discrete: bool = False):
+            a0: float = 1.0, k_begin: int = 0, k_end: Optional[int] = None, discrete: bool = False,
+            field: Optional[np.ndarray] = None):
     """Advance (x, y) in place over steps [k_begin, k_end) of the pump table.
 
-    ``discrete`` selects the discrete variant (dSB): the coupling uses sgn(x_j)."""
+    ``discrete`` selects the discrete variant (dSB): the coupling uses sgn(x_j).  ``field``
+    (length n) is the deformation term h: the coupling becomes c0 (J x + h)."""
     assert x.dtype == np.float64 and y.dtype == np.float64
     assert x.flags.c_contiguous and y.flags.c_contiguous
     n, R = x.shape
     pump = _c(pump, np.float64)
     if k_end is None:
         k_end = pump.shape[0]
+    h = None if field is None else _c(field, np.float64)
+    assert h is None or h.shape == (n,)
     _load().or_sb_run(g.n, _p(g.row_ptr), _p(g.col), _p(g.val), R, k_begin, k_end, _p(pump),
-                      dt, c0_, a0, _p(x), _p(y), int(discrete))
+                      dt, c0_, a0, _p(x), _p(y), int(discrete), None if h is None else _p(h))
     return x, y
 
 
 def bsb_step_dense(J: np.ndarray, x: np.ndarray, y: np.ndarray, p: float, dt: float, c0_: float,
                    a0: float = 1.0, product_format: Optional[str] = None, walls: bool = True,
-                   discrete: bool = False):
+                   discrete: bool = False, field: Optional[np.ndarray] = None):
     """One bSB step in FP64 with a dense J, returning (x', y').
 
     ``product_format`` (None, "f16", "bf16") rounds the x that enters the coupling
@@ -282,6 +286,8 @@ def bsb_step_dense(J: np.ndarray, x: np.ndarray, y: np.ndarray, p: float, dt: fl
     else:
         xq = x if product_format is None else quant.round_to(product_format, x)
     z = np.asarray(J, dtype=np.float64) @ xq
+    if field is not None:
+        z = z + np.asarray(field, dtype=np.float64)[:, None]
     y2 = y + (-(a0 - p) * x + c0_ * z) * dt
     x2 = x + a0 * y2 * dt
     if not walls:
@@ -375,15 +381,31 @@ def flip_crossing(g: CSR, s) -> CSR:
     return CSR(g.n, g.row_ptr, g.col, val)
 
 
+def deformation_field(seed: int, n: int, R: int, attempt: int, amplitude: float) -> np.ndarray:
+    """Deformation term h of refinement attempt ``attempt`` (1, 2, ...): the adaptive
+    strategy of the SNP-based method (Methods) perturbs a stuck round with a field.  The
+    paper gives no formula; this reading draws h_i = amplitude (2 u_i - 1) with u_i the
+    SplitMix64 output of the round's seed at draw 2 n R + (attempt - 1) n + i (the draws
+    after those of the initial state) mapped to [0, 1) by its top 53 bits."""
+    k0 = 2 * n * R + (attempt - 1) * n
+    u = np.array([(splitmix64(seed, k0 + i) >> 11) * 2.0 ** -53 for i in range(n)], dtype=np.float64)
+    return amplitude * (2.0 * u - 1.0)
+
+
 def refine(g: CSR, init_h1: np.ndarray, R: int, steps: int, dt: float = 0.5, seed: int = 0,
-           max_rounds: int = 15, integer: bool = False) -> Dict[str, object]:
+           max_rounds: int = 15, integer: bool = False, greedy_pass: bool = True,
+           deform: float = 0.0, deform_tries: int = 0) -> Dict[str, object]:
     """Iterative refinement of the SNP-based method (Eqs. 15-17).
 
-    Round t solves the current graph (seed + t).  A component stops when its cut is not
-    positive or its partition puts every vertex on one side; otherwise the vertices of its
-    smaller subset (the s = -1 subset on a tie) add one to their flip counter C and every
-    edge crossing the partition changes sign.  Haplotype 1 is H1 where C is even and H2
-    where C is odd.
+    Round t solves the current graph (seed + t).  With deform > 0, while a component still
+    being refined has a negative cut, the round is solved again (at most deform_tries
+    times, same seed) under the deformation field of amplitude deform / c0 (so that the
+    force c0 h_i stays within deform), and each such component takes the new spins when
+    their cut is higher (the adaptive strategy of the Methods for persistent negative
+    cuts).  A component stops when its cut is not positive or its partition puts every
+    vertex on one side; otherwise the vertices of its smaller subset (the s = -1 subset on
+    a tie) add one to their flip counter C and every edge crossing the partition changes
+    sign.  Haplotype 1 is H1 where C is even and H2 where C is odd.
     """
     comp, nc = components(g)
     C = np.zeros(g.n, dtype=np.int64)
@@ -391,12 +413,25 @@ def refine(g: CSR, init_h1: np.ndarray, R: int, steps: int, dt: float = 0.5, see
     cur = g
     round_cuts = []
     rounds = 0
+    deformed = 0
     for t in range(max_rounds):
         if done.all():
             break
-        r = solve(cur, R, steps, dt, seed=seed + t, integer=integer)
-        s = r["best"]
+        r = solve(cur, R, steps, dt, seed=seed + t, integer=integer, greedy_pass=greedy_pass)
+        s = r["best"].copy()
         cut_c = cuts(cur, comp, nc, s)[0] if nc else np.zeros(0)
+        for a in range(1, deform_tries + 1 if deform > 0 else 1):
+            stuck = [c for c in range(nc) if not done[c] and cut_c[c] < 0]
+            if not stuck:
+                break
+            h = deformation_field(seed + t, g.n, R, a, deform / r["c0"])
+            r2 = solve(cur, R, steps, dt, seed=seed + t, integer=integer, greedy_pass=greedy_pass, field=h)
+            deformed += 1
+            cut2 = cuts(cur, comp, nc, r2["best"])[0]
+            for c in stuck:
+                if cut2[c] > cut_c[c]:
+                    s[comp == c] = r2["best"][comp == c]
+                    cut_c[c] = cut2[c]
         s_eff = np.ones(g.n, dtype=np.int8)
         applied = 0.0
         for c in range(nc):
@@ -420,7 +455,7 @@ def refine(g: CSR, init_h1: np.ndarray, R: int, steps: int, dt: float = 0.5, see
     h1 = np.where(comp >= 0, np.where(C % 2 == 1, 1 - init_h1.astype(np.int64), init_h1), -1).astype(np.int8)
     block = np.where(comp >= 0, comp, -1).astype(np.int32)
     return dict(h1=h1, block=block, flips=C, rounds=rounds, round_cuts=round_cuts, comp=comp,
-                n_comp=nc)
+                n_comp=nc, deformed=deformed)
 
 
 # --------------------------------------------------------------------------
@@ -430,7 +465,8 @@ def refine(g: CSR, init_h1: np.ndarray, R: int, steps: int, dt: float = 0.5, see
 def solve(g: CSR, R: int, steps: int, dt: float = 0.5, c0_: Optional[float] = None,
           a0: float = 1.0, seed: int = 0, greedy_pass: bool = True, integer: bool = False,
           x0: Optional[np.ndarray] = None, y0: Optional[np.ndarray] = None,
-          pump: Optional[np.ndarray] = None, discrete: bool = False) -> Dict[str, object]:
+          pump: Optional[np.ndarray] = None, discrete: bool = False,
+          field: Optional[np.ndarray] = None) -> Dict[str, object]:
     comp, nc = components(g)
     if c0_ is None or c0_ <= 0:
         c0_ = c0(g)
@@ -441,7 +477,7 @@ def solve(g: CSR, R: int, steps: int, dt: float = 0.5, c0_: Optional[float] = No
         y = np.array(y0, dtype=np.float64, order="C")
     if pump is None:
         pump = pump_linear(steps)
-    bsb_run(g, x, y, pump, dt, c0_, a0, discrete=discrete)
+    bsb_run(g, x, y, pump, dt, c0_, a0, discrete=discrete, field=field)
     s = signs(x)
     cut = cuts(g, comp, nc, s)
     best, best_r = select(comp, nc, s, cut)

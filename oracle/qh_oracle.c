@@ -349,10 +349,14 @@ void or_init(uint64_t seed, int64_t n, int R, double *x, double *y) {
 /* for k in [k_begin, k_end), all R replicas side by side.  discrete = 1 gives  */
 /* the discrete variant of the same family (dSB): the coupling term uses        */
 /* sgn(x_j) (sgn(0) = +1) in place of x_j; everything else is unchanged.        */
+/* field (NULL = none) is the deformation term h of the adaptive strategy       */
+/* (Methods, SNP "SB algorithm solution"): a per-vertex field that joins the    */
+/* coupling, c0 (sum_j J_ij x_j + h_i), as the field of an Ising Hamiltonian    */
+/* -1/2 x'Jx - h'x does in the bifurcation equations.                           */
 /* ------------------------------------------------------------------------- */
 void or_sb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                int R, int64_t k_begin, int64_t k_end, const double *pump,
-               double dt, double c0, double a0, double *x, double *y, int discrete) {
+               double dt, double c0, double a0, double *x, double *y, int discrete, const double *field) {
     double *xnew = malloc((size_t)(n * R) * sizeof(double));
     double *z = malloc((size_t)(n * R) * sizeof(double));
     for (int64_t k = k_begin; k < k_end; ++k) {
@@ -369,8 +373,9 @@ void or_sb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const doub
                 else
                     for (int r = 0; r < R; ++r) zi[r] += J * xj[r];
             }
+            const double hi = field ? field[i] : 0.0;
             for (int r = 0; r < R; ++r) {
-                double yi = y[i * R + r] + (-(a0 - p) * x[i * R + r] + c0 * zi[r]) * dt;
+                double yi = y[i * R + r] + (-(a0 - p) * x[i * R + r] + c0 * (zi[r] + hi)) * dt;
                 double xi = x[i * R + r] + a0 * yi * dt;
                 if (fabs(xi) > 1.0) { xi = xi > 0 ? 1.0 : -1.0; yi = 0.0; }
                 y[i * R + r] = yi;
@@ -385,7 +390,7 @@ void or_sb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const doub
 void or_bsb_run(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                 int R, int64_t k_begin, int64_t k_end, const double *pump,
                 double dt, double c0, double a0, double *x, double *y) {
-    or_sb_run(n, row_ptr, col, val, R, k_begin, k_end, pump, dt, c0, a0, x, y, 0);
+    or_sb_run(n, row_ptr, col, val, R, k_begin, k_end, pump, dt, c0, a0, x, y, 0, NULL);
 }
 
 /* Linear pump 0 -> 1 with both ends included. */

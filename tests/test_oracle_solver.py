@@ -294,3 +294,122 @@ def test_dsb_greedy_hits_bruteforce_optimum(seed, n, integer):
     opt, _ = bruteforce.maxcut(D)
     r = oracle.solve(g, R=64, steps=1000, dt=0.5, seed=seed, integer=integer, discrete=True)
     assert r["best_cut"] == pytest.approx(opt, abs=1e-9)
+
+
+# ---------------------------------------------------------------- deformation field h
+
+def test_field_step_by_hand_zero_coupling():
+    """With J = 0 the field is the whole coupling force: y' = y + (-(a0 - p) x + c0 h) dt."""
+    g = csr_from_dense(np.zeros((2, 2)))
+    x = np.array([[0.05], [-0.08]])
+    y = np.array([[-0.02], [0.01]])
+    oracle.bsb_run(g, x, y, np.array([0.3]), dt=0.5, c0_=0.5, a0=1.0, field=np.array([0.4, -1.0]))
+    # vertex 0: y = -0.02 + (-0.7*0.05 + 0.5*0.4)*0.5 = 0.0625 ; x = 0.05 + 0.03125
+    assert y[0, 0] == pytest.approx(0.0625, abs=1e-16) and x[0, 0] == pytest.approx(0.08125, abs=1e-16)
+    # vertex 1: y = 0.01 + (0.7*0.08 - 0.5)*0.5 = -0.212 ; x = -0.08 - 0.106
+    assert y[1, 0] == pytest.approx(-0.212, abs=1e-15) and x[1, 0] == pytest.approx(-0.186, abs=1e-15)
+
+
+@pytest.mark.parametrize("discrete", [False, True])
+def test_field_equals_coupling_to_a_clamped_spin(discrete):
+    """h_i acts as a coupling J_i,a = h_i to an extra spin held at x_a = +1: stepping the
+    graph with that vertex appended (and re-clamped before every step) gives the field
+    run bit for bit, its coupling being the last term of every row's sum."""
+    rng = np.random.default_rng(7)
+    n, R, steps = 24, 8, 60
+    D = random_graph(3, n, 0.4, integer=False)
+    h = rng.normal(size=n) * 0.8
+    h[::5] = 0.0                                   # some vertices without a field
+    g = csr_from_dense(D)
+    A = np.zeros((n + 1, n + 1))
+    A[:n, :n] = D
+    A[:n, n] = A[n, :n] = h
+    ga = csr_from_dense(A)
+    pump = oracle.pump_linear(steps)
+    c0 = oracle.c0(g)
+    x, y = oracle.init_state(9, n, R)
+    oracle.bsb_run(g, x, y, pump, 0.5, c0, 1.0, discrete=discrete, field=h)
+    xa, ya = oracle.init_state(9, n + 1, R)
+    xa[:n], ya[:n] = oracle.init_state(9, n, R)
+    for k in range(steps):
+        xa[n], ya[n] = 1.0, 0.0
+        oracle.bsb_run(ga, xa, ya, pump, 0.5, c0, 1.0, k, k + 1, discrete=discrete)
+    assert np.array_equal(x, xa[:n]) and np.array_equal(y, ya[:n])
+    # the dense helper's field agrees with the sparse run for one step
+    x0, y0 = oracle.init_state(2, n, R)
+    x2, y2 = oracle.bsb_step_dense(D, x0, y0, 0.4, 0.5, c0, 1.0, discrete=discrete, field=h)
+    oracle.bsb_run(g, x0, y0, np.array([0.0, 0.4]), 0.5, c0, 1.0, 1, 2, discrete=discrete, field=h)
+    assert np.allclose(x2, x0, rtol=0, atol=1e-15) and np.allclose(y2, y0, rtol=0, atol=1e-15)
+
+
+def test_field_zero_and_mirror_symmetry():
+    """h = 0 is the plain step; (x, y, h) -> (-x, -y, -h) mirrors the whole trajectory."""
+    D = random_graph(5, 30, 0.3, integer=False)
+    g = csr_from_dense(D)
+    pump = oracle.pump_linear(200)
+    xa, ya = oracle.init_state(1, 30, 16)
+    xb, yb = xa.copy(), ya.copy()
+    oracle.bsb_run(g, xa, ya, pump, 0.5, oracle.c0(g), 1.0)
+    oracle.bsb_run(g, xb, yb, pump, 0.5, oracle.c0(g), 1.0, field=np.zeros(30))
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    h = np.random.default_rng(4).normal(size=30)
+    xp, yp = oracle.init_state(6, 30, 16)
+    xm, ym = -xp, -yp
+    oracle.bsb_run(g, xp, yp, pump, 0.5, oracle.c0(g), 1.0, field=h)
+    oracle.bsb_run(g, xm, ym, pump, 0.5, oracle.c0(g), 1.0, field=-h)
+    assert np.array_equal(xm, -xp) and np.array_equal(ym, -yp)
+
+
+def test_dominant_field_fixes_the_ground_state():
+    """When |h_i| exceeds sum_j |J_ij| the Ising energy -x'Jx/2 - h'x is lowest at
+    x = sgn(h) (each spin's field outweighs every coupling), and bSB reaches it in
+    every replica."""
+    D = random_graph(11, 20, 0.5, integer=False)
+    g = csr_from_dense(D)
+    rng = np.random.default_rng(12)
+    sgn = np.where(rng.random(20) < 0.5, -1.0, 1.0)
+    h = sgn * (np.abs(D).sum(axis=1) + 0.5)
+    r = oracle.solve(g, 32, 400, 0.5, seed=2, greedy_pass=False, field=h)
+    assert np.array_equal(r["spins"], np.repeat(sgn.astype(np.int8)[:, None], 32, axis=1))
+    # and by brute force no other spin vector has lower field energy
+    n = 12
+    Ds, hs = D[:n, :n], h[:n]
+    best, arg = None, None
+    for m in range(1 << n):
+        s = np.array([1.0 if (m >> i) & 1 else -1.0 for i in range(n)])
+        e = -0.5 * s @ Ds @ s - hs @ s
+        if best is None or e < best:
+            best, arg = e, s
+    assert np.array_equal(arg, sgn[:n])
+
+
+def test_deformed_refinement_properties():
+    """Adaptive deformation of the refinement: without a negative cut nothing changes; on
+    weights gauge-flipped around a good partition (where the one-sided partition is near
+    optimal, so rough spins cut negatively) the deformed attempts run, the applied cut
+    never drops, and the flip counters still carry exactly the sum of the applied cuts."""
+    w = synth.snp_small(24, n_snp=800)
+    g = oracle.build_graph(w, "snp_llr")
+    plain = oracle.refine(g, w.init_h1, 32, 300, 0.5, seed=1, max_rounds=1)
+    deformed = oracle.refine(g, w.init_h1, 32, 300, 0.5, seed=1, max_rounds=1, deform=0.5, deform_tries=3)
+    assert plain["round_cuts"][0] > 0 and deformed["deformed"] == 0
+    assert np.array_equal(plain["flips"], deformed["flips"]) and plain["round_cuts"] == deformed["round_cuts"]
+    # later rounds, whose weights are already near a good partition, do get stuck
+    later = oracle.refine(g, w.init_h1, 32, 300, 0.5, seed=1, max_rounds=4, deform=0.5, deform_tries=3)
+    g2 = oracle.flip_crossing(g, oracle.solve(g, 16, 600, 0.5, seed=1)["best"])
+    a = oracle.refine(g2, w.init_h1, 16, 2, 0.5, seed=3, max_rounds=2, greedy_pass=False)
+    b = oracle.refine(g2, w.init_h1, 16, 2, 0.5, seed=3, max_rounds=2, greedy_pass=False, deform=0.5,
+                      deform_tries=4)
+    assert a["deformed"] == 0 and b["deformed"] >= 1
+    assert sum(b["round_cuts"][:1]) >= sum(a["round_cuts"][:1])
+    for rr in (a, b, plain, later):
+        gg = g if rr is plain or rr is later else g2
+        S = np.where(rr["flips"] % 2 == 1, -1, 1).astype(np.int8)
+        total = oracle.cuts(gg, rr["comp"], rr["n_comp"], S).sum()
+        assert total == pytest.approx(sum(rr["round_cuts"]), rel=1e-12, abs=1e-9)
+    # the field of attempt a draws right after the initial state's draws of the round
+    n, R = 5, 4
+    h = oracle.deformation_field(77, n, R, 2, 3.0)
+    k0 = 2 * n * R + n
+    u = np.array([(oracle.splitmix64(77, k0 + i) >> 11) * 2.0 ** -53 for i in range(n)])
+    assert np.array_equal(h, 3.0 * (2.0 * u - 1.0)) and np.all(np.abs(h) <= 3.0)
