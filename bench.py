@@ -67,13 +67,13 @@ def calibrate_copy():
 def kernel_source_hash(kernel="k_dense_step"):
     """Hash of a step kernel's source.  k_dense_step: the dense-tile section of bsb.hip
     (from StepArgs to the skyline banner, the update helpers included); k_dense_persistent:
-    bsb_persistent.hip; k_band_step: the update helpers and the skyline section of bsb.hip.
+    persistent_kernel.h; k_band_step: the update helpers and the skyline section of bsb.hip.
     formats.h (the number formats) is part of every hash."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_25762_amd", "csrc")
     if kernel.startswith("k_dense_persistent"):
-        h.update(open(os.path.join(csrc, "bsb_persistent.hip"), "rb").read())
+        h.update(open(os.path.join(csrc, "persistent_kernel.h"), "rb").read())
     elif kernel.startswith("k_band_step"):
         src = open(os.path.join(csrc, "bsb.hip")).read()
         a = src.index("struct StepArgs")

@@ -193,6 +193,13 @@ typedef struct {
                             fences (L2 write-back / invalidate); 2 = every access of the copy
                             is device-coherent, no cache-wide fences; 0 = the autotuner's
                             choice or 1.  Bit-identical either way. */
+    const float *field;  /* deformation term h of the adaptive strategy (Methods, SNP-based
+                            solution): device float [n], the same for every replica, added
+                            to the coupling sum of every step, y += (-(a0 - p_k) x_i +
+                            c0 (sum_j J_ij x_j + h_i)) dt, the field of an Ising energy
+                            -x'Jx/2 - h'x.  NULL = no field (the plain bSB step).  Batched
+                            solves take it packed like the results (block b's vertices from
+                            its vertex offset).  Caller-owned; read during the call only. */
 } qh_bsb_opts;
 
 /* Result buffers (all device, caller-owned; optional ones may be NULL).
@@ -297,7 +304,13 @@ qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream);
 
 /* Iterative refinement of the SNP-based method (Eqs. 15-17), SNP graphs only.  Round t
  * (t = 0 .. max_rounds-1) runs qh_bsb_solve with opts (seed + t, readout on, whole
- * schedule) on the current weights.  A component is finished for good when the cut of
+ * schedule) on the current weights.  Adaptive deformation (Methods, SNP-based solution;
+ * deform > 0 and deform_tries > 0): while a component still being refined has a negative
+ * cut, round t is solved again, at most deform_tries times, under the deformation field
+ * h_i = (deform / c0) (2 u_i - 1) (opts.field replaced; u_i from SplitMix64 with the
+ * round's seed at draw 2 n R + (a - 1) n + i for attempt a = 1, 2, ...), and each such
+ * component takes the attempt's spins when their cut is higher.  deform = 0 or
+ * deform_tries = 0: no deformation.  A component is finished for good when the cut of
  * its selected spins is not positive or they put all its vertices on one side.  In each
  * other component the vertices of the smaller subset S_min (the s = -1 subset on a tie)
  * add one to their flip counter C, and every edge crossing the partition changes sign
@@ -309,10 +322,13 @@ qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream);
  *  round_cuts host double [max_rounds] cut applied in each round, summed over the
  *             components that flipped (optional)
  *  rounds     host int32           rounds that flipped something (optional)
+ *  deformed   host int32           deformed solves run, over all rounds (optional)
  * Synchronises the stream.  Errors: EUNSUPPORTED (read graph), EINVAL (max_rounds < 1,
- * init = 0, options as for qh_bsb_solve), ENUMERIC, ENOMEM, EHIP. */
-qh_status qh_refine(qh_graph *g, const qh_bsb_opts *opts, int32_t max_rounds, int8_t *h1, int32_t *block,
-                    int32_t *flips, double *round_cuts, int32_t *rounds, void *stream);
+ * deform or deform_tries negative, init = 0, options as for qh_bsb_solve), ENUMERIC,
+ * ENOMEM, EHIP. */
+qh_status qh_refine(qh_graph *g, const qh_bsb_opts *opts, int32_t max_rounds, float deform, int32_t deform_tries,
+                    int8_t *h1, int32_t *block, int32_t *flips, double *round_cuts, int32_t *rounds,
+                    int32_t *deformed, void *stream);
 
 const char *qh_last_error(void);
 const char *qh_version(void);

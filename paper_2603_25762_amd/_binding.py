@@ -67,7 +67,8 @@ class _BsbOpts(ctypes.Structure):
                 ("readout", ctypes.c_int32), ("greedy", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("plan", ctypes.c_int32),
                 ("replica_tile", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("tiles_in_flight", ctypes.c_int32), ("persistent_sync", ctypes.c_int32)]
+                ("tiles_in_flight", ctypes.c_int32), ("persistent_sync", ctypes.c_int32),
+                ("field", P)]
 
 
 class _Result(ctypes.Structure):
@@ -117,7 +118,8 @@ def load():
                                  ctypes.POINTER(_BatchedResult), P],
         "qh_phase": [P, P, P, P, P],
         "qh_flip_crossing": [P, P, P],
-        "qh_refine": [P, ctypes.POINTER(_BsbOpts), ctypes.c_int32, P, P, P, ctypes.POINTER(ctypes.c_double),
+        "qh_refine": [P, ctypes.POINTER(_BsbOpts), ctypes.c_int32, ctypes.c_float, ctypes.c_int32, P, P, P,
+                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                       ctypes.POINTER(ctypes.c_int32), P],
         "qh_solve_plan_info": [P, ctypes.c_int32, ctypes.POINTER(_PlanInfo)],
     }
@@ -238,22 +240,44 @@ def build_graph(frag_ptr: torch.Tensor, snp: torch.Tensor, allele: torch.Tensor,
     return Graph(h.value)
 
 
+def _check_field(field: Optional[torch.Tensor], n: int):
+    if field is None:
+        return
+    if field.dtype != torch.float32 or field.device.type != "cuda" or not field.is_contiguous():
+        raise TypeError("field must be a contiguous float32 device tensor")
+    if field.numel() != n:
+        raise ValueError(f"field holds {field.numel()} values for {n} vertices")
+
+
+def adaptive_schedule(n: int) -> Dict[str, int]:
+    """The SNP-based method's size-adaptive bSB settings (Tables 1 and 2, footnotes):
+    500 iterations below 5,000 vertices and 1,000 otherwise, 100 samples, at most 15
+    refinement rounds.  The solvers take 16, 32 or a multiple of 64 replicas, so the
+    100 samples become the next such count, 128 (more samples never lower the best cut
+    of a component)."""
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    return dict(steps=500 if n < 5000 else 1000, samples=100, replicas=128, max_rounds=15)
+
+
 def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float = 0.0,
               a0: float = 1.0, pump: Optional[torch.Tensor] = None, seed: int = 0,
               init: bool = True, x: Optional[torch.Tensor] = None, y: Optional[torch.Tensor] = None,
               step_begin: int = 0, step_end: int = 0, readout: bool = True, greedy: bool = True,
               use_graph: bool = False, all_spins: bool = False, per_component: bool = False,
               plan: int = 0, replica_tile: int = 0, discrete: bool = False, tiles_in_flight: int = 0,
-              persistent_sync: int = 0,
+              persistent_sync: int = 0, field: Optional[torch.Tensor] = None,
               out: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
     """Runs bSB; returns device tensors (best_spins, cuts, best_cut, selected_cut, ...).
 
     ``x``/``y`` (float32 [n, R]) give the starting state when ``init`` is False and
-    receive the final state when passed.  ``out`` may supply preallocated result
-    tensors (keys as returned) so that repeated calls allocate nothing.
+    receive the final state when passed.  ``field`` (float32 [n], device) is the
+    deformation term h added to every row's coupling sum.  ``out`` may supply
+    preallocated result tensors (keys as returned) so that repeated calls allocate nothing.
     """
     inf = g.info()
     n, nc = inf["n"], inf["n_comp"]
+    _check_field(field, n)
     dev = "cuda"
     res = {} if out is None else dict(out)
     keep = {}
@@ -287,7 +311,7 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
         res["pump"] = pump
     opts = _BsbOpts(replicas, steps, step_begin, step_end, dt, c0, a0, _ptr(pump), seed & (2**64 - 1),
                     int(init), int(readout), int(greedy), int(use_graph), int(plan), int(replica_tile),
-                    int(discrete), int(tiles_in_flight), int(persistent_sync))
+                    int(discrete), int(tiles_in_flight), int(persistent_sync), _ptr(field))
     r = _Result(_ptr(x), _ptr(y), _ptr(keep.get("best_spins")), _ptr(keep.get("cuts")),
                 _ptr(keep.get("cut_rc")), _ptr(keep.get("best_replica")), _ptr(keep.get("selected_cut")),
                 _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")))
@@ -298,10 +322,15 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
 def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt: float = 0.5,
                       c0: float = 0.0, a0: float = 1.0, seed: int = 0, greedy: bool = True,
                       use_graph: bool = False, plan: int = 0, return_state: bool = False,
-                      discrete: bool = False, stream=None) -> Dict[str, torch.Tensor]:
-    """All graphs in one launch; per-block results packed at ``vertex_offset`` / ``b * replicas``."""
+                      discrete: bool = False, field: Optional[torch.Tensor] = None,
+                      stream=None) -> Dict[str, torch.Tensor]:
+    """All graphs in one launch; per-block results packed at ``vertex_offset`` / ``b * replicas``.
+
+    ``field`` (float32 [sum n], device) is packed the same way: block b's deformation
+    term from ``vertex_offset[b]``."""
     ns = [g.info()["n"] for g in graphs]
     total = int(sum(ns))
+    _check_field(field, total)
     nb = len(graphs)
     dev = "cuda"
     res = dict(best_spins=torch.empty(max(total, 1), dtype=torch.int8, device=dev),
@@ -313,7 +342,7 @@ def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt:
         res["y"] = torch.empty(max(total * replicas, 1), dtype=torch.float32, device=dev)
     arr = (ctypes.c_void_p * max(nb, 1))(*[g.handle.value for g in graphs])
     opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
-                    int(use_graph), plan, 0, int(discrete), 0, 0)
+                    int(use_graph), plan, 0, int(discrete), 0, 0, _ptr(field))
     r = _BatchedResult(_ptr(res["best_spins"]), _ptr(res["cuts"]), _ptr(res["best_cut"]),
                        _ptr(res["selected_cut"]), _ptr(res.get("x")), _ptr(res.get("y")), 0)
     _check(load().qh_bsb_solve_batched(arr, nb, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
@@ -341,8 +370,11 @@ def flip_crossing(g: Graph, spins: torch.Tensor, stream=None):
 
 def refine(g: Graph, replicas: int, steps: int, *, max_rounds: int = 15, dt: float = 0.5, c0: float = 0.0,
            a0: float = 1.0, seed: int = 0, greedy: bool = True, use_graph: bool = False, plan: int = 0,
-           discrete: bool = False, stream=None) -> Dict[str, object]:
-    """Multi-round SNP refinement: h1, block (device), flips (device), round_cuts, rounds."""
+           discrete: bool = False, deform: float = 0.0, deform_tries: int = 0,
+           stream=None) -> Dict[str, object]:
+    """Multi-round SNP refinement: h1, block (device), flips (device), round_cuts, rounds,
+    deformed (re-solves under the deformation field, taken while a component's cut is
+    negative: at most ``deform_tries`` per round, field amplitude ``deform / c0``)."""
     inf = g.info()
     n, n_snp = inf["n"], inf["n_snp"]
     h1 = torch.empty(max(n_snp, 1), dtype=torch.int8, device="cuda")
@@ -350,9 +382,12 @@ def refine(g: Graph, replicas: int, steps: int, *, max_rounds: int = 15, dt: flo
     flips = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
     rc = (ctypes.c_double * max_rounds)()
     rounds = ctypes.c_int32(0)
+    deformed = ctypes.c_int32(0)
     opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
-                    int(use_graph), plan, 0, int(discrete), 0, 0)
-    _check(load().qh_refine(g.handle, ctypes.byref(opts), max_rounds, _ptr(h1), _ptr(block), _ptr(flips), rc,
-                            ctypes.byref(rounds), _stream(stream)))
+                    int(use_graph), plan, 0, int(discrete), 0, 0, None)
+    _check(load().qh_refine(g.handle, ctypes.byref(opts), max_rounds, float(deform), int(deform_tries), _ptr(h1),
+                            _ptr(block), _ptr(flips), rc, ctypes.byref(rounds), ctypes.byref(deformed),
+                            _stream(stream)))
     k = rounds.value
-    return dict(h1=h1[:n_snp], block=block[:n_snp], flips=flips[:n], round_cuts=list(rc[:k]), rounds=k)
+    return dict(h1=h1[:n_snp], block=block[:n_snp], flips=flips[:n], round_cuts=list(rc[:k]), rounds=k,
+                deformed=deformed.value)

@@ -13,7 +13,7 @@ OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libqhap.so")
 OBJ_DIR = os.path.join(ROOT, "_build", "qhap")
 
-SOURCES = ["api.hip", "graph_build.hip", "bsb.hip", "bsb_persistent.hip", "phase.hip", "batched.hip", "refine.hip", "readout.hip", "memory.hip"]
+SOURCES = ["api.hip", "graph_build.hip", "bsb.hip", "bsb_persistent.hip", "bsb_persistent_field.hip", "phase.hip", "batched.hip", "refine.hip", "readout.hip", "memory.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -237,12 +237,14 @@ qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream) {
     });
 }
 
-qh_status qh_refine(qh_graph *g, const qh_bsb_opts *opts, int32_t max_rounds, int8_t *h1, int32_t *block,
-                    int32_t *flips, double *round_cuts, int32_t *rounds, void *stream) {
+qh_status qh_refine(qh_graph *g, const qh_bsb_opts *opts, int32_t max_rounds, float deform, int32_t deform_tries,
+                    int8_t *h1, int32_t *block, int32_t *flips, double *round_cuts, int32_t *rounds,
+                    int32_t *deformed, void *stream) {
     return guarded([&] {
         if (!g || !h1 || !block) fail(QH_EINVAL, "null argument");
         validate_opts(opts);
-        refine(g, opts, max_rounds, h1, block, flips, round_cuts, rounds, (hipStream_t)stream);
+        refine(g, opts, max_rounds, deform, deform_tries, h1, block, flips, round_cuts, rounds, deformed,
+               (hipStream_t)stream);
     });
 }
 

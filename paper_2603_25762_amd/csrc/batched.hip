@@ -80,6 +80,7 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
     const float *pump = o->pump ? o->pump : linear_pump(*plans[0], o->steps, st);
 
     std::vector<BlockDesc> desc(nb);
+    int64_t foff = 0;   // the field is packed like the results: block b from its vertex offset
     for (int b = 0; b < nb; ++b) {
         const qh_graph *g = gs[b];
         SolvePlan &p = *plans[b];
@@ -93,6 +94,8 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         d.y = p.y.p;
         d.c0 = (float)(o->c0 > 0.0 ? o->c0 : g->c0_auto);
         d.discrete = o->variant == 1;
+        d.field = o->field ? o->field + foff : nullptr;
+        foff += g->n;
         if (d.kind == 0) {
             d.n_rt = g->n_rt;
             d.t_ptr = g->t_ptr.p;

@@ -27,13 +27,6 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // initial state: SplitMix64 (Steele, Lea & Flood 2014), draw k = 2 (r n + i) + {0, 1}
 // ---------------------------------------------------------------------------
 
-__device__ inline uint64_t sm64_draw(uint64_t seed, uint64_t k) {
-    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
 __global__ void k_init(uint64_t seed, int64_t n, int R, float *__restrict__ x, float *__restrict__ y) {
     int64_t total = n * R;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -76,7 +69,14 @@ struct StepArgs {
     int k;
     int discrete;   // 1: the coupling takes sgn(x_j) (discrete variant), 0: x_j
     float bscale;   // band blocks: power of two undoing the scale of their binary16 encoding (1: none)
+    const float *field;   // deformation field h [n] joining the coupling sum (nullptr: none)
 };
+
+// The coupling sum of row i with the deformation field added: the field enters after the
+// whole sum J x, so every step kernel rounds it identically.
+__device__ inline float with_field(float z, int64_t i, const StepArgs &s) {
+    return s.field ? z + s.field[i] : z;
+}
 
 
 __device__ inline void bsb_update(float z, float &x, float &y, float coef, const StepArgs &s) {
@@ -221,6 +221,7 @@ __device__ inline void dense_update(const float4_t (&acc)[NB], const float (&xo)
             if (i < n) {
                 float z = acc[b][q];
                 if constexpr (DT == QH_FP8_ROWSCALE) z *= row_scale[i];
+                z = with_field(z, i, sa);
                 const int64_t idx = i * R + r;
                 float xv = xo[b][q], yv = yo[b][q];
                 bsb_update(z, xv, yv, coef, sa);
@@ -376,6 +377,7 @@ __global__ __launch_bounds__(256) void k_sky_step(
         for (int e = 0; e < len; ++e) z += ld_val<DT>(s_val, off + e) * coupling_value(xc[(int64_t)e * R], sa.discrete);
         if (row_chunk_ptr)
             for (int c = row_chunk_ptr[u]; c < row_chunk_ptr[u + 1]; ++c) z += hub_part[(int64_t)c * R + r];
+        z = with_field(z, u, sa);
         const int64_t idx = u * R + r;
         float xv = x_in[idx], yv = y[idx];
         bsb_update(z, xv, yv, coef, sa);
@@ -414,7 +416,8 @@ __device__ inline void band_column(const uint8_t *bb_val, int64_t e0, float (&v)
 // my_cp: lanes 0..kBandRows hold row_chunk_ptr of rows blk*kBandRows + lane.
 // NT: the state goes out with non-temporal stores (graphs with long-range rows, where it
 // leaves the L2 to the long-range gathers; measured on the Pore-C workload).
-template <bool NT>
+// FLD = false compiles the deformation field out (launches without one).
+template <bool NT, bool FLD = true>
 __device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int64_t r, const float (&z)[kBandRows],
                                          const float (&xo)[kBandRows], const float (&yo)[kBandRows], int32_t my_cp,
                                          const int32_t *__restrict__ row_chunk_ptr,
@@ -451,6 +454,7 @@ __device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int6
                 for (; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
             }
         }
+        if constexpr (FLD) zi = with_field(zi, u, sa);
         const int64_t idx = u * R + r;
         float xv = xo[i], yv = yo[i];
         bsb_update(zi, xv, yv, coef, sa);
@@ -471,7 +475,7 @@ __device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int6
 // long-range lists of the block's rows follow, then the fused update.
 // One band block of rows [blk*16, blk*16 + 16) for the lane's replica r (inactive lanes
 // skip every memory access).  Shared by the per-step and batched kernels.
-template <int DT, bool NT = false>
+template <int DT, bool NT = false, bool FLD = true>
 __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_t r, bool active,
                                        const int64_t *__restrict__ bb_off, const int32_t *__restrict__ bb_lo,
                                        const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
@@ -517,7 +521,7 @@ __device__ inline void band_block_step(int64_t blk, int64_t n, int64_t R, int64_
     if (!active) return;
 #pragma unroll
     for (int i = 0; i < RB; ++i) z[i] *= sa.bscale;   // exact: a power of two
-    band_block_finish<NT>(blk, n, R, r, z, xo, yo, my_cp, row_chunk_ptr, hub_part, x_out, y, coef, sa);
+    band_block_finish<NT, FLD>(blk, n, R, r, z, xo, yo, my_cp, row_chunk_ptr, hub_part, x_out, y, coef, sa);
 }
 
 // The same band block on the matrix cores: a band block is a dense 16 x W matrix stored
@@ -584,6 +588,7 @@ __device__ inline void band_block_step_mfma(int64_t blk, int64_t n, int64_t R, i
             float zi = acc[b][q] * sa.bscale;
             if (row_chunk_ptr)
                 for (int c = cb; c < ce; ++c) zi += hub_part[(int64_t)c * R + r];
+            zi = with_field(zi, u, sa);
             const int64_t idx = u * R + r;
             float xv = xo[b][q], yv = yo[b][q];
             bsb_update(zi, xv, yv, coef, sa);
@@ -606,7 +611,7 @@ __global__ __launch_bounds__(256) void k_band_step_mfma(
                                  row_chunk_ptr, hub_part, x_in, x_out, y, sa.a0 - sa.pump[sa.k], sa);
 }
 
-template <int DT, bool NT>
+template <int DT, bool NT, bool FLD>
 __global__ __launch_bounds__(256) void k_band_step(
     int64_t n, int R, int64_t n_bblk, int64_t G, const int64_t *__restrict__ bb_off,
     const int32_t *__restrict__ bb_lo, const int32_t *__restrict__ bb_w, const uint8_t *__restrict__ bb_val,
@@ -618,8 +623,8 @@ __global__ __launch_bounds__(256) void k_band_step(
     const int64_t blk = xcd_remap(blockIdx.x, G) * 4 + wave;
     if (blk >= n_bblk) return;
     const int64_t r = (int64_t)blockIdx.y * 64 + lane;
-    band_block_step<DT, NT>(blk, n, R, r, true, bb_off, bb_lo, bb_w, bb_val, row_chunk_ptr, hub_part, x_in, x_out,
-                            y, sa.a0 - sa.pump[sa.k], sa);
+    band_block_step<DT, NT, FLD>(blk, n, R, r, true, bb_off, bb_lo, bb_w, bb_val, row_chunk_ptr, hub_part, x_in,
+                                 x_out, y, sa.a0 - sa.pump[sa.k], sa);
 }
 
 // ---------------------------------------------------------------------------
@@ -664,7 +669,7 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
         float *xb = B.x, *yb = B.y;
         block_init<R>(B, seed, tid);
         const bool dense16 = B.kind == 0 && B.dtype != QH_F32;
-        StepArgs sa{B.c0, dt, a0, pump, 0, B.discrete, B.bscale};
+        StepArgs sa{B.c0, dt, a0, pump, 0, B.discrete, B.bscale, B.field};
         float *cur = xb, *oth = B.xs;
         for (int s = 0; s < steps; ++s) {
             sa.k = s;
@@ -729,7 +734,7 @@ __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restric
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int2 I = items[xcd_remap(blockIdx.x, n_items)];
     const BlockDesc &B = blocks[I.x];
-    const StepArgs sa{B.c0, dt, a0, pump, k, B.discrete, B.bscale};
+    const StepArgs sa{B.c0, dt, a0, pump, k, B.discrete, B.bscale, B.field};
     const float coef = a0 - pump[k];
     const int cur = k & 1;
     const int64_t n = B.n;
@@ -939,10 +944,15 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
     if (sk == kSkyBandFma && !(RT == 64 && g->n_bblk > 0)) sk = kSkyRows;
     if (sk == kSkyBandMfma && g->n_bblk == 0) sk = kSkyRows;
     const int64_t GB = ceil_div(g->n_bblk, 4);
-#define QH_BAND_NT(DTV, NTV)                                                                                    \
-    hipLaunchKernelGGL((k_band_step<DTV, NTV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, R, \
-                       g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                          \
+#define QH_BAND_K(DTV, NTV, FLDV)                                                                                 \
+    hipLaunchKernelGGL((k_band_step<DTV, NTV, FLDV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, \
+                       R, g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                         \
                        lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sa)
+#define QH_BAND_NT(DTV, NTV)                                            \
+    do {                                                                \
+        if (sa.field) QH_BAND_K(DTV, NTV, true);                        \
+        else QH_BAND_K(DTV, NTV, false);                                \
+    } while (0)
 #define QH_BAND(DTV)                                                    \
     do {                                                                \
         if (lr) QH_BAND_NT(DTV, true);                                  \
@@ -990,6 +1000,7 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
 #undef QH_BANDM
 #undef QH_BAND
 #undef QH_BAND_NT
+#undef QH_BAND_K
 #undef QH_SKY
 #undef QH_PK
 #undef QH_HUB
@@ -1008,6 +1019,7 @@ static int run_steps(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, cons
     sa.pump = pump;
     sa.discrete = o->variant == 1;
     sa.bscale = g->bb_scale;
+    sa.field = o->field;
     int cur = 0;
     for (int k = kb; k < ke; ++k) {
         sa.k = k;
@@ -1036,7 +1048,7 @@ __global__ void k_zero_i32(int64_t n, int *__restrict__ p) {
 
 // Steps [kb, ke) in one cooperative launch; the state is in p.xa / p.y / p.ha.
 static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, double c0, double dt, double a0,
-                           int kb, int ke, int discrete, int coherent, hipStream_t st) {
+                           int kb, int ke, int discrete, const float *field, int coherent, hipStream_t st) {
     PersistPlan &pp = *p.pp;
     hipLaunchKernelGGL(k_zero_i32, dim3(grid_for((int64_t)pp.flags.n)), dim3(256), 0, st, (int64_t)pp.flags.n,
                        pp.flags.p);
@@ -1068,6 +1080,7 @@ static void run_persistent(const qh_graph *g, SolvePlan &p, const float *pump, d
     pa.a0 = (float)a0;
     pa.pump = pump;
     pa.discrete = discrete;
+    pa.field = field;
     pa.lds_j_bytes = pp.lds_j_bytes;
     pa.lds_tab_off = pp.lds_tab_off;
     pa.max_wg_tiles = pp.max_wg_tiles;
@@ -1119,7 +1132,7 @@ static void autotune_dense(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o
             if (!x_pingpong(g)) x_to_h(g, p, n, R, o->variant == 1, st);
             QH_HIP(hipEventRecord(e0, st));
             if (cand > 0) run_steps(g, p, o, pump, c0, a0, 0, nt, st);
-            else run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, o->variant == 1, cand < 0, st);
+            else run_persistent(g, p, pump, c0, o->dt, a0, 0, nt, o->variant == 1, o->field, cand < 0, st);
             QH_HIP(hipEventRecord(e1, st));
             QH_HIP(hipEventSynchronize(e1));
         }
@@ -1266,11 +1279,11 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     if (persistent) {
         const int coherent = o->persistent_sync == 2 || (o->persistent_sync == 0 && p.tuned_coh);
         p.last_coh = coherent;
-        run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, o->variant == 1, coherent, st);
+        run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, o->variant == 1, o->field, coherent, st);
     } else if (ke > kb && n > 0) {
         if (o->use_graph) {
             auto key = std::make_tuple(kb, ke, (int)g->dtype, c0, o->dt, a0, pump, R,
-                                       (p.run_rt * 8 + p.run_depth) * 2 + (o->variant == 1));
+                                       (p.run_rt * 8 + p.run_depth) * 2 + (o->variant == 1), o->field);
             if (!p.exec || p.graph_key != key) {
                 if (p.exec) { (void)hipGraphExecDestroy(p.exec); p.exec = nullptr; }
                 if (p.graph) { (void)hipGraphDestroy(p.graph); p.graph = nullptr; }

@@ -138,7 +138,7 @@ struct SolvePlan {
     // captured step loop
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::tuple<int, int, int, double, double, double, const float *, int, int> graph_key{};
+    std::tuple<int, int, int, double, double, double, const float *, int, int, const float *> graph_key{};
     ~SolvePlan() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -285,8 +285,9 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out);
 
 // phase.hip
 void phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);
-void refine(qh_graph *g, const qh_bsb_opts *o, int max_rounds, int8_t *h1, int32_t *block, int32_t *flips,
-            double *round_cuts, int32_t *rounds_out, hipStream_t st);
+void refine(qh_graph *g, const qh_bsb_opts *o, int max_rounds, float deform, int deform_tries, int8_t *h1,
+            int32_t *block, int32_t *flips, double *round_cuts, int32_t *rounds_out, int32_t *deformed_out,
+            hipStream_t st);
 
 // Device-side descriptor of one block of a batched solve.
 struct BlockDesc {
@@ -307,6 +308,7 @@ struct BlockDesc {
     int32_t discrete;           // 1: the coupling takes sgn(x_j)
     uint16_t *h0, *h1;          // dense 16/8-bit: product copies [n_pad/8][R][8]
     float *xs;                  // dense f32 / band: second x buffer [n_pad][R]
+    const float *field;         // deformation field of the block's vertices [n] (nullptr: none)
 };
 void launch_batched(int R, int workers, const BlockDesc *blocks, const int32_t *sched_ptr, const int32_t *sched,
                     int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
@@ -317,6 +319,14 @@ int batched_workers_per_cu(int R);
 constexpr int kBatchClasses = 7;   // dense F32/F16/BF16/FP8, band F32/F16/BF16
 void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, const int64_t *class_ptr,
                           int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
+// SplitMix64 (Steele, Lea & Flood 2014): the k-th output of the generator seeded with seed
+__device__ inline uint64_t sm64_draw(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 SolvePlan &solve_plan(const qh_graph *g, int R, hipStream_t st);
 const float *linear_pump(SolvePlan &p, int steps, hipStream_t st);   // p_k = k / (steps - 1)
 

@@ -24,6 +24,7 @@ struct PersistArgs {
     float c0, dt, a0;
     const float *pump;
     int discrete;               // 1: the 16-bit copy holds sgn(x) (discrete variant)
+    const float *field;         // deformation field h [n] added to the coupling sum (nullptr: none)
     int64_t lds_j_bytes;
     int64_t lds_tab_off;        // LDS offset of the tables: slots of the own stored tiles [max_wg_tiles],
                                 // then the column tiles staged from memory and their slots [max_ct] each
@@ -47,5 +48,8 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
 // instead of cache-wide fences (both give identical results)
 void launch_persistent(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, int coherent,
                        hipStream_t st);
+// the same with args.field set (the kernels that add the deformation field)
+void launch_persistent_field(const qh_graph *g, const PersistPlan &pp, const PersistArgs &args, int coherent,
+                             hipStream_t st);
 
 }  // namespace qh

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 import paper_2603_25762_amd as qh
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -29,3 +31,15 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_string():
     assert qh.version().startswith("qhap-gfx950")
+
+
+def test_adaptive_schedule_follows_the_paper():
+    """SNP-based settings adapted to graph size (Tables 1 and 2, footnotes): 500 iterations
+    below 5,000 vertices, 1,000 from there on, 100 samples (run as 128 replicas, the
+    replica counts being 16, 32 or multiples of 64) and at most 15 refinement rounds."""
+    for n, steps in ((0, 500), (1, 500), (4999, 500), (5000, 1000), (120_000, 1000)):
+        a = qh.adaptive_schedule(n)
+        assert a["steps"] == steps and a["samples"] == 100 and a["max_rounds"] == 15
+        assert a["replicas"] >= a["samples"] and a["replicas"] % 64 == 0
+    with pytest.raises(ValueError):
+        qh.adaptive_schedule(-1)

@@ -149,11 +149,16 @@ def test_skyline_stored_values_bit_exact(dtype):
 
 # ----------------------------------------------------------------------------- one step
 
-def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, plan=0, discrete=False):
+def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, plan=0, discrete=False,
+                   field=False):
     n = J.shape[0]
     rng = np.random.default_rng(rng_seed)
     x0 = f32(rng.uniform(-1.0, 1.0, (n, R)))
     y0 = f32(rng.uniform(-0.6, 0.6, (n, R)))
+    # deformation field: a few units of the typical coupling sum, zero on some rows
+    h = f32(rng.normal(0.0, 1.0, n) * max(1.0, float(np.abs(J).sum(axis=1).mean()))) if field else None
+    if field:
+        h[::7] = 0.0
     pump = np.linspace(0.0, 1.0, steps).astype(np.float32)
     c0 = 0.4 / max(1.0, float(np.sqrt((J ** 2).sum() / max(n - 1, 1))))
     c0 = float(np.float32(c0))
@@ -162,15 +167,21 @@ def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, pl
     x = torch.tensor(x0, dtype=torch.float32, device="cuda").contiguous()
     y = torch.tensor(y0, dtype=torch.float32, device="cuda").contiguous()
     qh.bsb_solve(g, R, steps, dt=dt, c0=c0, pump=torch.tensor(pump, device="cuda"), init=False,
-                 x=x, y=y, step_begin=k, step_end=k + 1, readout=False, plan=plan, discrete=discrete)
+                 x=x, y=y, step_begin=k, step_end=k + 1, readout=False, plan=plan, discrete=discrete,
+                 field=None if h is None else torch.tensor(h, dtype=torch.float32, device="cuda"))
     xg, yg = cpu(x).astype(np.float64), cpu(y).astype(np.float64)
-    xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False, discrete=discrete)
-    xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True, discrete=discrete)
+    xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False, discrete=discrete,
+                                   field=h)
+    xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True, discrete=discrete,
+                                   field=h)
     if discrete:
         xq = np.ones_like(x0)
     else:
         xq = x0 if product_format is None else quant.round_to(product_format, x0)
-    tol_x, tol_y = step_bounds(np.abs(J) @ np.abs(xq), x0, y0, p, dt, c0)
+    mag = np.abs(J) @ np.abs(xq)
+    if h is not None:
+        mag = mag + np.abs(h)[:, None]
+    tol_x, tol_y = step_bounds(mag, x0, y0, p, dt, c0)
     ambiguous = np.abs(np.abs(xu) - 1.0) <= tol_x
     ok = ~ambiguous
     assert ok.mean() > 0.9
@@ -213,6 +224,134 @@ def test_skyline_one_step_discrete(dtype, plan):
     assert g.info()["longrange_nnz"] > 0
     J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
     _one_step_case(g, J, dtype, 64, 800, None, plan=plan, discrete=True)
+
+
+@pytest.mark.parametrize("plan", [1, 2])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])
+def test_dense_one_step_field(dtype, plan):
+    """Deformation field h on the dense paths: y' = y + (-(a0 - p) x + c0 (J x + h)) dt."""
+    if plan == 2 and dtype == "f32":
+        pytest.skip("the persistent plan is offered for 16- and 8-bit dense storage")
+    w = synth.read_small(13, n_snp=300, n_reads=150, span=(20, 60))
+    g = gpu_graph(w, "read_signed", dtype)
+    J = stored_J(oracle_graph(w).dense(), dtype)
+    _one_step_case(g, J, dtype, 64, 900, FMT[dtype], plan=plan, field=True)
+    _one_step_case(g, J, dtype, 32, 901, None, plan=plan, discrete=True, field=True)
+
+
+@pytest.mark.parametrize("plan", [3, 4, 5])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_skyline_one_step_field(dtype, plan):
+    """The field on the SNP step kernels, with long-range rows (chunk partials) present."""
+    w = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
+    g = gpu_graph(w, "snp_llr", dtype, band_limit=100)
+    assert g.info()["longrange_nnz"] > 0
+    J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
+    _one_step_case(g, J, dtype, 64, 902, None, plan=plan, field=True)
+
+
+def test_field_solves_match_oracle_plans_and_batches():
+    """Whole solves under a field: the oracle's cut within 0.1 %; h = 0 is the plain solve
+    bit for bit; every dense plan, the band kernels and the batched plans agree bit for
+    bit with the per-step solve of each graph."""
+    rng = np.random.default_rng(5)
+    w = synth.read_tiny()
+    g = gpu_graph(w, "read_signed", "f16")
+    go = oracle_graph(w)
+    n = g.info()["n"]
+    h = f32(rng.normal(0.0, 2.0, n))
+    ht = torch.tensor(h, dtype=torch.float32, device="cuda")
+    ro = oracle.solve(go, 16, 1000, 0.5, seed=11, integer=True, field=h)
+    rg = qh.bsb_solve(g, 16, 1000, seed=11, field=ht)
+    assert _gap(ro["best_cut"], float(cpu(rg["best_cut"])[0])) <= 1e-3
+    # h = 0 is no field
+    for gg, plan in ((g, 1), (gpu_graph(synth.snp_small(61, n_snp=400), "snp_llr", "bf16"), 4)):
+        m = gg.info()["n"]
+        xa = torch.empty((m, 32), dtype=torch.float32, device="cuda")
+        xb = torch.empty_like(xa)
+        qh.bsb_solve(gg, 32, 200, seed=3, x=xa, readout=False, plan=plan)
+        qh.bsb_solve(gg, 32, 200, seed=3, x=xb, readout=False, plan=plan,
+                     field=torch.zeros(m, dtype=torch.float32, device="cuda"))
+        assert torch.equal(xa, xb)
+    # dense plans: per-step, persistent (both synchronisations), captured graph
+    wm = synth.read_mhc(seed=78, n_snp=1500, n_reads=1000, region=500_000)
+    gm = gpu_graph(wm, "read_signed", "f16")
+    nm = gm.info()["n"]
+    hm = torch.tensor(f32(rng.normal(0.0, 3.0, nm)), dtype=torch.float32, device="cuda")
+    outs = []
+    for plan, sync, ug in ((1, 0, False), (2, 1, False), (2, 2, False), (1, 0, True)):
+        x = torch.empty((nm, 64), dtype=torch.float32, device="cuda")
+        y = torch.empty((nm, 64), dtype=torch.float32, device="cuda")
+        r = qh.bsb_solve(gm, 64, 300, seed=31, x=x, y=y, plan=plan, persistent_sync=sync, use_graph=ug, field=hm)
+        outs.append((x, y, r))
+    x0 = torch.empty((nm, 64), dtype=torch.float32, device="cuda")
+    qh.bsb_solve(gm, 64, 300, seed=31, x=x0, plan=1)
+    assert not torch.equal(x0, outs[0][0])            # the field changes the run
+    for o in outs[1:]:
+        assert torch.equal(outs[0][0], o[0]) and torch.equal(outs[0][1], o[1])
+        assert torch.equal(outs[0][2]["best_cut"], o[2]["best_cut"])
+    # SNP band kernels: rows = band FMA bit for bit, band MFMA to rounding
+    wp = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
+    gp = gpu_graph(wp, "snp_llr", "f32", band_limit=100)
+    npv = gp.info()["n"]
+    hp = torch.tensor(f32(rng.normal(0.0, 1.0, npv)), dtype=torch.float32, device="cuda")
+    xs = {}
+    for plan in (3, 4, 5):
+        xs[plan] = torch.empty((npv, 64), dtype=torch.float32, device="cuda")
+        qh.bsb_solve(gp, 64, 200, seed=4, x=xs[plan], readout=False, plan=plan, field=hp)
+    assert torch.equal(xs[3], xs[4])
+    assert float((xs[3] - xs[5]).abs().max()) <= 1e-2
+    # batched: packed field, each block equal to its single solve
+    blocks = [synth.read_small(50, n_snp=200, n_reads=40), synth.snp_small(60, n_snp=350), w]
+    kinds = ["read_signed", "snp_llr", "read_signed"]
+    gs = [gpu_graph(b, k, d) for b, k, d in zip(blocks, kinds, ["fp8", "bf16", "f16"])]
+    ns = [gg.info()["n"] for gg in gs]
+    hb = torch.tensor(f32(rng.normal(0.0, 2.0, sum(ns))), dtype=torch.float32, device="cuda")
+    for plan in (1, 2):
+        rb = qh.bsb_solve_batched(gs, 32, 300, seed=9, return_state=True, plan=plan, field=hb)
+        off = rb["vertex_offset"]
+        for b, gg in enumerate(gs):
+            lo, hi = int(off[b]), int(off[b + 1])
+            xs1 = torch.empty(ns[b], 32, dtype=torch.float32, device="cuda")
+            rs = qh.bsb_solve(gg, 32, 300, seed=9, plan=1, x=xs1, field=hb[lo:hi].contiguous())
+            assert torch.equal(rb["x"][lo * 32:hi * 32], xs1.reshape(-1)), (plan, b)
+            assert torch.equal(rb["best_cut"][b:b + 1], rs["best_cut"]), (plan, b)
+    with pytest.raises(ValueError):
+        qh.bsb_solve(g, 16, 10, field=ht[:-1])
+    with pytest.raises(TypeError):
+        qh.bsb_solve(g, 16, 10, field=ht.double())
+
+
+def test_refine_deformation_matches_oracle():
+    """Adaptive deformation in the library's refinement equals the oracle's: on weights
+    gauge-flipped around a good partition, rough two-step rounds (no greedy pass) cut
+    negatively, so deformed re-solves run; the number run, the rounds, the applied cuts
+    and the flip counters agree, and the weights are restored."""
+    w = synth.snp_small(24, n_snp=800)
+    go = oracle_graph(w, "snp_llr")
+    s0 = oracle.solve(go, 16, 600, 0.5, seed=1)["best"]
+    g = gpu_graph(w, "snp_llr", "f32")
+    n = g.info()["n"]
+    qh.flip_crossing(g, torch.tensor(s0, dtype=torch.int8, device="cuda"))
+    g2 = oracle.flip_crossing(go, s0)
+    master = cpu(g.export_rows(0, n))
+    ro = oracle.refine(g2, w.init_h1, 16, 2, 0.5, seed=3, max_rounds=3, greedy_pass=False, deform=0.5,
+                       deform_tries=4)
+    rr = qh.refine(g, 16, 2, seed=3, max_rounds=3, greedy=False, deform=0.5, deform_tries=4)
+    assert np.array_equal(cpu(g.export_rows(0, n)), master)
+    assert ro["deformed"] >= 1
+    assert rr["deformed"] == ro["deformed"] and rr["rounds"] == ro["rounds"]
+    assert np.allclose(rr["round_cuts"], ro["round_cuts"], rtol=1e-9, atol=1e-9)
+    assert np.array_equal(cpu(rr["flips"]), ro["flips"])
+    # full-length rounds: the flip counters carry exactly the applied cuts
+    rr = qh.refine(g, 16, 300, seed=3, max_rounds=4, deform=0.5, deform_tries=2)
+    assert np.array_equal(cpu(g.export_rows(0, n)), master)
+    comp, nc = oracle.components(g2)
+    S = np.where(cpu(rr["flips"]) % 2 == 1, -1, 1).astype(np.int8)
+    assert oracle.cuts(g2, comp, nc, S).sum() == pytest.approx(sum(rr["round_cuts"]), rel=1e-9, abs=1e-9)
+    with pytest.raises(qh.QhapError) as e:
+        qh.refine(g, 16, 10, deform=-1.0, deform_tries=1)
+    assert e.value.status == qh.Status.EINVAL
 
 
 def test_discrete_whole_solves_match_oracle_and_plans():
