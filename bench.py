@@ -267,7 +267,7 @@ def main():
     if ref is not None and ref.get("nnz") == nnz:
         out["oracle_best_cut"] = ref["best_cut"]
         out["cut_gap"] = (ref["best_cut"] - best_cut) / abs(ref["best_cut"])
-    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth))
+    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth, w.pos))
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, R, STEPS, DT, seed, a.cpu_sample_steps)
@@ -357,7 +357,7 @@ def bench_snp(a):
                              launch_us=round(step_us, 3), bytes_per_launch=bytes_,
                              note="per bSB step (all kernels of one step)"),
                autotune=tune)
-    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth))
+    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth, w.pos))
     print(json.dumps(out), flush=True)
 
 
@@ -397,12 +397,17 @@ def bench_batched(a):
     print(json.dumps(out), flush=True)
 
 
-def phasing_errors(h1, block, truth):
+def phasing_errors(h1, block, truth, pos=None):
     """Switch error and orientation-free Hamming error against the planted haplotype
-    (consecutive phased SNPs of each block; unphased SNPs skipped)."""
+    (consecutive phased SNPs of each block; unphased SNPs skipped), the phased fraction
+    (phasing completeness: every input SNP is a true heterozygous site here, so SNP
+    completeness is the same number) and, given positions, the haplotype N50 in bp (block
+    span = last - first phased position + 1; the span where the descending running sum
+    first reaches half the total)."""
     import numpy as np
     sw = pairs = mis = tot = 0
     ok = (h1 >= 0) & (block >= 0)
+    spans = []
     for b in np.unique(block[ok]):
         idx = np.nonzero(ok & (block == b))[0]
         rel = h1[idx] == truth[idx]
@@ -411,8 +416,15 @@ def phasing_errors(h1, block, truth):
         m = int(np.count_nonzero(~rel))
         mis += min(m, idx.shape[0] - m)
         tot += idx.shape[0]
-    return dict(switch_error=sw / pairs if pairs else 0.0, hamming_error_min=mis / tot if tot else 0.0,
-                phased_fraction=float(ok.mean()))
+        if pos is not None:
+            spans.append(int(pos[idx[-1]]) - int(pos[idx[0]]) + 1)
+    out = dict(switch_error=sw / pairs if pairs else 0.0, hamming_error_min=mis / tot if tot else 0.0,
+               phased_fraction=float(ok.mean()) if ok.size else 0.0)
+    if pos is not None:
+        sp = np.sort(np.array(spans, dtype=np.int64))[::-1]
+        cs = np.cumsum(sp)
+        out["haplotype_n50_bp"] = int(sp[np.searchsorted(2 * cs, cs[-1] if cs.size else 0)]) if sp.size else 0
+    return out
 
 
 def cpu_baseline(w, R, STEPS, DT, seed, sample_steps):

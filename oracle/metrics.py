@@ -58,3 +58,33 @@ def hamming_error(h1, truth, block=None, literal: bool = True) -> float:
         mis += m if literal else min(m, idx.shape[0] - m)
         n += idx.shape[0]
     return mis / n if n else 0.0
+
+
+def haplotype_n50(h1, block, pos) -> int:
+    """Haplotype N50 (Methods, evaluation metrics): a block is the set of phased SNPs that
+    share a block label, its size the genomic span pos[last] - pos[first] + 1 in bp;
+    ranked by size, descending, the N50 is the size at which the running sum first
+    reaches half the total span.  0 when nothing is phased."""
+    pos = np.asarray(pos)
+    spans = sorted((int(pos[idx[-1]] - pos[idx[0]] + 1) for idx in _blocks(h1, block)), reverse=True)
+    total = sum(spans)
+    run = 0
+    for s in spans:
+        run += s
+        if 2 * run >= total:
+            return s
+    return 0
+
+
+def phasing_completeness(h1, block=None) -> float:
+    """Phased heterozygous sites over all heterozygous sites of the input."""
+    h1 = np.asarray(h1)
+    n = h1.shape[0]
+    phased = sum(idx.shape[0] for idx in _blocks(h1, block))
+    return phased / n if n else 0.0
+
+
+def snp_completeness(h1, n_true: int, block=None) -> float:
+    """Phased heterozygous SNPs over the true heterozygous variants of the reference."""
+    phased = sum(idx.shape[0] for idx in _blocks(h1, block))
+    return phased / n_true if n_true else 0.0

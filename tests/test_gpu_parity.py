@@ -46,6 +46,8 @@ READ_CASES = {
     "tiny": lambda: synth.read_tiny(),
     "ragged300": lambda: synth.read_small(5, n_snp=400, n_reads=300, span=(10, 60)),
     "sparse_many_comps": lambda: synth.read_small(6, n_snp=2000, n_reads=130, span=(3, 12)),
+    # reads plus Pore-C contact fragments, which the read-based method merges unweighted
+    "porec_merged": lambda: synth.snp_porec(43, n_snp=600, n_edges=500, zipf_s=1.0),
 }
 
 
@@ -63,6 +65,11 @@ def test_read_graph_bit_exact(kind, case):
     assert np.array_equal(cpu(g.components()), comp)
     assert info["nnz"] == go.nnz
     assert info["c0_auto"] == pytest.approx(oracle.c0(go), rel=1e-15)
+    if case == "porec_merged":
+        # Pore-C fragments join the read graph without their down-weighting factor
+        assert np.any(w.alpha != 1.0)
+        g1 = gpu_graph(w, kind, with_alpha=False)
+        assert torch.equal(g1.export_rows(0, go.n), g.export_rows(0, go.n))
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])

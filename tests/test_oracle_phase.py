@@ -33,6 +33,46 @@ def test_metrics_skip_unphased_and_blocks():
     assert metrics.switch_error(h, t) == pytest.approx(1 / 4)
 
 
+
+def test_n50_and_completeness_by_hand():
+    """Evaluation metrics (Methods): N50 over block spans, phasing and SNP completeness."""
+    pos = np.array([0, 10, 99, 200, 249, 300, 329, 400, 419, 500])
+    # blocks: {0,1,2} span 100; {3,4} span 50; {5,6} span 30; {7,8} span 20; SNP 9 unphased
+    h1 = np.array([0, 1, 1, 0, 0, 1, 0, 1, 1, -1])
+    blk = np.array([0, 0, 0, 1, 1, 2, 2, 3, 3, 4])
+    # spans 100, 50, 30, 20 (total 200): the running sum reaches 100 at the first block
+    assert metrics.haplotype_n50(h1, blk, pos) == 100
+    # spans 40, 30, 20, 10 (total 100): 40 < 50, 70 >= 50
+    pos2 = np.array([0, 39, 100, 129, 200, 219, 300, 309])
+    assert metrics.haplotype_n50(np.zeros(8, int), np.repeat(np.arange(4), 2), pos2) == 30
+    # block labels are arbitrary and -1 marks an unphased SNP (like h1 = -1)
+    blk3 = np.array([7, 7, 7, 2, 2, 9, 9, 4, 4, -1])
+    assert metrics.haplotype_n50(h1, blk3, pos) == 100
+    assert metrics.phasing_completeness(h1, blk) == pytest.approx(0.9)
+    assert metrics.snp_completeness(h1, 12, blk) == pytest.approx(9 / 12)
+    assert metrics.haplotype_n50(-np.ones(4, int), np.zeros(4, int), np.arange(4)) == 0
+    assert metrics.phasing_completeness(np.zeros(0, int)) == 0.0
+
+
+def test_bench_phasing_report_equals_oracle_metrics():
+    """bench.py's own phasing report (switch error, orientation-free Hamming error, phased
+    fraction, N50) against the oracle's metrics on random phasings with ragged blocks."""
+    import bench
+    rng = np.random.default_rng(3)
+    for trial in range(20):
+        n = int(rng.integers(1, 400))
+        truth = rng.integers(0, 2, n)
+        h1 = np.where(rng.random(n) < 0.1, -1, rng.integers(0, 2, n))
+        blk = np.sort(rng.integers(-1, max(2, n // 30), n))
+        pos = np.cumsum(rng.integers(1, 500, n))
+        r = bench.phasing_errors(h1, blk, truth, pos)
+        assert r["switch_error"] == pytest.approx(metrics.switch_error(h1, truth, blk), abs=1e-15)
+        assert r["hamming_error_min"] == pytest.approx(metrics.hamming_error(h1, truth, blk, literal=False),
+                                                       abs=1e-15)
+        assert r["phased_fraction"] == pytest.approx(metrics.phasing_completeness(h1, blk), abs=1e-15)
+        assert r["haplotype_n50_bp"] == metrics.haplotype_n50(h1, blk, pos)
+
+
 # ---------------------------------------------------------------- Eqs. (7)-(8) voting
 
 def vote_case(c1p, c1m, c2p, c2m, init=0):
