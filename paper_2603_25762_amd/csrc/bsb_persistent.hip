@@ -46,6 +46,57 @@ static std::vector<int> group_widths(int R) {
     return out;
 }
 
+// Contiguous partition of the row tiles into exactly `wpg` parts of 1..L row tiles each
+// that minimises the largest part's work (cum = prefix sums of the per-row-tile work):
+// binary search on that bound, each bound checked by greedy packing (extending a part as
+// far as both limits allow needs the fewest parts); then the heaviest parts with two or
+// more row tiles are split at their balance point until there are wpg parts (a split
+// never raises the bound).  Returns the wpg + 1 cut points, or nothing when no such
+// partition exists.
+static std::vector<int32_t> partition_rows(const std::vector<int64_t> &cum, int64_t n_rt, int wpg, int L) {
+    if (wpg < 1 || n_rt < wpg || ceil_div(n_rt, wpg) > L) return {};
+    std::vector<int32_t> cut;
+    auto pack = [&](int64_t B) -> bool {
+        cut.assign(1, 0);
+        int64_t cur = 0;
+        while (cur < n_rt) {
+            int64_t e = cur + 1;
+            if (cum[e] - cum[cur] > B) return false;
+            while (e < n_rt && e - cur < L && cum[e + 1] - cum[cur] <= B) ++e;
+            cut.push_back((int32_t)e);
+            cur = e;
+            if ((int64_t)cut.size() - 1 > wpg) return false;
+        }
+        return true;
+    };
+    int64_t lo = 0, hi = cum[n_rt];
+    for (int64_t rt = 0; rt < n_rt; ++rt) lo = std::max(lo, cum[rt + 1] - cum[rt]);
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (pack(mid)) hi = mid;
+        else lo = mid + 1;
+    }
+    if (!pack(lo)) return {};
+    while ((int64_t)cut.size() - 1 < wpg) {
+        int best = -1;
+        int64_t bw = -1;
+        for (int q = 0; q + 1 < (int)cut.size(); ++q)
+            if (cut[q + 1] - cut[q] >= 2 && cum[cut[q + 1]] - cum[cut[q]] > bw) {
+                bw = cum[cut[q + 1]] - cum[cut[q]];
+                best = q;
+            }
+        if (best < 0) return {};
+        const int64_t a = cut[best], b = cut[best + 1];
+        int64_t at = a + 1, av = -1;
+        for (int64_t m = a + 1; m < b; ++m) {
+            const int64_t v = std::max(cum[m] - cum[a], cum[b] - cum[m]);
+            if (av < 0 || v < av) { av = v; at = m; }
+        }
+        cut.insert(cut.begin() + best + 1, (int32_t)at);
+    }
+    return cut;
+}
+
 // Decide whether the persistent plan applies and build its tables.  Returns false
 // (and leaves `pp.ok` false) when the state or J would not fit on chip.
 bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_t st) {
@@ -69,29 +120,22 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
     int max_wpg = (int)std::min<int64_t>(n_rt, n_cu / ng);
     for (int wpg = max_wpg; wpg >= 1; --wpg) {
         if (ceil_div(n_rt, wpg) > kMaxT) break;   // fewer workgroups only makes T larger
-        // contiguous partition balanced by stored tiles (+1 per row tile for the update)
+        // contiguous partition whose busiest workgroup has the least work (stored tiles + 1
+        // per row tile for the update); the fewest row tiles per workgroup on a tie, which
+        // selects the kernel with the smaller register budget
         std::vector<int64_t> work(n_rt + 1, 0);
         for (int64_t rt = 0; rt < n_rt; ++rt) work[rt + 1] = work[rt] + (tptr[rt + 1] - tptr[rt]) + 1;
-        std::vector<int32_t> wg_rt(wpg + 1, 0);
-        int64_t cur = 0;
-        bool ok = true;
-        for (int w = 0; w < wpg; ++w) {
-            wg_rt[w] = (int32_t)cur;
-            int64_t e;
-            if (w == wpg - 1) {
-                e = n_rt;
-            } else {
-                const int64_t target = work[n_rt] * (w + 1) / wpg;
-                e = cur + 1;
-                while (e < n_rt && work[e] < target) ++e;
-                const int64_t max_e = n_rt - (wpg - w - 1);
-                if (e > max_e) e = max_e;
-            }
-            if (e <= cur || e - cur > kMaxT) { ok = false; break; }
-            cur = e;
+        std::vector<int32_t> wg_rt;
+        int64_t best_b = -1;
+        for (int L : {2, 4, kMaxT}) {
+            std::vector<int32_t> cut = partition_rows(work, n_rt, wpg, L);
+            if (cut.empty()) continue;
+            int64_t b = 0;
+            for (int w = 0; w < wpg; ++w) b = std::max(b, work[cut[w + 1]] - work[cut[w]]);
+            if (best_b < 0 || b < best_b) { best_b = b; wg_rt = cut; }
         }
-        wg_rt[wpg] = (int32_t)n_rt;
-        if (!ok || cur != n_rt) continue;
+        if (wg_rt.empty()) continue;
+        bool ok = true;
         std::vector<int32_t> owner(n_rt);
         for (int w = 0; w < wpg; ++w)
             for (int32_t rt = wg_rt[w]; rt < wg_rt[w + 1]; ++rt) owner[rt] = w;
