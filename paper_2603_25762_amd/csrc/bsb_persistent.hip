@@ -120,11 +120,13 @@ bool build_persistent_plan(const qh_graph *g, int R, PersistPlan &pp, hipStream_
     int max_wpg = (int)std::min<int64_t>(n_rt, n_cu / ng);
     for (int wpg = max_wpg; wpg >= 1; --wpg) {
         if (ceil_div(n_rt, wpg) > kMaxT) break;   // fewer workgroups only makes T larger
-        // contiguous partition whose busiest workgroup has the least work (stored tiles + 1
-        // per row tile for the update); the fewest row tiles per workgroup on a tie, which
-        // selects the kernel with the smaller register budget
+        // contiguous partition whose busiest workgroup has the least work (two units per
+        // stored tile for its loads and MFMAs, one per row tile for the update and publish:
+        // the weighting measured fastest on the read graphs, against 1:1 and 1:0); the
+        // fewest row tiles per workgroup on a tie, which selects the kernel with the smaller
+        // register budget
         std::vector<int64_t> work(n_rt + 1, 0);
-        for (int64_t rt = 0; rt < n_rt; ++rt) work[rt + 1] = work[rt] + (tptr[rt + 1] - tptr[rt]) + 1;
+        for (int64_t rt = 0; rt < n_rt; ++rt) work[rt + 1] = work[rt] + 2 * (tptr[rt + 1] - tptr[rt]) + 1;
         std::vector<int32_t> wg_rt;
         int64_t best_b = -1;
         for (int L : {2, 4, kMaxT}) {
