@@ -99,6 +99,10 @@ typedef struct {
     int32_t dtype;       /* qh_dtype */
     int32_t linkage_k;   /* SNP_LLR: 1..10 (10 = every pair inside a fragment) */
     int32_t band_limit;  /* SKYLINE: max column distance kept in the band; 0 = no limit */
+    int64_t max_device_bytes; /* cap on the device memory the graph may own (qh_graph_info
+                            .device_bytes); 0 = no cap.  Checked before the master weights and
+                            each storage copy are allocated, and on the finished graph:
+                            ENOMEM (nothing kept) when the graph would exceed it. */
 } qh_graph_opts;
 
 typedef struct qh_graph qh_graph;
@@ -125,8 +129,9 @@ typedef struct {
  * Computes the FP64 master values, the connected components (single-vertex
  * components get label -1), the storage copy in `dtype`, and what qh_phase needs.
  * Synchronises `stream`.  Errors: EINVAL for malformed fragments (index out of range,
- * non-ascending SNPs, bad enum), EUNSUPPORTED for kind/storage/dtype combinations
- * not offered, ENOMEM, EHIP. */
+ * non-ascending SNPs, bad enum, max_device_bytes < 0), EUNSUPPORTED for
+ * kind/storage/dtype combinations not offered, ENOMEM (also when the graph would
+ * exceed opts->max_device_bytes), EHIP. */
 qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_graph_opts *opts,
                          qh_graph **out, void *stream);
 

@@ -83,6 +83,7 @@ qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_gr
         if (!read_kind && (opts->linkage_k < 1 || opts->linkage_k > 10))
             fail(QH_EINVAL, "linkage_k must be in 1..10");
         if (opts->band_limit < 0) fail(QH_EINVAL, "band_limit < 0");
+        if (opts->max_device_bytes < 0) fail(QH_EINVAL, "max_device_bytes < 0");
         hipStream_t st = (hipStream_t)stream;
         std::unique_ptr<qh_graph> g(new qh_graph());
         static std::atomic<uint64_t> next_serial{1};
@@ -92,6 +93,7 @@ qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_gr
         g->storage = opts->storage;
         g->dtype = opts->dtype;
         g->n_snp = snps->n_snp;
+        g->max_bytes = opts->max_device_bytes;
         if (read_kind) build_read_graph(g.get(), reads, snps, st);
         else build_snp_graph(g.get(), reads, snps, opts->linkage_k, opts->band_limit, st);
         finalize_graph(g.get(), st);

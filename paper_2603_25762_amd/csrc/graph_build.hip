@@ -757,6 +757,15 @@ void upload_components(qh_graph *g, const std::vector<int32_t> &comp, int64_t n_
 // read graph
 // ---------------------------------------------------------------------------
 
+// The device-memory cap of a graph: fail with ENOMEM before allocating `more` bytes of
+// owned storage when the graph would then exceed it (owned = the buffers counted in
+// device_bytes; `have` = what it already owns).
+static void charge(const qh_graph *g, int64_t have, int64_t more, const char *what) {
+    if (g->max_bytes > 0 && have + more > g->max_bytes)
+        fail(QH_ENOMEM, "graph needs more than max_device_bytes = %lld (%s: %lld bytes on top of %lld)",
+             (long long)g->max_bytes, what, (long long)more, (long long)have);
+}
+
 static void pack_dense_storage(qh_graph *g, const int32_t *W, int negate, hipStream_t st) {
     int64_t F = g->n;
     int64_t n_rt = ceil_div(F, kTile);
@@ -782,6 +791,8 @@ static void pack_dense_storage(qh_graph *g, const int32_t *W, int negate, hipStr
     g->t_col.upload(tcol.data(), tcol.size(), st);
     DevBuf<int32_t> trow_d(trow.size());
     trow_d.upload(trow.data(), trow.size(), st);
+    charge(g, (int64_t)(g->m_ptr.bytes() + g->m_col.bytes() + g->m_val.bytes()),
+           std::max<int64_t>(g->n_tiles, 1) * kTileElems * dtype_bytes(g->dtype), "dense tiles");
     g->t_val.alloc((size_t)std::max<int64_t>(g->n_tiles, 1) * kTileElems * dtype_bytes(g->dtype));
     if (g->dtype == QH_FP8_ROWSCALE) {
         DevBuf<double> rmax(F);
@@ -919,6 +930,7 @@ void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStrea
     std::vector<int64_t> ptr(F + 1, 0);
     for (int64_t i = 0; i < F; ++i) ptr[i + 1] = ptr[i] + cnt_h[i];
     g->nnz = ptr[F];
+    charge(g, 0, (F + 1) * 8 + g->nnz * 12, "FP64 master weights");
     g->m_ptr.alloc(F + 1);
     g->m_ptr.upload(ptr.data(), F + 1, st);
     g->m_col.alloc(g->nnz);
@@ -1130,6 +1142,7 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
     std::vector<int64_t> mptr(n + 1, 0);
     for (int32_t u = 0; u < n; ++u) mptr[u + 1] = mptr[u] + cnt_h[u];
     g->nnz = mptr[n];
+    charge(g, 0, ((int64_t)n + 1) * 8 + g->nnz * 12, "FP64 master weights");
     g->m_ptr.alloc(n + 1);
     g->m_ptr.upload(mptr.data(), n + 1, st);
     g->m_col.alloc(g->nnz);
@@ -1200,6 +1213,8 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
         g->bb_lo.upload(blo.data(), nb, st);
         g->bb_w.alloc(nb);
         g->bb_w.upload(bw.data(), nb, st);
+        charge(g, (int64_t)(g->m_ptr.bytes() + g->m_col.bytes() + g->m_val.bytes()),
+               std::max<int64_t>(boff[nb], 1) * eb, "band blocks");
         g->bb_val.alloc((size_t)std::max<int64_t>(boff[nb], 1) * eb);
         g->bb_dtype = g->dtype;
         if (nb) {
@@ -1267,11 +1282,16 @@ void finalize_graph(qh_graph *g, hipStream_t st) {
         g->greedy_eps = 1e-12 * m;
     }
     g->device_bytes = (int64_t)(g->m_ptr.bytes() + g->m_col.bytes() + g->m_val.bytes() + g->comp.bytes() +
-                                g->comp_order.bytes() + g->t_ptr.bytes() + g->t_col.bytes() + g->t_val.bytes() +
+                                g->comp_first.bytes() + g->comp_order.bytes() + g->chunk_comp.bytes() +
+                                g->chunk_begin.bytes() + g->chunk_end.bytes() + g->comp_chunk_ptr.bytes() +
+                                g->t_ptr.bytes() + g->t_col.bytes() + g->t_val.bytes() +
                                 g->row_scale.bytes() + g->s_off.bytes() + g->s_lo.bytes() + g->s_len.bytes() +
-                                g->s_val.bytes() + g->l_ptr.bytes() + g->l_col.bytes() + g->l_val.bytes() +
-                                g->cov_ptr.bytes() + g->cov_frag.bytes() + g->cov_M.bytes() +
-                                g->init_h1.bytes());
+                                g->s_val.bytes() + g->bb_off.bytes() + g->bb_lo.bytes() + g->bb_w.bytes() +
+                                g->bb_val.bytes() + g->l_ptr.bytes() + g->l_col.bytes() + g->l_val.bytes() +
+                                g->row_chunk_ptr.bytes() + g->hub_chunk_beg.bytes() + g->hub_chunk_end.bytes() +
+                                g->lr_pk_ptr.bytes() + g->cov_ptr.bytes() + g->cov_frag.bytes() +
+                                g->cov_M.bytes() + g->init_h1.bytes());
+    charge(g, g->device_bytes, 0, "the finished graph");
 }
 
 void export_master_rows(const qh_graph *g, int64_t r0, int64_t r1, double *out, hipStream_t st) {

@@ -15,7 +15,7 @@ import oracle
 import paper_2603_25762_amd as qh
 import synth
 from oracle import metrics, quant
-from gpu_helpers import cpu, f32, gpu_graph, oracle_graph, snp_abs_terms, step_bounds
+from gpu_helpers import cpu, device_reads, f32, gpu_graph, oracle_graph, snp_abs_terms, step_bounds
 
 pytestmark = pytest.mark.gpu
 
@@ -904,6 +904,30 @@ def test_error_paths():
     with pytest.raises(qh.QhapError) as e:
         qh.bsb_solve(g, 16, 1, init=False, x=x, y=y, step_begin=1, step_end=1)
     assert e.value.status == qh.Status.ENUMERIC
+
+
+@pytest.mark.parametrize("kind,dtype", [("read_signed", "fp8"), ("snp_llr", "bf16")])
+def test_device_memory_cap(kind, dtype):
+    """max_device_bytes: a graph that fits is built unchanged at exactly its footprint; one
+    byte less, or a tiny cap, fails with ENOMEM and keeps nothing; a negative cap is EINVAL."""
+    w = synth.snp_porec(43, n_snp=600, n_edges=500, zipf_s=1.0) if kind == "snp_llr" else synth.read_tiny()
+    d = device_reads(w)
+    kw = dict(kind=kind, dtype=dtype, alpha=d["alpha"], band_limit=100 if kind == "snp_llr" else 0)
+    g = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], **kw)
+    need = g.info()["device_bytes"]
+    assert need > 0
+    g2 = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], max_device_bytes=need, **kw)
+    assert g2.info()["device_bytes"] == need
+    # (SNP weights are FP64 atomic sums: equal up to the order of the additions)
+    assert torch.allclose(g2.export_rows(0, g.info()["n"]), g.export_rows(0, g.info()["n"]), rtol=1e-12, atol=1e-12)
+    for cap, status in ((need - 1, qh.Status.ENOMEM), (4096, qh.Status.ENOMEM), (-1, qh.Status.EINVAL)):
+        with pytest.raises(qh.QhapError) as e:
+            qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], max_device_bytes=cap,
+                           **kw)
+        assert e.value.status == status, cap
+    # the library still works after the refusals
+    r = qh.bsb_solve(g, 16 if kind != "snp_llr" else 64, 50, seed=1)
+    assert np.isfinite(float(cpu(r["best_cut"])[0]))
 
 
 def test_degenerate_graphs():
