@@ -265,6 +265,19 @@ typedef struct {
 
 qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *out);
 
+/* Runs the plan-0 autotuner for (graph, opts->replicas) on its own: the timing runs on
+ * scratch state that qh_bsb_solve makes on its first plan-0 call, with opts' schedule.
+ * *chosen receives *opts with plan, replica_tile, tiles_in_flight and persistent_sync
+ * set to the choice: a qh_bsb_solve with them runs the same kernels without tuning (and
+ * gives the same results, every candidate being bit-identical).  us_per_step (host float
+ * [2], optional): the chosen plan's measured microseconds per step; SNP graphs: [band
+ * FMA, band MFMA].  cache_path (optional): one JSON line is appended to this file with
+ * the graph's shape (n, nnz, kind, storage, dtype, dense_tiles), the replica count, the
+ * chosen options and the timings, for a later process to reuse.  Synchronises the stream.
+ * Errors: EINVAL (options as for qh_bsb_solve; the cache file cannot be opened), EHIP. */
+qh_status qh_autotune(const qh_graph *g, const qh_bsb_opts *opts, qh_bsb_opts *chosen, float *us_per_step,
+                      const char *cache_path, void *stream);
+
 /* Many independent graphs (phasing blocks) solved together: every block runs the same
  * schedule (steps, dt, a0, pump, seed) with its own c0 (opts->c0 <= 0: each block's
  * c0_auto), and block b's results equal qh_bsb_solve on graph b with the same options,

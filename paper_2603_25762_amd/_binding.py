@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import ctypes
 import enum
+import json
 import os
 from typing import Dict, Optional, Sequence
 
@@ -123,6 +124,8 @@ def load():
                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                       ctypes.POINTER(ctypes.c_int32), P],
         "qh_solve_plan_info": [P, ctypes.c_int32, ctypes.POINTER(_PlanInfo)],
+        "qh_autotune": [P, ctypes.POINTER(_BsbOpts), ctypes.POINTER(_BsbOpts), ctypes.POINTER(ctypes.c_float),
+                        ctypes.c_char_p, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -318,6 +321,39 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
                 _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")))
     _check(load().qh_bsb_solve(g.handle, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
     return res
+
+
+_TUNED = ("plan", "replica_tile", "tiles_in_flight", "persistent_sync")
+
+
+def autotune(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float = 0.0, a0: float = 1.0,
+             discrete: bool = False, cache_path: Optional[str] = None, stream=None) -> Dict[str, object]:
+    """Runs the plan-0 autotuner for (graph, replicas) on its own and returns the chosen
+    options (keys plan, replica_tile, tiles_in_flight, persistent_sync: pass them to
+    bsb_solve to skip tuning) plus us_per_step; with cache_path, appends them as one JSON
+    line for load_tuned."""
+    opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, 0, 1, 0, 0, 0, 0, 0, int(discrete), 0, 0, None)
+    chosen = _BsbOpts()
+    us = (ctypes.c_float * 2)()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(load().qh_autotune(g.handle, ctypes.byref(opts), ctypes.byref(chosen), us, path, _stream(stream)))
+    out = {k: int(getattr(chosen, k)) for k in _TUNED}
+    out["us_per_step"] = [float(us[0]), float(us[1])]
+    return out
+
+
+def load_tuned(cache_path: str, g: Graph, replicas: int) -> Optional[Dict[str, int]]:
+    """The options of the last line of an autotune cache written for a graph of this shape
+    (n, nnz, kind, storage, dtype, dense_tiles) and replica count, or None."""
+    inf = g.info()
+    found = None
+    with open(cache_path) as f:
+        for line in f:
+            rec = json.loads(line)
+            if rec["replicas"] == replicas and all(rec[k] == inf[k] for k in ("n", "nnz", "kind", "storage", "dtype",
+                                                                              "dense_tiles")):
+                found = {k: int(rec[k]) for k in _TUNED}
+    return found
 
 
 def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt: float = 0.5,

@@ -1,5 +1,6 @@
 // C ABI entry points: argument validation, error capture, ownership.
 #include <cstdarg>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -208,6 +209,35 @@ qh_status qh_solve_plan_info(const qh_graph *g, int32_t replicas, qh_plan_info *
     return guarded([&] {
         if (!g || !out) fail(QH_EINVAL, "null argument");
         plan_info(g, replicas, out);
+    });
+}
+
+qh_status qh_autotune(const qh_graph *g, const qh_bsb_opts *opts, qh_bsb_opts *chosen, float *us_per_step,
+                      const char *cache_path, void *stream) {
+    return guarded([&] {
+        if (!g || !chosen) fail(QH_EINVAL, "null argument");
+        validate_opts(opts);
+        float us[2] = {0.0f, 0.0f};
+        qh_bsb_opts c{};
+        autotune(g, opts, &c, us, (hipStream_t)stream);
+        QH_HIP(hipStreamSynchronize((hipStream_t)stream));
+        if (cache_path) {
+            FILE *f = std::fopen(cache_path, "a");
+            if (!f) fail(QH_EINVAL, "cannot open the cache file %s", cache_path);
+            std::fprintf(f,
+                         "{\"n\": %lld, \"nnz\": %lld, \"kind\": %d, \"storage\": %d, \"dtype\": %d, "
+                         "\"dense_tiles\": %lld, \"replicas\": %d, \"plan\": %d, \"replica_tile\": %d, "
+                         "\"tiles_in_flight\": %d, \"persistent_sync\": %d, \"us_per_step\": [%.4f, %.4f]}\n",
+                         (long long)g->n, (long long)g->nnz, g->kind, g->storage, g->dtype, (long long)g->n_tiles,
+                         opts->replicas, c.plan, c.replica_tile, c.tiles_in_flight, c.persistent_sync, us[0], us[1]);
+            const bool bad = std::ferror(f) != 0;
+            if (std::fclose(f) != 0 || bad) fail(QH_EINVAL, "cannot write the cache file %s", cache_path);
+        }
+        *chosen = c;
+        if (us_per_step) {
+            us_per_step[0] = us[0];
+            us_per_step[1] = us[1];
+        }
     });
 }
 

@@ -1209,6 +1209,52 @@ const float *linear_pump(SolvePlan &p, int steps, hipStream_t st) {
     return p.pump_lin.p;
 }
 
+// Runs the plan-0 autotuner for (graph, opts->replicas) without a solve and returns the
+// choice as explicit options (plan, replica_tile, tiles_in_flight, persistent_sync) that
+// make a later qh_bsb_solve skip the tuning and run the same kernels.
+void autotune(const qh_graph *g, const qh_bsb_opts *o, qh_bsb_opts *chosen, float *us, hipStream_t st) {
+    int cur_dev = 0;
+    QH_HIP(hipGetDevice(&cur_dev));
+    if (cur_dev != g->device) fail(QH_EINVAL, "graph lives on device %d, current device is %d", g->device, cur_dev);
+    const int R = o->replicas;
+    SolvePlan &p = solve_plan(g, R, st);
+    const double c0 = o->c0 > 0.0 ? o->c0 : g->c0_auto;
+    const double a0 = o->a0 > 0.0 ? o->a0 : 1.0;
+    const float *pump = o->pump ? o->pump : linear_pump(p, o->steps, st);
+    *chosen = *o;
+    chosen->replica_tile = 0;
+    chosen->tiles_in_flight = 0;
+    chosen->persistent_sync = 0;
+    us[0] = us[1] = 0.0f;
+    if (g->n == 0) { chosen->plan = 1; return; }
+    if (g->storage == QH_STORE_DENSE) {
+        const bool dense16 = !x_pingpong(g);
+        if (dense16 && !p.pp_tried) {
+            p.pp = std::make_shared<PersistPlan>();
+            build_persistent_plan(g, R, *p.pp, st);
+            p.pp_tried = true;
+        }
+        if (!p.tuned_plan) autotune_dense(g, p, o, pump, c0, a0, st);
+        if (dense16 && p.pp && p.pp->ok && p.tuned_plan == 2) {
+            chosen->plan = 2;
+            chosen->persistent_sync = p.tuned_coh ? 2 : 1;
+            us[0] = p.tuned_coh ? p.tuned_us_coh : p.tuned_us[1];
+        } else {
+            chosen->plan = 1;
+            if (R >= 64) {
+                chosen->replica_tile = p.tuned_rt ? p.tuned_rt : 64;
+                if (chosen->replica_tile == 64) chosen->tiles_in_flight = p.tuned_depth;
+            }
+            us[0] = p.tuned_us[0];
+        }
+    } else {
+        if (!p.sky_tuned) autotune_sky(g, p, o, pump, c0, a0, st);
+        chosen->plan = p.sky_best == kSkyBandMfma ? 5 : p.sky_best == kSkyBandFma ? 4 : 3;
+        us[0] = p.sky_us[kSkyBandFma];
+        us[1] = p.sky_us[kSkyBandMfma];
+    }
+}
+
 void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStream_t st) {
     int cur_dev = 0;
     QH_HIP(hipGetDevice(&cur_dev));

@@ -245,6 +245,7 @@ void flip_crossing(qh_graph *g, const int8_t *spins, hipStream_t st);
 
 // bsb.hip
 void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStream_t st);
+void autotune(const qh_graph *g, const qh_bsb_opts *o, qh_bsb_opts *chosen, float *us, hipStream_t st);
 
 // What the readout needs of a graph (a single graph, or the block-diagonal union of a batch).
 struct ReadoutView {

@@ -7,6 +7,8 @@ software rounding), one bSB step (<= 1e-5 of the step's own magnitude), the
 FP64 readout (exact for integer weights), phasing (exact), and the final best
 cut of a whole solve (<= 0.1 % below the FP64 oracle, equal switch error).
 """
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -928,6 +930,37 @@ def test_device_memory_cap(kind, dtype):
     # the library still works after the refusals
     r = qh.bsb_solve(g, 16 if kind != "snp_llr" else 64, 50, seed=1)
     assert np.isfinite(float(cpu(r["best_cut"])[0]))
+
+
+def test_autotune_cache_and_explicit_options(tmp_path):
+    """qh_autotune on its own: the chosen options, passed explicitly, run the tuned kernels
+    with the plan-0 solve's results bit for bit; the cache file holds one JSON line per
+    tuning and load_tuned finds the options again by graph shape and replica count."""
+    path = str(tmp_path / "tune.jsonl")
+    wm = synth.read_mhc(seed=78, n_snp=1500, n_reads=1000, region=500_000)
+    cases = [(gpu_graph(wm, "read_signed", "f16"), 64, (1, 2)),
+             (gpu_graph(synth.snp_small(14, n_snp=1500), "snp_llr", "f16"), 64, (3, 4, 5))]
+    for g, R, plans in cases:
+        ch = qh.autotune(g, R, 200, cache_path=path)
+        assert ch["plan"] in plans and ch["us_per_step"][0] > 0.0
+        opts = {k: ch[k] for k in ("plan", "replica_tile", "tiles_in_flight", "persistent_sync")}
+        n = g.info()["n"]
+        xa = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        xb = torch.empty_like(xa)
+        ra = qh.bsb_solve(g, R, 200, seed=3, x=xa)
+        rb = qh.bsb_solve(g, R, 200, seed=3, x=xb, **opts)
+        assert torch.equal(xa, xb) and torch.equal(ra["best_cut"], rb["best_cut"])
+        info = g.plan_info(R)
+        if ch["plan"] == 2:
+            assert info["plan_used"] == 2 and info["persistent_sync"] == ch["persistent_sync"]
+        elif ch["plan"] == 1:
+            assert info["plan_used"] == 1 and info["replica_tile"] == ch["replica_tile"]
+        else:
+            assert info["skyline_kernel"] == ch["plan"]
+        assert qh.load_tuned(path, g, R) == opts
+    lines = open(path).read().splitlines()
+    assert len(lines) == 2 and all(json.loads(line)["replicas"] == 64 for line in lines)
+    assert qh.load_tuned(path, cases[0][0], 128) is None
 
 
 def test_degenerate_graphs():
