@@ -103,6 +103,11 @@ typedef struct {
                             .device_bytes); 0 = no cap.  Checked before the master weights and
                             each storage copy are allocated, and on the finished graph:
                             ENOMEM (nothing kept) when the graph would exceed it. */
+    int32_t deterministic; /* SNP_LLR: 1 = each Eq. (14) term is rounded to a multiple of
+                            2^-40 (|term| clamped to 2^20) and the terms are summed in 64-bit
+                            integers, so the weights are bit-identical from build to build
+                            (the FP64 sum of atomics, 0, depends on the order of the additions
+                            in its last bits).  Read graphs are integer sums: exact either way. */
 } qh_graph_opts;
 
 typedef struct qh_graph qh_graph;

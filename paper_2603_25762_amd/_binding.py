@@ -48,7 +48,7 @@ class _Snps(ctypes.Structure):
 class _GraphOpts(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("storage", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("linkage_k", ctypes.c_int32), ("band_limit", ctypes.c_int32),
-                ("max_device_bytes", ctypes.c_int64)]
+                ("max_device_bytes", ctypes.c_int64), ("deterministic", ctypes.c_int32)]
 
 
 class _GraphInfo(ctypes.Structure):
@@ -223,7 +223,8 @@ def build_graph(frag_ptr: torch.Tensor, snp: torch.Tensor, allele: torch.Tensor,
                 phred: Optional[torch.Tensor], init_h1: torch.Tensor, *, kind: str = "read_signed",
                 storage: Optional[str] = None, dtype: str = "f32",
                 alpha: Optional[torch.Tensor] = None, linkage_k: int = 10,
-                band_limit: int = 0, max_device_bytes: int = 0, stream=None) -> Graph:
+                band_limit: int = 0, max_device_bytes: int = 0, deterministic: bool = False,
+                stream=None) -> Graph:
     if storage is None:
         storage = "skyline" if kind == "snp_llr" else "dense"
     for t, dt in ((frag_ptr, torch.int64), (snp, torch.int32), (allele, torch.uint8),
@@ -237,7 +238,8 @@ def build_graph(frag_ptr: torch.Tensor, snp: torch.Tensor, allele: torch.Tensor,
     reads = _Reads(frag_ptr.numel() - 1, _ptr(frag_ptr), _ptr(snp), _ptr(allele), _ptr(phred),
                    _ptr(alpha))
     snps = _Snps(init_h1.numel(), _ptr(init_h1))
-    opts = _GraphOpts(KIND[kind], STORAGE[storage], DTYPE[dtype], linkage_k, band_limit, max_device_bytes)
+    opts = _GraphOpts(KIND[kind], STORAGE[storage], DTYPE[dtype], linkage_k, band_limit, max_device_bytes,
+                      int(deterministic))
     h = ctypes.c_void_p()
     _check(load().qh_build_graph(ctypes.byref(reads), ctypes.byref(snps), ctypes.byref(opts),
                                  ctypes.byref(h), _stream(stream)))

@@ -95,6 +95,8 @@ qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_gr
         g->dtype = opts->dtype;
         g->n_snp = snps->n_snp;
         g->max_bytes = opts->max_device_bytes;
+        if (opts->deterministic != 0 && opts->deterministic != 1) fail(QH_EINVAL, "deterministic must be 0 or 1");
+        g->deterministic = opts->deterministic;
         if (read_kind) build_read_graph(g.get(), reads, snps, st);
         else build_snp_graph(g.get(), reads, snps, opts->linkage_k, opts->band_limit, st);
         finalize_graph(g.get(), st);

@@ -386,6 +386,14 @@ __global__ void k_pack_tiles(int64_t F, const int32_t *__restrict__ W, int negat
 // normalisation of Eq. (14).  J = -w, so each pair term enters J with a + sign.
 // One thread per kept observation (fragment f, rank a); it handles the pairs
 // (a, b) with a < b <= a + L of its fragment.
+// In-place conversion of fixed-point sums (int64 multiples of 2^-40) to FP64.
+__global__ void k_fixed_to_f64(int64_t n, double *__restrict__ v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const long long q = __builtin_bit_cast(long long, v[i]);
+        v[i] = (double)q * 0x1p-40;
+    }
+}
+
 __global__ void k_snp_pairs(int64_t n_kept, const int64_t *__restrict__ kept_obs,
                             const int32_t *__restrict__ kept_frag, const int64_t *__restrict__ kept_ptr,
                             const int32_t *__restrict__ snp, const int8_t *__restrict__ M,
@@ -393,7 +401,7 @@ __global__ void k_snp_pairs(int64_t n_kept, const int64_t *__restrict__ kept_obs
                             const double *__restrict__ qconf, int linkage_k, int32_t band_limit,
                             const int64_t *__restrict__ s_off, const int32_t *__restrict__ s_lo,
                             double *__restrict__ s_val64, const int64_t *__restrict__ l_ptr,
-                            const int32_t *__restrict__ l_col, double *__restrict__ l_val64) {
+                            const int32_t *__restrict__ l_col, double *__restrict__ l_val64, int fixed) {
     for (int64_t kk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; kk < n_kept;
          kk += (int64_t)gridDim.x * blockDim.x) {
         int32_t f = kept_frag[kk];
@@ -417,16 +425,24 @@ __global__ void k_snp_pairs(int64_t n_kept, const int64_t *__restrict__ kept_obs
             double sgn = (Mu * (int)M[tv] > 0) ? 1.0 : -1.0;
             double l = sgn * log10(p_cis / p_trans);
             double term = af * l / (double)(ns - 1);   // enters J = -w with + sign
+            // fixed = 1: the term as a multiple of 2^-40 (|term| clamped to 2^20), summed with
+            // integer atomics, whose result does not depend on the order of the additions
+            const double tc = term < -0x1p20 ? -0x1p20 : (term > 0x1p20 ? 0x1p20 : term);
+            const unsigned long long tq = (unsigned long long)(long long)__builtin_rint(tc * 0x1p40);
+            auto add = [&](double *p) {
+                if (fixed) atomicAdd((unsigned long long *)p, tq);
+                else unsafeAtomicAdd(p, term);
+            };
             if (band_limit == 0 || v - u <= band_limit) {
-                unsafeAtomicAdd(&s_val64[s_off[u] + (v - s_lo[u])], term);
-                unsafeAtomicAdd(&s_val64[s_off[v] + (u - s_lo[v])], term);
+                add(&s_val64[s_off[u] + (v - s_lo[u])]);
+                add(&s_val64[s_off[v] + (u - s_lo[v])]);
             } else {
                 int64_t lo = l_ptr[u], hi = l_ptr[u + 1];
                 while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < v) lo = m + 1; else hi = m; }
-                unsafeAtomicAdd(&l_val64[lo], term);
+                add(&l_val64[lo]);
                 lo = l_ptr[v]; hi = l_ptr[v + 1];
                 while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < u) lo = m + 1; else hi = m; }
-                unsafeAtomicAdd(&l_val64[lo], term);
+                add(&l_val64[lo]);
             }
         }
     }
@@ -1127,8 +1143,15 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
         hipLaunchKernelGGL(k_snp_pairs, dim3(grid_for(n_kept, 256, 1 << 20)), dim3(256), 0, st, n_kept,
                            kept_obs_d.p, kept_frag_d.p, kept_ptr_d.p, r->snp, M.p, r->phred, r->alpha, qconf.p,
                            linkage_k, (int32_t)band_limit, g->s_off.p, g->s_lo.p, s_val64.p, g->l_ptr.p,
-                           g->l_col.p, l_val64.p);
+                           g->l_col.p, l_val64.p, g->deterministic);
         QH_CHECK_LAUNCH();
+        if (g->deterministic) {
+            if (slots) hipLaunchKernelGGL(k_fixed_to_f64, dim3(grid_for(slots)), dim3(256), 0, st, (int64_t)slots,
+                                          s_val64.p);
+            if (l_nnz) hipLaunchKernelGGL(k_fixed_to_f64, dim3(grid_for(l_nnz)), dim3(256), 0, st, (int64_t)l_nnz,
+                                          l_val64.p);
+            QH_CHECK_LAUNCH();
+        }
     }
     // master CSR
     DevBuf<int64_t> cnt(n);

@@ -150,6 +150,7 @@ struct SolvePlan {
 struct qh_graph {
     uint64_t serial = 0;   // unique per graph in the process (keys cached batch plans)
     int64_t max_bytes = 0; // cap on the device memory the graph owns (0: none)
+    int deterministic = 0; // SNP weights summed in fixed point (order-independent)
     int device = 0;
     int kind = 0, storage = 0, dtype = 0;
     int64_t n = 0;         // vertices

@@ -932,6 +932,30 @@ def test_device_memory_cap(kind, dtype):
     assert np.isfinite(float(cpu(r["best_cut"])[0]))
 
 
+def test_deterministic_snp_build():
+    """deterministic = 1: fixed-point sums give the same SNP weights bit for bit on every
+    build (and so the same solve), within 2^-40 per Eq. (14) term of the oracle's FP64 sum."""
+    w = synth.snp_porec(43, n_snp=1200, n_edges=1500, zipf_s=1.0)
+    d = device_reads(w)
+    kw = dict(kind="snp_llr", dtype="bf16", alpha=d["alpha"], band_limit=100, deterministic=True)
+    g1 = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], **kw)
+    g2 = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], **kw)
+    n = g1.info()["n"]
+    assert g1.info()["longrange_nnz"] > 0
+    m1, m2 = g1.export_rows(0, n), g2.export_rows(0, n)
+    assert torch.equal(m1, m2)
+    assert torch.equal(g1.export_rows(0, n, stored=True), g2.export_rows(0, n, stored=True))
+    J = oracle_graph(w, "snp_llr").dense()
+    diff = np.abs(cpu(m1) - J)
+    # each entry sums at most a few hundred terms, each rounded by at most 2^-41; entries
+    # that are not FP64 cancellation residue keep their place
+    assert diff.max() <= 1e3 * 2.0 ** -41
+    assert np.all(cpu(m1)[np.abs(J) > 1e-9] != 0)
+    r1 = qh.bsb_solve(g1, 64, 200, seed=2)
+    r2 = qh.bsb_solve(g2, 64, 200, seed=2)
+    assert torch.equal(r1["best_spins"], r2["best_spins"]) and torch.equal(r1["best_cut"], r2["best_cut"])
+
+
 def test_autotune_cache_and_explicit_options(tmp_path):
     """qh_autotune on its own: the chosen options, passed explicitly, run the tuned kernels
     with the plan-0 solve's results bit for bit; the cache file holds one JSON line per
