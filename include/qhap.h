@@ -128,6 +128,8 @@ typedef struct {
     int32_t band_dtype;      /* SKYLINE: encoding of the band blocks the step kernel reads: the
                                 graph's dtype, or QH_F16 for a BF16 graph whose band values are
                                 all exactly representable in binary16 (same values) */
+    double total_weight;     /* W = -1/2 sum_ab J_ab (the edge weights of A = -J summed once):
+                                the Ising energy of Eq. (5) is E(s) = W - 2 cut(s) */
 } qh_graph_info;
 
 /* Builds J from fragments (Methods: read-based Eqs. 1-3, SNP-based Eqs. 9-14).
@@ -222,7 +224,9 @@ typedef struct {
  *  selected_cut  double [1]    cut of the selected spins before greedy (optional)
  *  best_cut      double [1]    cut of best_spins
  *  all_spins     int8 [n][R]   every replica's signs (optional)
- *  greedy_rounds int32 [1]     rounds that flipped something (optional, host or device: device) */
+ *  greedy_rounds int32 [1]     rounds that flipped something (optional, host or device: device)
+ *  best_energy   double [1]    Ising energy of best_spins, E = -1/2 s'Js (Eq. 5) = W - 2 best_cut
+ *                              (optional; readout = 1) */
 typedef struct {
     float *x;
     float *y;
@@ -234,6 +238,7 @@ typedef struct {
     double *best_cut;
     int8_t *all_spins;
     int32_t *greedy_rounds;
+    double *best_energy;
 } qh_result;
 
 /* Runs bSB on one graph.  Synchronises the stream only when greedy = 1.

@@ -58,7 +58,7 @@ class _GraphInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("kind", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("integer_weights", ctypes.c_int32), ("c0_auto", ctypes.c_double),
-                ("band_dtype", ctypes.c_int32)]
+                ("band_dtype", ctypes.c_int32), ("total_weight", ctypes.c_double)]
 
 
 class _BsbOpts(ctypes.Structure):
@@ -76,7 +76,7 @@ class _BsbOpts(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("x", P), ("y", P), ("best_spins", P), ("cuts", P), ("cut_rc", P),
                 ("best_replica", P), ("selected_cut", P), ("best_cut", P), ("all_spins", P),
-                ("greedy_rounds", P)]
+                ("greedy_rounds", P), ("best_energy", P)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -304,6 +304,7 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
         alloc("best_cut", (1,), torch.float64)
         alloc("selected_cut", (1,), torch.float64)
         alloc("greedy_rounds", (1,), torch.int32, zero=True)
+        alloc("best_energy", (1,), torch.float64)
         if all_spins:
             alloc("all_spins", (n, replicas), torch.int8)
         if per_component:
@@ -320,7 +321,8 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
                     int(discrete), int(tiles_in_flight), int(persistent_sync), _ptr(field))
     r = _Result(_ptr(x), _ptr(y), _ptr(keep.get("best_spins")), _ptr(keep.get("cuts")),
                 _ptr(keep.get("cut_rc")), _ptr(keep.get("best_replica")), _ptr(keep.get("selected_cut")),
-                _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")))
+                _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")),
+                _ptr(keep.get("best_energy")))
     _check(load().qh_bsb_solve(g.handle, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
     return res
 

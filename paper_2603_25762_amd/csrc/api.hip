@@ -142,6 +142,7 @@ qh_status qh_graph_get_info(const qh_graph *g, qh_graph_info *out) {
         i.dtype = g->dtype;
         i.integer_weights = g->integer ? 1 : 0;
         i.c0_auto = g->c0_auto;
+        i.total_weight = g->total_weight;
         i.band_dtype = g->storage == QH_STORE_SKYLINE ? g->bb_dtype : g->dtype;
         *out = i;
     });

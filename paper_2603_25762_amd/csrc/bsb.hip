@@ -1199,6 +1199,11 @@ static void autotune_sky(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, 
     (void)hipEventDestroy(e1);
 }
 
+// Eq. (5): E(s) = -1/2 s'Js = W - 2 cut(s), with W = -1/2 sum_ab J_ab
+__global__ void k_energy(double W, const double *__restrict__ cut, double *__restrict__ e) {
+    if (threadIdx.x == 0) e[0] = W - 2.0 * cut[0];
+}
+
 const float *linear_pump(SolvePlan &p, int steps, hipStream_t st) {
     if (p.pump_steps != steps) {
         p.pump_lin.alloc(steps);
@@ -1362,6 +1367,10 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     if (res->y && nR) QH_HIP(hipMemcpyAsync(res->y, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (!o->readout) return;
     readout(view_of(g), p, R, xfin, p.y.p, res, o->greedy != 0, st);
+    if (res->best_energy) {
+        hipLaunchKernelGGL(k_energy, dim3(1), dim3(64), 0, st, g->total_weight, res->best_cut, res->best_energy);
+        QH_CHECK_LAUNCH();
+    }
 }
 
 

@@ -570,6 +570,23 @@ __global__ void k_pack_band(int64_t n, int64_t n_bblk, const int64_t *__restrict
 }
 
 // Deterministic partial sums of squares (fixed grid, fixed order per block).
+// part[b] = sum of v[t] (sq = 0) or v[t]^2 (sq = 1) over block b's contiguous range, in a
+// fixed order (a deterministic total once the host adds the parts in order)
+__global__ void k_sum_partial(int64_t n, const double *__restrict__ v, double *__restrict__ part, int sq) {
+    __shared__ double sh[256];
+    int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    int64_t b = blockIdx.x * per, e = b + per < n ? b + per : n;
+    double acc = 0.0;
+    for (int64_t t = b + threadIdx.x; t < e; t += blockDim.x) acc += sq ? v[t] * v[t] : v[t];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 __global__ void k_sumsq_partial(int64_t n, const double *__restrict__ v, double *__restrict__ part) {
     __shared__ double sh[256];
     int64_t per = (n + gridDim.x - 1) / gridDim.x;
@@ -1289,6 +1306,12 @@ void finalize_graph(qh_graph *g, hipStream_t st) {
         auto ph = download(part.p, parts, st);
         double ss = 0.0;
         for (double v : ph) ss += v;
+        hipLaunchKernelGGL(k_sum_partial, dim3(parts), dim3(256), 0, st, g->nnz, g->m_val.p, part.p, 0);
+        QH_CHECK_LAUNCH();
+        auto pw = download(part.p, parts, st);
+        double sj = 0.0;
+        for (double v : pw) sj += v;
+        g->total_weight = -0.5 * sj;
         if (ss > 0.0 && g->n >= 2) {
             double sigma = std::sqrt(ss / ((double)g->n * (double)(g->n - 1)));
             g->c0_auto = 0.5 / (sigma * std::sqrt((double)g->n));

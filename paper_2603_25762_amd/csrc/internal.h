@@ -223,6 +223,7 @@ struct qh_graph {
     qh::DevBuf<int8_t> cov_M;
 
     double c0_auto = 0.0;
+    double total_weight = 0.0;   // -1/2 sum of the master J (fixed-order sum)
     double greedy_eps = 0.0;
     int64_t device_bytes = 0;
 

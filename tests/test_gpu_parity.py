@@ -932,6 +932,23 @@ def test_device_memory_cap(kind, dtype):
     assert np.isfinite(float(cpu(r["best_cut"])[0]))
 
 
+@pytest.mark.parametrize("kind,dtype", [("read_signed", "f16"), ("snp_llr", "f32")])
+def test_best_energy_matches_eq5(kind, dtype):
+    """best_energy is the Ising energy E(s) = -1/2 s'Js of the returned spins (Eq. 5), here
+    evaluated by the oracle's dense J in FP64; total_weight is -1/2 sum J."""
+    w = synth.read_small(13, n_snp=300, n_reads=150, span=(20, 60)) if kind == "read_signed" else \
+        synth.snp_small(14, n_snp=800)
+    g = gpu_graph(w, kind, dtype)
+    J = oracle_graph(w, kind).dense()
+    assert g.info()["total_weight"] == pytest.approx(-0.5 * J.sum(), rel=1e-12)
+    r = qh.bsb_solve(g, 32, 300, seed=4)
+    s = cpu(r["best_spins"]).astype(np.float64)
+    e = -0.5 * s @ J @ s
+    assert float(cpu(r["best_energy"])[0]) == pytest.approx(e, rel=1e-10, abs=1e-9)
+    assert float(cpu(r["best_energy"])[0]) == pytest.approx(g.info()["total_weight"] - 2 * float(cpu(r["best_cut"])[0]),
+                                                            rel=1e-14, abs=1e-12)
+
+
 def test_deterministic_snp_build():
     """deterministic = 1: fixed-point sums give the same SNP weights bit for bit on every
     build (and so the same solve), within 2^-40 per Eq. (14) term of the oracle's FP64 sum."""
