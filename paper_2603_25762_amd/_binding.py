@@ -327,6 +327,31 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
     return res
 
 
+def energy_trace(g: Graph, replicas: int, steps: int, every: int, *, dt: float = 0.5, c0: float = 0.0,
+                 a0: float = 1.0, seed: int = 0, discrete: bool = False, plan: int = 1,
+                 stream=None) -> Dict[str, object]:
+    """Ising energy (Eq. 5) of every replica's signs every `every` steps of one schedule
+    (the convergence view of the solver comparison): step ranges of one solve, resumed
+    from the state the previous range left, read out without the greedy pass.  Returns
+    steps (the step count after each range), energy (float64 [len(steps), replicas]) and
+    best (the lowest energy per range)."""
+    if every < 1 or steps < 1:
+        raise ValueError("steps and every must be >= 1")
+    n = g.info()["n"]
+    W = g.info()["total_weight"]
+    x = torch.empty((max(n, 1), replicas), dtype=torch.float32, device="cuda")[:n]
+    y = torch.empty_like(x)
+    marks, rows = [], []
+    for k in range(0, steps, every):
+        ke = min(steps, k + every)
+        r = bsb_solve(g, replicas, steps, dt=dt, c0=c0, a0=a0, seed=seed, init=(k == 0), x=x, y=y,
+                      step_begin=k, step_end=ke, greedy=False, discrete=discrete, plan=plan, stream=stream)
+        rows.append(W - 2.0 * r["cuts"].double())
+        marks.append(ke)
+    energy = torch.stack(rows).cpu().numpy()
+    return dict(steps=marks, energy=energy, best=energy.min(axis=1))
+
+
 _TUNED = ("plan", "replica_tile", "tiles_in_flight", "persistent_sync")
 
 

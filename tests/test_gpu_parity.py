@@ -949,6 +949,27 @@ def test_best_energy_matches_eq5(kind, dtype):
                                                             rel=1e-14, abs=1e-12)
 
 
+def test_energy_trace_resumes_one_schedule():
+    """energy_trace runs one schedule in step ranges: its last row is the energy (Eq. 5) of
+    every replica after a straight solve of the same schedule, bit for bit, and its first
+    rows match the oracle's energies of the same steps' signs."""
+    w = synth.read_tiny()
+    g = gpu_graph(w, "read_signed", "f32")
+    tr = qh.energy_trace(g, 16, 300, 100, seed=7)
+    assert tr["steps"] == [100, 200, 300] and tr["energy"].shape == (3, 16)
+    r = qh.bsb_solve(g, 16, 300, seed=7, greedy=False, plan=1)
+    W = g.info()["total_weight"]
+    assert np.array_equal(tr["energy"][-1], W - 2.0 * cpu(r["cuts"]))
+    go = oracle_graph(w)
+    J = go.dense()
+    x, y = oracle.init_state(7, go.n, 16)
+    oracle.bsb_run(go, x, y, oracle.pump_linear(300), 0.5, oracle.c0(go), 1.0, 0, 100)
+    s = np.where(x >= 0, 1.0, -1.0)
+    e = -0.5 * np.einsum("ir,ij,jr->r", s, J, s)
+    assert np.allclose(tr["energy"][0], e, rtol=0, atol=1e-9)
+    assert tr["best"][-1] <= tr["best"][0]
+
+
 def test_deterministic_snp_build():
     """deterministic = 1: fixed-point sums give the same SNP weights bit for bit on every
     build (and so the same solve), within 2^-40 per Eq. (14) term of the oracle's FP64 sum."""
