@@ -430,6 +430,19 @@ def phase(g: Graph, spins: torch.Tensor, n_snp: Optional[int] = None, stream=Non
     return h1[:n_snp], block[:n_snp]
 
 
+def refine_adaptive(g: Graph, *, seed: int = 0, deform: float = 0.0, deform_tries: int = 0,
+                    stream=None) -> Dict[str, object]:
+    """The SNP-based method with its size-adaptive settings (adaptive_schedule: steps by
+    graph size, 128 replicas for the 100 samples, up to 15 rounds) and, with deform > 0,
+    the deformation of rounds stuck at a negative cut.  Returns refine's outputs plus the
+    settings used."""
+    a = adaptive_schedule(g.info()["n"])
+    out = refine(g, a["replicas"], a["steps"], max_rounds=a["max_rounds"], seed=seed, deform=deform,
+                 deform_tries=deform_tries, stream=stream)
+    out["schedule"] = a
+    return out
+
+
 def flip_crossing(g: Graph, spins: torch.Tensor, stream=None):
     _check(load().qh_flip_crossing(g.handle, _ptr(spins), _stream(stream)))
 

@@ -715,6 +715,18 @@ def test_refine_gauge_identity_restore_and_single_round(dtype):
     assert r1["round_cuts"][0] == pytest.approx(float(cpu(rs["best_cut"])[0]), rel=1e-12)
 
 
+def test_refine_adaptive_schedule_planted_twin():
+    """The size-adaptive settings end to end on an error-free planted twin: 500 steps below
+    5,000 vertices, 128 replicas, at most 15 rounds; the haplotypes keep at most a few
+    switches (the solver is a heuristic; FP16 storage, 900 SNPs: 2 switches measured)."""
+    w = synth.snp_small(8, n_snp=900, error=0.0)
+    g = gpu_graph(w, "snp_llr", "f16")
+    rr = qh.refine_adaptive(g, seed=2, deform=0.5, deform_tries=2)
+    assert rr["schedule"]["steps"] == 500 and rr["schedule"]["replicas"] == 128
+    assert 1 <= rr["rounds"] <= 15
+    assert metrics.switch_error(cpu(rr["h1"]), w.truth, cpu(rr["block"])) <= 0.01
+
+
 def test_refine_planted_twin_and_errors():
     w = synth.snp_small(8, n_snp=600, error=0.0)
     g = gpu_graph(w, "snp_llr", "f32")
