@@ -104,10 +104,14 @@ typedef struct {
                             each storage copy are allocated, and on the finished graph:
                             ENOMEM (nothing kept) when the graph would exceed it. */
     int32_t deterministic; /* SNP_LLR: 1 = each Eq. (14) term is rounded to a multiple of
-                            2^-40 (|term| clamped to 2^20) and the terms are summed in 64-bit
-                            integers, so the weights are bit-identical from build to build
-                            (the FP64 sum of atomics, 0, depends on the order of the additions
-                            in its last bits).  Read graphs are integer sums: exact either way. */
+                            2^-40 and the terms are summed in 64-bit integers, so the weights
+                            are bit-identical from build to build (the FP64 sum of atomics, 0,
+                            depends on the order of the additions in its last bits).  This
+                            trades the relative error bound of the FP64 sum (<= 1e-12 of the
+                            summed |terms|) for an absolute one: at most 2^-41 per term, which
+                            for very small weights is larger in relative terms.  A term of
+                            magnitude 2^20 or more fails the build with ENUMERIC.  Read graphs
+                            are integer sums: exact either way. */
 } qh_graph_opts;
 
 typedef struct qh_graph qh_graph;
@@ -129,7 +133,10 @@ typedef struct {
                                 graph's dtype, or QH_F16 for a BF16 graph whose band values are
                                 all exactly representable in binary16 (same values) */
     double total_weight;     /* W = -1/2 sum_ab J_ab (the edge weights of A = -J summed once):
-                                the Ising energy of Eq. (5) is E(s) = W - 2 cut(s) */
+                                the Ising energy of Eq. (5) is E(s) = W - 2 cut(s).  Kept current
+                                by qh_flip_crossing. */
+    int64_t largest_component; /* vertices of the largest connected component (0 when every
+                                component is a single vertex) */
 } qh_graph_info;
 
 /* Builds J from fragments (Methods: read-based Eqs. 1-3, SNP-based Eqs. 9-14).
@@ -212,6 +219,17 @@ typedef struct {
                             -x'Jx/2 - h'x.  NULL = no field (the plain bSB step).  Batched
                             solves take it packed like the results (block b's vertices from
                             its vertex offset).  Caller-owned; read during the call only. */
+    int32_t eval_every;  /* readout cadence m (Methods, SB algorithm solution: the best of many
+                            samples; the solver comparison follows the energy over the run).
+                            0: the spins are read out after the last step only.  m > 0: they
+                            are also read out after steps step_begin + m, step_begin + 2m, ...
+                            (and always after the last step); every evaluation computes the FP64
+                            cut of every replica and component, and each component keeps the
+                            best (evaluation, replica) seen so far -- largest cut, ties to the
+                            earlier evaluation, then the lower replica -- whose spins become
+                            best_spins (before the greedy pass).  The trajectory is the same as
+                            with m = 0.  Needs readout = 1 and use_graph = 0 (EINVAL otherwise);
+                            batched solves take 0 only. */
 } qh_bsb_opts;
 
 /* Result buffers (all device, caller-owned; optional ones may be NULL).
@@ -226,7 +244,13 @@ typedef struct {
  *  all_spins     int8 [n][R]   every replica's signs (optional)
  *  greedy_rounds int32 [1]     rounds that flipped something (optional, host or device: device)
  *  best_energy   double [1]    Ising energy of best_spins, E = -1/2 s'Js (Eq. 5) = W - 2 best_cut
- *                              (optional; readout = 1) */
+ *                              (optional; readout = 1)
+ *  energy        double [n_eval][R]  Ising energy (Eq. 5) of every replica's signs at each
+ *                              evaluation (optional; readout = 1), n_eval = 1 when eval_every = 0,
+ *                              else max(1, ceil((step_end - step_begin) / eval_every)); row e is
+ *                              the state after step min(step_begin + (e + 1) m, step_end).
+ *  With eval_every > 0: cuts and cut_rc are those of the last evaluation; best_replica[c] and
+ *  selected_cut refer to the best-so-far pick of each component. */
 typedef struct {
     float *x;
     float *y;
@@ -239,12 +263,14 @@ typedef struct {
     int8_t *all_spins;
     int32_t *greedy_rounds;
     double *best_energy;
+    double *energy;
 } qh_result;
 
 /* Runs bSB on one graph.  Synchronises the stream only when greedy = 1.
  * Errors: EINVAL (replicas not 16/32/64k, steps < 1, range outside the schedule,
- * init = 0 without x/y, readout without best_spins/cuts/best_cut), ENUMERIC when the
- * final state holds NaN/Inf (checked when readout = 1), ENOMEM, EHIP. */
+ * init = 0 without x/y, readout without best_spins/cuts/best_cut, eval_every < 0 or
+ * eval_every > 0 with readout = 0 or use_graph = 1), ENUMERIC when the state read out holds
+ * NaN/Inf (checked when readout = 1), ENOMEM, EHIP. */
 qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *res, void *stream);
 
 /* Step-loop plan chosen for (graph, replicas) by earlier solves.  plan_used: 0 = no solve
@@ -301,7 +327,13 @@ qh_status qh_autotune(const qh_graph *g, const qh_bsb_opts *opts, qh_bsb_opts *c
  *  best_spins int8 [sum n]; cuts double [n_blocks * R]; best_cut double [n_blocks];
  *  selected_cut double [n_blocks] (optional); x, y optional float [sum n * R];
  *  plan_used (host output) the plan that ran.  Greedy is applied per block when
- *  requested.  Synchronises the stream. */
+ *  requested.  opts->use_graph = 1 runs the per-step plan from a captured hipGraph: the step
+ *  launches are captured once per list of graphs, R and schedule (steps, dt, a0, pump, seed)
+ *  and replayed by later calls with the same ones (the library keeps the last few batches);
+ *  results are those of plan 1, bit for bit.  use_graph with plan 2 is EUNSUPPORTED, and
+ *  plan 0 with use_graph runs plan 1 without tuning.  eval_every must be 0.  readout = 0
+ *  runs the dynamics only (the result arrays other than x and y may then be NULL).
+ *  Synchronises the stream. */
 typedef struct {
     int8_t *best_spins;
     double *cuts;
@@ -327,7 +359,9 @@ qh_status qh_phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *
                    void *stream);
 
 /* Eq. 15: J_uv <- -J_uv for every edge whose endpoints disagree in `spins` (device
- * int8 [n]); updates the master and the stored copy in place. */
+ * int8 [n]); updates the master and the stored copy in place and recomputes
+ * qh_graph_info.total_weight (c0_auto depends on J^2 only and does not change).
+ * Synchronises the stream. */
 qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream);
 
 /* Iterative refinement of the SNP-based method (Eqs. 15-17), SNP graphs only.  Round t
@@ -357,6 +391,24 @@ qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream);
 qh_status qh_refine(qh_graph *g, const qh_bsb_opts *opts, int32_t max_rounds, float deform, int32_t deform_tries,
                     int8_t *h1, int32_t *block, int32_t *flips, double *round_cuts, int32_t *rounds,
                     int32_t *deformed, void *stream);
+
+/* Size-adaptive bSB settings of the SNP-based method (Tables 1 and 2, footnotes): 500
+ * iterations for graphs below 5,000 nodes and 1,000 otherwise, 100 samples, at most 15
+ * refinement rounds.  `size` is the vertex count the rule is applied to.  The paper solves
+ * components independently; here the components of one graph share one schedule, so pass
+ * the largest component's size (qh_graph_info.largest_component): every component then gets
+ * at least the paper's count for its own size.  The solvers take 16, 32 or a multiple of 64
+ * replicas, so the 100 samples run as replicas = 128 (more samples never lower the best cut
+ * of a component).  Host output; no device work.  Errors: EINVAL (null out, size < 0). */
+typedef struct {
+    int32_t steps;
+    int32_t samples;     /* the paper's sample count */
+    int32_t replicas;    /* replicas the solvers run for those samples */
+    int32_t max_rounds;  /* refinement rounds (qh_refine's max_rounds) */
+    int64_t size;        /* the vertex count the rule was applied to */
+} qh_schedule;
+
+qh_status qh_adaptive_schedule(int64_t size, qh_schedule *out);
 
 const char *qh_last_error(void);
 const char *qh_version(void);

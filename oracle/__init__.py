@@ -462,11 +462,38 @@ def refine(g: CSR, init_h1: np.ndarray, R: int, steps: int, dt: float = 0.5, see
 # whole solve, as the library's bsb_solve defines it
 # --------------------------------------------------------------------------
 
+def merge_best(g: CSR, comp: np.ndarray, n_comp: int, spin_sets):
+    """Best sample seen so far per component (the best-of-many-samples rule of the SB
+    solution, applied over several readouts of one run): over a sequence of spin sets
+    s_e [n, R], component c keeps the (e, r) with the largest cut, ties going to the
+    earlier readout, then the lower replica; returns (spins oriented so that the
+    component's lowest vertex reads +1, cut per component, replica per component)."""
+    best = np.ones(g.n, dtype=np.int8)
+    best_cut = np.full(max(n_comp, 0), -np.inf)
+    best_rep = np.zeros(max(n_comp, 0), dtype=np.int32)
+    for s in spin_sets:
+        cut = cuts(g, comp, n_comp, s)                       # [R, n_comp]
+        pick, pick_r = select(comp, n_comp, s, cut)
+        for c in range(n_comp):
+            v = cut[pick_r[c], c]
+            if v > best_cut[c]:
+                best_cut[c] = v
+                best_rep[c] = pick_r[c]
+                best[comp == c] = pick[comp == c]
+    return best, best_cut, best_rep
+
+
 def solve(g: CSR, R: int, steps: int, dt: float = 0.5, c0_: Optional[float] = None,
           a0: float = 1.0, seed: int = 0, greedy_pass: bool = True, integer: bool = False,
           x0: Optional[np.ndarray] = None, y0: Optional[np.ndarray] = None,
           pump: Optional[np.ndarray] = None, discrete: bool = False,
-          field: Optional[np.ndarray] = None) -> Dict[str, object]:
+          field: Optional[np.ndarray] = None, eval_every: int = 0) -> Dict[str, object]:
+    """Whole solve: bSB steps, signs, FP64 cuts, best replica per component, greedy pass.
+
+    ``eval_every`` = m > 0 reads the signs out after every m steps (and after the last):
+    each component keeps its best sample over all readouts (``merge_best``), and the Ising
+    energy -1/2 s'Js (Eq. 5) of every replica at every readout is returned as ``energy``
+    [n_eval, R].  With m = 0 there is one readout, after the last step."""
     comp, nc = components(g)
     if c0_ is None or c0_ <= 0:
         c0_ = c0(g)
@@ -477,15 +504,23 @@ def solve(g: CSR, R: int, steps: int, dt: float = 0.5, c0_: Optional[float] = No
         y = np.array(y0, dtype=np.float64, order="C")
     if pump is None:
         pump = pump_linear(steps)
-    bsb_run(g, x, y, pump, dt, c0_, a0, discrete=discrete, field=field)
-    s = signs(x)
+    marks = list(range(eval_every, steps, eval_every)) if eval_every > 0 else []
+    marks.append(steps)
+    spin_sets, energy_rows = [], []
+    k = 0
+    for k1 in marks:
+        bsb_run(g, x, y, pump, dt, c0_, a0, k, k1, discrete=discrete, field=field)
+        k = k1
+        spin_sets.append(signs(x))
+        energy_rows.append(energy(g, spin_sets[-1]))
+    s = spin_sets[-1]
     cut = cuts(g, comp, nc, s)
-    best, best_r = select(comp, nc, s, cut)
-    sel_cut = float(sum(cut[best_r[c], c] for c in range(nc)))
+    best, best_c, best_r = merge_best(g, comp, nc, spin_sets)
+    sel_cut = float(sum(best_c[c] for c in range(nc)))
     rounds = 0
     if greedy_pass:
         best, rounds = greedy(g, best, greedy_eps(g, integer))
     final = float(cuts(g, comp, nc, best).sum())
     return dict(comp=comp, n_comp=nc, c0=c0_, x=x, y=y, spins=s, cuts=cut.sum(axis=1),
                 cut_rc=cut, best=best, best_r=best_r, selected_cut=sel_cut, best_cut=final,
-                greedy_rounds=rounds)
+                greedy_rounds=rounds, energy=np.array(energy_rows), eval_steps=marks)

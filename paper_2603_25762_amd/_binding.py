@@ -58,7 +58,8 @@ class _GraphInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("kind", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("integer_weights", ctypes.c_int32), ("c0_auto", ctypes.c_double),
-                ("band_dtype", ctypes.c_int32), ("total_weight", ctypes.c_double)]
+                ("band_dtype", ctypes.c_int32), ("total_weight", ctypes.c_double),
+                ("largest_component", ctypes.c_int64)]
 
 
 class _BsbOpts(ctypes.Structure):
@@ -70,13 +71,13 @@ class _BsbOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("plan", ctypes.c_int32),
                 ("replica_tile", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("tiles_in_flight", ctypes.c_int32), ("persistent_sync", ctypes.c_int32),
-                ("field", P)]
+                ("field", P), ("eval_every", ctypes.c_int32)]
 
 
 class _Result(ctypes.Structure):
     _fields_ = [("x", P), ("y", P), ("best_spins", P), ("cuts", P), ("cut_rc", P),
                 ("best_replica", P), ("selected_cut", P), ("best_cut", P), ("all_spins", P),
-                ("greedy_rounds", P), ("best_energy", P)]
+                ("greedy_rounds", P), ("best_energy", P), ("energy", P)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -87,6 +88,11 @@ class _PlanInfo(ctypes.Structure):
                 ("tiles_in_flight", ctypes.c_int32), ("skyline_kernel", ctypes.c_int32),
                 ("skyline_us", ctypes.c_float * 2), ("persistent_sync", ctypes.c_int32),
                 ("us_persistent_coherent", ctypes.c_float)]
+
+
+class _Schedule(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("samples", ctypes.c_int32), ("replicas", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32), ("size", ctypes.c_int64)]
 
 
 class _BatchedResult(ctypes.Structure):
@@ -126,6 +132,7 @@ def load():
         "qh_solve_plan_info": [P, ctypes.c_int32, ctypes.POINTER(_PlanInfo)],
         "qh_autotune": [P, ctypes.POINTER(_BsbOpts), ctypes.POINTER(_BsbOpts), ctypes.POINTER(ctypes.c_float),
                         ctypes.c_char_p, P],
+        "qh_adaptive_schedule": [ctypes.c_int64, ctypes.POINTER(_Schedule)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -212,9 +219,15 @@ class Graph:
             self._h = ctypes.c_void_p(0)
 
     def __del__(self):
+        # No HIP call while the interpreter shuts down: by then a profiler or the runtime may
+        # already have torn down (the process releases device memory on exit anyway).
         try:
+            import sys
+            if sys.is_finalizing():
+                return
             if self._h is not None and self._h.value and _lib is not None:
                 _lib.qh_graph_free(self._h)
+                self._h = ctypes.c_void_p(0)
         except Exception:
             pass
 
@@ -255,15 +268,15 @@ def _check_field(field: Optional[torch.Tensor], n: int):
         raise ValueError(f"field holds {field.numel()} values for {n} vertices")
 
 
-def adaptive_schedule(n: int) -> Dict[str, int]:
-    """The SNP-based method's size-adaptive bSB settings (Tables 1 and 2, footnotes):
-    500 iterations below 5,000 vertices and 1,000 otherwise, 100 samples, at most 15
-    refinement rounds.  The solvers take 16, 32 or a multiple of 64 replicas, so the
-    100 samples become the next such count, 128 (more samples never lower the best cut
-    of a component)."""
-    if n < 0:
-        raise ValueError("n must be >= 0")
-    return dict(steps=500 if n < 5000 else 1000, samples=100, replicas=128, max_rounds=15)
+def adaptive_schedule(size) -> Dict[str, int]:
+    """The library's size-adaptive bSB settings (qh_adaptive_schedule): steps, samples,
+    replicas, max_rounds and the size the rule was applied to.  ``size`` is a vertex count,
+    or a Graph, whose largest component is used."""
+    if isinstance(size, Graph):
+        size = size.info()["largest_component"]
+    sc = _Schedule()
+    _check(load().qh_adaptive_schedule(int(size), ctypes.byref(sc)))
+    return {name: int(getattr(sc, name)) for name, _ in _Schedule._fields_}
 
 
 def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float = 0.0,
@@ -272,14 +285,18 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
               step_begin: int = 0, step_end: int = 0, readout: bool = True, greedy: bool = True,
               use_graph: bool = False, all_spins: bool = False, per_component: bool = False,
               plan: int = 0, replica_tile: int = 0, discrete: bool = False, tiles_in_flight: int = 0,
-              persistent_sync: int = 0, field: Optional[torch.Tensor] = None,
-              out: Optional[Dict[str, torch.Tensor]] = None, stream=None) -> Dict[str, torch.Tensor]:
+              persistent_sync: int = 0, field: Optional[torch.Tensor] = None, eval_every: int = 0,
+              energy: bool = False, out: Optional[Dict[str, torch.Tensor]] = None,
+              stream=None) -> Dict[str, torch.Tensor]:
     """Runs bSB; returns device tensors (best_spins, cuts, best_cut, selected_cut, ...).
 
     ``x``/``y`` (float32 [n, R]) give the starting state when ``init`` is False and
     receive the final state when passed.  ``field`` (float32 [n], device) is the
-    deformation term h added to every row's coupling sum.  ``out`` may supply
-    preallocated result tensors (keys as returned) so that repeated calls allocate nothing.
+    deformation term h added to every row's coupling sum.  ``eval_every`` > 0 reads the
+    spins out every that many steps and keeps each component's best so far; ``energy``
+    returns the Ising energy of every replica at each evaluation (float64 [n_eval, R]).
+    ``out`` may supply preallocated result tensors (keys as returned) so that repeated
+    calls allocate nothing.
     """
     inf = g.info()
     n, nc = inf["n"], inf["n_comp"]
@@ -310,6 +327,10 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
         if per_component:
             alloc("cut_rc", (replicas, nc), torch.float64)
             alloc("best_replica", (nc,), torch.int32)
+        if energy:
+            span = (step_end or steps) - step_begin
+            n_eval = max(1, -(-span // eval_every)) if eval_every > 0 else 1
+            alloc("energy", (n_eval, replicas), torch.float64)
     if x is not None:
         res["x"] = x
     if y is not None:
@@ -318,11 +339,11 @@ def bsb_solve(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float
         res["pump"] = pump
     opts = _BsbOpts(replicas, steps, step_begin, step_end, dt, c0, a0, _ptr(pump), seed & (2**64 - 1),
                     int(init), int(readout), int(greedy), int(use_graph), int(plan), int(replica_tile),
-                    int(discrete), int(tiles_in_flight), int(persistent_sync), _ptr(field))
+                    int(discrete), int(tiles_in_flight), int(persistent_sync), _ptr(field), int(eval_every))
     r = _Result(_ptr(x), _ptr(y), _ptr(keep.get("best_spins")), _ptr(keep.get("cuts")),
                 _ptr(keep.get("cut_rc")), _ptr(keep.get("best_replica")), _ptr(keep.get("selected_cut")),
                 _ptr(keep.get("best_cut")), _ptr(keep.get("all_spins")), _ptr(keep.get("greedy_rounds")),
-                _ptr(keep.get("best_energy")))
+                _ptr(keep.get("best_energy")), _ptr(keep.get("energy")))
     _check(load().qh_bsb_solve(g.handle, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
     return res
 
@@ -331,24 +352,15 @@ def energy_trace(g: Graph, replicas: int, steps: int, every: int, *, dt: float =
                  a0: float = 1.0, seed: int = 0, discrete: bool = False, plan: int = 1,
                  stream=None) -> Dict[str, object]:
     """Ising energy (Eq. 5) of every replica's signs every `every` steps of one schedule
-    (the convergence view of the solver comparison): step ranges of one solve, resumed
-    from the state the previous range left, read out without the greedy pass.  Returns
-    steps (the step count after each range), energy (float64 [len(steps), replicas]) and
-    best (the lowest energy per range)."""
+    (the convergence view of the solver comparison): one solve with eval_every = every,
+    read out without the greedy pass.  Returns steps (the step count of each evaluation),
+    energy (float64 [len(steps), replicas]) and best (the lowest energy per evaluation)."""
     if every < 1 or steps < 1:
         raise ValueError("steps and every must be >= 1")
-    n = g.info()["n"]
-    W = g.info()["total_weight"]
-    x = torch.empty((max(n, 1), replicas), dtype=torch.float32, device="cuda")[:n]
-    y = torch.empty_like(x)
-    marks, rows = [], []
-    for k in range(0, steps, every):
-        ke = min(steps, k + every)
-        r = bsb_solve(g, replicas, steps, dt=dt, c0=c0, a0=a0, seed=seed, init=(k == 0), x=x, y=y,
-                      step_begin=k, step_end=ke, greedy=False, discrete=discrete, plan=plan, stream=stream)
-        rows.append(W - 2.0 * r["cuts"].double())
-        marks.append(ke)
-    energy = torch.stack(rows).cpu().numpy()
+    r = bsb_solve(g, replicas, steps, dt=dt, c0=c0, a0=a0, seed=seed, greedy=False, discrete=discrete,
+                  plan=plan, eval_every=every, energy=True, stream=stream)
+    energy = r["energy"].cpu().numpy()
+    marks = [min(steps, (e + 1) * every) for e in range(energy.shape[0])]
     return dict(steps=marks, energy=energy, best=energy.min(axis=1))
 
 
@@ -361,7 +373,7 @@ def autotune(g: Graph, replicas: int, steps: int, *, dt: float = 0.5, c0: float 
     options (keys plan, replica_tile, tiles_in_flight, persistent_sync: pass them to
     bsb_solve to skip tuning) plus us_per_step; with cache_path, appends them as one JSON
     line for load_tuned."""
-    opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, 0, 1, 0, 0, 0, 0, 0, int(discrete), 0, 0, None)
+    opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, 0, 1, 0, 0, 0, 0, 0, int(discrete), 0, 0, None, 0)
     chosen = _BsbOpts()
     us = (ctypes.c_float * 2)()
     path = None if cache_path is None else os.fsencode(cache_path)
@@ -388,12 +400,12 @@ def load_tuned(cache_path: str, g: Graph, replicas: int) -> Optional[Dict[str, i
 def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt: float = 0.5,
                       c0: float = 0.0, a0: float = 1.0, seed: int = 0, greedy: bool = True,
                       use_graph: bool = False, plan: int = 0, return_state: bool = False,
-                      discrete: bool = False, field: Optional[torch.Tensor] = None,
+                      discrete: bool = False, field: Optional[torch.Tensor] = None, readout: bool = True,
                       stream=None) -> Dict[str, torch.Tensor]:
     """All graphs in one launch; per-block results packed at ``vertex_offset`` / ``b * replicas``.
 
     ``field`` (float32 [sum n], device) is packed the same way: block b's deformation
-    term from ``vertex_offset[b]``."""
+    term from ``vertex_offset[b]``.  ``readout`` False runs the dynamics only."""
     ns = [g.info()["n"] for g in graphs]
     total = int(sum(ns))
     _check_field(field, total)
@@ -407,8 +419,8 @@ def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt:
         res["x"] = torch.empty(max(total * replicas, 1), dtype=torch.float32, device=dev)
         res["y"] = torch.empty(max(total * replicas, 1), dtype=torch.float32, device=dev)
     arr = (ctypes.c_void_p * max(nb, 1))(*[g.handle.value for g in graphs])
-    opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
-                    int(use_graph), plan, 0, int(discrete), 0, 0, _ptr(field))
+    opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, int(readout), int(greedy),
+                    int(use_graph), plan, 0, int(discrete), 0, 0, _ptr(field), 0)
     r = _BatchedResult(_ptr(res["best_spins"]), _ptr(res["cuts"]), _ptr(res["best_cut"]),
                        _ptr(res["selected_cut"]), _ptr(res.get("x")), _ptr(res.get("y")), 0)
     _check(load().qh_bsb_solve_batched(arr, nb, ctypes.byref(opts), ctypes.byref(r), _stream(stream)))
@@ -436,7 +448,7 @@ def refine_adaptive(g: Graph, *, seed: int = 0, deform: float = 0.0, deform_trie
     graph size, 128 replicas for the 100 samples, up to 15 rounds) and, with deform > 0,
     the deformation of rounds stuck at a negative cut.  Returns refine's outputs plus the
     settings used."""
-    a = adaptive_schedule(g.info()["n"])
+    a = adaptive_schedule(g)
     out = refine(g, a["replicas"], a["steps"], max_rounds=a["max_rounds"], seed=seed, deform=deform,
                  deform_tries=deform_tries, stream=stream)
     out["schedule"] = a
@@ -463,7 +475,7 @@ def refine(g: Graph, replicas: int, steps: int, *, max_rounds: int = 15, dt: flo
     rounds = ctypes.c_int32(0)
     deformed = ctypes.c_int32(0)
     opts = _BsbOpts(replicas, steps, 0, 0, dt, c0, a0, None, seed & (2**64 - 1), 1, 1, int(greedy),
-                    int(use_graph), plan, 0, int(discrete), 0, 0, None)
+                    int(use_graph), plan, 0, int(discrete), 0, 0, None, 0)
     _check(load().qh_refine(g.handle, ctypes.byref(opts), max_rounds, float(deform), int(deform_tries), _ptr(h1),
                             _ptr(block), _ptr(flips), rc, ctypes.byref(rounds), ctypes.byref(deformed),
                             _stream(stream)))

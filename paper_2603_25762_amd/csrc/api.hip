@@ -144,6 +144,7 @@ qh_status qh_graph_get_info(const qh_graph *g, qh_graph_info *out) {
         i.c0_auto = g->c0_auto;
         i.total_weight = g->total_weight;
         i.band_dtype = g->storage == QH_STORE_SKYLINE ? g->bb_dtype : g->dtype;
+        i.largest_component = g->largest_comp;
         *out = i;
     });
 }
@@ -192,6 +193,7 @@ static void validate_opts(const qh_bsb_opts *o) {
         fail(QH_EINVAL, "persistent_sync must be 0, 1 or 2, got %d", o->persistent_sync);
     if (o->tiles_in_flight != 0 && o->tiles_in_flight != 2 && o->tiles_in_flight != 4)
         fail(QH_EINVAL, "tiles_in_flight must be 0, 2 or 4, got %d", o->tiles_in_flight);
+    if (o->eval_every < 0) fail(QH_EINVAL, "eval_every must be >= 0, got %d", o->eval_every);
     const int t = o->replica_tile;
     if (t != 0 && (!(t == 16 || t == 32 || t == 64) || R < 64))
         fail(QH_EINVAL, "replica_tile must be 0, or 16, 32 or 64 with R >= 64, got %d", t);
@@ -204,6 +206,9 @@ qh_status qh_bsb_solve(const qh_graph *g, const qh_bsb_opts *opts, qh_result *re
         if (!opts->init && (!res->x || !res->y)) fail(QH_EINVAL, "init = 0 needs x and y");
         if (opts->readout && (!res->best_spins || !res->cuts || !res->best_cut))
             fail(QH_EINVAL, "readout needs best_spins, cuts and best_cut");
+        if (opts->eval_every > 0 && !opts->readout) fail(QH_EINVAL, "eval_every > 0 needs readout = 1");
+        if (opts->eval_every > 0 && opts->use_graph)
+            fail(QH_EINVAL, "eval_every > 0 reads out between steps: it needs use_graph = 0");
         bsb_solve(g, opts, res, (hipStream_t)stream);
     });
 }
@@ -251,8 +256,9 @@ qh_status qh_bsb_solve_batched(const qh_graph *const *graphs, int32_t n_graphs,
         validate_opts(opts);
         for (int b = 0; b < n_graphs; ++b)
             if (!graphs[b]) fail(QH_EINVAL, "null graph %d", b);
-        if (!res->best_spins || !res->cuts || !res->best_cut)
-            fail(QH_EINVAL, "batched solve needs best_spins, cuts and best_cut");
+        if (opts->readout && (!res->best_spins || !res->cuts || !res->best_cut))
+            fail(QH_EINVAL, "batched readout needs best_spins, cuts and best_cut");
+        if (opts->eval_every != 0) fail(QH_EINVAL, "batched solves read out after the last step only (eval_every = 0)");
         bsb_solve_batched(graphs, n_graphs, opts, res, (hipStream_t)stream);
     });
 }
@@ -280,6 +286,20 @@ qh_status qh_refine(qh_graph *g, const qh_bsb_opts *opts, int32_t max_rounds, fl
         validate_opts(opts);
         refine(g, opts, max_rounds, deform, deform_tries, h1, block, flips, round_cuts, rounds, deformed,
                (hipStream_t)stream);
+    });
+}
+
+qh_status qh_adaptive_schedule(int64_t size, qh_schedule *out) {
+    return guarded([&] {
+        if (!out) fail(QH_EINVAL, "null argument");
+        if (size < 0) fail(QH_EINVAL, "size must be >= 0, got %lld", (long long)size);
+        qh_schedule s{};
+        s.size = size;
+        s.steps = s.size < 5000 ? 500 : 1000;
+        s.samples = 100;
+        s.replicas = 128;
+        s.max_rounds = 15;
+        *out = s;
     });
 }
 

@@ -38,6 +38,23 @@ static void store_batch_plan(const std::vector<uint64_t> &key, int plan) {
     g_plan_cache[key] = plan;
 }
 
+// The per-step plan's launches captured once for a batch (graph serials + R) and one set of
+// launch arguments (block table, work items, steps, dt, a0, pump, seed): replayed while the
+// key matches.  The block table and item list it points to live here too, so a replay never
+// reads a freed buffer; the few most recent batches are kept.  An entry is destroyed when a
+// newer batch pushes it out; those still listed at process exit are left to the process's
+// end (no static destructor touches the runtime while it tears itself down).
+struct CapturedBatch {
+    std::vector<uint64_t> key;           // graph serials..., R, device
+    DevBuf<BlockDesc> desc;
+    DevBuf<int2> items;
+    int64_t class_ptr[kBatchClasses + 1] = {0};
+    std::tuple<int, float, float, const float *, uint64_t> args{};
+    hipGraphExec_t exec = nullptr;
+};
+static std::vector<CapturedBatch *> g_captured;   // most recent last; at most kCapturedBatches
+constexpr size_t kCapturedBatches = 4;
+
 static double block_cost(const qh_graph *g, int R) {
     const double eb = dtype_bytes(g->dtype);
     const double state = (double)g->n * R * 12.0;
@@ -175,8 +192,72 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         else launch_batched_steps(R, nb, d_desc.p, d_items.p, class_ptr, steps, (float)o->dt, (float)a0, pump,
                                   seed, st);
     };
+    // use_graph: the per-step plan replayed from a captured hipGraph.  The capture reads the
+    // block table and items from buffers owned by the cache entry; the table is uploaded into
+    // it on every call (same graphs and R: same layout), so a replay sees this call's c0,
+    // variant and field.
+    auto run_captured = [&](int steps, uint64_t seed) {
+        std::vector<uint64_t> key(nb + 2);
+        for (int b = 0; b < nb; ++b) key[b] = gs[b]->serial;
+        key[nb] = (uint64_t)R;
+        key[nb + 1] = (uint64_t)dev;
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        CapturedBatch *cb = nullptr;
+        for (size_t i = 0; i < g_captured.size(); ++i)
+            if (g_captured[i]->key == key) {
+                cb = g_captured[i];
+                g_captured.erase(g_captured.begin() + i);
+                break;
+            }
+        if (!cb) {
+            cb = new CapturedBatch();
+            cb->key = key;
+            cb->desc.alloc(nb);
+            cb->items.alloc(std::max<int64_t>(n_items, 1));
+            if (n_items)
+                QH_HIP(hipMemcpyAsync(cb->items.p, items.data(), n_items * sizeof(int2), hipMemcpyHostToDevice, st));
+            std::copy(class_ptr, class_ptr + kBatchClasses + 1, cb->class_ptr);
+        }
+        g_captured.push_back(cb);   // most recent last
+        if (g_captured.size() > kCapturedBatches) {
+            // drop the least recent entry once no queued replay can still read its buffers
+            CapturedBatch *old = g_captured.front();
+            g_captured.erase(g_captured.begin());
+            QH_HIP(hipDeviceSynchronize());
+            if (old->exec) (void)hipGraphExecDestroy(old->exec);
+            delete old;
+        }
+        QH_HIP(hipMemcpyAsync(cb->desc.p, desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
+        const auto args = std::make_tuple(steps, (float)o->dt, (float)a0, pump, seed);
+        if (!cb->exec || cb->args != args) {
+            if (cb->exec) { (void)hipGraphExecDestroy(cb->exec); cb->exec = nullptr; }
+            hipStream_t cs;
+            QH_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            QH_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            try {
+                launch_batched_steps(R, nb, cb->desc.p, cb->items.p, cb->class_ptr, steps, (float)o->dt, (float)a0,
+                                     pump, seed, cs);
+            } catch (...) {
+                hipGraph_t junk = nullptr;
+                (void)hipStreamEndCapture(cs, &junk);
+                if (junk) (void)hipGraphDestroy(junk);
+                (void)hipStreamDestroy(cs);
+                throw;
+            }
+            QH_HIP(hipStreamEndCapture(cs, &graph));
+            QH_HIP(hipStreamDestroy(cs));
+            const hipError_t e = hipGraphInstantiate(&cb->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) { cb->exec = nullptr; fail_hip(e, "hipGraphInstantiate", __FILE__, __LINE__); }
+            cb->args = args;
+        }
+        QH_HIP(hipGraphLaunch(cb->exec, st));
+    };
+    if (o->use_graph && o->plan == 2)
+        fail(QH_EUNSUPPORTED, "the whole-block plan is one launch already; use_graph applies to the per-step plan");
     int plan = o->plan == 2 ? 2 : 1;
-    if (o->plan == 0 && o->steps > 0) {
+    if (o->plan == 0 && o->steps > 0 && !o->use_graph) {
         std::vector<uint64_t> key(nb + 1);
         for (int b = 0; b < nb; ++b) key[b] = gs[b]->serial;
         key[nb] = (uint64_t)R;
@@ -202,11 +283,32 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
             store_batch_plan(key, plan);
         }
     }
-    if (o->steps > 0) run(plan, o->steps, o->seed);
+    if (o->steps > 0) {
+        if (o->use_graph) run_captured(o->steps, o->seed);
+        else run(plan, o->steps, o->seed);
+    }
     res->plan_used = plan;
     // the per-step plan ping-pongs x like the single-graph solve; the whole-block plan
     // leaves the final x in the first half
     const int final_half = plan == 1 ? (o->steps & 1) : 0;
+
+    if (!o->readout) {   // dynamics only: the final state of every block, when asked for
+        int64_t off = 0;
+        for (int b = 0; b < nb; ++b) {
+            const qh_graph *g = gs[b];
+            SolvePlan &p = *plans[b];
+            const int64_t nR = g->n * R;
+            const bool pingpong = !(g->storage == QH_STORE_DENSE && g->dtype != QH_F32);
+            const float *xfin = (pingpong && final_half) ? p.xb.p : p.xa.p;
+            if (res->x && nR)
+                QH_HIP(hipMemcpyAsync(res->x + off * R, xfin, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+            if (res->y && nR)
+                QH_HIP(hipMemcpyAsync(res->y + off * R, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+            off += g->n;
+        }
+        QH_HIP(hipStreamSynchronize(st));
+        return;
+    }
 
     // readout of every block in one launch per kernel: FP64 cuts, component selection,
     // optional greedy, cut of the result

@@ -1328,9 +1328,43 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     };
     load_state();
     if (ke > kb && n > 0) p.last_plan = persistent ? 2 : 1;
+    const int coherent = o->persistent_sync == 2 || (o->persistent_sync == 0 && p.tuned_coh);
+    if (persistent) p.last_coh = coherent;
+    if (o->eval_every > 0) {
+        // read out after every eval_every steps: the step loop runs in ranges, each starting
+        // from the state the previous one left in xa / y (and the 16-bit copy made from xa,
+        // the same bits the step kernels write), so the trajectory is that of one range
+        const int m = o->eval_every;
+        EvalArgs ev;
+        ev.W = g->total_weight;
+        int k0 = kb;
+        for (ev.index = 0;; ++ev.index) {
+            const int k1 = (int)std::min<int64_t>(ke, (int64_t)k0 + m);
+            int fh = 0;
+            if (k1 > k0 && n > 0) {
+                if (persistent) run_persistent(g, p, pump, c0, o->dt, a0, k0, k1, o->variant == 1, o->field, coherent, st);
+                else fh = run_steps(g, p, o, pump, c0, a0, k0, k1, st);
+            }
+            if (fh && !dense16 && nR)   // ping-pong paths: the range ended in the second half
+                QH_HIP(hipMemcpyAsync(p.xa.p, p.xb.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+            ev.last = k1 >= ke;
+            ev.energy_row = res->energy ? res->energy + (int64_t)ev.index * R : nullptr;
+            if (ev.last) {
+                if (res->x && nR) QH_HIP(hipMemcpyAsync(res->x, p.xa.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+                if (res->y && nR) QH_HIP(hipMemcpyAsync(res->y, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
+            }
+            readout(view_of(g), p, R, p.xa.p, p.y.p, res, o->greedy != 0, st, ev.last, &ev);
+            if (ev.last) break;
+            if (dense16) x_to_h(g, p, n, R, o->variant == 1, st);
+            k0 = k1;
+        }
+        if (res->best_energy) {
+            hipLaunchKernelGGL(k_energy, dim3(1), dim3(64), 0, st, g->total_weight, res->best_cut, res->best_energy);
+            QH_CHECK_LAUNCH();
+        }
+        return;
+    }
     if (persistent) {
-        const int coherent = o->persistent_sync == 2 || (o->persistent_sync == 0 && p.tuned_coh);
-        p.last_coh = coherent;
         run_persistent(g, p, pump, c0, o->dt, a0, kb, ke, o->variant == 1, o->field, coherent, st);
     } else if (ke > kb && n > 0) {
         if (o->use_graph) {
@@ -1366,7 +1400,14 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
     if (res->x && nR) QH_HIP(hipMemcpyAsync(res->x, xfin, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (res->y && nR) QH_HIP(hipMemcpyAsync(res->y, p.y.p, nR * sizeof(float), hipMemcpyDeviceToDevice, st));
     if (!o->readout) return;
-    readout(view_of(g), p, R, xfin, p.y.p, res, o->greedy != 0, st);
+    if (res->energy) {
+        EvalArgs ev;   // one evaluation, after the last step
+        ev.W = g->total_weight;
+        ev.energy_row = res->energy;
+        readout(view_of(g), p, R, xfin, p.y.p, res, o->greedy != 0, st, true, &ev);
+    } else {
+        readout(view_of(g), p, R, xfin, p.y.p, res, o->greedy != 0, st);
+    }
     if (res->best_energy) {
         hipLaunchKernelGGL(k_energy, dim3(1), dim3(64), 0, st, g->total_weight, res->best_cut, res->best_energy);
         QH_CHECK_LAUNCH();

@@ -382,10 +382,6 @@ __global__ void k_pack_tiles(int64_t F, const int32_t *__restrict__ W, int negat
 
 // ---- SNP graph (Eqs. 9-14) -------------------------------------------------
 
-// Eqs. (9), (11)-(13) with the per-fragment factor alpha and the 1/(|S_i|-1)
-// normalisation of Eq. (14).  J = -w, so each pair term enters J with a + sign.
-// One thread per kept observation (fragment f, rank a); it handles the pairs
-// (a, b) with a < b <= a + L of its fragment.
 // In-place conversion of fixed-point sums (int64 multiples of 2^-40) to FP64.
 __global__ void k_fixed_to_f64(int64_t n, double *__restrict__ v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -394,6 +390,11 @@ __global__ void k_fixed_to_f64(int64_t n, double *__restrict__ v) {
     }
 }
 
+// Eqs. (9), (11)-(13) with the per-fragment factor alpha and the 1/(|S_i|-1)
+// normalisation of Eq. (14).  J = -w, so each pair term enters J with a + sign.
+// One thread per kept observation (fragment f, rank a); it handles the pairs
+// (a, b) with a < b <= a + L of its fragment.  In fixed-point mode a term of magnitude
+// 2^20 or more cannot be represented: *clamped is set and the build fails.
 __global__ void k_snp_pairs(int64_t n_kept, const int64_t *__restrict__ kept_obs,
                             const int32_t *__restrict__ kept_frag, const int64_t *__restrict__ kept_ptr,
                             const int32_t *__restrict__ snp, const int8_t *__restrict__ M,
@@ -401,7 +402,8 @@ __global__ void k_snp_pairs(int64_t n_kept, const int64_t *__restrict__ kept_obs
                             const double *__restrict__ qconf, int linkage_k, int32_t band_limit,
                             const int64_t *__restrict__ s_off, const int32_t *__restrict__ s_lo,
                             double *__restrict__ s_val64, const int64_t *__restrict__ l_ptr,
-                            const int32_t *__restrict__ l_col, double *__restrict__ l_val64, int fixed) {
+                            const int32_t *__restrict__ l_col, double *__restrict__ l_val64, int fixed,
+                            int32_t *__restrict__ clamped) {
     for (int64_t kk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; kk < n_kept;
          kk += (int64_t)gridDim.x * blockDim.x) {
         int32_t f = kept_frag[kk];
@@ -428,6 +430,7 @@ __global__ void k_snp_pairs(int64_t n_kept, const int64_t *__restrict__ kept_obs
             // fixed = 1: the term as a multiple of 2^-40 (|term| clamped to 2^20), summed with
             // integer atomics, whose result does not depend on the order of the additions
             const double tc = term < -0x1p20 ? -0x1p20 : (term > 0x1p20 ? 0x1p20 : term);
+            if (fixed && !(fabs(term) < 0x1p20)) *clamped = 1;
             const unsigned long long tq = (unsigned long long)(long long)__builtin_rint(tc * 0x1p40);
             auto add = [&](double *p) {
                 if (fixed) atomicAdd((unsigned long long *)p, tq);
@@ -753,6 +756,8 @@ void upload_components(qh_graph *g, const std::vector<int32_t> &comp, int64_t n_
             if (first[comp[i]] < 0) first[comp[i]] = (int32_t)i;
             cnt[comp[i] + 1]++;
         }
+    g->largest_comp = 0;
+    for (int64_t c = 0; c < n_comp; ++c) g->largest_comp = std::max(g->largest_comp, cnt[c + 1]);
     for (int64_t c = 0; c < n_comp; ++c) cnt[c + 1] += cnt[c];
     std::vector<int32_t> order(cnt[n_comp]);
     std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
@@ -1157,12 +1162,17 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
     s_val64.zero(st);
     l_val64.zero(st);
     if (n_kept) {
+        DevBuf<int32_t> clamped(1);
+        clamped.zero(st);
         hipLaunchKernelGGL(k_snp_pairs, dim3(grid_for(n_kept, 256, 1 << 20)), dim3(256), 0, st, n_kept,
                            kept_obs_d.p, kept_frag_d.p, kept_ptr_d.p, r->snp, M.p, r->phred, r->alpha, qconf.p,
                            linkage_k, (int32_t)band_limit, g->s_off.p, g->s_lo.p, s_val64.p, g->l_ptr.p,
-                           g->l_col.p, l_val64.p, g->deterministic);
+                           g->l_col.p, l_val64.p, g->deterministic, clamped.p);
         QH_CHECK_LAUNCH();
         if (g->deterministic) {
+            if (download(clamped.p, 1, st)[0])
+                fail(QH_ENUMERIC, "deterministic build: an Eq. (14) term reaches 2^20 in magnitude, beyond the "
+                                  "fixed-point range (build with deterministic = 0)");
             if (slots) hipLaunchKernelGGL(k_fixed_to_f64, dim3(grid_for(slots)), dim3(256), 0, st, (int64_t)slots,
                                           s_val64.p);
             if (l_nnz) hipLaunchKernelGGL(k_fixed_to_f64, dim3(grid_for(l_nnz)), dim3(256), 0, st, (int64_t)l_nnz,
@@ -1296,22 +1306,33 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
 // shared finishing steps
 // ---------------------------------------------------------------------------
 
+// W = -1/2 sum_ab J_ab over the master values (Eq. 5: E(s) = W - 2 cut(s)), summed in a fixed
+// order (1,024 strided partials, then the partials in index order), so equal weights give an
+// equal W bit for bit.
+static void refresh_total_weight(qh_graph *g, hipStream_t st) {
+    g->total_weight = 0.0;
+    if (!g->nnz) return;
+    const int parts = 1024;
+    DevBuf<double> part(parts);
+    hipLaunchKernelGGL(k_sum_partial, dim3(parts), dim3(256), 0, st, g->nnz, g->m_val.p, part.p, 0);
+    QH_CHECK_LAUNCH();
+    auto pw = download(part.p, parts, st);
+    double sj = 0.0;
+    for (double v : pw) sj += v;
+    g->total_weight = -0.5 * sj;
+}
+
 void finalize_graph(qh_graph *g, hipStream_t st) {
     // c0 = 0.5 / (sigma sqrt(n)), sigma^2 = sum J^2 / (n (n - 1))
     const int parts = 1024;
     DevBuf<double> part(parts);
+    refresh_total_weight(g, st);
     if (g->nnz) {
         hipLaunchKernelGGL(k_sumsq_partial, dim3(parts), dim3(256), 0, st, g->nnz, g->m_val.p, part.p);
         QH_CHECK_LAUNCH();
         auto ph = download(part.p, parts, st);
         double ss = 0.0;
         for (double v : ph) ss += v;
-        hipLaunchKernelGGL(k_sum_partial, dim3(parts), dim3(256), 0, st, g->nnz, g->m_val.p, part.p, 0);
-        QH_CHECK_LAUNCH();
-        auto pw = download(part.p, parts, st);
-        double sj = 0.0;
-        for (double v : pw) sj += v;
-        g->total_weight = -0.5 * sj;
         if (ss > 0.0 && g->n >= 2) {
             double sigma = std::sqrt(ss / ((double)g->n * (double)(g->n - 1)));
             g->c0_auto = 0.5 / (sigma * std::sqrt((double)g->n));
@@ -1376,7 +1397,9 @@ void flip_crossing(qh_graph *g, const int8_t *spins, hipStream_t st) {
         hipLaunchKernelGGL(k_flip_band, dim3((unsigned)std::min<int64_t>(g->n_bblk, 1 << 20)), dim3(256), 0, st,
                            g->n, g->n_bblk, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p, g->bb_dtype, spins);
     QH_CHECK_LAUNCH();
-    // solve plans hold no copy of J; nothing else to refresh
+    // the flipped edges change W = -1/2 sum J (by twice their old weight); c0 depends on J^2
+    // only and the greedy tolerance on |J|, so they stay.  Solve plans hold no copy of J.
+    refresh_total_weight(g, st);
 }
 
 }  // namespace qh

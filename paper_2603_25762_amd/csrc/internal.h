@@ -135,6 +135,10 @@ struct SolvePlan {
     DevBuf<double> part1;           // [n_chunks] partials for one vector
     DevBuf<double> cut1;            // [n_comp]
     DevBuf<float> hub_part;         // [n_hub_chunks][R] long-range partial sums of hub rows
+    // readout every eval_every steps: best (evaluation, replica) so far per component
+    DevBuf<double> ev_cut;          // [n_comp] its cut
+    DevBuf<int32_t> ev_r;           // [n_comp] its replica
+    DevBuf<int8_t> ev_take;         // [n_comp] 1 when the current evaluation replaced it
     // captured step loop
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -166,6 +170,7 @@ struct qh_graph {
     // Components (labels in order of lowest vertex, -1 = singleton).
     qh::DevBuf<int32_t> comp;        // [n]
     int64_t n_comp = 0;
+    int64_t largest_comp = 0;        // vertices of the largest component
     qh::DevBuf<int32_t> comp_first;  // [n_comp] lowest vertex
     qh::DevBuf<int32_t> comp_order;  // vertices of non-singleton components sorted by (comp, vertex)
     int64_t n_ord = 0;               // length of comp_order
@@ -261,9 +266,19 @@ struct ReadoutView {
     const double *eps_v = nullptr;     // per-vertex tolerance (overrides eps when set)
 };
 ReadoutView view_of(const qh_graph *g);
-// finish = false leaves the non-finite check to the caller (p.counter[1] != 0 after a sync)
+// One evaluation of a solve read out every eval_every steps: its index, whether it is the
+// last, and the energy row it fills (nullptr: none); W = -1/2 sum J.
+struct EvalArgs {
+    int index = 0;
+    bool last = true;
+    double W = 0.0;
+    double *energy_row = nullptr;
+};
+// finish = false leaves the non-finite check to the caller (p.counter[1] != 0 after a sync).
+// ev != nullptr: one evaluation of a solve read out every eval_every steps; only the last one
+// runs the greedy pass and the final cut (and the check, with finish).
 void readout(const ReadoutView &g, SolvePlan &p, int R, const float *xfin, const float *yfin, qh_result *res,
-             bool greedy, hipStream_t st, bool finish = true);
+             bool greedy, hipStream_t st, bool finish = true, const EvalArgs *ev = nullptr);
 void alloc_readout_scratch(SolvePlan &p, int64_t n, int64_t n_comp, int64_t n_chunks, int R);
 
 // One block of a batched readout: its graph view, final state, plan scratch and result slots.

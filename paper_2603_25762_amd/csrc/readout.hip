@@ -246,6 +246,41 @@ __global__ void k_pick(int64_t n, const int64_t *ptr, const int32_t *col, const 
     pick_body(QH_G, n, ptr, col, g, eps_all, eps_v, flag, count);
 }
 __global__ void k_apply_flips(int64_t n, const int8_t *flag, int8_t *s) { apply_flips_body(QH_G, n, flag, s); }
+
+// Readout every eval_every steps: component c's pick of this evaluation (replica best_r[c])
+// replaces the best so far when its cut is larger (the first evaluation always replaces).
+__global__ void k_eval_merge(int64_t n_comp, const double *__restrict__ cut_rc, const int32_t *__restrict__ best_r,
+                             int first, double *__restrict__ best_cut, int32_t *__restrict__ best_rr,
+                             int8_t *__restrict__ take) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n_comp; c += gridDim.x * (int64_t)blockDim.x) {
+        const double v = cut_rc[(int64_t)best_r[c] * n_comp + c];
+        const bool t = first || v > best_cut[c];
+        if (t) {
+            best_cut[c] = v;
+            best_rr[c] = best_r[c];
+        }
+        take[c] = t ? 1 : 0;
+    }
+}
+
+// Spins of the components whose pick was replaced, oriented so that the component's lowest
+// vertex reads +1; single-vertex components read +1.
+__global__ void k_eval_take(int64_t n, int R, const int32_t *__restrict__ comp, const int32_t *__restrict__ comp_first,
+                            const int32_t *__restrict__ best_r, const int8_t *__restrict__ take,
+                            const int8_t *__restrict__ s, int8_t *__restrict__ best) {
+    for (int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; a < n; a += gridDim.x * (int64_t)blockDim.x) {
+        const int c = comp[a];
+        if (c < 0) { best[a] = 1; continue; }
+        if (!take[c]) continue;
+        const int rb = best_r[c];
+        best[a] = (int8_t)(s[a * R + rb] * s[(int64_t)comp_first[c] * R + rb]);
+    }
+}
+
+// Eq. (5): E_r = W - 2 cut_r for every replica
+__global__ void k_energy_row(int R, double W, const double *__restrict__ cuts, double *__restrict__ e) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < R; r += gridDim.x * blockDim.x) e[r] = W - 2.0 * cuts[r];
+}
 #undef QH_G
 
 void alloc_readout_scratch(SolvePlan &p, int64_t n, int64_t n_comp, int64_t n_chunks, int R) {
@@ -281,12 +316,12 @@ ReadoutView view_of(const qh_graph *g) {
 }
 
 void readout(const ReadoutView &g, SolvePlan &p, int R, const float *xfin, const float *yfin, qh_result *res,
-             bool greedy, hipStream_t st, bool finish) {
+             bool greedy, hipStream_t st, bool finish, const EvalArgs *ev) {
     const int64_t n = g.n;
     const int64_t nR = n * R;
 
-    // signs + non-finite watchdog
-    QH_HIP(hipMemsetAsync(p.counter.p, 0, 4 * sizeof(int32_t), st));
+    // signs + non-finite watchdog (kept over the evaluations of one solve)
+    if (!ev || ev->index == 0) QH_HIP(hipMemsetAsync(p.counter.p, 0, 4 * sizeof(int32_t), st));
     if (nR) {
         hipLaunchKernelGGL(k_signs, dim3(grid_for(nR)), dim3(256), 0, st, n, R, xfin, yfin, p.spins.p,
                            p.counter.p + 1);
@@ -305,21 +340,55 @@ void readout(const ReadoutView &g, SolvePlan &p, int R, const float *xfin, const
                            g.comp_chunk_ptr, p.part.p, p.cut_rc.p);
         hipLaunchKernelGGL(k_select, dim3(grid_for(nc)), dim3(256), 0, st, nc, R, p.cut_rc.p, p.best_r.p);
         hipLaunchKernelGGL(k_replica_totals, dim3(grid_for(R)), dim3(256), 0, st, nc, R, p.cut_rc.p, res->cuts);
-        hipLaunchKernelGGL(k_selected_total, dim3(1), dim3(256), 0, st, nc, p.cut_rc.p, p.best_r.p,
-                           res->selected_cut ? res->selected_cut : res->best_cut);
+        if (!ev)
+            hipLaunchKernelGGL(k_selected_total, dim3(1), dim3(256), 0, st, nc, p.cut_rc.p, p.best_r.p,
+                               res->selected_cut ? res->selected_cut : res->best_cut);
         QH_CHECK_LAUNCH();
     } else {
         QH_HIP(hipMemsetAsync(res->cuts, 0, R * sizeof(double), st));
         QH_HIP(hipMemsetAsync(res->selected_cut ? res->selected_cut : res->best_cut, 0, sizeof(double), st));
     }
-    if (res->cut_rc && nc)
-        QH_HIP(hipMemcpyAsync(res->cut_rc, p.cut_rc.p, nc * R * sizeof(double), hipMemcpyDeviceToDevice, st));
-    if (res->best_replica && nc)
-        QH_HIP(hipMemcpyAsync(res->best_replica, p.best_r.p, nc * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-    if (n) {
-        hipLaunchKernelGGL(k_best_spins, dim3(grid_for(n)), dim3(256), 0, st, n, R, g.comp, g.comp_first,
-                           p.best_r.p, p.spins.p, res->best_spins);
+    if (ev && ev->energy_row) {
+        hipLaunchKernelGGL(k_energy_row, dim3(grid_for(R)), dim3(256), 0, st, R, ev->W, res->cuts, ev->energy_row);
         QH_CHECK_LAUNCH();
+    }
+    if (res->cut_rc && nc && (!ev || ev->last))
+        QH_HIP(hipMemcpyAsync(res->cut_rc, p.cut_rc.p, nc * R * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (ev) {
+        // best (evaluation, replica) so far per component, its spins into best_spins
+        if (ev->index == 0 && p.ev_cut.n < (size_t)std::max<int64_t>(nc, 1)) {
+            p.ev_cut.alloc(std::max<int64_t>(nc, 1));
+            p.ev_r.alloc(std::max<int64_t>(nc, 1));
+            p.ev_take.alloc(std::max<int64_t>(nc, 1));
+        }
+        if (nc) {
+            hipLaunchKernelGGL(k_eval_merge, dim3(grid_for(nc)), dim3(256), 0, st, nc, p.cut_rc.p, p.best_r.p,
+                               ev->index == 0 ? 1 : 0, p.ev_cut.p, p.ev_r.p, p.ev_take.p);
+            QH_CHECK_LAUNCH();
+        }
+        if (n) {
+            hipLaunchKernelGGL(k_eval_take, dim3(grid_for(n)), dim3(256), 0, st, n, R, g.comp, g.comp_first,
+                               p.best_r.p, p.ev_take.p, p.spins.p, res->best_spins);
+            QH_CHECK_LAUNCH();
+        }
+        if (!ev->last) return;
+        if (nc) {
+            hipLaunchKernelGGL(k_selected_total, dim3(1), dim3(256), 0, st, nc, p.ev_cut.p, (const int32_t *)nullptr,
+                               res->selected_cut ? res->selected_cut : res->best_cut);
+            QH_CHECK_LAUNCH();
+            if (res->best_replica)
+                QH_HIP(hipMemcpyAsync(res->best_replica, p.ev_r.p, nc * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                      st));
+        }
+    } else {
+        if (res->best_replica && nc)
+            QH_HIP(hipMemcpyAsync(res->best_replica, p.best_r.p, nc * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                  st));
+        if (n) {
+            hipLaunchKernelGGL(k_best_spins, dim3(grid_for(n)), dim3(256), 0, st, n, R, g.comp, g.comp_first,
+                               p.best_r.p, p.spins.p, res->best_spins);
+            QH_CHECK_LAUNCH();
+        }
     }
     int32_t rounds = 0;
     if (greedy && n && nc) {

@@ -8,5 +8,5 @@ take its output as their input.
 """
 from .workloads import (  # noqa: F401
     Workload, Batch, read_tiny, read_mhc, snp_chrom, snp_porec, batched_blocks,
-    snp_small, read_small, by_name, CONFIGS,
+    snp_small, read_small, by_name, CONFIGS, CHROM_GAP_BP, workload_hash, batch_hash, stratified_subset,
 )

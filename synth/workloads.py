@@ -198,6 +198,11 @@ def read_mhc(seed: int = 2000, n_snp: int = 12000, n_reads: int = 8000,
 # SNP-based workloads (vertices = SNPs)
 # ----------------------------------------------------------------------------
 
+# Mean SNP spacing of the chromosome-scale model: 1,430 bp gives 40 linked SNPs per SNP on
+# average (10.0 M couplings over 250,000 SNPs) with 30x of 20 kb reads at linkage depth 10/10.
+CHROM_GAP_BP = 1430.0
+
+
 def snp_small(seed: int, n_snp: int = 2000, coverage: float = 30.0, read_mean: float = 20000.0,
               sigma_log: float = 0.3, gap_mean: float = 1000.0, error: float = 0.06,
               q=(7, 40), name: str = "snp_small") -> Workload:
@@ -219,8 +224,9 @@ def snp_small(seed: int, n_snp: int = 2000, coverage: float = 30.0, read_mean: f
 
 
 def snp_chrom(seed: int = 3000, n_snp: int = 250_000, error: float = 0.06) -> Workload:
-    """250,000 SNPs, ~1 kb gaps, 30x of lognormal 20 kb reads, Phred 7-40."""
-    w = snp_small(seed, n_snp=n_snp, error=error, name="snp_chrom")
+    """250,000 SNPs, 1.43 kb mean gaps (40 couplings per SNP), 30x of lognormal 20 kb reads,
+    Phred 7-40."""
+    w = snp_small(seed, n_snp=n_snp, gap_mean=CHROM_GAP_BP, error=error, name="snp_chrom")
     return w
 
 
@@ -287,7 +293,7 @@ def _add_porec(rng, w: Workload, n_edges: int, zipf_s: float, d_range, alpha_ran
 def snp_porec(seed: int = 4000, n_snp: int = 250_000, n_edges: int = 600_000,
               error: float = 0.06, zipf_s: float = 0.6) -> Workload:
     """Chromosome workload plus pairwise Pore-C contacts (100 kb - 100 Mb)."""
-    base = snp_small(seed, n_snp=n_snp, error=error, name="snp_porec")
+    base = snp_small(seed, n_snp=n_snp, gap_mean=CHROM_GAP_BP, error=error, name="snp_porec")
     rng = np.random.default_rng(seed + 7)
     w = _add_porec(rng, base, n_edges, zipf_s, (1e5, 1e8), (0.1, 0.5), error, (7, 40))
     w.solve.update(dict(storage="skyline_long", dtype="bf16", replicas=64, steps=4000))
@@ -318,11 +324,44 @@ def batched_blocks(seed: int = 5000, n_blocks: int = 3000, n_lo: int = 50, n_hi:
                              name=f"block{b}_read")
             blk.solve.update(dict(dtype="fp8", replicas=32, steps=500))
         else:
-            blk = snp_small(bseed, n_snp=nb, error=error_snp, name=f"block{b}_snp")
+            blk = snp_small(bseed, n_snp=nb, gap_mean=CHROM_GAP_BP, error=error_snp, name=f"block{b}_snp")
             blk.solve.update(dict(dtype="bf16", replicas=32, steps=500))
         blocks.append(blk)
     return Batch(name="batched", blocks=blocks,
                  solve=dict(replicas=32, steps=500, dt=0.5))
+
+
+def workload_hash(w: Workload) -> str:
+    """SHA-256 of a workload's input arrays (fragments, qualities, factors, initial and
+    planted haplotypes): stored next to reference results so that a change of the generator
+    is noticed."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (w.frag_ptr, w.snp, w.allele, w.phred, w.alpha, w.init_h1, w.truth):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def batch_hash(batch: Batch) -> str:
+    """SHA-256 over the workload hashes of a batch's blocks, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for w in batch.blocks:
+        h.update(workload_hash(w).encode())
+    return h.hexdigest()
+
+
+def stratified_subset(batch: Batch, stride: int = 20) -> List[int]:
+    """Block indices of a stratified sample of a batched workload: within each block kind
+    (even blocks dense read graphs, odd blocks SNP graphs) the blocks are ranked by vertex
+    count (reads for read blocks, SNPs for SNP blocks) and every stride-th is taken from rank
+    stride // 2 on, so the sample spans the whole size range of both kinds."""
+    out: List[int] = []
+    for parity in (0, 1):
+        idx = [b for b in range(len(batch.blocks)) if b % 2 == parity]
+        idx.sort(key=lambda b: (batch.blocks[b].n_frag if parity == 0 else batch.blocks[b].n_snp, b))
+        out += idx[stride // 2::stride]
+    return sorted(out)
 
 
 CONFIGS = {

@@ -34,12 +34,14 @@ def test_version_string():
 
 
 def test_adaptive_schedule_follows_the_paper():
-    """SNP-based settings adapted to graph size (Tables 1 and 2, footnotes): 500 iterations
-    below 5,000 vertices, 1,000 from there on, 100 samples (run as 128 replicas, the
-    replica counts being 16, 32 or multiples of 64) and at most 15 refinement rounds."""
+    """SNP-based settings adapted to graph size (Tables 1 and 2, footnotes), from the C entry
+    point (host only): 500 iterations below 5,000 vertices, 1,000 from there on, 100 samples
+    (run as 128 replicas, the replica counts being 16, 32 or multiples of 64) and at most 15
+    refinement rounds."""
     for n, steps in ((0, 500), (1, 500), (4999, 500), (5000, 1000), (120_000, 1000)):
         a = qh.adaptive_schedule(n)
         assert a["steps"] == steps and a["samples"] == 100 and a["max_rounds"] == 15
-        assert a["replicas"] >= a["samples"] and a["replicas"] % 64 == 0
-    with pytest.raises(ValueError):
+        assert a["replicas"] >= a["samples"] and a["replicas"] % 64 == 0 and a["size"] == n
+    with pytest.raises(qh.QhapError) as e:
         qh.adaptive_schedule(-1)
+    assert e.value.status == qh.Status.EINVAL

@@ -851,6 +851,28 @@ def test_batched_matches_single_solves(R, plan):
         assert _gap(ro["best_cut"], float(cpu(rs["best_cut"])[0])) <= 1e-3, b
 
 
+def test_batched_graph_replay_equals_per_step_plan():
+    """use_graph = 1: the per-step plan's launches captured once and replayed.  Every replay
+    (with eager solves and syncs in between, and a recapture for another seed) gives the
+    per-step plan's results bit for bit; the whole-block plan refuses it."""
+    blocks = [synth.read_small(50 + b, n_snp=200, n_reads=40 + 30 * b) for b in range(3)] + \
+             [synth.snp_small(60 + b, n_snp=150 + 200 * b) for b in range(2)]
+    kinds = ["read_signed"] * 3 + ["snp_llr"] * 2
+    dtypes = ["fp8", "f16", "f32", "bf16", "f16"]
+    gs = [gpu_graph(w, k, d) for w, k, d in zip(blocks, kinds, dtypes)]
+    for seed in (9, 9, 10, 9):
+        ref = qh.bsb_solve_batched(gs, 32, 200, seed=seed, plan=1, return_state=True)
+        torch.cuda.synchronize()
+        rg = qh.bsb_solve_batched(gs, 32, 200, seed=seed, use_graph=True, return_state=True)
+        assert rg["plan_used"] == 1
+        for k in ("x", "y", "cuts", "best_spins", "best_cut", "selected_cut"):
+            assert torch.equal(rg[k], ref[k]), (seed, k)
+        qh.bsb_solve(gs[0], 32, 50, seed=1)      # eager work between replays
+    with pytest.raises(qh.QhapError) as e:
+        qh.bsb_solve_batched(gs, 32, 20, plan=2, use_graph=True)
+    assert e.value.status == qh.Status.EUNSUPPORTED
+
+
 def test_batched_errors_and_empty_batch():
     w = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
     g_lr = gpu_graph(w, "snp_llr", "f32", band_limit=100)
@@ -964,8 +986,8 @@ def test_best_energy_matches_eq5(kind, dtype):
 
 
 def test_energy_trace_resumes_one_schedule():
-    """energy_trace runs one schedule in step ranges: its last row is the energy (Eq. 5) of
-    every replica after a straight solve of the same schedule, bit for bit, and its first
+    """energy_trace is one solve read out every 100 steps: its last row is the energy (Eq. 5)
+    of every replica after a straight solve of the same schedule, bit for bit, and its first
     rows match the oracle's energies of the same steps' signs."""
     w = synth.read_tiny()
     g = gpu_graph(w, "read_signed", "f32")
@@ -982,6 +1004,97 @@ def test_energy_trace_resumes_one_schedule():
     e = -0.5 * np.einsum("ir,ij,jr->r", s, J, s)
     assert np.allclose(tr["energy"][0], e, rtol=0, atol=1e-9)
     assert tr["best"][-1] <= tr["best"][0]
+
+
+EVAL_CASES = {
+    # (workload, kind, dtype, R, steps, m, plan)
+    "read_f32": (lambda: synth.read_tiny(), "read_signed", "f32", 16, 300, 70, 1),
+    "read_f16_persistent": (lambda: synth.read_mhc(seed=78, n_snp=1500, n_reads=1000, region=500_000),
+                            "read_signed", "f16", 64, 200, 45, 2),
+    "read_fp8_step": (lambda: synth.read_small(16, n_snp=300, n_reads=140), "read_signed", "fp8", 32, 150, 40, 1),
+    "snp_f16_band": (lambda: synth.snp_small(19, n_snp=1200), "snp_llr", "f16", 64, 200, 60, 4),
+    "porec_bf16": (lambda: synth.snp_porec(45, n_snp=2000, n_edges=2500, zipf_s=1.0), "snp_llr", "bf16", 64, 120,
+                   50, 0),
+}
+
+
+@pytest.mark.parametrize("case", list(EVAL_CASES))
+def test_eval_every_matches_the_readout_definition(case):
+    """Readouts every m steps (eval_every): the trajectory is the straight solve's (final
+    state bit-identical); the energy row of readout e is -1/2 s'Js (Eq. 5, oracle's FP64
+    dense J) of the signs after that readout's step, which a straight solve ending there
+    returns; best_spins (no greedy) and selected_cut are the oracle's best-so-far merge of
+    those readouts' signs (merge_best), exactly."""
+    make, kind, dtype, R, steps, m, plan = EVAL_CASES[case]
+    w = make()
+    g = gpu_graph(w, kind, dtype, band_limit=64 if case.startswith("porec") else 0)
+    n = g.info()["n"]
+    go = oracle_graph(w, kind)
+    J = go.dense()
+    comp, nc = oracle.components(go)
+    xe = torch.empty((n, R), dtype=torch.float32, device="cuda")
+    r = qh.bsb_solve(g, R, steps, seed=9, greedy=False, plan=plan, eval_every=m, energy=True, x=xe,
+                     per_component=True)
+    marks = list(range(m, steps, m)) + [steps]
+    E = cpu(r["energy"])
+    assert E.shape == (len(marks), R)
+    sets = []
+    for e, k1 in enumerate(marks):
+        xs = torch.empty((n, R), dtype=torch.float32, device="cuda")
+        rs = qh.bsb_solve(g, R, steps, seed=9, greedy=False, plan=plan, step_end=k1, all_spins=True, x=xs)
+        sp = cpu(rs["all_spins"])
+        sets.append(sp)
+        sd = sp.astype(np.float64)
+        ref = -0.5 * np.einsum("ir,ij,jr->r", sd, J, sd)
+        scale = max(1.0, float(np.abs(J).sum()))
+        assert np.allclose(E[e], ref, rtol=0, atol=1e-12 * scale), e
+        if k1 == steps:
+            assert torch.equal(xs, xe)          # readouts do not disturb the trajectory
+    best, best_c, best_r = oracle.merge_best(go, comp, nc, sets)
+    assert np.array_equal(cpu(r["best_spins"]), best)
+    assert np.array_equal(cpu(r["best_replica"]), best_r)
+    assert float(cpu(r["selected_cut"])[0]) == pytest.approx(float(best_c.sum()), rel=1e-12, abs=1e-9)
+    W = g.info()["total_weight"]
+    assert np.array_equal(E[-1], W - 2.0 * cpu(r["cuts"]))
+
+
+def test_eval_every_rejects_bad_combinations():
+    g = gpu_graph(synth.read_tiny(), "read_signed", "f32")
+    for kw in (dict(eval_every=-1), dict(eval_every=10, use_graph=True), dict(eval_every=10, readout=False)):
+        with pytest.raises(qh.QhapError) as e:
+            qh.bsb_solve(g, 16, 50, **kw)
+        assert e.value.status == qh.Status.EINVAL, kw
+
+
+def test_eval_every_whole_solve_tracks_the_oracle():
+    """A whole solve with readouts every 100 steps against the oracle's at the same schedule
+    (FP32 read graph): best cut within 0.1 %, and never below the plain solve's selected cut."""
+    w = synth.read_small(13, n_snp=300, n_reads=150, span=(20, 60))
+    g = gpu_graph(w, "read_signed", "f32")
+    go = oracle_graph(w)
+    r = qh.bsb_solve(g, 32, 500, seed=4, eval_every=100)
+    ro = oracle.solve(go, 32, 500, 0.5, seed=4, integer=True, eval_every=100)
+    cut = float(cpu(r["best_cut"])[0])
+    assert (ro["best_cut"] - cut) / abs(ro["best_cut"]) <= 1e-3
+    rp = qh.bsb_solve(g, 32, 500, seed=4)
+    assert float(cpu(r["selected_cut"])[0]) >= float(cpu(rp["selected_cut"])[0])
+
+
+def test_flip_crossing_refreshes_total_weight():
+    """Eq. (15) flips the sign of every crossing edge: total_weight (-1/2 sum J) follows, and
+    best_energy of a solve on the flipped graph is -1/2 s'Js with the flipped J (the
+    oracle's flip_crossing)."""
+    w = synth.snp_small(22, n_snp=1000)
+    g = gpu_graph(w, "snp_llr", "f32")
+    go = oracle_graph(w, "snp_llr")
+    rng = np.random.default_rng(3)
+    s = np.where(rng.random(go.n) < 0.5, 1, -1).astype(np.int8)
+    qh.flip_crossing(g, qh.to_device(s))
+    Jf = oracle.flip_crossing(go, s).dense()
+    assert g.info()["total_weight"] == pytest.approx(-0.5 * Jf.sum(), rel=1e-12, abs=1e-9)
+    r = qh.bsb_solve(g, 64, 200, seed=6)
+    b = cpu(r["best_spins"]).astype(np.float64)
+    assert float(cpu(r["best_energy"])[0]) == pytest.approx(-0.5 * b @ Jf @ b, rel=1e-10, abs=1e-8)
 
 
 def test_deterministic_snp_build():

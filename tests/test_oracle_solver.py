@@ -413,3 +413,57 @@ def test_deformed_refinement_properties():
     k0 = 2 * n * R + n
     u = np.array([(oracle.splitmix64(77, k0 + i) >> 11) * 2.0 ** -53 for i in range(n)])
     assert np.array_equal(h, 3.0 * (2.0 * u - 1.0)) and np.all(np.abs(h) <= 3.0)
+
+
+def test_eval_every_readouts():
+    """Readouts every m steps (the best of many samples over one run).  Pins: the energy of
+    every readout is -1/2 s'Js of that readout's signs, which equals W - 2 cut (Eq. 5,
+    W = -1/2 sum J) for every replica; one readout after the last step (m = 0, or m at least
+    the step count) is the plain solve; more readouts never lower the selected cut of any
+    component (the last readout is among them); the merge keeps, per component, the largest
+    cut over all readouts, which brute enumeration over (readout, replica) confirms."""
+    w = synth.read_tiny()
+    g = oracle.build_graph(w, "read_signed")
+    comp, nc = oracle.components(g)
+    W = -0.5 * float(g.val.sum())
+    plain = oracle.solve(g, 16, 300, 0.5, seed=5, integer=True, greedy_pass=False)
+    same = oracle.solve(g, 16, 300, 0.5, seed=5, integer=True, greedy_pass=False, eval_every=300)
+    assert np.array_equal(plain["best"], same["best"]) and plain["selected_cut"] == same["selected_cut"]
+    assert plain["energy"].shape == (1, 16) and same["eval_steps"] == [300]
+    ev = oracle.solve(g, 16, 300, 0.5, seed=5, integer=True, greedy_pass=False, eval_every=70)
+    assert ev["eval_steps"] == [70, 140, 210, 280, 300] and ev["energy"].shape == (5, 16)
+    assert np.array_equal(ev["x"], plain["x"])                     # readouts leave the run alone
+    # energies against W - 2 cut, readout by readout
+    x, y = oracle.init_state(5, g.n, 16)
+    pump = oracle.pump_linear(300)
+    k = 0
+    best_by_comp = np.full(nc, -np.inf)
+    for e, k1 in enumerate(ev["eval_steps"]):
+        oracle.bsb_run(g, x, y, pump, 0.5, oracle.c0(g), 1.0, k, k1)
+        k = k1
+        s = oracle.signs(x)
+        cut = oracle.cuts(g, comp, nc, s)
+        assert np.allclose(ev["energy"][e], W - 2.0 * cut.sum(axis=1), rtol=0, atol=1e-9)
+        best_by_comp = np.maximum(best_by_comp, cut.max(axis=0))
+    assert ev["selected_cut"] == pytest.approx(float(best_by_comp.sum()), abs=1e-9)
+    assert ev["selected_cut"] >= plain["selected_cut"]
+    got = oracle.cuts(g, comp, nc, ev["best"])[0]
+    assert np.allclose(got, best_by_comp, atol=1e-9)
+    # orientation: the lowest vertex of every component reads +1
+    for c in range(nc):
+        assert ev["best"][np.nonzero(comp == c)[0][0]] == 1
+
+
+def test_merge_best_ties_go_to_the_earlier_readout():
+    """Two readouts with equal cuts: the first one's spins are kept (hand case on a
+    two-component graph)."""
+    D = np.zeros((4, 4))
+    D[0, 1] = D[1, 0] = -1.0          # J = -1: the cut of edge (0, 1) is 1 when split
+    D[2, 3] = D[3, 2] = -2.0
+    g = csr_from_dense(D)
+    comp, nc = oracle.components(g)
+    s1 = np.array([[1], [-1], [1], [1]], dtype=np.int8)     # comp 0 cut 1, comp 1 cut 0
+    s2 = np.array([[-1], [1], [1], [-1]], dtype=np.int8)    # comp 0 cut 1 (mirror), comp 1 cut 2
+    best, bc, br = oracle.merge_best(g, comp, nc, [s1, s2])
+    assert list(bc) == [1.0, 2.0]
+    assert list(best) == [1, -1, 1, -1]
