@@ -358,6 +358,19 @@ qh_status qh_bsb_solve_batched(const qh_graph *const *graphs, int32_t n_graphs,
 qh_status qh_phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block,
                    void *stream);
 
+/* qh_phase for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same outputs as qh_phase, bit
+ * for bit, with the per-component counters of the SNP parity round held in a static device
+ * array of the library (4 MiB per device, kept until the process ends) instead of memory
+ * allocated per call.  It allocates nothing, does not synchronise the stream, and clears the
+ * counters with a kernel (no memset node when captured).  Limit: SNP graphs of at most 2^19
+ * connected components (EINVAL beyond; read graphs have no limit, their vote needs no
+ * scratch).  Every call on one device shares that array: calls that overlap on one device
+ * (two streams, or two threads) race and may return wrong haplotypes; serialise them.
+ * Errors: EINVAL (null argument, too many components, graph on another device), EHIP. */
+qh_status qh_phase_noalloc(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block,
+                           void *stream);
+
 /* Eq. 15: J_uv <- -J_uv for every edge whose endpoints disagree in `spins` (device
  * int8 [n]); updates the master and the stored copy in place and recomputes
  * qh_graph_info.total_weight (c0_auto depends on J^2 only and does not change).

@@ -125,6 +125,7 @@ def load():
         "qh_bsb_solve_batched": [P, ctypes.c_int32, ctypes.POINTER(_BsbOpts),
                                  ctypes.POINTER(_BatchedResult), P],
         "qh_phase": [P, P, P, P, P],
+        "qh_phase_noalloc": [P, P, P, P, P],
         "qh_flip_crossing": [P, P, P],
         "qh_refine": [P, ctypes.POINTER(_BsbOpts), ctypes.c_int32, ctypes.c_float, ctypes.c_int32, P, P, P,
                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
@@ -429,16 +430,24 @@ def bsb_solve_batched(graphs: Sequence[Graph], replicas: int, steps: int, *, dt:
     return res
 
 
-def phase(g: Graph, spins: torch.Tensor, n_snp: Optional[int] = None, stream=None):
-    """Haplotype 1 allele per SNP (-1 = unphased) and the phase-block label per SNP."""
+def phase(g: Graph, spins: torch.Tensor, n_snp: Optional[int] = None, stream=None, noalloc: bool = False,
+          out=None):
+    """Haplotype 1 allele per SNP (-1 = unphased) and the phase-block label per SNP.
+
+    ``noalloc`` calls qh_phase_noalloc (no device allocation inside the library); ``out``
+    may supply the (h1, block) tensors."""
     if spins.dtype != torch.int8:
         raise TypeError("spins must be int8")
     inf = g.info()
     if n_snp is None:
         n_snp = inf["n_snp"]
-    h1 = torch.empty(max(n_snp, 1), dtype=torch.int8, device="cuda")
-    block = torch.empty(max(n_snp, 1), dtype=torch.int32, device="cuda")
-    _check(load().qh_phase(g.handle, _ptr(spins), _ptr(h1), _ptr(block), _stream(stream)))
+    if out is None:
+        h1 = torch.empty(max(n_snp, 1), dtype=torch.int8, device="cuda")
+        block = torch.empty(max(n_snp, 1), dtype=torch.int32, device="cuda")
+    else:
+        h1, block = out
+    fn = load().qh_phase_noalloc if noalloc else load().qh_phase
+    _check(fn(g.handle, _ptr(spins), _ptr(h1), _ptr(block), _stream(stream)))
     return h1[:n_snp], block[:n_snp]
 
 

@@ -271,6 +271,13 @@ qh_status qh_phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *
     });
 }
 
+qh_status qh_phase_noalloc(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, void *stream) {
+    return guarded([&] {
+        if (!g || !spins || !h1 || !block) fail(QH_EINVAL, "null argument");
+        phase_noalloc(g, spins, h1, block, (hipStream_t)stream);
+    });
+}
+
 qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream) {
     return guarded([&] {
         if (!g || !spins) fail(QH_EINVAL, "null argument");

@@ -304,6 +304,7 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out);
 
 // phase.hip
 void phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);
+void phase_noalloc(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);
 void refine(qh_graph *g, const qh_bsb_opts *o, int max_rounds, float deform, int deform_tries, int8_t *h1,
             int32_t *block, int32_t *flips, double *round_cuts, int32_t *rounds_out, int32_t *deformed_out,
             hipStream_t st);

@@ -6,10 +6,18 @@
 //  majorities and one-sided majorities are special cases of the same rule.
 //  SNP graphs: one parity round, Eqs. (16)-(17).
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 
 namespace qh {
+
+// Counters of qh_phase_noalloc: the s = +1 and s = -1 vertex counts of up to
+// kNoAllocMaxComp components, in device memory that the library never allocates at run
+// time.  Each device holds its own copy for the life of the process; host code reaches it
+// only through the address hipGetSymbolAddress returns on that device.
+constexpr int64_t kNoAllocMaxComp = (int64_t)1 << 19;
+static __device__ __align__(256) int32_t scratch[2 * kNoAllocMaxComp];
 
 __global__ void k_phase_vote(int32_t n_snp, const int64_t *__restrict__ cov_ptr, const int32_t *__restrict__ cov_frag,
                              const int8_t *__restrict__ cov_M, const int32_t *__restrict__ comp,
@@ -63,6 +71,50 @@ __global__ void k_phase_parity(int64_t n, const int32_t *__restrict__ comp, cons
 static int grid_for(int64_t n) {
     int64_t g = ceil_div(n, 256);
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+__global__ void k_zero_counts(int64_t n, int32_t *__restrict__ p) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// Device address of `scratch` on device `dev`, looked up once per device with that device
+// current (the symbol's host-side name is not a device address).
+static int32_t *scratch_on(int dev) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static int32_t *addr[kMaxDevices] = {nullptr};
+    if (dev < 0 || dev >= kMaxDevices) fail(QH_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        QH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        addr[dev] = (int32_t *)p;
+    }
+    return addr[dev];
+}
+
+void phase_noalloc(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st) {
+    if (g->kind != QH_SNP_LLR) {   // the vote uses no scratch memory
+        phase(g, spins, h1, block, st);
+        return;
+    }
+    if (g->n_comp > kNoAllocMaxComp)
+        fail(QH_EINVAL, "qh_phase_noalloc holds counters for at most %lld components, the graph has %lld",
+             (long long)kNoAllocMaxComp, (long long)g->n_comp);
+    int dev = 0;
+    QH_HIP(hipGetDevice(&dev));
+    if (dev != g->device) fail(QH_EINVAL, "graph lives on device %d, current device is %d", g->device, dev);
+    int32_t *cnt = scratch_on(dev);
+    if (!g->n) return;
+    const int64_t nc = std::max<int64_t>(g->n_comp, 1);
+    // the counters keep the previous call's values: clear them (a kernel, so that a captured
+    // stream records no memset node)
+    hipLaunchKernelGGL(k_zero_counts, dim3(grid_for(2 * nc)), dim3(256), 0, st, 2 * nc, cnt);
+    hipLaunchKernelGGL(k_comp_sizes, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, g->comp.p, spins, cnt, cnt + nc);
+    hipLaunchKernelGGL(k_phase_parity, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, g->comp.p, spins, cnt, cnt + nc,
+                       g->init_h1.p, h1, block);
+    QH_CHECK_LAUNCH();
 }
 
 void phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st) {
