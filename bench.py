@@ -1,18 +1,26 @@
-"""Benchmark: bSB edge-updates/s of the whole phasing job on one MI355X.
+"""Benchmark: bSB edge-updates/s of the phasing hot path on one MI355X.
 
-One benchmark step = one pass of the whole hot path over one synthetic batch:
-build_graph (encode + read-graph weights + components + tiles + quantize) ->
-bsb_solve (init, 2,000 fused bSB steps over 256 replicas, FP64 cuts, per-component
-selection, greedy pass) -> phase.  Inputs (fragments) are resident in HBM before
-the timed region starts.
+Default workload (the line of record): ``batched`` -- 3,000 independent phasing blocks with
+log-uniform sizes of 50-5,000 vertices, even blocks dense read graphs stored as FP8 with
+per-row scales, odd blocks SNP graphs stored as BF16 (skyline band), R = 32 replicas, 500
+bSB steps (the paper's count for graphs below 5,000 nodes), dt = 0.5, linear pump, c0 auto
+per block.  One benchmark step = one batched solve of all blocks: seeded initial state,
+500 fused bSB steps of every block (the per-step plan replayed from a captured hipGraph),
+FP64 cuts of every replica and component, per-component selection and the greedy pass.
+The graphs are built before the timed region (the metric counts solver work; graph
+construction and time-to-phase are reported beside it).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f16] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched|read_mhc|snp_chrom|snp_porec]
+                    [--no-cpu-baseline] [--no-extras]
 
-Prints one JSON line.
+Prints one JSON line.  ``--workload read_mhc | snp_chrom | snp_porec`` measure the other
+configurations (the MHC-scale dense read graph, the chromosome SNP graph, the SNP graph with
+Pore-C contacts) with the same fields.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,7 +31,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "bSB edge-updates/s (nnz×replicas×steps) at ≤0.1% cut gap vs FP64 oracle"
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 2500.0, "f32": 157.3}  # fp8 codes run on f16 MFMA
+# dense MFMA peaks (TFLOP/s); FP8 tiles are expanded to binary16 and multiplied on the f16 MFMA
+PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 2500.0, "f32": 157.3}
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+COPY_BYTES = 1 << 30
 
 
 def parse():
@@ -31,26 +42,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="read_mhc", choices=["read_mhc", "snp_chrom", "snp_porec", "batched"],
-                    help="read_mhc (default) is the benchmark line; the others profile the SNP and batched paths")
+    ap.add_argument("--workload", default="batched", choices=["batched", "read_mhc", "snp_chrom", "snp_porec"])
     ap.add_argument("--dtype", default=None, choices=["f32", "f16", "bf16", "fp8"],
-                    help="default: f16 (read_mhc, snp_chrom), bf16 (snp_porec); batched blocks carry their own")
-    ap.add_argument("--graph", type=int, default=0,
-                    help="1: capture the step loop in a hipGraph (pays off only when a graph is solved again; "
-                         "every job here builds a fresh graph, so the default launches the steps directly)")
+                    help="read_mhc / snp_*: storage of J (default f16, f16, bf16); batched blocks carry their own")
+    ap.add_argument("--graph", type=int, default=None,
+                    help="1: replay the step loop from a captured hipGraph (default for batched, whose graphs "
+                         "are built once); 0: direct launches (default for the others, which build a fresh "
+                         "graph per job)")
     ap.add_argument("--plan", type=int, default=0,
-                    help="0 auto (persistent when it applies), 1 one kernel per step, 2 persistent")
-    ap.add_argument("--persistent-sync", type=int, default=0, choices=[0, 1, 2],
-                    help="persistent plan: 0 tuned, 1 cache-wide fences, 2 device-coherent accesses")
+                    help="0 auto; batched: 1 per-step, 2 whole-block; read_mhc: 1 per-step, 2 persistent")
+    ap.add_argument("--persistent-sync", type=int, default=0, choices=[0, 1, 2])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=2000)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the time-to-phase and plain-FP32 measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device copy of 1 GiB (3 times): the reference kernel that scales "
                          "the FETCH_SIZE / WRITE_SIZE counters to HBM bytes")
     return ap.parse_args()
-
-
-COPY_BYTES = 1 << 30
 
 
 def calibrate_copy():
@@ -64,37 +72,34 @@ def calibrate_copy():
     print(json.dumps(dict(copy_bytes_read=COPY_BYTES, copy_bytes_written=COPY_BYTES, launches=3)), flush=True)
 
 
-def kernel_source_hash(kernel="k_dense_step"):
-    """Hash of a step kernel's source.  k_dense_step: the dense-tile section of bsb.hip
-    (from StepArgs to the skyline banner, the update helpers included); k_dense_persistent:
-    persistent_kernel.h; k_band_step: the update helpers and the skyline section of bsb.hip.
-    formats.h (the number formats) is part of every hash."""
-    import hashlib
-    h = hashlib.sha256()
+# ----------------------------------------------------------------------------- helpers
+
+def _section(src, begin, end):
+    a = src.index(begin)
+    return src[a:src.index(end, a + len(begin))]
+
+
+def kernel_source_hash(kernel):
+    """Hash of the source a step kernel is compiled from (its section of bsb.hip, the shared
+    update helpers, formats.h), so that counter summaries taken on older code are not used."""
     csrc = os.path.join(ROOT, "paper_2603_25762_amd", "csrc")
+    h = hashlib.sha256()
     if kernel.startswith("k_dense_persistent"):
         h.update(open(os.path.join(csrc, "persistent_kernel.h"), "rb").read())
-    elif kernel.startswith("k_band_step"):
-        src = open(os.path.join(csrc, "bsb.hip")).read()
-        a = src.index("struct StepArgs")
-        b = src.index("struct StepArgs") + src[a:].index("// ------", 1)
-        h.update(src[a:b].encode())                      # StepArgs and the update helpers
-        a = src.index("// skyline band + long-range CSR")
-        b = src.index("// batched blocks:")
-        h.update(src[a:b].encode())                      # the skyline / band kernels
     else:
         src = open(os.path.join(csrc, "bsb.hip")).read()
-        a = src.index("struct StepArgs")
-        b = src.index("// skyline band + long-range CSR")
-        h.update(src[a:b].encode())
+        h.update(_section(src, "struct StepArgs", "// skyline band + long-range CSR").encode())
+        if kernel.startswith("k_band_step") or kernel.startswith("k_lr_packets") or "band" in kernel:
+            h.update(_section(src, "// skyline band + long-range CSR", "// batched blocks:").encode())
+        if kernel.startswith("k_batched"):
+            h.update(_section(src, "// batched blocks:", "// host orchestration").encode())
     h.update(open(os.path.join(csrc, "formats.h"), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, replica_tile=None, depth=None):
-    """HBM bytes per launch of `kernel` from the committed counter summaries (the
-    `traffic:` lines of profiles/*.md), or None when none covers this kernel and
-    configuration or the kernel's source changed since the counters were taken."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summaries (the `traffic:`
+    lines of profiles/*.md), or None when none covers it or its source changed since."""
     import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         vals = {}
@@ -102,299 +107,48 @@ def measured_traffic(kernel, replica_tile=None, depth=None):
             if line.startswith("traffic:"):
                 k, _, v = line[len("traffic:"):].strip().partition("=")
                 vals[k.strip()] = v.strip()
-        if vals.get("kernel") != kernel or vals.get("source_sha") != kernel_source_hash(kernel):
-            continue
-        if replica_tile is not None and int(vals.get("replica_tile", 0)) != replica_tile:
-            continue
-        if depth is not None and int(vals.get("tiles_in_flight", 2)) != depth:
-            continue
-        return int(float(vals["hbm_bytes_per_launch"]))
+        if vals.get("kernel") == kernel and vals.get("source_sha") == kernel_source_hash(kernel):
+            return int(float(vals["hbm_bytes_per_launch"]))
     return None
 
 
-def main():
-    a = parse()
-    if a.calibrate_copy:
-        calibrate_copy()
-        return
-    if a.gpus != 1:
-        print(f"bench.py drives one GPU; --gpus {a.gpus} is not offered (sharding replicas across GPUs "
-              "is described in the design notes only)", file=sys.stderr)
-        sys.exit(2)
-    if a.workload in ("snp_chrom", "snp_porec"):
-        return bench_snp(a)
-    if a.workload == "batched":
-        return bench_batched(a)
-    if a.dtype is None:
-        a.dtype = "f16"
-    import numpy as np
-    import torch
-
-    import paper_2603_25762_amd as qh
-    import synth
-
-    R, STEPS, DT = 256, 2000, 0.5
-    ref_path = os.path.join(ROOT, "tests", "golden", "read_mhc_reference.json")
-    ref = json.load(open(ref_path)) if os.path.exists(ref_path) else None
-    seed = ref["seed"] if ref else 2026
-
-    torch.cuda.set_device(0)
-    w = synth.read_mhc()
-    d = {k: qh.to_device(v) for k, v in w.arrays().items()}
-    torch.cuda.synchronize()
-
-    plan = a.plan
-    tune = None
-    if plan == 0:
-        # let the library's autotuner pick the step-loop plan for this graph and replica count,
-        # then run every timed job with that plan (the tuner itself stays out of the timed region)
-        g = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"],
-                           kind="read_signed", dtype=a.dtype)
-        qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, plan=0, readout=False)
-        tune = g.plan_info(R)
-        plan = tune["plan_used"]
-        g.free()
-    # the tuned per-step tile and depth, or the tuned persistent variant, passed explicitly to
-    # every job's fresh graph
-    kw = {}
-    if tune is not None and plan == 1:
-        kw = dict(replica_tile=tune["replica_tile"], tiles_in_flight=tune["tiles_in_flight"])
-    elif tune is not None and plan == 2:
-        kw = dict(persistent_sync=tune["persistent_sync"])
-    elif plan == 2:
-        kw = dict(persistent_sync=a.persistent_sync)
-
-    def job():
-        g = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"],
-                           kind="read_signed", dtype=a.dtype)
-        r = qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan, **kw)
-        h1, blk = qh.phase(g, r["best_spins"])
-        return g, r, h1, blk
-
-    for _ in range(a.warmup):
-        g, r, h1, blk = job()
-        g.free()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for _ in range(a.steps):
-        g, r, h1, blk = job()
-        results.append((g, r, h1, blk))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / a.steps
-    g, r, h1, blk = results[-1]
-    info = g.info()
-    nnz = info["nnz"]
-    value = nnz * R * STEPS / (ms_per_step * 1e-3)
-    best_cut = float(r["best_cut"].cpu()[0])
-    for gg, *_ in results[:-1]:
-        gg.free()
-
-    # solve-only rate and the dominant kernel (the fused dense step) timed with HIP events on
-    # the stream the library launches on (torch's current stream)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan, **kw)
-    torch.cuda.synchronize()
-    ev0.record()
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), plan=plan, **kw)
-    ev1.record()
-    torch.cuda.synchronize()
-    solve_ms = ev0.elapsed_time(ev1)
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), readout=False, plan=plan, **kw)
-    torch.cuda.synchronize()
-    ev0.record()
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=bool(a.graph), readout=False, plan=plan, **kw)
-    ev1.record()
-    torch.cuda.synchronize()
-    loop_ms = ev0.elapsed_time(ev1)
-    step_us = loop_ms * 1e3 / STEPS
-
-    tiles = info["dense_tiles"]
-    n = info["n"]
-    eb = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}[a.dtype]
-    copy = 0 if a.dtype == "f32" else 2 + 2          # 16-bit product copy of x: written once, read once
-    if plan == 2:
-        # one launch runs every step: J and the fp32 state cross HBM once; the 16-bit copy of x
-        # is exchanged every step
-        launches_steps = STEPS
-        launch_us = loop_ms * 1e3
-        flops = 2.0 * tiles * 4096 * R * STEPS
-        bytes_ = tiles * 4096 * eb + n * R * 16 + STEPS * n * R * copy
-        sync_name = {1: "fences", 2: "coherent"}.get(kw.get("persistent_sync"), "fences")
-        kernel = f"k_dense_persistent<{a.dtype}, {sync_name}>"
+def roofline(bound, bytes_, flops, launch_us, dtype, kernel, **extra):
+    """achieved / peak for the dominant kernel: algorithmic bytes (hbm) or flops (mfma) of one
+    launch over its measured average duration."""
+    gbs = bytes_ / (launch_us * 1e-6) / 1e9
+    tfs = flops / (launch_us * 1e-6) / 1e12
+    hbm_frac, mfma_frac = gbs / PEAK_HBM_GBS, tfs / PEAK_TFLOPS[dtype]
+    if bound == "hbm":
+        r = dict(bound="hbm", achieved=round(gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s", frac=round(hbm_frac, 4))
     else:
-        # one launch = one step: the stored tiles once, x and y read and written once, the
-        # 16-bit copy written and read once (re-reads of x columns by other row tiles are
-        # cache traffic, not algorithmic)
-        launches_steps = 1
-        launch_us = step_us
-        flops = 2.0 * tiles * 4096 * R               # executed MFMA work of one launch (one step)
-        bytes_ = tiles * 4096 * eb + n * R * 16 + n * R * copy
-        kernel = f"k_dense_step<{a.dtype}>"
-    ach_tf = flops / (launch_us * 1e-6) / 1e12
-    ach_gbs = bytes_ / (launch_us * 1e-6) / 1e9
-    frac_m = ach_tf / PEAK_TFLOPS[a.dtype]
-    frac_h = ach_gbs / PEAK_HBM_GBS
-    rtile = (tune or {}).get("replica_tile") or 64
-    depth = (tune or {}).get("tiles_in_flight") or 2
-    traffic = measured_traffic(kernel, rtile, depth) if plan != 2 else measured_traffic(kernel)
-    if frac_m >= frac_h:
-        roof = dict(bound="mfma", achieved=round(ach_tf, 2), peak=PEAK_TFLOPS[a.dtype], unit="TFLOP/s",
-                    frac=round(frac_m, 4), traffic=traffic)
-    else:
-        roof = dict(bound="hbm", achieved=round(ach_gbs, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=round(frac_h, 4), traffic=traffic)
-    roof.update(kernel=kernel, replica_tile=rtile if plan != 2 else None,
-                tiles_in_flight=depth if plan != 2 else None, launch_us=round(launch_us, 3),
-                steps_per_launch=launches_steps,
-                us_per_bsb_step=round(step_us, 3), flop_per_launch=flops, bytes_per_launch=bytes_,
-                mfma_frac=round(frac_m, 4), hbm_frac=round(frac_h, 4), source_sha=kernel_source_hash(kernel))
-
-    out = dict(metric=METRIC, value=value, unit="edge-updates/s", n_gpus=1, steps=a.steps,
-               warmup=a.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True,
-               scaling="weak", vs_baseline=None, dtype=a.dtype, data="synthetic",
-               config=dict(workload="read_mhc: 4 Mb region, 12,000 het SNPs, 8,000 lognormal 15 kb reads, "
-                                    "1-8% allele errors; dense 8000x8000 signed read graph",
-                           n=n, nnz=nnz, dense_tiles=tiles, replicas=R, bsb_steps=STEPS, dt=DT,
-                           storage="dense 64x64 tiles (zero tiles skipped)", precision=a.dtype,
-                           plan="persistent" if plan == 2 else "per-step",
-                           parallelism="single GPU"),
-               solve_ms=round(solve_ms, 3), solve_edge_updates_per_s=nnz * R * STEPS / (solve_ms * 1e-3),
-               best_cut=best_cut, roofline=roof)
-    if tune is not None:
-        out["autotune"] = tune
-    if ref is not None and ref.get("nnz") == nnz:
-        out["oracle_best_cut"] = ref["best_cut"]
-        out["cut_gap"] = (ref["best_cut"] - best_cut) / abs(ref["best_cut"])
-    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth, w.pos))
-
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, R, STEPS, DT, seed, a.cpu_sample_steps)
-    print(json.dumps(out), flush=True)
+        r = dict(bound="mfma", achieved=round(tfs, 2), peak=PEAK_TFLOPS[dtype], unit="TFLOP/s",
+                 frac=round(mfma_frac, 4))
+    r["traffic"] = measured_traffic(kernel)
+    r.update(kernel=kernel, launch_us=round(launch_us, 3), bytes_per_launch=int(bytes_), flop_per_launch=flops,
+             hbm_frac=round(hbm_frac, 4), mfma_frac=round(mfma_frac, 4), source_sha=kernel_source_hash(kernel))
+    r.update(extra)
+    return r
 
 
-def _time_loop(fn, reps=1):
+def golden(name, hash_):
+    """Oracle reference results for a workload, when the stored input hash matches."""
+    path = os.path.join(GOLDEN, f"{name}_reference.json")
+    if not os.path.exists(path):
+        return None
+    ref = json.load(open(path))
+    return ref if ref.get("hash") == hash_ else None
+
+
+def event_ms(fn):
     """HIP-event time (ms) of fn() on torch's current stream, which the library launches on."""
     import torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fn()
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(reps):
-        fn()
+    fn()
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps
-
-
-def bench_snp(a):
-    """SNP-based chromosome-scale workloads: skyline band (+ long-range CSR for Pore-C)."""
-    import torch
-    import paper_2603_25762_amd as qh
-    import synth
-    porec = a.workload == "snp_porec"
-    dtype = a.dtype or ("bf16" if porec else "f16")
-    R, STEPS, DT, SEED = 64, (4000 if porec else 3000), 0.5, 7
-    band = 64 if porec else 0     # every read pair stays in the band, every Pore-C contact goes long-range
-    torch.cuda.set_device(0)
-    w = synth.snp_porec() if porec else synth.snp_chrom()
-    d = {k: qh.to_device(v) for k, v in w.arrays().items()}
-    torch.cuda.synchronize()
-
-    def build():
-        return qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="snp_llr",
-                              dtype=dtype, alpha=d["alpha"], band_limit=band)
-
-    # the autotuner times the two band kernels once (untimed); every job then runs its choice
-    g = build()
-    qh.bsb_solve(g, R, STEPS, dt=DT, seed=SEED, plan=0, readout=False)
-    tune = g.plan_info(R)
-    plan = tune["skyline_kernel"]
-    g.free()
-
-    def job():
-        g = build()
-        r = qh.bsb_solve(g, R, STEPS, dt=DT, seed=SEED, use_graph=bool(a.graph), plan=plan)
-        h1, blk = qh.phase(g, r["best_spins"])
-        return g, r, h1, blk
-
-    for _ in range(a.warmup):
-        job()[0].free()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = [job() for _ in range(a.steps)]
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / a.steps
-    g, r, h1, blk = res[-1]
-    for gg, *_ in res[:-1]:
-        gg.free()
-    info = g.info()
-    nnz, n = info["nnz"], info["n"]
-    loop_ms = _time_loop(lambda: qh.bsb_solve(g, R, STEPS, dt=DT, seed=SEED, use_graph=bool(a.graph),
-                                              readout=False, plan=plan))
-    step_us = loop_ms * 1e3 / STEPS
-    # one step: the stored band (no column indices) and the long-range CSR once, x and y read
-    # and written once (gathers of x rows by long-range entries are cache traffic)
-    lr = info["longrange_nnz"]
-    bytes_ = info["stored_bytes"] + n * R * 16
-    ach = bytes_ / (step_us * 1e-6) / 1e9
-    kernel = ("k_band_step_mfma" if plan == 5 else "k_band_step" if plan == 4 else "k_sky_step") + \
-        ("+k_lr_packets" if lr else "") + f"<{dtype}>"
-    out = dict(metric=METRIC, value=nnz * R * STEPS / (ms * 1e-3), unit="edge-updates/s", n_gpus=1,
-               steps=a.steps, warmup=a.warmup, ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype=dtype, data="synthetic",
-               config=dict(workload=("snp_porec: snp_chrom plus 600,000 Pore-C contacts (distance ~ d^-1.1, "
-                                     "100 kb-100 Mb, Zipf anchors), band limit 64" if porec else
-                                     "snp_chrom: 250,000 het SNPs, 30x of 20 kb reads, 6% errors, Phred 7-40"),
-                           n=n, nnz=nnz, longrange_nnz=lr, replicas=R, bsb_steps=STEPS, dt=DT,
-                           storage="skyline band blocks" + (" + long-range packets" if lr else ""),
-                           parallelism="single GPU"),
-               roofline=dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                             frac=round(ach / PEAK_HBM_GBS, 4),
-                             traffic=None if lr else measured_traffic(kernel), kernel=kernel,
-                             source_sha=kernel_source_hash(kernel),
-                             launch_us=round(step_us, 3), bytes_per_launch=bytes_,
-                             note="per bSB step (all kernels of one step)"),
-               autotune=tune)
-    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth, w.pos))
-    print(json.dumps(out), flush=True)
-
-
-def bench_batched(a):
-    """3,000 uneven blocks (dense FP8 read blocks, BF16 SNP blocks), R = 32, 500 steps.
-    Graphs are built before the timed region; one step = one batched solve."""
-    import torch
-    import paper_2603_25762_amd as qh
-    import synth
-    R, STEPS, DT, SEED = 32, 500, 0.5, 11
-    torch.cuda.set_device(0)
-    batch = synth.batched_blocks()
-    gs = []
-    for i, w in enumerate(batch.blocks):
-        d = {k: qh.to_device(v) for k, v in w.arrays().items()}
-        kind = "read_signed" if i % 2 == 0 else "snp_llr"
-        gs.append(qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind=kind,
-                                 dtype=w.solve["dtype"], alpha=d["alpha"] if kind == "snp_llr" else None))
-    torch.cuda.synchronize()
-    nnz = sum(g.info()["nnz"] for g in gs)
-    r = None
-    for _ in range(a.warmup):
-        r = qh.bsb_solve_batched(gs, R, STEPS, dt=DT, seed=SEED, plan=a.plan)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        r = qh.bsb_solve_batched(gs, R, STEPS, dt=DT, seed=SEED, plan=a.plan)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / a.steps
-    out = dict(metric=METRIC, value=nnz * R * STEPS / (ms * 1e-3), unit="edge-updates/s", n_gpus=1,
-               steps=a.steps, warmup=a.warmup, ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak",
-               vs_baseline=None, dtype="fp8+bf16", data="synthetic",
-               config=dict(workload="batched: 3,000 blocks, log-uniform 50-5,000 vertices, even blocks dense "
-                                    "FP8 read graphs, odd blocks BF16 SNP graphs",
-                           blocks=len(gs), nnz=nnz, replicas=R, bsb_steps=STEPS, dt=DT,
-                           plan_used=r["plan_used"], parallelism="single GPU"))
-    print(json.dumps(out), flush=True)
+    return e0.elapsed_time(e1)
 
 
 def phasing_errors(h1, block, truth, pos=None):
@@ -427,24 +181,406 @@ def phasing_errors(h1, block, truth, pos=None):
     return out
 
 
-def cpu_baseline(w, R, STEPS, DT, seed, sample_steps):
-    """The FP64 oracle on the host cores: full graph build + a bounded sample of bSB steps,
-    extrapolated linearly to the whole job in edge-updates/s."""
+def _timed_jobs(job, steps, warmup):
+    """Run warmup untimed jobs, then time exactly `steps` jobs between device
+    synchronisations; returns (ms per job, last job's result)."""
+    import torch
+    res = None
+    for _ in range(warmup):
+        res = job(res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = job(res)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / max(steps, 1), res
+
+
+# ----------------------------------------------------------------------------- batched (default)
+
+BATCH_R, BATCH_STEPS, BATCH_DT, BATCH_SEED = 32, 500, 0.5, 11
+BATCH_CPU_SAMPLE = (0, 5)       # oracle sample: the stratified subset's blocks 0, 5, 10, ...
+
+
+def build_batch(qh, batch, dtype=None, alpha_for_reads=False):
+    gs = []
+    for i, w in enumerate(batch.blocks):
+        d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+        kind = "read_signed" if i % 2 == 0 else "snp_llr"
+        gs.append(qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind=kind,
+                                 dtype=dtype or w.solve["dtype"], alpha=d["alpha"] if kind == "snp_llr" else None))
+    return gs
+
+
+def batch_gaps(qh, gs, r, batch, ref):
+    """Cut gap of every block of the oracle's subset, and whether its switch error equals the
+    oracle's (the block's h1 from qh_phase on the block's selected spins)."""
+    import numpy as np
+    bc = r["best_cut"].cpu().numpy()
+    off = r["vertex_offset"]
+    gaps, se_eq, ses = [], 0, []
+    for blk in ref["blocks"]:
+        b = blk["block"]
+        gaps.append((blk["best_cut"] - float(bc[b])) / abs(blk["best_cut"]))
+        h1, bl = qh.phase(gs[b], r["best_spins"][int(off[b]):int(off[b + 1])])
+        se = phasing_errors(h1.cpu().numpy(), bl.cpu().numpy(), batch.blocks[b].truth)["switch_error"]
+        se_eq += int(se == blk["switch_error"])
+        ses.append(se)
+    gaps = np.array(gaps)
+    tot_ref = sum(b["best_cut"] for b in ref["blocks"])
+    tot = sum(float(bc[b["block"]]) for b in ref["blocks"])
+    return dict(cut_gap=float(gaps.max()), cut_gap_mean=float(gaps.mean()), cut_gap_total=(tot_ref - tot) / abs(tot_ref),
+                blocks_over_0p1pct=int((gaps > 1e-3).sum()), blocks_compared=len(gaps),
+                switch_error_equal=se_eq, switch_error_mean=float(np.mean(ses)),
+                oracle_switch_error_mean=float(np.mean([b["switch_error"] for b in ref["blocks"]])))
+
+
+def cpu_baseline_batched(batch, ref):
+    """The FP64 oracle on the host cores: a bounded sample of the batch's blocks (graph built
+    untimed, then the whole solve: bSB steps, cuts, selection, greedy), in edge-updates/s."""
+    import oracle
+    first, stride = BATCH_CPU_SAMPLE
+    sample = [b["block"] for b in ref["blocks"]][first::stride]
+    eu = 0.0
+    t = 0.0
+    for b in sample:
+        kind = "read_signed" if b % 2 == 0 else "snp_llr"
+        g = oracle.build_graph(batch.blocks[b], kind)
+        t0 = time.perf_counter()
+        oracle.solve(g, BATCH_R, BATCH_STEPS, BATCH_DT, seed=BATCH_SEED, integer=kind != "snp_llr")
+        t += time.perf_counter() - t0
+        eu += g.nnz * BATCH_R * BATCH_STEPS
+    return dict(value=eu / t, unit="edge-updates/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{len(sample)} of the 3,000 blocks (every {stride}th block of the oracle's stratified 5% "
+                       f"subset from its {first}th, all sizes and both kinds; {eu:.3e} edge-updates, "
+                       f"{eu / 3.0e13 * 100:.2f}% of the job): whole oracle solves (R = {BATCH_R}, {BATCH_STEPS} "
+                       f"steps, cuts, selection, greedy), graph builds untimed; {t:.1f} s")
+
+
+def bench_batched(a):
+    import numpy as np
+    import torch
+
+    import paper_2603_25762_amd as qh
+    import synth
+
+    R, STEPS, DT, SEED = BATCH_R, BATCH_STEPS, BATCH_DT, BATCH_SEED
+    use_graph = True if a.graph is None else bool(a.graph)
+    torch.cuda.set_device(0)
+    batch = synth.batched_blocks()
+    ref = golden("batched", synth.batch_hash(batch))
+    t0 = time.perf_counter()
+    gs = build_batch(qh, batch)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    infos = [g.info() for g in gs]
+    nnz = sum(i["nnz"] for i in infos)
+    dense = [i for i, inf in enumerate(infos) if inf["storage"] == 0]
+    sparse = [i for i, inf in enumerate(infos) if inf["storage"] != 0]
+    plan = 1 if use_graph else a.plan
+    kw = dict(dt=DT, seed=SEED, use_graph=use_graph, plan=plan)
+
+    def job(_):
+        return qh.bsb_solve_batched(gs, R, STEPS, **kw)
+
+    ms, r = _timed_jobs(job, a.steps, a.warmup)
+    value = nnz * R * STEPS / (ms * 1e-3)
+
+    # dominant kernel: the dense FP8 class (one launch per step over every dense block's row
+    # tiles), timed with HIP events on the library's stream: the dense blocks solved as a
+    # batch of their own, dynamics only, so the 500 launches of that class are all it runs
+    sub_d = [gs[i] for i in dense]
+    sub_s = [gs[i] for i in sparse]
+    qh.bsb_solve_batched(sub_d, R, STEPS, readout=False, **kw)              # capture / warm
+    dense_us = event_ms(lambda: qh.bsb_solve_batched(sub_d, R, STEPS, readout=False, **kw)) * 1e3 / STEPS
+    qh.bsb_solve_batched(sub_s, R, STEPS, readout=False, **kw)
+    band_us = event_ms(lambda: qh.bsb_solve_batched(sub_s, R, STEPS, readout=False, **kw)) * 1e3 / STEPS
+    n_d = np.array([infos[i]["n"] for i in dense], dtype=np.float64)
+    # per dense block and step: N^2 FP8 entries, N row scales, and per (row, replica) x and y
+    # read and written (16 B) plus the 16-bit copy of x written and read (4 B)
+    dense_bytes = float((n_d ** 2).sum() + 4 * n_d.sum() + 20 * n_d.sum() * R)
+    dense_flops = float(2 * (n_d ** 2).sum() * R)
+    n_s = np.array([infos[i]["n"] for i in sparse], dtype=np.float64)
+    band_bytes = float(sum(infos[i]["stored_bytes"] - 16 * infos[i]["n"] for i in sparse) + 16 * n_s.sum() * R)
+    roof = roofline("hbm", dense_bytes, dense_flops, dense_us, "fp8", "k_batched_rowtile<fp8>",
+                    steps_per_launch=1, per_step_us={"dense_fp8_class": round(dense_us, 2),
+                                                     "band_class": round(band_us, 2)},
+                    band_class_hbm_frac=round(band_bytes / (band_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                    band_class_bytes_per_launch=int(band_bytes),
+                    note="dense FP8 class per step: sum_b (N_b^2 + 4 N_b + 20 N_b R) bytes, 2 N_b^2 R flop")
+
+    out = dict(metric=METRIC, value=value, unit="edge-updates/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+               ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="fp8+bf16 storage, fp32 accumulate", data="synthetic",
+               config=dict(workload="batched: 3,000 independent phasing blocks, vertex counts log-uniform 50-5,000; "
+                                    "even blocks dense read graphs (FP8 + row scales), odd blocks SNP graphs "
+                                    "(BF16 band); R = 32, 500 bSB steps, dt = 0.5, linear pump, c0 auto per block",
+                           blocks=len(gs), dense_blocks=len(dense), snp_blocks=len(sparse), nnz=int(nnz),
+                           dense_entries=int((n_d ** 2).sum()), vertices=int(sum(i["n"] for i in infos)),
+                           replicas=R, bsb_steps=STEPS, dt=DT, seed=SEED,
+                           plan="per-step, hipGraph replay" if use_graph else f"plan {r['plan_used']}",
+                           parallelism="single GPU"),
+               plan_used=r["plan_used"], build_s=round(build_s, 3), roofline=roof)
+    if ref is not None:
+        out.update(batch_gaps(qh, gs, r, batch, ref))
+        out["oracle_reference"] = "tests/golden/batched_reference.json (stratified 5% subset: 150 blocks)"
+    if not a.no_extras:
+        out["time_to_phase_ms"] = round(time_to_phase_batched(qh, batch, R, STEPS, DT, SEED), 1)
+        out["fp32_form"] = fp32_form_batched(qh, batch, R, STEPS, DT, SEED, ref, a)
+    for g in gs:
+        g.free()
+    if not a.no_cpu_baseline and ref is not None:
+        out["cpu_baseline"] = cpu_baseline_batched(batch, ref)
+    print(json.dumps(out), flush=True)
+
+
+def time_to_phase_batched(qh, batch, R, STEPS, DT, SEED):
+    """Host fragments in -> haplotypes out for the whole batch: H2D of every block's
+    fragments, graph builds, the batched solve, the phasing of every block, D2H."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gs = build_batch(qh, batch)
+    r = qh.bsb_solve_batched(gs, R, STEPS, dt=DT, seed=SEED)
+    off = r["vertex_offset"]
+    outs = [qh.phase(g, r["best_spins"][int(off[b]):int(off[b + 1])]) for b, g in enumerate(gs)]
+    h1 = torch.cat([o[0] for o in outs]).cpu()
+    blk = torch.cat([o[1] for o in outs]).cpu()
+    ms = (time.perf_counter() - t0) * 1e3
+    del h1, blk
+    for g in gs:
+        g.free()
+    return ms
+
+
+def fp32_form_batched(qh, batch, R, STEPS, DT, SEED, ref, a):
+    """The plain FP32 form on the same batch: every block's J stored in FP32."""
+    import torch
+    gs = build_batch(qh, batch, dtype="f32")
+    nnz = sum(g.info()["nnz"] for g in gs)
+    kw = dict(dt=DT, seed=SEED, use_graph=True, plan=1)
+    r = qh.bsb_solve_batched(gs, R, STEPS, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = qh.bsb_solve_batched(gs, R, STEPS, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    out = dict(value=nnz * R * STEPS / (ms * 1e-3), ms_per_step=round(ms, 3))
+    if ref is not None:
+        g = batch_gaps(qh, gs, r, batch, ref)
+        out.update(cut_gap=g["cut_gap"], switch_error_equal=g["switch_error_equal"])
+    for g in gs:
+        g.free()
+    return out
+
+
+# ----------------------------------------------------------------------------- read_mhc
+
+def bench_read_mhc(a):
+    import torch
+
+    import paper_2603_25762_amd as qh
+    import synth
+
+    dtype = a.dtype or "f16"
+    R, STEPS, DT = 256, 2000, 0.5
+    torch.cuda.set_device(0)
+    w = synth.read_mhc()
+    ref = golden("read_mhc", synth.workload_hash(w))
+    seed = ref["seed"] if ref else 2026
+    d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+    torch.cuda.synchronize()
+
+    def build():
+        return qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="read_signed",
+                              dtype=dtype)
+
+    plan, kw = a.plan, {}
+    if plan == 0:   # the autotuner picks the plan once (untimed); every job then runs it
+        g = build()
+        qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, plan=0, readout=False)
+        tune = g.plan_info(R)
+        g.free()
+        plan = tune["plan_used"]
+        kw = dict(replica_tile=tune["replica_tile"], tiles_in_flight=tune["tiles_in_flight"]) if plan == 1 else \
+            dict(persistent_sync=tune["persistent_sync"])
+    elif plan == 2:
+        kw = dict(persistent_sync=a.persistent_sync)
+    use_graph = bool(a.graph) if a.graph is not None else False
+
+    def job(prev):
+        if prev is not None:
+            prev[0].free()
+        g = build()
+        r = qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=use_graph, plan=plan, **kw)
+        h1, blk = qh.phase(g, r["best_spins"])
+        return g, r, h1, blk
+
+    ms, (g, r, h1, blk) = _timed_jobs(job, a.steps, a.warmup)
+    info = g.info()
+    nnz, n, tiles = info["nnz"], info["n"], info["dense_tiles"]
+    value = nnz * R * STEPS / (ms * 1e-3)
+    best_cut = float(r["best_cut"].cpu()[0])
+    solve_ms = event_ms(lambda: qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=use_graph, plan=plan, **kw))
+    loop_ms = event_ms(lambda: qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, use_graph=use_graph, readout=False,
+                                            plan=plan, **kw))
+    eb = {"f32": 4, "f16": 2, "bf16": 2, "fp8": 1}[dtype]
+    # algorithmic work (§ measurement): 2 nnz R flop per step on the true nonzeros
+    if plan == 2:
+        kernel = f"k_dense_persistent<{dtype}, {'coherent' if kw.get('persistent_sync') == 2 else 'fences'}>"
+        launch_us, steps_per_launch = loop_ms * 1e3, STEPS
+    else:
+        kernel, launch_us, steps_per_launch = f"k_dense_step<{dtype}>", loop_ms * 1e3 / STEPS, 1
+    flops = 2.0 * nnz * R * steps_per_launch
+    copy = 0 if dtype == "f32" else 4
+    bytes_ = (tiles * 4096 * eb + n * R * 16 + steps_per_launch * n * R * copy) if plan == 2 else \
+        (tiles * 4096 * eb + n * R * (16 + copy))
+    roof = roofline("mfma", bytes_, flops, launch_us, dtype, kernel, steps_per_launch=steps_per_launch,
+                    us_per_bsb_step=round(loop_ms * 1e3 / STEPS, 3),
+                    executed_flop_per_launch=2.0 * tiles * 4096 * R * steps_per_launch,
+                    executed_mfma_frac=round(2.0 * tiles * 4096 * R * steps_per_launch / (launch_us * 1e-6) / 1e12
+                                             / PEAK_TFLOPS[dtype], 4))
+    out = dict(metric=METRIC, value=value, unit="edge-updates/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+               ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype=f"{dtype} storage, fp32 accumulate", data="synthetic",
+               config=dict(workload="read_mhc: 4 Mb region, 12,000 het SNPs, 8,000 lognormal 15 kb reads, 1-8% "
+                                    "allele errors; dense 8000x8000 signed read graph; R = 256, 2,000 steps",
+                           n=n, nnz=nnz, dense_tiles=tiles, replicas=R, bsb_steps=STEPS, dt=DT, precision=dtype,
+                           plan="persistent" if plan == 2 else "per-step", parallelism="single GPU"),
+               solve_ms=round(solve_ms, 3), solve_edge_updates_per_s=nnz * R * STEPS / (solve_ms * 1e-3),
+               best_cut=best_cut, roofline=roof, plan_options=kw)
+    if ref is not None:
+        out.update(oracle_best_cut=ref["best_cut"], cut_gap=(ref["best_cut"] - best_cut) / abs(ref["best_cut"]),
+                   oracle_switch_error=ref["switch_error"])
+    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth, w.pos))
+    if not a.no_extras:
+        out["time_to_phase_ms"] = round(time_to_phase_single(qh, w, "read_signed", dtype, R, STEPS, DT, seed,
+                                                             plan=plan, **kw), 2)
+    g.free()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_single(w, "read_signed", R, STEPS, DT, seed, STEPS)
+    print(json.dumps(out), flush=True)
+
+
+def time_to_phase_single(qh, w, kind, dtype, R, STEPS, DT, seed, band_limit=0, **kw):
+    """Host fragments in -> haplotypes out: H2D, graph build, solve, phase, D2H."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+    g = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind=kind, dtype=dtype,
+                       alpha=d["alpha"] if kind == "snp_llr" else None, band_limit=band_limit)
+    r = qh.bsb_solve(g, R, STEPS, dt=DT, seed=seed, **kw)
+    h1, blk = qh.phase(g, r["best_spins"])
+    h1, blk = h1.cpu(), blk.cpu()
+    ms = (time.perf_counter() - t0) * 1e3
+    g.free()
+    return ms
+
+
+def cpu_baseline_single(w, kind, R, STEPS, DT, seed, sample_steps):
+    """The FP64 oracle on the host cores: full graph build + the first `sample_steps` bSB
+    steps, extrapolated linearly to the whole solve, in edge-updates/s."""
     import oracle
     t0 = time.perf_counter()
-    g = oracle.build_graph(w, "read_signed")
+    g = oracle.build_graph(w, kind)
     t_build = time.perf_counter() - t0
     x, y = oracle.init_state(seed, g.n, R)
-    pump = oracle.pump_linear(STEPS)
     t0 = time.perf_counter()
-    oracle.bsb_run(g, x, y, pump, DT, oracle.c0(g), 1.0, 0, sample_steps)
+    oracle.bsb_run(g, x, y, oracle.pump_linear(STEPS), DT, oracle.c0(g), 1.0, 0, sample_steps)
     t_steps = time.perf_counter() - t0
     t_job = t_build + t_steps * STEPS / sample_steps
-    return dict(value=g.nnz * R * STEPS / t_job, unit="edge-updates/s", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"oracle graph build (full) + bSB steps 0..{sample_steps} of {STEPS} (R={R}), "
-                       f"extrapolated linearly to the whole job; build {t_build:.2f} s, "
-                       f"{sample_steps} steps {t_steps:.2f} s")
+    return dict(value=g.nnz * R * STEPS / t_job, unit="edge-updates/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"oracle graph build (full) + bSB steps 0..{sample_steps} of {STEPS} (R={R}), extrapolated "
+                       f"linearly to the whole job; build {t_build:.2f} s, {sample_steps} steps {t_steps:.2f} s")
+
+
+# ----------------------------------------------------------------------------- SNP graphs
+
+def bench_snp(a):
+    import torch
+
+    import paper_2603_25762_amd as qh
+    import synth
+
+    porec = a.workload == "snp_porec"
+    name = a.workload
+    dtype = a.dtype or ("bf16" if porec else "f16")
+    R, STEPS, DT, SEED = 64, (4000 if porec else 3000), 0.5, 7
+    band = 64 if porec else 0     # every read pair stays in the band, every Pore-C contact goes long-range
+    torch.cuda.set_device(0)
+    w = synth.snp_porec() if porec else synth.snp_chrom()
+    ref = golden(name, synth.workload_hash(w))
+    d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+    torch.cuda.synchronize()
+
+    def build():
+        return qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="snp_llr",
+                              dtype=dtype, alpha=d["alpha"], band_limit=band)
+
+    g = build()     # the autotuner times the band kernels once (untimed); every job then runs its choice
+    qh.bsb_solve(g, R, STEPS, dt=DT, seed=SEED, plan=0, readout=False)
+    tune = g.plan_info(R)
+    plan = tune["skyline_kernel"]     # 3 per-row, 4 band FMA, 5 band MFMA: the plan that runs it
+    g.free()
+    use_graph = bool(a.graph) if a.graph is not None else False
+
+    def job(prev):
+        if prev is not None:
+            prev[0].free()
+        g = build()
+        r = qh.bsb_solve(g, R, STEPS, dt=DT, seed=SEED, use_graph=use_graph, plan=plan)
+        h1, blk = qh.phase(g, r["best_spins"])
+        return g, r, h1, blk
+
+    ms, (g, r, h1, blk) = _timed_jobs(job, a.steps, a.warmup)
+    info = g.info()
+    nnz, n, lr = info["nnz"], info["n"], info["longrange_nnz"]
+    loop_ms = event_ms(lambda: qh.bsb_solve(g, R, STEPS, dt=DT, seed=SEED, use_graph=use_graph, readout=False,
+                                            plan=plan))
+    step_us = loop_ms * 1e3 / STEPS
+    # one step: the stored band (no column indices) and the long-range CSR once, x and y read
+    # and written once (gathers of x rows by long-range entries are cache traffic)
+    bytes_ = info["stored_bytes"] - 16 * n + n * R * 16
+    kernel = {4: "k_band_step", 5: "k_band_step_mfma", 3: "k_sky_step"}[plan] + ("+k_lr_packets" if lr else "")
+    roof = roofline("hbm", bytes_, 2.0 * nnz * R, step_us, "f32", kernel + f"<{dtype}>",
+                    note="one launch = one bSB step (all kernels of the step)")
+    best_cut = float(r["best_cut"].cpu()[0])
+    out = dict(metric=METRIC, value=nnz * R * STEPS / (ms * 1e-3), unit="edge-updates/s", n_gpus=1, steps=a.steps,
+               warmup=a.warmup, ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype=f"{dtype} storage, fp32 accumulate", data="synthetic",
+               config=dict(workload=("snp_porec: snp_chrom plus 600,000 Pore-C contacts (distance ~ d^-1.1, "
+                                     "100 kb-100 Mb, Zipf anchors), band limit 64" if porec else
+                                     "snp_chrom: 250,000 het SNPs, 30x of 20 kb reads, 6% errors, Phred 7-40") +
+                           f"; R = {R}, {STEPS} steps",
+                           n=n, nnz=nnz, longrange_nnz=lr, replicas=R, bsb_steps=STEPS, dt=DT,
+                           storage="skyline band blocks" + (" + long-range packets" if lr else ""),
+                           parallelism="single GPU"),
+               best_cut=best_cut, roofline=roof, autotune=tune)
+    if ref is not None:
+        out.update(oracle_best_cut=ref["best_cut"], cut_gap=(ref["best_cut"] - best_cut) / abs(ref["best_cut"]),
+                   oracle_switch_error=ref["switch_error"])
+    out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth, w.pos))
+    if not a.no_extras:
+        out["time_to_phase_ms"] = round(time_to_phase_single(qh, w, "snp_llr", dtype, R, STEPS, DT, SEED,
+                                                             band_limit=band, plan=plan), 2)
+    g.free()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_single(w, "snp_llr", R, STEPS, DT, SEED, 60)
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    a = parse()
+    if a.calibrate_copy:
+        calibrate_copy()
+        return
+    if a.gpus != 1:
+        print(f"bench.py drives one GPU; --gpus {a.gpus} is not offered (how the path would shard across GPUs "
+              "is described in the design notes only)", file=sys.stderr)
+        sys.exit(2)
+    {"batched": bench_batched, "read_mhc": bench_read_mhc, "snp_chrom": bench_snp,
+     "snp_porec": bench_snp}[a.workload](a)
 
 
 if __name__ == "__main__":

@@ -270,21 +270,12 @@ def bsb_run(g: CSR, x: np.ndarray, y: np.ndarray, pump: np.ndarray, dt: float, c
 
 
 def bsb_step_dense(J: np.ndarray, x: np.ndarray, y: np.ndarray, p: float, dt: float, c0_: float,
-                   a0: float = 1.0, product_format: Optional[str] = None, walls: bool = True,
-                   discrete: bool = False, field: Optional[np.ndarray] = None):
-    """One bSB step in FP64 with a dense J, returning (x', y').
-
-    ``product_format`` (None, "f16", "bf16") rounds the x that enters the coupling
-    product J x to that format, which is what the reduced-precision forms multiply;
-    the update itself keeps x and y unrounded.
-    """
-    from . import quant
+                   a0: float = 1.0, walls: bool = True, discrete: bool = False,
+                   field: Optional[np.ndarray] = None):
+    """One bSB step in FP64 with a dense J, returning (x', y')."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
-    if discrete:
-        xq = np.where(x >= 0.0, 1.0, -1.0)       # sgn(x), sgn(0) = +1: exact in every format
-    else:
-        xq = x if product_format is None else quant.round_to(product_format, x)
+    xq = np.where(x >= 0.0, 1.0, -1.0) if discrete else x      # dSB: sgn(x), sgn(0) = +1
     z = np.asarray(J, dtype=np.float64) @ xq
     if field is not None:
         z = z + np.asarray(field, dtype=np.float64)[:, None]

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "formats.h"
 #include "internal.h"
@@ -763,6 +764,102 @@ __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restric
     }
 }
 
+// Product of one whole 64-row tile by one wave: the four 16-row strips share the B fragments
+// (the 16-bit copy of x), which the wave loads once per stored tile instead of once per strip.
+// Strip s's MFMAs run in dense_product's order (tile, column half, replica block), and a slot
+// past t_end adds an exact zero there (an accumulator that starts at +0 never becomes -0), so
+// each strip's sum equals the four-wave product's bit for bit whatever U is.
+template <int DT, int NB, int U>
+__device__ inline void dense_product_rowtile(float4_t (&acc)[4][NB], int t_beg, int t_end,
+                                             const int32_t *__restrict__ t_col, const uint8_t *__restrict__ t_val,
+                                             const uint16_t *__restrict__ h_in, int64_t R, int lane) {
+    static_assert(DT != QH_F32, "the whole-tile product takes 16/8-bit tiles");
+    const int l16 = lane & 15, g4 = lane >> 4;
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[s4][b] = float4_t{0.f, 0.f, 0.f, 0.f};
+    using RawA = typename std::conditional<DT == QH_FP8_ROWSCALE, uint2, half8_t>::type;
+    for (int t = t_beg; t < t_end; t += U) {
+        RawA a[U][8];
+        half8_t bv[U][2][NB];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int tt = t + u < t_end ? t + u : t_end - 1;
+            const int64_t j0 = (int64_t)t_col[tt] * kTile;
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                if constexpr (DT == QH_FP8_ROWSCALE)
+                    a[u][f] = *(const uint2 *)(t_val + (int64_t)tt * kTileElems + ((f * 64 + lane) << 3));
+                else
+                    a[u][f] = *(const half8_t *)((const uint16_t *)t_val + (int64_t)tt * kTileElems + ((f * 64 + lane) << 3));
+            }
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                const int64_t jg = (j0 + kb * 32) / 8 + g4;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) bv[u][kb][b] = *(const half8_t *)(h_in + (jg * R + b * 16 + l16) * 8);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (t + u >= t_end) break;        // wave-uniform: past the row tile's last stored tile
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    half8_t av;
+                    if constexpr (DT == QH_FP8_ROWSCALE) av = e4m3x8_to_f16_scaled(a[u][s4 * 2 + kb]);
+                    else av = a[u][s4 * 2 + kb];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        if constexpr (DT == QH_BF16) {
+                            bf16x8_t aw, bw;
+                            __builtin_memcpy(&aw, &av, 16);
+                            __builtin_memcpy(&bw, &bv[u][kb][b], 16);
+                            acc[s4][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bw, acc[s4][b], 0, 0, 0);
+                        } else {
+                            acc[s4][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv[u][kb][b], acc[s4][b], 0, 0, 0);
+                        }
+                    }
+                }
+        }
+    }
+}
+
+// One step of the dense 16/8-bit blocks of one class, one row tile per wave (work item =
+// (block, row tile); four items per workgroup, adjacent items of a block sharing its x
+// columns in the CU's cache).  The same arithmetic as k_batched_step's dense path.
+template <int DT, int NB>
+__global__ __launch_bounds__(256) void k_batched_rowtile(const BlockDesc *__restrict__ blocks,
+                                                         const int2 *__restrict__ items, int64_t n_items, int k,
+                                                         float dt, float a0, const float *__restrict__ pump) {
+    constexpr int64_t R = NB * 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t n_groups = (n_items + 3) / 4;
+    const int64_t item = xcd_remap(blockIdx.x, n_groups) * 4 + wave;
+    if (item >= n_items) return;
+    const int2 I = items[item];
+    const BlockDesc &B = blocks[I.x];
+    const StepArgs sa{B.c0, dt, a0, pump, k, B.discrete, B.bscale, B.field};
+    const float coef = a0 - pump[k];
+    const int cur = k & 1;
+    const uint16_t *hin = cur ? B.h1 : B.h0;
+    uint16_t *hout = cur ? B.h0 : B.h1;
+    const int64_t rt = I.y;
+    float4_t acc[4][NB];
+    dense_product_rowtile<DT, NB, 2>(acc, B.t_ptr[rt], B.t_ptr[rt + 1], B.t_col, B.t_val, hin, R, lane);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int64_t rowbase = rt * kTile + s4 * 16 + 4 * (lane >> 4);
+        float xo[NB][4], yo[NB][4];
+        dense_load_state<NB>(xo, yo, rowbase, B.n, B.x, B.y, R, 0, lane);
+        dense_update<DT, NB>(acc[s4], xo, yo, rowbase, B.n, R, 0, lane, B.row_scale, B.x, B.y, hout, coef, sa);
+    }
+}
+
 template <int NB>
 __global__ __launch_bounds__(256) void k_batched_init(const BlockDesc *__restrict__ blocks, uint64_t seed) {
     block_init<NB * 16>(blocks[blockIdx.x], seed, threadIdx.x);
@@ -775,15 +872,19 @@ static void launch_class(int cls, dim3 grid, hipStream_t st, const BlockDesc *bl
 #define QH_CLS(KD, DTV)                                                                                  \
     hipLaunchKernelGGL((k_batched_step<KD, DTV, NB>), grid, dim3(256), 0, st, blocks, items, n_items, k, dt, \
                        a0, pump)
+#define QH_RT(DTV)                                                                                           \
+    hipLaunchKernelGGL((k_batched_rowtile<DTV, NB>), dim3((unsigned)ceil_div(n_items, 4)), dim3(256), 0, st, \
+                       blocks, items, n_items, k, dt, a0, pump)
     switch (cls) {
         case 0: QH_CLS(0, QH_F32); break;
-        case 1: QH_CLS(0, QH_F16); break;
-        case 2: QH_CLS(0, QH_BF16); break;
-        case 3: QH_CLS(0, QH_FP8_ROWSCALE); break;
+        case 1: QH_RT(QH_F16); break;
+        case 2: QH_RT(QH_BF16); break;
+        case 3: QH_RT(QH_FP8_ROWSCALE); break;
         case 4: QH_CLS(1, QH_F32); break;
         case 5: QH_CLS(1, QH_F16); break;
         default: QH_CLS(1, QH_BF16); break;
     }
+#undef QH_RT
 #undef QH_CLS
 }
 

@@ -6,6 +6,7 @@ import torch
 
 import oracle
 import paper_2603_25762_amd as qh
+from oracle import quant
 
 
 def device_reads(w):
@@ -47,3 +48,30 @@ def f32(a):
 
 def cpu(t: torch.Tensor) -> np.ndarray:
     return t.detach().cpu().numpy()
+
+
+# Unit roundoff of the 16-bit copy of x the dense 16/8-bit product multiplies (binary16 for
+# F16 and FP8 tiles, bfloat16 for BF16 tiles), and the absolute error bound below binary16's
+# normal range (its subnormal spacing 2^-24, halved).
+COPY_UNIT = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+COPY_ABS = {"f16": 2.0 ** -25, "bf16": 0.0}
+
+
+def step_with_rounded_copy(J, x, y, p, dt, c0, a0=1.0, fmt=None, walls=True, discrete=False, field=None):
+    """The precision form's step as the dense 16/8-bit kernels compute it, in FP64: the
+    coupling product multiplies the copy of x rounded to ``fmt`` (binary16 or bfloat16, round
+    to nearest even), the update keeps x and y unrounded.  A model of the kernels, kept in
+    the tests: the oracle's step (oracle.bsb_step_dense) is the unrounded definition."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if discrete or fmt is None:
+        return oracle.bsb_step_dense(J, x, y, p, dt, c0, a0, walls=walls, discrete=discrete, field=field)
+    z = np.asarray(J, dtype=np.float64) @ quant.round_to(fmt, x)
+    if field is not None:
+        z = z + np.asarray(field, dtype=np.float64)[:, None]
+    y2 = y + (-(a0 - p) * x + c0 * z) * dt
+    x2 = x + a0 * y2 * dt
+    if not walls:
+        return x2, y2
+    wall = np.abs(x2) > 1.0
+    return np.where(wall, np.sign(x2), x2), np.where(wall, 0.0, y2)

@@ -17,7 +17,8 @@ import oracle
 import paper_2603_25762_amd as qh
 import synth
 from oracle import metrics, quant
-from gpu_helpers import cpu, device_reads, f32, gpu_graph, oracle_graph, snp_abs_terms, step_bounds
+from gpu_helpers import (COPY_ABS, COPY_UNIT, cpu, device_reads, f32, gpu_graph, oracle_graph, snp_abs_terms,
+                         step_bounds, step_with_rounded_copy)
 
 pytestmark = pytest.mark.gpu
 
@@ -179,10 +180,10 @@ def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, pl
                  x=x, y=y, step_begin=k, step_end=k + 1, readout=False, plan=plan, discrete=discrete,
                  field=None if h is None else torch.tensor(h, dtype=torch.float32, device="cuda"))
     xg, yg = cpu(x).astype(np.float64), cpu(y).astype(np.float64)
-    xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False, discrete=discrete,
-                                   field=h)
-    xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True, discrete=discrete,
-                                   field=h)
+    xu, yu = step_with_rounded_copy(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False, discrete=discrete,
+                                    field=h)
+    xo, yo = step_with_rounded_copy(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True, discrete=discrete,
+                                    field=h)
     if discrete:
         xq = np.ones_like(x0)
     else:
@@ -210,6 +211,46 @@ def test_dense_one_step(dtype, R, plan):
     g = gpu_graph(w, "read_signed", dtype)
     J = stored_J(oracle_graph(w).dense(), dtype)
     _one_step_case(g, J, dtype, R, 100 + R, FMT[dtype], plan=plan)
+
+
+@pytest.mark.parametrize("plan", [1, 2])
+@pytest.mark.parametrize("dtype", ["f16", "bf16", "fp8"])
+def test_dense_one_step_against_unrounded_oracle(dtype, plan):
+    """The 16-bit copy of x that the 16/8-bit dense products multiply, bounded against the
+    oracle's unrounded step (stored J, FP64, x itself in the product): rounding x_j to the
+    copy's format moves it by at most u |x_j| + a (u = 2^-11 for binary16, used by F16 and FP8
+    tiles; 2^-8 for bfloat16; a = 2^-25 below binary16's normal range), so the coupling sum
+    moves by at most sum_j |J_ij| (u |x_j| + a), y by c0 dt times that and x by a0 dt times
+    y's bound, on top of the FP32 step tolerance."""
+    w = synth.read_small(13, n_snp=300, n_reads=150, span=(20, 60))
+    g = gpu_graph(w, "read_signed", dtype)
+    J = stored_J(oracle_graph(w).dense(), dtype)
+    n, R, k, steps, dt = J.shape[0], 64, 37, 100, 0.5
+    fmt = FMT[dtype]
+    rng = np.random.default_rng(321)
+    x0 = f32(rng.uniform(-1.0, 1.0, (n, R)))
+    y0 = f32(rng.uniform(-0.6, 0.6, (n, R)))
+    pump = np.linspace(0.0, 1.0, steps).astype(np.float32)
+    c0 = float(np.float32(0.4 / max(1.0, float(np.sqrt((J ** 2).sum() / (n - 1))))))
+    p = float(pump[k])
+    x = torch.tensor(x0, dtype=torch.float32, device="cuda").contiguous()
+    y = torch.tensor(y0, dtype=torch.float32, device="cuda").contiguous()
+    qh.bsb_solve(g, R, steps, dt=dt, c0=c0, pump=torch.tensor(pump, device="cuda"), init=False, x=x, y=y,
+                 step_begin=k, step_end=k + 1, readout=False, plan=plan)
+    xg, yg = cpu(x).astype(np.float64), cpu(y).astype(np.float64)
+    xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, walls=False)
+    xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, walls=True)
+    tol_x, tol_y = step_bounds(np.abs(J) @ np.abs(x0), x0, y0, p, dt, c0)
+    copy = c0 * dt * (np.abs(J) @ (COPY_UNIT[fmt] * np.abs(x0) + COPY_ABS[fmt]))
+    tol_y = tol_y + copy
+    tol_x = tol_x + dt * copy
+    ok = np.abs(np.abs(xu) - 1.0) > tol_x        # entries not within the tolerance of a wall
+    assert ok.mean() > 0.9
+    assert np.all(np.abs(yg - yo)[ok] <= tol_y[ok])
+    assert np.all(np.abs(xg - xo)[ok] <= tol_x[ok])
+    # the bound is not vacuous: the copy's effect is visible and of the size it predicts
+    dev = np.abs(yg - yo)[ok]
+    assert dev.max() > 1e-3 * copy[ok].max()
 
 
 @pytest.mark.parametrize("plan", [1, 2])
