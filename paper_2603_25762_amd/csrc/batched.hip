@@ -49,6 +49,7 @@ struct CapturedBatch {
     DevBuf<BlockDesc> desc;
     DevBuf<int2> items;
     int64_t class_ptr[kBatchClasses + 1] = {0};
+    std::vector<XcdSplit> splits;
     std::tuple<int, float, float, const float *, uint64_t> args{};
     hipGraphExec_t exec = nullptr;
 };
@@ -139,21 +140,37 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
     DevBuf<BlockDesc> d_desc(nb);
     QH_HIP(hipMemcpyAsync(d_desc.p, desc.data(), nb * sizeof(BlockDesc), hipMemcpyHostToDevice, st));
 
-    // per-step plan: work items grouped by class (storage x dtype), largest blocks first
-    // within a class, items of a block adjacent
+    // per-step plan: work items grouped by class (storage x dtype); within a class the blocks
+    // are spread over the XCDs by the longest-processing-time rule on their bytes per step
+    // (a block's items stay on one XCD, whose L2 then holds its x copy), and each XCD's list
+    // runs its largest blocks first, items of a block adjacent.  Sorted blocks split into
+    // contiguous ranges per XCD would give one XCD all the longest row tiles.
     std::vector<int2> items;
     int64_t class_ptr[kBatchClasses + 1] = {0};
+    std::vector<XcdSplit> splits(kBatchClasses);
     auto class_of = [](const qh_graph *g) {
         if (g->storage == QH_STORE_DENSE)
             return g->dtype == QH_F32 ? 0 : g->dtype == QH_F16 ? 1 : g->dtype == QH_BF16 ? 2 : 3;
         return g->bb_dtype == QH_F32 ? 4 : g->bb_dtype == QH_F16 ? 5 : 6;
     };
     for (int c = 0; c < kBatchClasses; ++c) {
+        std::vector<std::vector<int32_t>> lists(kXcds);
+        double load[kXcds] = {0};
         for (int b : order) {
-            const qh_graph *g = gs[b];
-            if (class_of(g) != c) continue;
-            const int64_t m = g->storage == QH_STORE_DENSE ? g->n_rt : ceil_div(g->n_bblk, 4);
-            for (int64_t i = 0; i < m; ++i) items.push_back(make_int2(b, (int)i));
+            if (class_of(gs[b]) != c) continue;
+            const int x = (int)(std::min_element(load, load + kXcds) - load);
+            load[x] += cost[b];
+            lists[x].push_back(b);
+        }
+        XcdSplit &xs = splits[c];
+        xs.off[0] = 0;
+        for (int x = 0; x < kXcds; ++x) {
+            for (int b : lists[x]) {
+                const qh_graph *g = gs[b];
+                const int64_t m = g->storage == QH_STORE_DENSE ? g->n_rt : ceil_div(g->n_bblk, 4);
+                for (int64_t i = 0; i < m; ++i) items.push_back(make_int2(b, (int)i));
+            }
+            xs.off[x + 1] = (int64_t)items.size() - class_ptr[c];
         }
         class_ptr[c + 1] = (int64_t)items.size();
     }
@@ -189,8 +206,8 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
     auto run = [&](int plan, int steps, uint64_t seed) {
         if (plan == 2) launch_batched(R, workers, d_desc.p, d_sptr.p, d_sched.p, steps, (float)o->dt, (float)a0, pump,
                                       seed, st);
-        else launch_batched_steps(R, nb, d_desc.p, d_items.p, class_ptr, steps, (float)o->dt, (float)a0, pump,
-                                  seed, st);
+        else launch_batched_steps(R, nb, d_desc.p, d_items.p, class_ptr, splits.data(), steps, (float)o->dt,
+                                  (float)a0, pump, seed, st);
     };
     // use_graph: the per-step plan replayed from a captured hipGraph.  The capture reads the
     // block table and items from buffers owned by the cache entry; the table is uploaded into
@@ -217,6 +234,7 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
             if (n_items)
                 QH_HIP(hipMemcpyAsync(cb->items.p, items.data(), n_items * sizeof(int2), hipMemcpyHostToDevice, st));
             std::copy(class_ptr, class_ptr + kBatchClasses + 1, cb->class_ptr);
+            cb->splits = splits;
         }
         g_captured.push_back(cb);   // most recent last
         if (g_captured.size() > kCapturedBatches) {
@@ -236,8 +254,8 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
             hipGraph_t graph = nullptr;
             QH_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
             try {
-                launch_batched_steps(R, nb, cb->desc.p, cb->items.p, cb->class_ptr, steps, (float)o->dt, (float)a0,
-                                     pump, seed, cs);
+                launch_batched_steps(R, nb, cb->desc.p, cb->items.p, cb->class_ptr, cb->splits.data(), steps,
+                                     (float)o->dt, (float)a0, pump, seed, cs);
             } catch (...) {
                 hipGraph_t junk = nullptr;
                 (void)hipStreamEndCapture(cs, &junk);

@@ -731,12 +731,15 @@ __global__ __launch_bounds__(256) void k_batched(const BlockDesc *__restrict__ b
 // occupancy) that of its own path.
 template <int KIND, int DT, int NB>
 __global__ __launch_bounds__(256) void k_batched_step(const BlockDesc *__restrict__ blocks,
-                                                      const int2 *__restrict__ items, int64_t n_items, int k,
+                                                      const int2 *__restrict__ items, XcdSplit xs, int k,
                                                       float dt, float a0, const float *__restrict__ pump) {
     constexpr int64_t R = NB * 16;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int2 I = items[xcd_remap(blockIdx.x, n_items)];
+    const int xcd = blockIdx.x % kXcds;
+    const int64_t item = xs.off[xcd] + blockIdx.x / kXcds;
+    if (item >= xs.off[xcd + 1]) return;
+    const int2 I = items[item];
     const BlockDesc &B = blocks[I.x];
     const StepArgs sa{B.c0, dt, a0, pump, k, B.discrete, B.bscale, B.field};
     const float coef = a0 - pump[k];
@@ -841,22 +844,22 @@ __device__ inline void dense_product_rowtile(float4_t (&acc)[S][NB], int t_beg, 
     }
 }
 
-// One step of the dense 16/8-bit blocks of one class: work item = (block, row tile), served
-// by 4 / S waves of S strips each (four waves per workgroup; adjacent items of a block share
-// its x columns in the CU's cache).  The same arithmetic as k_batched_step's dense path.
+// One step of the dense 16/8-bit blocks of one class: work item = (block, row tile), one wave
+// each, four per workgroup, taken from the list of the XCD that runs the workgroup (adjacent
+// items of a block share its x columns in the CU's cache and the XCD's L2).  The same
+// arithmetic as k_batched_step's dense path.
 template <int DT, int NB>
 __global__ __launch_bounds__(256) void k_batched_rowtile(const BlockDesc *__restrict__ blocks,
-                                                         const int2 *__restrict__ items, int64_t n_items, int k,
+                                                         const int2 *__restrict__ items, XcdSplit xs, int k,
                                                          float dt, float a0, const float *__restrict__ pump) {
-    constexpr int S = 4, WPI = 4 / S;   // strips per wave, waves per item
+    constexpr int S = 4;   // strips per wave: the whole row tile
     constexpr int64_t R = NB * 16;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t n_groups = (n_items * WPI + 3) / 4;
-    const int64_t gw = xcd_remap(blockIdx.x, n_groups) * 4 + wave;
-    const int64_t item = gw / WPI;
-    if (item >= n_items) return;
-    const int s0 = (int)(gw % WPI) * S;
+    const int xcd = blockIdx.x % kXcds;
+    const int64_t item = xs.off[xcd] + (int64_t)(blockIdx.x / kXcds) * 4 + wave;
+    if (item >= xs.off[xcd + 1]) return;
+    const int s0 = 0;
     const int2 I = items[item];
     const BlockDesc &B = blocks[I.x];
     const StepArgs sa{B.c0, dt, a0, pump, k, B.discrete, B.bscale, B.field};
@@ -882,15 +885,23 @@ __global__ __launch_bounds__(256) void k_batched_init(const BlockDesc *__restric
 }
 
 // classes: 0-3 dense F32/F16/BF16/FP8, 4-6 band F32/F16/BF16 (kBatchClasses in total)
+// Workgroups of one class's launch: kXcds times the longest XCD list (in workgroups of
+// `per` items), so that workgroup q * kXcds + x serves XCD x's q-th group.
+static unsigned xcd_grid(const XcdSplit &xs, int per) {
+    int64_t m = 0;
+    for (int x = 0; x < kXcds; ++x) m = std::max(m, ceil_div(xs.off[x + 1] - xs.off[x], per));
+    return (unsigned)(m * kXcds);
+}
+
 template <int NB>
-static void launch_class(int cls, dim3 grid, hipStream_t st, const BlockDesc *blocks, const int2 *items,
-                         int64_t n_items, int k, float dt, float a0, const float *pump) {
+static void launch_class(int cls, hipStream_t st, const BlockDesc *blocks, const int2 *items, const XcdSplit &xs,
+                         int k, float dt, float a0, const float *pump) {
 #define QH_CLS(KD, DTV)                                                                                  \
-    hipLaunchKernelGGL((k_batched_step<KD, DTV, NB>), grid, dim3(256), 0, st, blocks, items, n_items, k, dt, \
-                       a0, pump)
+    hipLaunchKernelGGL((k_batched_step<KD, DTV, NB>), dim3(xcd_grid(xs, 1)), dim3(256), 0, st, blocks, items, xs, \
+                       k, dt, a0, pump)
 #define QH_RT(DTV)                                                                                           \
-    hipLaunchKernelGGL((k_batched_rowtile<DTV, NB>), dim3((unsigned)ceil_div(n_items, 4)), dim3(256), 0, st,     \
-                       blocks, items, n_items, k, dt, a0, pump)
+    hipLaunchKernelGGL((k_batched_rowtile<DTV, NB>), dim3(xcd_grid(xs, 4)), dim3(256), 0, st, blocks, items, xs, \
+                       k, dt, a0, pump)
     switch (cls) {
         case 0: QH_CLS(0, QH_F32); break;
         case 1: QH_RT(QH_F16); break;
@@ -905,16 +916,15 @@ static void launch_class(int cls, dim3 grid, hipStream_t st, const BlockDesc *bl
 }
 
 void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, const int64_t *class_ptr,
-                          int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st) {
+                          const XcdSplit *splits, int steps, float dt, float a0, const float *pump, uint64_t seed,
+                          hipStream_t st) {
 #define QH_BSTEPS(NBV)                                                                                    \
     do {                                                                                                  \
         hipLaunchKernelGGL(k_batched_init<NBV>, dim3(nb), dim3(256), 0, st, blocks, seed);               \
         for (int k = 0; k < steps; ++k)                                                                  \
-            for (int c = 0; c < kBatchClasses; ++c) {                                                    \
-                const int64_t m = class_ptr[c + 1] - class_ptr[c];                                       \
-                if (m) launch_class<NBV>(c, dim3((unsigned)m), st, blocks, items + class_ptr[c], m, k, dt, a0, \
-                                         pump);                                                          \
-            }                                                                                            \
+            for (int c = 0; c < kBatchClasses; ++c)                                                      \
+                if (class_ptr[c + 1] > class_ptr[c])                                                     \
+                    launch_class<NBV>(c, st, blocks, items + class_ptr[c], splits[c], k, dt, a0, pump);  \
     } while (0)
     switch (R) {
         case 16: QH_BSTEPS(1); break;

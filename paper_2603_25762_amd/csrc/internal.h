@@ -337,8 +337,16 @@ int batched_workers_per_cu(int R);
 // work items (x = block, y = row tile of a dense block or group of four band blocks);
 // class c's items are items[class_ptr[c] .. class_ptr[c + 1])
 constexpr int kBatchClasses = 7;   // dense F32/F16/BF16/FP8, band F32/F16/BF16
+// The items of one class split into one list per XCD: XCD x (the XCD that runs workgroup
+// blockIdx.x when blockIdx.x % 8 == x) works through items [off[x], off[x + 1]) of the
+// class, in order.  Whole blocks go to one XCD (their x copy stays in that XCD's L2).
+constexpr int kXcds = 8;
+struct XcdSplit {
+    int64_t off[kXcds + 1];
+};
 void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, const int64_t *class_ptr,
-                          int steps, float dt, float a0, const float *pump, uint64_t seed, hipStream_t st);
+                          const XcdSplit *splits, int steps, float dt, float a0, const float *pump, uint64_t seed,
+                          hipStream_t st);
 // SplitMix64 (Steele, Lea & Flood 2014): the k-th output of the generator seeded with seed
 __device__ inline uint64_t sm64_draw(uint64_t seed, uint64_t k) {
     uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
