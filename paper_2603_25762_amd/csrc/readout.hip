@@ -45,6 +45,49 @@ __device__ inline void cut_rows_body(int64_t bx, int64_t gx, int64_t n_ord, int 
                                      const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                      const double *__restrict__ val, const int8_t *__restrict__ s,
                                      double *__restrict__ rowcut) {
+    if (R % 8 == 0) {
+        // eight replicas per thread: one 8-byte spin gather per entry serves all eight, and
+        // each replica's sum takes the entries in CSR order as below
+        const int G = R / 8;
+        QH_FOR(t, n_ord * G) {
+            const int64_t v = t / G;
+            const int g8 = (int)(t - v * G);
+            const int64_t a = order[v];
+            int8_t sa[8];
+            __builtin_memcpy(sa, s + a * R + 8 * g8, 8);
+            double racc[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) racc[q] = 0.0;
+            int64_t e = ptr[a];
+            const int64_t e1 = ptr[a + 1];
+            for (; e + 8 <= e1; e += 8) {
+                int32_t c[8];
+                double w[8];
+                uint2 sb[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) { c[k] = col[e + k]; w[k] = val[e + k]; }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sb[k] = *(const uint2 *)(s + (int64_t)c[k] * R + 8 * g8);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    int8_t b8[8];
+                    __builtin_memcpy(b8, &sb[k], 8);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) racc[q] += -w[k] * (1.0 - (double)(sa[q] * b8[q]));
+                }
+            }
+            for (; e < e1; ++e) {
+                int8_t b8[8];
+                __builtin_memcpy(b8, s + (int64_t)col[e] * R + 8 * g8, 8);
+                const double w = val[e];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) racc[q] += -w * (1.0 - (double)(sa[q] * b8[q]));
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) rowcut[v * R + 8 * g8 + q] = racc[q];
+        }
+        return;
+    }
     QH_FOR(t, n_ord * R) {
         const int64_t v = t / R;
         const int r = (int)(t - v * R);
@@ -207,6 +250,9 @@ __device__ inline void apply_flips_body(int64_t bx, int64_t gx, int64_t n, const
 
 #undef QH_FOR
 
+// threads per vertex of cut_rows_body: one per eight replicas when R is a multiple of 8
+static inline int64_t rows_threads(int R) { return R % 8 == 0 ? R / 8 : R; }
+
 // ----------------------------------------------------------------------------- single graph
 
 #define QH_G blockIdx.x, gridDim.x
@@ -332,7 +378,8 @@ void readout(const ReadoutView &g, SolvePlan &p, int R, const float *xfin, const
     // FP64 cuts per replica and component
     const int64_t nc = g.n_comp;
     if (nc) {
-        hipLaunchKernelGGL(k_cut_rows, dim3(grid_for(g.n_ord * R)), dim3(256), 0, st, g.n_ord, R, g.comp_order,
+        hipLaunchKernelGGL(k_cut_rows, dim3(grid_for(g.n_ord * rows_threads(R))), dim3(256), 0, st, g.n_ord, R,
+                           g.comp_order,
                            g.m_ptr, g.m_col, g.m_val, p.spins.p, p.rowcut.p);
         hipLaunchKernelGGL(k_cut_chunks, dim3(grid_for(g.n_chunks * R)), dim3(256), 0, st, g.n_chunks, R,
                            g.chunk_begin, g.chunk_end, p.rowcut.p, p.part.p);
@@ -529,7 +576,7 @@ void readout_batched(const std::vector<ReadoutDesc> &descs, int R, bool greedy, 
         for (int b = 0; b < nb; ++b) w[b + 1] = w[b] + work(descs[b]);
     };
     fill(kSigns, [&](const ReadoutDesc &d) { return grid_for(d.n * R); });
-    fill(kRowsR, [&](const ReadoutDesc &d) { return grid_for(d.n_ord * R); });
+    fill(kRowsR, [&](const ReadoutDesc &d) { return grid_for(d.n_ord * rows_threads(R)); });
     fill(kChunksR, [&](const ReadoutDesc &d) { return grid_for(d.n_chunks * R); });
     fill(kReduce, [&](const ReadoutDesc &d) { return (int)std::max<int64_t>(1, std::min<int64_t>(d.n_comp, 1 << 20)); });
     fill(kComp, [&](const ReadoutDesc &d) { return grid_for(d.n_comp); });
