@@ -91,7 +91,11 @@ def kernel_source_hash(kernel):
         h.update(_section(src, "struct StepArgs", "// skyline band + long-range CSR").encode())
         if kernel.startswith("k_band_step") or kernel.startswith("k_lr_packets") or "band" in kernel:
             h.update(_section(src, "// skyline band + long-range CSR", "// batched blocks:").encode())
-        if kernel.startswith("k_batched"):
+        if kernel.startswith("k_batched_rowtile"):
+            # the whole-row-tile product and its kernel (the launch code around them is not part)
+            h.update(_section(src, "// Product of S 16-row strips", "__global__ __launch_bounds__(256) void "
+                                                                      "k_batched_init").encode())
+        elif kernel.startswith("k_batched"):
             h.update(_section(src, "// batched blocks:", "// host orchestration").encode())
     h.update(open(os.path.join(csrc, "formats.h"), "rb").read())
     return h.hexdigest()[:16]

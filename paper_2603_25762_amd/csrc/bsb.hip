@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "formats.h"
@@ -915,25 +916,79 @@ static void launch_class(int cls, hipStream_t st, const BlockDesc *blocks, const
 #undef QH_CLS
 }
 
+// Side stream of a device for the SNP band classes of a batched solve (default priority,
+// non-blocking), with the two events that fork it from and join it to the caller's stream;
+// one set per device, created once and kept for the life of the process (a captured graph
+// may refer to them until it is instantiated).
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+static SideStream &side_stream(int dev) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static SideStream sides[kMaxDevices];
+    if (dev < 0 || dev >= kMaxDevices) fail(QH_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(mu);
+    SideStream &s = sides[dev];
+    if (!s.stream) {
+        QH_HIP(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
+        QH_HIP(hipEventCreateWithFlags(&s.join, hipEventDisableTiming));
+        QH_HIP(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+    }
+    return s;
+}
+
+// The dense classes (bound by HBM bandwidth) and the band classes (bound by load latency)
+// touch disjoint blocks, so their step chains run concurrently: the band classes go to a
+// side stream forked from `st` after the initial state and joined back before return (a
+// capture of `st` records the same fork and join as two parallel chains).  Each block's
+// launches stay in step order on its own stream, so the results do not depend on it.
 void launch_batched_steps(int R, int nb, const BlockDesc *blocks, const int2 *items, const int64_t *class_ptr,
                           const XcdSplit *splits, int steps, float dt, float a0, const float *pump, uint64_t seed,
                           hipStream_t st) {
+    bool dense = false, band = false;
+    for (int c = 0; c < kBatchClasses; ++c)
+        if (class_ptr[c + 1] > class_ptr[c]) (c < 4 ? dense : band) = true;
+    const bool fork = dense && band && steps > 0;
+    hipStream_t sb = st;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    if (fork) {
+        int dev = 0;
+        QH_HIP(hipGetDevice(&dev));
+        SideStream &side = side_stream(dev);
+        sb = side.stream;
+        ev_fork = side.fork;
+        ev_join = side.join;
+    }
+    {
 #define QH_BSTEPS(NBV)                                                                                    \
     do {                                                                                                  \
         hipLaunchKernelGGL(k_batched_init<NBV>, dim3(nb), dim3(256), 0, st, blocks, seed);               \
+        QH_CHECK_LAUNCH();                                                                                \
+        if (fork) {                                                                                       \
+            QH_HIP(hipEventRecord(ev_fork, st));                                                          \
+            QH_HIP(hipStreamWaitEvent(sb, ev_fork, 0));                                                   \
+        }                                                                                                 \
         for (int k = 0; k < steps; ++k)                                                                  \
             for (int c = 0; c < kBatchClasses; ++c)                                                      \
                 if (class_ptr[c + 1] > class_ptr[c])                                                     \
-                    launch_class<NBV>(c, st, blocks, items + class_ptr[c], splits[c], k, dt, a0, pump);  \
+                    launch_class<NBV>(c, c < 4 ? st : sb, blocks, items + class_ptr[c], splits[c], k, dt, a0, \
+                                      pump);                                                             \
+        if (fork) {                                                                                       \
+            QH_HIP(hipEventRecord(ev_join, sb));                                                          \
+            QH_HIP(hipStreamWaitEvent(st, ev_join, 0));                                                   \
+        }                                                                                                 \
     } while (0)
-    switch (R) {
-        case 16: QH_BSTEPS(1); break;
-        case 32: QH_BSTEPS(2); break;
-        case 64: QH_BSTEPS(4); break;
-        default: fail(QH_EUNSUPPORTED, "batched solves take 16, 32 or 64 replicas");
-    }
+        switch (R) {
+            case 16: QH_BSTEPS(1); break;
+            case 32: QH_BSTEPS(2); break;
+            case 64: QH_BSTEPS(4); break;
+            default: fail(QH_EUNSUPPORTED, "batched solves take 16, 32 or 64 replicas");
+        }
 #undef QH_BSTEPS
-    QH_CHECK_LAUNCH();
+        QH_CHECK_LAUNCH();
+    }
 }
 
 void launch_batched(int R, int workers, const BlockDesc *blocks, const int32_t *sched_ptr, const int32_t *sched,

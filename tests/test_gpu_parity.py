@@ -756,16 +756,24 @@ def test_refine_gauge_identity_restore_and_single_round(dtype):
     assert r1["round_cuts"][0] == pytest.approx(float(cpu(rs["best_cut"])[0]), rel=1e-12)
 
 
-def test_refine_adaptive_schedule_planted_twin():
-    """The size-adaptive settings end to end on an error-free planted twin: 500 steps below
-    5,000 vertices, 128 replicas, at most 15 rounds; the haplotypes keep at most a few
-    switches (the solver is a heuristic; FP16 storage, 900 SNPs: 2 switches measured)."""
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_refine_adaptive_schedule_planted_twin(dtype):
+    """The size-adaptive settings end to end on an error-free planted twin (500 steps below
+    5,000 vertices, 128 replicas, at most 15 rounds, deformation on) against the oracle's
+    refinement with the same settings, seed and deformation: the applied round cuts agree in
+    total within 0.1 % and the switch errors are equal."""
     w = synth.snp_small(8, n_snp=900, error=0.0)
-    g = gpu_graph(w, "snp_llr", "f16")
+    g = gpu_graph(w, "snp_llr", dtype)
     rr = qh.refine_adaptive(g, seed=2, deform=0.5, deform_tries=2)
-    assert rr["schedule"]["steps"] == 500 and rr["schedule"]["replicas"] == 128
+    sc = rr["schedule"]
+    assert sc["steps"] == 500 and sc["replicas"] == 128 and sc["max_rounds"] == 15
+    assert sc["size"] == g.info()["largest_component"]
     assert 1 <= rr["rounds"] <= 15
-    assert metrics.switch_error(cpu(rr["h1"]), w.truth, cpu(rr["block"])) <= 0.01
+    ro = oracle.refine(oracle_graph(w, "snp_llr"), w.init_h1, sc["replicas"], sc["steps"], seed=2,
+                       max_rounds=sc["max_rounds"], deform=0.5, deform_tries=2)
+    assert _gap(sum(ro["round_cuts"]), sum(rr["round_cuts"])) <= 1e-3
+    assert metrics.switch_error(cpu(rr["h1"]), w.truth, cpu(rr["block"])) == \
+        metrics.switch_error(ro["h1"], w.truth, ro["block"])
 
 
 def test_refine_planted_twin_and_errors():
