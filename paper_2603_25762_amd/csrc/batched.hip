@@ -358,6 +358,7 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
         d.chunk_end = v.chunk_end;
         d.comp_chunk_ptr = v.comp_chunk_ptr;
         d.eps = v.eps;
+        d.integer = g->integer ? 1 : 0;
         d.x = xfin;
         d.y = p.y.p;
         d.spins = p.spins.p;

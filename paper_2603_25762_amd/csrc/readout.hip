@@ -494,7 +494,52 @@ __device__ inline int slice_of(const int32_t *__restrict__ wg, int nb, int64_t &
     return lo;
 }
 
-enum : int { kSigns, kRowsR, kChunksR, kReduce, kComp, kOne, kVert, kRows1, kChunks1, kSlices };
+// Integer weights: FP64 sums of integers (all below 2^53) are exact in any order, so one
+// wave takes one row and its lanes take the entries, with coalesced loads and a tree sum at
+// the end; the result equals the one-thread-per-row loop of gain_body / cut_rows_body bit
+// for bit (no term is -0 in the gain; in the cut a -0 term leaves a +0 sum +0 either way).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// rows [0, n_rows) of a slice, one per wave: a = order ? order[v] : v;
+// out[v] = pre(a) * sum_j -w_j t(s_a, s_j) with t = s_j (gain) or 1 - s_a s_j (cut)
+template <bool GAIN>
+__device__ inline void rows_wave_body(int64_t bx, int64_t gx, int64_t n_rows, const int32_t *__restrict__ order,
+                                      const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                      const double *__restrict__ val, const int8_t *__restrict__ s,
+                                      double *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t v = bx * 4 + wave; v < n_rows; v += gx * 4) {
+        const int64_t a = order ? order[v] : v;
+        const int sa = s[a];
+        const int64_t e1 = ptr[a + 1];
+        double acc = 0.0;
+        for (int64_t e = ptr[a] + lane; e < e1; e += 4 * 64) {   // four entries per lane in flight
+            int32_t c[4];
+            double w[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t ek = e + 64 * k;
+                c[k] = ek < e1 ? col[ek] : 0;
+                w[k] = ek < e1 ? val[ek] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (e + 64 * k >= e1) break;
+                const int sb = s[c[k]];
+                acc += GAIN ? -w[k] * (double)sb : -w[k] * (1.0 - (double)(sa * sb));
+            }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) out[v] = GAIN ? (double)sa * acc : acc;
+    }
+}
+
+enum : int { kSigns, kRowsR, kChunksR, kReduce, kComp, kOne, kVert, kRows1, kChunks1, kGain, kSlices };
 
 #define QH_B(slice)                                     \
     int64_t bx, gx;                                     \
@@ -508,6 +553,10 @@ __global__ void kb_signs(const ReadoutDesc *tbl, const int32_t *wg, int nb, int 
 __global__ void kb_cut_rows(const ReadoutDesc *tbl, const int32_t *wg, int nb, int R, int final_cut) {
     QH_B(final_cut ? kRows1 : kRowsR);
     if (D.n_comp == 0) return;
+    if (final_cut && D.integer) {
+        rows_wave_body<false>(bx, gx, D.n_ord, D.comp_order, D.m_ptr, D.m_col, D.m_val, D.best_spins, D.rowcut);
+        return;
+    }
     cut_rows_body(bx, gx, D.n_ord, final_cut ? 1 : R, D.comp_order, D.m_ptr, D.m_col, D.m_val,
                   final_cut ? D.best_spins : D.spins, D.rowcut);
 }
@@ -548,8 +597,12 @@ __global__ void kb_best_spins(const ReadoutDesc *tbl, const int32_t *wg, int nb,
     best_spins_body(bx, gx, D.n, R, D.comp, D.comp_first, D.best_r, D.spins, D.best_spins);
 }
 __global__ void kb_gain(const ReadoutDesc *tbl, const int32_t *wg, int nb) {
-    QH_B(kVert);
+    QH_B(kGain);
     if (D.n_comp == 0) return;
+    if (D.integer) {
+        rows_wave_body<true>(bx, gx, D.n, nullptr, D.m_ptr, D.m_col, D.m_val, D.best_spins, D.gain);
+        return;
+    }
     gain_body(bx, gx, D.n, D.m_ptr, D.m_col, D.m_val, D.best_spins, D.gain);
 }
 __global__ void kb_pick(const ReadoutDesc *tbl, const int32_t *wg, int nb, int32_t *count) {
@@ -582,7 +635,9 @@ void readout_batched(const std::vector<ReadoutDesc> &descs, int R, bool greedy, 
     fill(kComp, [&](const ReadoutDesc &d) { return grid_for(d.n_comp); });
     fill(kOne, [&](const ReadoutDesc &) { return 1; });
     fill(kVert, [&](const ReadoutDesc &d) { return grid_for(d.n); });
-    fill(kRows1, [&](const ReadoutDesc &d) { return grid_for(d.n_ord); });
+    // the integer blocks' R = 1 row sums take one wave per row (four rows per workgroup)
+    fill(kRows1, [&](const ReadoutDesc &d) { return d.integer ? grid_for(d.n_ord, 4) : grid_for(d.n_ord); });
+    fill(kGain, [&](const ReadoutDesc &d) { return d.integer ? grid_for(d.n, 4) : grid_for(d.n); });
     fill(kChunks1, [&](const ReadoutDesc &d) { return grid_for(d.n_chunks); });
     auto total = [&](int slice) { return (unsigned)wg[(size_t)slice * (nb + 1) + nb]; };
     DevBuf<ReadoutDesc> d_tbl(nb);
@@ -604,7 +659,7 @@ void readout_batched(const std::vector<ReadoutDesc> &descs, int R, bool greedy, 
     QH_CHECK_LAUNCH();
     if (greedy) {
         for (int it = 0; it < 100000; ++it) {
-            hipLaunchKernelGGL(kb_gain, dim3(total(kVert)), dim3(256), 0, st, T, W, nb);
+            hipLaunchKernelGGL(kb_gain, dim3(total(kGain)), dim3(256), 0, st, T, W, nb);
             QH_HIP(hipMemsetAsync(d_cnt.p, 0, sizeof(int32_t), st));
             hipLaunchKernelGGL(kb_pick, dim3(total(kVert)), dim3(256), 0, st, T, W, nb, d_cnt.p);
             QH_CHECK_LAUNCH();
