@@ -206,14 +206,32 @@ BATCH_R, BATCH_STEPS, BATCH_DT, BATCH_SEED = 32, 500, 0.5, 11
 BATCH_CPU_SAMPLE = (0, 5)       # oracle sample: the stratified subset's blocks 0, 5, 10, ...
 
 
-def build_batch(qh, batch, dtype=None, alpha_for_reads=False):
-    gs = []
-    for i, w in enumerate(batch.blocks):
-        d = {k: qh.to_device(v) for k, v in w.arrays().items()}
+def batch_inputs(qh, batch):
+    """Every block's fragment arrays on the device from one host-to-device copy per array
+    kind: the blocks' arrays are views into the concatenation."""
+    import numpy as np
+    names = ("frag_ptr", "snp", "allele", "phred", "alpha", "init_h1")
+    arrs = [w.arrays() for w in batch.blocks]
+    views = [dict() for _ in arrs]
+    for k in names:
+        parts = [np.ascontiguousarray(a[k]) for a in arrs]
+        off = np.concatenate([[0], np.cumsum([p.size for p in parts])]).astype(np.int64)
+        dev = qh.to_device(np.concatenate(parts))
+        for b in range(len(arrs)):
+            views[b][k] = dev[int(off[b]):int(off[b + 1])]
+    return views
+
+
+def build_batch(qh, batch, dtype=None):
+    """The batch's graphs (even blocks read graphs, odd blocks SNP graphs), built together by
+    qh_build_graphs."""
+    specs = []
+    for i, (w, d) in enumerate(zip(batch.blocks, batch_inputs(qh, batch))):
         kind = "read_signed" if i % 2 == 0 else "snp_llr"
-        gs.append(qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind=kind,
-                                 dtype=dtype or w.solve["dtype"], alpha=d["alpha"] if kind == "snp_llr" else None))
-    return gs
+        specs.append(dict(frag_ptr=d["frag_ptr"], snp=d["snp"], allele=d["allele"], phred=d["phred"],
+                          init_h1=d["init_h1"], kind=kind, dtype=dtype or w.solve["dtype"],
+                          alpha=d["alpha"] if kind == "snp_llr" else None))
+    return qh.build_graphs(specs)
 
 
 def batch_gaps(qh, gs, r, batch, ref):
@@ -344,14 +362,17 @@ def bench_batched(a):
 
 def time_to_phase_batched(qh, batch, R, STEPS, DT, SEED):
     """Host fragments in -> haplotypes out for the whole batch: H2D of every block's
-    fragments, graph builds, the batched solve, the phasing of every block, D2H."""
+    fragments (one copy per array kind), the graph builds (qh_build_graphs), the batched
+    solve, the phasing of every block, D2H."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gs = build_batch(qh, batch)
     r = qh.bsb_solve_batched(gs, R, STEPS, dt=DT, seed=SEED)
     off = r["vertex_offset"]
-    outs = [qh.phase(g, r["best_spins"][int(off[b]):int(off[b + 1])]) for b, g in enumerate(gs)]
+    # qh_phase_noalloc: its counters live in the library's static scratch, so the calls (one
+    # stream, in order) need no allocation and no synchronisation each
+    outs = [qh.phase(g, r["best_spins"][int(off[b]):int(off[b + 1])], noalloc=True) for b, g in enumerate(gs)]
     h1 = torch.cat([o[0] for o in outs]).cpu()
     blk = torch.cat([o[1] for o in outs]).cpu()
     ms = (time.perf_counter() - t0) * 1e3

@@ -5,7 +5,8 @@
  * Max-Cut and solving the Ising form with ballistic simulated bifurcation
  * (bSB).  This library implements that path on one GPU:
  *
- *   qh_build_graph  reads + SNPs  -> coupling matrix J      (Methods, graph construction)
+ *   qh_build_graph  reads + SNPs  -> coupling matrix J      (Methods, graph construction;
+ *                                                              qh_build_graphs: many at once)
  *   qh_bsb_solve    J             -> spins, FP64 cuts        (Methods, SB algorithm solution)
  *   qh_phase        J, spins      -> haplotype 1 per SNP     (Methods, consistency processing /
  *                                                              SNP-based parity reconstruction)
@@ -21,6 +22,8 @@
  *    Work is stream-ordered; device outputs are valid once the stream has
  *    synchronised.  Calls that must read back a count (graph build, the greedy
  *    pass) synchronise the stream themselves and say so.
+ *  - The library recycles its device temporaries in stream order: make its calls from
+ *    one host thread at a time (qh_build_graphs runs host threads of its own inside).
  *  - Spin / momentum state is laid out [n][R] (replica index fastest), FP32.
  *  - Ising convention (Eqs. 4-6): E(s) = -1/2 s^T J s, A = -J, and
  *    cut(s) = 1/4 sum_{a,b} A_ab (1 - s_a s_b).
@@ -148,6 +151,21 @@ typedef struct {
  * exceed opts->max_device_bytes), EHIP. */
 qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_graph_opts *opts,
                          qh_graph **out, void *stream);
+
+/* Builds `count` graphs (Methods, as qh_build_graph for each): reads[i], snps[i] and
+ * opts[i] describe graph i, out[i] receives it.  Host threads (`threads`, 0 = 8, at
+ * most 64) take the graphs in index order, each building on a stream of its own, so
+ * that the synchronisations inside one build overlap the work of the others; the
+ * result is the same as count calls of qh_build_graph.  The device is synchronised first
+ * (the fragment arrays may be written on `stream`); every graph is complete on return.
+ * No other call of the library may run on another host thread meanwhile.
+ * On failure no graph is returned (out is left untouched, graphs already built are
+ * freed), the status is that of a graph that failed and qh_last_error names its index;
+ * building stops early.  The caller owns the graphs (qh_graph_free each).  Errors as for qh_build_graph, and
+ * EINVAL for count < 0 or threads outside 0..64. */
+qh_status qh_build_graphs(int64_t count, const qh_reads *reads, const qh_snps *snps,
+                          const qh_graph_opts *opts, qh_graph **out, int32_t threads,
+                          void *stream);
 
 qh_status qh_graph_free(qh_graph *g);
 qh_status qh_graph_get_info(const qh_graph *g, qh_graph_info *out);

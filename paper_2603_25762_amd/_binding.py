@@ -5,7 +5,7 @@ import ctypes
 import enum
 import json
 import os
-from typing import Dict, Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -116,6 +116,8 @@ def load():
     sig = {
         "qh_build_graph": [ctypes.POINTER(_Reads), ctypes.POINTER(_Snps), ctypes.POINTER(_GraphOpts),
                            ctypes.POINTER(P), P],
+        "qh_build_graphs": [ctypes.c_int64, ctypes.POINTER(_Reads), ctypes.POINTER(_Snps),
+                            ctypes.POINTER(_GraphOpts), ctypes.POINTER(P), ctypes.c_int32, P],
         "qh_graph_free": [P],
         "qh_graph_get_info": [P, ctypes.POINTER(_GraphInfo)],
         "qh_graph_export_rows": [P, ctypes.c_int64, ctypes.c_int64, P, P],
@@ -233,12 +235,11 @@ class Graph:
             pass
 
 
-def build_graph(frag_ptr: torch.Tensor, snp: torch.Tensor, allele: torch.Tensor,
+def _build_args(frag_ptr: torch.Tensor, snp: torch.Tensor, allele: torch.Tensor,
                 phred: Optional[torch.Tensor], init_h1: torch.Tensor, *, kind: str = "read_signed",
                 storage: Optional[str] = None, dtype: str = "f32",
                 alpha: Optional[torch.Tensor] = None, linkage_k: int = 10,
-                band_limit: int = 0, max_device_bytes: int = 0, deterministic: bool = False,
-                stream=None) -> Graph:
+                band_limit: int = 0, max_device_bytes: int = 0, deterministic: bool = False):
     if storage is None:
         storage = "skyline" if kind == "snp_llr" else "dense"
     for t, dt in ((frag_ptr, torch.int64), (snp, torch.int32), (allele, torch.uint8),
@@ -254,10 +255,39 @@ def build_graph(frag_ptr: torch.Tensor, snp: torch.Tensor, allele: torch.Tensor,
     snps = _Snps(init_h1.numel(), _ptr(init_h1))
     opts = _GraphOpts(KIND[kind], STORAGE[storage], DTYPE[dtype], linkage_k, band_limit, max_device_bytes,
                       int(deterministic))
+    return reads, snps, opts
+
+
+def build_graph(frag_ptr: torch.Tensor, snp: torch.Tensor, allele: torch.Tensor,
+                phred: Optional[torch.Tensor], init_h1: torch.Tensor, *, kind: str = "read_signed",
+                storage: Optional[str] = None, dtype: str = "f32",
+                alpha: Optional[torch.Tensor] = None, linkage_k: int = 10,
+                band_limit: int = 0, max_device_bytes: int = 0, deterministic: bool = False,
+                stream=None) -> Graph:
+    reads, snps, opts = _build_args(frag_ptr, snp, allele, phred, init_h1, kind=kind, storage=storage,
+                                    dtype=dtype, alpha=alpha, linkage_k=linkage_k, band_limit=band_limit,
+                                    max_device_bytes=max_device_bytes, deterministic=deterministic)
     h = ctypes.c_void_p()
     _check(load().qh_build_graph(ctypes.byref(reads), ctypes.byref(snps), ctypes.byref(opts),
                                  ctypes.byref(h), _stream(stream)))
     return Graph(h.value)
+
+
+def build_graphs(specs: Sequence[Dict[str, object]], *, threads: int = 0, stream=None) -> List[Graph]:
+    """Many graphs in one call (qh_build_graphs, host threads each on a stream of its own).
+    ``specs``: one dict of build_graph's arguments per graph (frag_ptr, snp, allele, phred,
+    init_h1 and any of its keyword arguments but stream)."""
+    n = len(specs)
+    if n == 0:
+        return []
+    reads = (_Reads * n)()
+    snps = (_Snps * n)()
+    opts = (_GraphOpts * n)()
+    for i, sp in enumerate(specs):
+        reads[i], snps[i], opts[i] = _build_args(**sp)
+    out = (ctypes.c_void_p * n)()
+    _check(load().qh_build_graphs(n, reads, snps, opts, out, threads, _stream(stream)))
+    return [Graph(out[i]) for i in range(n)]
 
 
 def _check_field(field: Optional[torch.Tensor], n: int):

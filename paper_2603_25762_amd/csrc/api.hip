@@ -5,6 +5,10 @@
 #include <new>
 
 #include <atomic>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "internal.h"
 
@@ -59,49 +63,135 @@ extern "C" {
 const char *qh_last_error(void) { return g_err; }
 const char *qh_version(void) { return "qhap-gfx950 0.1.0"; }
 
+}  // extern "C"
+
+namespace qh {
+
+// Validation and build of one graph on stream st (synchronised on return).
+static qh_graph *build_one(const qh_reads *reads, const qh_snps *snps, const qh_graph_opts *opts, hipStream_t st) {
+    if (reads->n_frag < 0) fail(QH_EINVAL, "n_frag < 0");
+    if (snps->n_snp < 0) fail(QH_EINVAL, "n_snp < 0");
+    if (reads->n_frag > 0 && (!reads->frag_ptr || !reads->snp || !reads->allele))
+        fail(QH_EINVAL, "null fragment array");
+    if (snps->n_snp > 0 && !snps->init_h1) fail(QH_EINVAL, "null init_h1");
+    if (opts->kind < QH_READ_CONFLICT || opts->kind > QH_SNP_LLR) fail(QH_EINVAL, "bad kind");
+    if (opts->storage < QH_STORE_DENSE || opts->storage > QH_STORE_SKYLINE)
+        fail(QH_EINVAL, "bad storage");
+    if (opts->dtype < QH_F32 || opts->dtype > QH_FP8_ROWSCALE) fail(QH_EINVAL, "bad dtype");
+    bool read_kind = opts->kind != QH_SNP_LLR;
+    if (read_kind && opts->storage != QH_STORE_DENSE)
+        fail(QH_EUNSUPPORTED, "read graphs use DENSE storage");
+    if (!read_kind && opts->storage != QH_STORE_SKYLINE)
+        fail(QH_EUNSUPPORTED, "SNP graphs use SKYLINE storage");
+    if (!read_kind && opts->dtype == QH_FP8_ROWSCALE)
+        fail(QH_EUNSUPPORTED, "FP8 row scales are offered on dense storage only");
+    if (!read_kind && opts->kind == QH_SNP_LLR && reads->n_frag > 0 && !reads->phred)
+        fail(QH_EINVAL, "SNP graphs need phred");
+    if (!read_kind && (opts->linkage_k < 1 || opts->linkage_k > 10))
+        fail(QH_EINVAL, "linkage_k must be in 1..10");
+    if (opts->band_limit < 0) fail(QH_EINVAL, "band_limit < 0");
+    if (opts->max_device_bytes < 0) fail(QH_EINVAL, "max_device_bytes < 0");
+    std::unique_ptr<qh_graph> g(new qh_graph());
+    static std::atomic<uint64_t> next_serial{1};
+    g->serial = next_serial.fetch_add(1);
+    QH_HIP(hipGetDevice(&g->device));
+    g->kind = opts->kind;
+    g->storage = opts->storage;
+    g->dtype = opts->dtype;
+    g->n_snp = snps->n_snp;
+    g->max_bytes = opts->max_device_bytes;
+    if (opts->deterministic != 0 && opts->deterministic != 1) fail(QH_EINVAL, "deterministic must be 0 or 1");
+    g->deterministic = opts->deterministic;
+    if (read_kind) build_read_graph(g.get(), reads, snps, st);
+    else build_snp_graph(g.get(), reads, snps, opts->linkage_k, opts->band_limit, st);
+    finalize_graph(g.get(), st);
+    QH_HIP(hipStreamSynchronize(st));
+    return g.release();
+}
+
+}  // namespace qh
+
+extern "C" {
+
 qh_status qh_build_graph(const qh_reads *reads, const qh_snps *snps, const qh_graph_opts *opts,
                          qh_graph **out, void *stream) {
     return guarded([&] {
         if (!reads || !snps || !opts || !out) fail(QH_EINVAL, "null argument");
-        if (reads->n_frag < 0) fail(QH_EINVAL, "n_frag < 0");
-        if (snps->n_snp < 0) fail(QH_EINVAL, "n_snp < 0");
-        if (reads->n_frag > 0 && (!reads->frag_ptr || !reads->snp || !reads->allele))
-            fail(QH_EINVAL, "null fragment array");
-        if (snps->n_snp > 0 && !snps->init_h1) fail(QH_EINVAL, "null init_h1");
-        if (opts->kind < QH_READ_CONFLICT || opts->kind > QH_SNP_LLR) fail(QH_EINVAL, "bad kind");
-        if (opts->storage < QH_STORE_DENSE || opts->storage > QH_STORE_SKYLINE)
-            fail(QH_EINVAL, "bad storage");
-        if (opts->dtype < QH_F32 || opts->dtype > QH_FP8_ROWSCALE) fail(QH_EINVAL, "bad dtype");
-        bool read_kind = opts->kind != QH_SNP_LLR;
-        if (read_kind && opts->storage != QH_STORE_DENSE)
-            fail(QH_EUNSUPPORTED, "read graphs use DENSE storage");
-        if (!read_kind && opts->storage != QH_STORE_SKYLINE)
-            fail(QH_EUNSUPPORTED, "SNP graphs use SKYLINE storage");
-        if (!read_kind && opts->dtype == QH_FP8_ROWSCALE)
-            fail(QH_EUNSUPPORTED, "FP8 row scales are offered on dense storage only");
-        if (!read_kind && opts->kind == QH_SNP_LLR && reads->n_frag > 0 && !reads->phred)
-            fail(QH_EINVAL, "SNP graphs need phred");
-        if (!read_kind && (opts->linkage_k < 1 || opts->linkage_k > 10))
-            fail(QH_EINVAL, "linkage_k must be in 1..10");
-        if (opts->band_limit < 0) fail(QH_EINVAL, "band_limit < 0");
-        if (opts->max_device_bytes < 0) fail(QH_EINVAL, "max_device_bytes < 0");
-        hipStream_t st = (hipStream_t)stream;
-        std::unique_ptr<qh_graph> g(new qh_graph());
-        static std::atomic<uint64_t> next_serial{1};
-        g->serial = next_serial.fetch_add(1);
-        QH_HIP(hipGetDevice(&g->device));
-        g->kind = opts->kind;
-        g->storage = opts->storage;
-        g->dtype = opts->dtype;
-        g->n_snp = snps->n_snp;
-        g->max_bytes = opts->max_device_bytes;
-        if (opts->deterministic != 0 && opts->deterministic != 1) fail(QH_EINVAL, "deterministic must be 0 or 1");
-        g->deterministic = opts->deterministic;
-        if (read_kind) build_read_graph(g.get(), reads, snps, st);
-        else build_snp_graph(g.get(), reads, snps, opts->linkage_k, opts->band_limit, st);
-        finalize_graph(g.get(), st);
-        QH_HIP(hipStreamSynchronize(st));
-        *out = g.release();
+        *out = build_one(reads, snps, opts, (hipStream_t)stream);
+    });
+}
+
+qh_status qh_build_graphs(int64_t count, const qh_reads *reads, const qh_snps *snps, const qh_graph_opts *opts,
+                          qh_graph **out, int32_t threads, void *stream) {
+    return guarded([&] {
+        if (count < 0) fail(QH_EINVAL, "count < 0");
+        if (threads < 0 || threads > 64) fail(QH_EINVAL, "threads must be in 0..64");
+        if (count == 0) return;
+        if (!reads || !snps || !opts || !out) fail(QH_EINVAL, "null argument");
+        std::vector<qh_graph *> built((size_t)count, nullptr);   // out is written on success only
+        const int nt = (int)std::min<int64_t>(threads ? threads : 8, count);
+        int dev = 0;
+        QH_HIP(hipGetDevice(&dev));
+        // inputs may come from the caller's stream; and with all queued work done, every block
+        // of the shared device-memory pool may serve any worker's stream
+        (void)stream;
+        QH_HIP(hipDeviceSynchronize());
+        std::atomic<int64_t> next{0};
+        std::atomic<bool> stop{false};
+        std::mutex mu;
+        qh_status first = QH_OK;
+        std::string msg;
+        auto record = [&](qh_status st, int64_t i) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (first == QH_OK) {
+                first = st;
+                msg = i >= 0 ? "graph " + std::to_string(i) + ": " + qh_last_error() : std::string(qh_last_error());
+            }
+            stop = true;
+        };
+        // Each worker builds on a stream of its own, so that one build's synchronisations
+        // overlap the others' work; the graphs are picked in index order.  A worker's
+        // temporaries are recycled through a device-memory pool of its own (stream-ordered
+        // reuse), which joins the shared pool once its stream is idle.
+        auto worker = [&]() {
+            hipStream_t ws = nullptr;
+            const qh_status st = guarded([&] {
+                QH_HIP(hipSetDevice(dev));
+                QH_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+                set_pool((uintptr_t)ws);
+                for (;;) {
+                    if (stop) break;
+                    const int64_t i = next.fetch_add(1);
+                    if (i >= count) break;
+                    const qh_status si = guarded([&] { built[i] = build_one(reads + i, snps + i, opts + i, ws); });
+                    if (si != QH_OK) {
+                        record(si, i);
+                        break;
+                    }
+                }
+            });
+            if (st != QH_OK) record(st, -1);
+            if (ws) {
+                (void)hipStreamSynchronize(ws);
+                set_pool(0);
+                merge_pool(dev, (uintptr_t)ws);
+                (void)hipStreamDestroy(ws);
+            }
+        };
+        std::vector<std::thread> pool;
+        try {
+            for (int t = 0; t < nt; ++t) pool.emplace_back(worker);
+        } catch (...) {
+            stop = true;
+            for (auto &th : pool) th.join();
+            throw;
+        }
+        for (auto &th : pool) th.join();
+        if (first != QH_OK) {
+            for (qh_graph *g : built) delete g;
+            fail(first, "%s", msg.c_str());
+        }
+        for (int64_t i = 0; i < count; ++i) out[i] = built[i];
     });
 }
 

@@ -35,6 +35,11 @@ void set_error(const char *fmt, ...);
 // Library device memory (memory.hip): size-classed blocks cached per device.
 void *device_alloc(size_t bytes);   // nullptr when the device is out of memory
 void device_free(void *p);
+// Pools of the block cache: the calling thread takes and returns blocks in pool `tag`
+// (0 = the shared pool); merge_pool moves pool `tag` of a device into the shared pool
+// (only once no queued work can still use its blocks).
+void set_pool(uintptr_t tag);
+void merge_pool(int device, uintptr_t tag);
 
 // Owning device buffer.
 template <class T>

@@ -8,6 +8,13 @@
 // is reallocated waits for the device first, and graphs (with their solve plans) are freed
 // only after a device synchronisation.  At most kCacheCap bytes per device stay cached;
 // a failed hipMalloc releases the device's cached blocks and tries once more.
+//
+// That argument holds within one stream.  Host threads that work on streams of their own
+// (the many-graph build) therefore get pools of their own: a thread with a pool tag
+// returns blocks only there, takes them from there first and else from the shared pool
+// (which the many-graph build only opens to its threads after a device synchronisation,
+// with its caller waiting), and its pool joins the shared one once its stream has been
+// synchronised.
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -21,9 +28,11 @@ namespace {
 constexpr size_t kCacheCap = (size_t)4 << 30;
 
 struct DeviceCache {
-    std::multimap<size_t, void *> idle;   // size class -> block
+    std::map<uintptr_t, std::multimap<size_t, void *>> idle;   // pool tag -> size class -> block
     size_t idle_bytes = 0;
 };
+
+thread_local uintptr_t t_pool = 0;   // 0: the shared pool
 
 struct Block {
     int device;
@@ -39,9 +48,10 @@ size_t size_class(size_t bytes) {
     return (bytes + q - 1) / q * q;
 }
 
-void trim(int device) {   // caller holds g_mu
+void trim(int device) {   // caller holds g_mu (hipFree waits for the device's work)
     DeviceCache &c = g_cache[device];
-    for (auto &kv : c.idle) (void)hipFree(kv.second);
+    for (auto &pool : c.idle)
+        for (auto &kv : pool.second) (void)hipFree(kv.second);
     c.idle.clear();
     c.idle_bytes = 0;
 }
@@ -54,13 +64,17 @@ void *device_alloc(size_t bytes) {
     const size_t cls = size_class(bytes == 0 ? 1 : bytes);
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceCache &c = g_cache[dev];
-    auto it = c.idle.find(cls);
-    if (it != c.idle.end()) {
-        void *p = it->second;
-        c.idle.erase(it);
-        c.idle_bytes -= cls;
-        g_live[p] = Block{dev, cls};
-        return p;
+    for (uintptr_t tag : {t_pool, (uintptr_t)0}) {
+        auto &pool = c.idle[tag];
+        auto it = pool.find(cls);
+        if (it != pool.end()) {
+            void *p = it->second;
+            pool.erase(it);
+            c.idle_bytes -= cls;
+            g_live[p] = Block{dev, cls};
+            return p;
+        }
+        if (tag == 0) break;
     }
     void *p = nullptr;
     if (hipMalloc(&p, cls) != hipSuccess) {
@@ -91,8 +105,21 @@ void device_free(void *p) {
         if (cur != b.device) (void)hipSetDevice(cur);
         return;
     }
-    c.idle.emplace(b.cls, p);
+    c.idle[t_pool].emplace(b.cls, p);
     c.idle_bytes += b.cls;
+}
+
+void set_pool(uintptr_t tag) { t_pool = tag; }
+
+void merge_pool(int device, uintptr_t tag) {
+    if (tag == 0) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    DeviceCache &c = g_cache[device];
+    auto it = c.idle.find(tag);
+    if (it == c.idle.end()) return;
+    auto &shared = c.idle[0];
+    for (auto &kv : it->second) shared.emplace(kv.first, kv.second);
+    c.idle.erase(it);
 }
 
 }  // namespace qh

@@ -45,3 +45,14 @@ def test_adaptive_schedule_follows_the_paper():
     with pytest.raises(qh.QhapError) as e:
         qh.adaptive_schedule(-1)
     assert e.value.status == qh.Status.EINVAL
+
+
+def test_build_graphs_validates_on_the_host():
+    """qh_build_graphs rejects a negative count and a thread count outside 0..64 before any
+    device call, and an empty batch is a no-op; the binding returns no graphs for no specs."""
+    lib = qh.load()
+    assert lib.qh_build_graphs(-1, None, None, None, None, 0, None) == qh.Status.EINVAL
+    assert lib.qh_build_graphs(1, None, None, None, None, 65, None) == qh.Status.EINVAL
+    assert lib.qh_build_graphs(1, None, None, None, None, -1, None) == qh.Status.EINVAL
+    assert lib.qh_build_graphs(0, None, None, None, None, 0, None) == qh.Status.OK
+    assert qh.build_graphs([]) == []

@@ -865,6 +865,61 @@ def test_porec_final_cut():
     assert _gap(ro["best_cut"], float(cpu(rg["best_cut"])[0])) <= 1e-3
 
 
+@pytest.mark.parametrize("threads", [0, 1, 5])
+def test_build_graphs_equals_single_builds(threads):
+    """qh_build_graphs (host threads, a stream each) returns the graphs that qh_build_graph
+    builds one by one: equal info, FP64 master and stored rows bit for bit, equal components
+    (deterministic builds: the default SNP build sums Eq. 14 terms with atomics, whose order,
+    and so the last bit, may change from one build to the next).  A malformed block fails
+    the whole call with its index, and no graph is returned."""
+    blocks = [synth.read_small(70 + b, n_snp=200, n_reads=30 + 25 * b) for b in range(6)] + \
+             [synth.snp_small(80 + b, n_snp=120 + 150 * b) for b in range(6)] + [synth.read_tiny()]
+    kinds = ["read_signed"] * 6 + ["snp_llr"] * 6 + ["read_conflict"]
+    dtypes = ["fp8", "f16", "bf16", "f32", "fp8", "f16", "bf16", "f16", "f32", "bf16", "f16", "f32", "f32"]
+    specs = []
+    for w, k, dt in zip(blocks, kinds, dtypes):
+        d = device_reads(w)
+        specs.append(dict(frag_ptr=d["frag_ptr"], snp=d["snp"], allele=d["allele"], phred=d["phred"],
+                          init_h1=d["init_h1"], kind=k, dtype=dt, alpha=d["alpha"], deterministic=True))
+    many = qh.build_graphs(specs, threads=threads)
+    assert len(many) == len(specs)
+    for b, (sp, gm) in enumerate(zip(specs, many)):
+        g1 = qh.build_graph(**sp)
+        assert g1.info() == gm.info(), b
+        n = g1.info()["n"]
+        assert torch.equal(g1.export_rows(0, n), gm.export_rows(0, n)), b
+        assert torch.equal(g1.export_rows(0, n, stored=True), gm.export_rows(0, n, stored=True)), b
+        assert torch.equal(g1.components(), gm.components()), b
+        g1.free()
+    for g in many:
+        g.free()
+    # many small blocks: every worker recycles its temporaries many times over
+    batch = synth.batched_blocks(91, n_blocks=240, n_lo=20, n_hi=300)
+    specs2 = []
+    for i, w in enumerate(batch.blocks):
+        d = device_reads(w)
+        k = "read_signed" if i % 2 == 0 else "snp_llr"
+        specs2.append(dict(frag_ptr=d["frag_ptr"], snp=d["snp"], allele=d["allele"], phred=d["phred"],
+                           init_h1=d["init_h1"], kind=k, dtype=w.solve["dtype"], alpha=d["alpha"],
+                           deterministic=True))
+    many = qh.build_graphs(specs2, threads=threads)
+    for b, (sp, gm) in enumerate(zip(specs2, many)):
+        g1 = qh.build_graph(**sp)
+        assert g1.info() == gm.info(), b
+        n = g1.info()["n"]
+        assert torch.equal(g1.export_rows(0, n, stored=True), gm.export_rows(0, n, stored=True)), b
+        assert torch.equal(g1.components(), gm.components()), b
+        g1.free()
+        gm.free()
+    bad = dict(specs[7])
+    snp = bad["snp"].clone()
+    snp[0] = bad["init_h1"].numel()           # a SNP index past the last SNP
+    bad["snp"] = snp
+    with pytest.raises(qh.QhapError) as e:
+        qh.build_graphs(specs[:7] + [bad] + specs[8:], threads=threads)
+    assert e.value.status == qh.Status.EINVAL and "graph 7" in str(e.value)
+
+
 @pytest.mark.parametrize("R,plan", [(16, 1), (32, 1), (64, 1), (16, 2), (32, 2), (64, 2), (32, 0)])
 def test_batched_matches_single_solves(R, plan):
     """Uneven blocks of every storage and dtype, per-step (1), whole-block (2) or autotuned
