@@ -267,6 +267,66 @@ __global__ void k_read_pairs(int32_t n_cols, const int64_t *__restrict__ cov_ptr
     }
 }
 
+// Rows of Eqs. (2)-(3), one workgroup per fragment p: the row's F counters live in LDS;
+// for every SNP j of p and every fragment q on j's coverage list (q != p) the row adds
+// M_pj M_qj (signed kind) or 1 where the two disagree (conflict kind) with an LDS atomic,
+// then goes out whole, zeros included.  p's observations are taken kRowObs at a time:
+// their coverage lists are concatenated (offsets in LDS) and the items split evenly over
+// the workgroup.  Integer sums, so the order of the additions does not matter.
+constexpr int kRowObs = 256;
+constexpr int64_t kRowLdsMaxF = 36864;   // F int32 counters per workgroup (144 KB of LDS)
+__global__ __launch_bounds__(256) void k_read_rows(int64_t F, const int64_t *__restrict__ fp,
+                                                   const int32_t *__restrict__ snp, const int8_t *__restrict__ M,
+                                                   const int64_t *__restrict__ cov_ptr,
+                                                   const int32_t *__restrict__ cov_frag,
+                                                   const int8_t *__restrict__ cov_M, int32_t *__restrict__ W,
+                                                   int conflict) {
+    extern __shared__ int32_t row[];            // [F]
+    __shared__ int64_t cbeg[kRowObs];           // coverage list of each observation of the chunk
+    __shared__ int32_t coff[kRowObs + 1];       // offsets of the lists in the concatenation
+    __shared__ int8_t cm[kRowObs];              // M_pj
+    const int tid = threadIdx.x;
+    for (int64_t p = blockIdx.x; p < F; p += gridDim.x) {
+        for (int64_t q = tid; q < F; q += 256) row[q] = 0;
+        const int64_t t0 = fp[p], t1 = fp[p + 1];
+        for (int64_t base = t0; base < t1; base += kRowObs) {
+            const int nb = (int)(t1 - base < kRowObs ? t1 - base : kRowObs);
+            if (tid < nb) {
+                const int32_t j = snp[base + tid];
+                const int64_t b = cov_ptr[j];
+                cbeg[tid] = b;
+                coff[tid + 1] = (int32_t)(cov_ptr[j + 1] - b);
+                cm[tid] = M[base + tid];
+            }
+            __syncthreads();    // (also: the zeroed row before the first atomic)
+            if (tid == 0) {
+                coff[0] = 0;
+                for (int k = 0; k < nb; ++k) coff[k + 1] += coff[k];
+            }
+            __syncthreads();
+            const int total = coff[nb];
+            for (int i = tid; i < total; i += 256) {
+                int lo = 0, hi = nb;            // the last observation k with coff[k] <= i
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (coff[mid] <= i) lo = mid;
+                    else hi = mid;
+                }
+                const int64_t c = cbeg[lo] + (i - coff[lo]);
+                const int32_t q = cov_frag[c];
+                if (q == p) continue;
+                const int prod = (int)cm[lo] * (int)cov_M[c];
+                const int v = conflict ? (prod == -1 ? 1 : 0) : prod;
+                if (v) atomicAdd(&row[q], v);
+            }
+            __syncthreads();    // the chunk's tables are read before the next chunk writes them
+        }
+        __syncthreads();
+        for (int64_t q = tid; q < F; q += 256) W[p * F + q] = row[q];
+        __syncthreads();        // the row is written out before the next fragment clears it
+    }
+}
+
 // Nonzero count per row of a dense int32 matrix (one wave per row).
 __global__ void k_dense_row_nnz(int64_t F, const int32_t *__restrict__ W, int64_t *__restrict__ cnt) {
     int lane = threadIdx.x & 63;
@@ -316,14 +376,17 @@ __global__ void k_tile_occupancy(int64_t F, int64_t n_rt, const int32_t *__restr
     if (threadIdx.x == 0) occ[rt * n_rt + ct] = (uint8_t)any;
 }
 
-// Per-row max |J| over the master CSR (one thread per row).
+// Per-row max |J| over the master CSR (one wave per row, coalesced; a maximum does not
+// depend on the order it is taken in).
 __global__ void k_row_absmax(int64_t n, const int64_t *__restrict__ ptr,
                              const double *__restrict__ val, double *__restrict__ out) {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t r = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); r < n;
+         r += (int64_t)gridDim.x * (blockDim.x >> 6)) {
         double m = 0.0;
-        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) m = fmax(m, fabs(val[e]));
-        out[r] = m;
+        for (int64_t e = ptr[r] + lane; e < ptr[r + 1]; e += 64) m = fmax(m, fabs(val[e]));
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+        if (lane == 0) out[r] = m;
     }
 }
 
@@ -837,7 +900,7 @@ static void pack_dense_storage(qh_graph *g, const int32_t *W, int negate, hipStr
         DevBuf<float> scale(F);
         g->row_scale.alloc(F);
         if (F) {
-            hipLaunchKernelGGL(k_row_absmax, dim3(grid_for(F)), dim3(256), 0, st, F, g->m_ptr.p, g->m_val.p,
+            hipLaunchKernelGGL(k_row_absmax, dim3(grid_for(F, 4)), dim3(256), 0, st, F, g->m_ptr.p, g->m_val.p,
                                rmax.p);
             hipLaunchKernelGGL(k_fp8_scales, dim3(grid_for(F)), dim3(256), 0, st, F, rmax.p, scale.p,
                                g->row_scale.p);
@@ -950,11 +1013,21 @@ void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStrea
     // Eqs. (2)-(3) into a dense int32 matrix
     int conflict = g->kind == QH_READ_CONFLICT;
     DevBuf<int32_t> W((size_t)std::max<int64_t>(F * F, 1));
-    W.zero(st);
-    if (S && F) {
-        hipLaunchKernelGGL(k_read_pairs, dim3((unsigned)std::min<int64_t>(S, 1 << 20)), dim3(256), 0, st, S,
-                           g->cov_ptr.p, g->cov_frag.p, g->cov_M.p, W.p, F, conflict);
+    if (F && F <= kRowLdsMaxF) {   // every row written whole
+        if (F * (int64_t)sizeof(int32_t) > 65536)
+            QH_HIP(hipFuncSetAttribute((const void *)k_read_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(kRowLdsMaxF * sizeof(int32_t))));
+        hipLaunchKernelGGL(k_read_rows, dim3((unsigned)std::min<int64_t>(F, 1 << 20)), dim3(256),
+                           (unsigned)(F * sizeof(int32_t)), st, F, r->frag_ptr, r->snp, M.p, g->cov_ptr.p,
+                           g->cov_frag.p, g->cov_M.p, W.p, conflict);
         QH_CHECK_LAUNCH();
+    } else {
+        W.zero(st);
+        if (S && F) {
+            hipLaunchKernelGGL(k_read_pairs, dim3((unsigned)std::min<int64_t>(S, 1 << 20)), dim3(256), 0, st, S,
+                               g->cov_ptr.p, g->cov_frag.p, g->cov_M.p, W.p, F, conflict);
+            QH_CHECK_LAUNCH();
+        }
     }
     // master CSR (J = -A for the conflict kind)
     DevBuf<int64_t> cnt(F);

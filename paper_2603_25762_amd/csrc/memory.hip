@@ -1,7 +1,8 @@
 // Device memory for the library's buffers: blocks are kept per device after release and
-// handed out again for a later request of the same size class, so that graph builds and
-// solves in a loop do not pay hipMalloc / hipFree (tens of microseconds each, and hipFree
-// waits for the whole device) for every buffer.
+// handed out again for a later request that fits (the smallest idle block of at least the
+// request's size class and at most twice it), so that graph builds and solves in a loop do
+// not pay hipMalloc / hipFree (tens of microseconds each, and hipFree waits for the whole
+// device) for every buffer, also when their sizes vary from one graph to the next.
 //
 // Reuse is safe because every release happens when no queued work can still use the
 // block: temporaries are released after their stream has been synchronised, a buffer that
@@ -66,12 +67,13 @@ void *device_alloc(size_t bytes) {
     DeviceCache &c = g_cache[dev];
     for (uintptr_t tag : {t_pool, (uintptr_t)0}) {
         auto &pool = c.idle[tag];
-        auto it = pool.find(cls);
-        if (it != pool.end()) {
+        auto it = pool.lower_bound(cls);
+        if (it != pool.end() && it->first <= 2 * cls) {
             void *p = it->second;
+            const size_t have = it->first;     // the block keeps its own size class
             pool.erase(it);
-            c.idle_bytes -= cls;
-            g_live[p] = Block{dev, cls};
+            c.idle_bytes -= have;
+            g_live[p] = Block{dev, have};
             return p;
         }
         if (tag == 0) break;
