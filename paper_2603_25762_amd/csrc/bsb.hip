@@ -65,6 +65,23 @@ __global__ void k_x_to_h(int64_t n, int R, const float *__restrict__ x, uint16_t
     }
 }
 
+// binary16 copy of x in the state layout [n][R] for the long-range gathers: a gather then
+// moves 2R bytes instead of 4R (|x| <= 1: binary16 keeps 11 significant bits down to 2^-14)
+__device__ inline uint16_t lr_copy_value(float x, int discrete) { return f32_to_f16_rne(coupling_value(x, discrete)); }
+
+__global__ void k_x_to_lh(int64_t total, const float *__restrict__ x, uint16_t *__restrict__ h, int discrete) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x)
+        h[t] = lr_copy_value(x[t], discrete);
+}
+
+// x_j as a long-range gather sees it: from the binary16 copy (H16) or from x itself
+template <bool H16>
+__device__ inline float lr_x(const float *x_in, const uint16_t *h_in, int64_t idx, int discrete) {
+    if constexpr (H16) return f16_bits_to_f32(h_in[idx]);
+    else return coupling_value(x_in[idx], discrete);
+}
+
 struct StepArgs {
     float c0, dt, a0;
     const float *pump;
@@ -72,7 +89,13 @@ struct StepArgs {
     int discrete;   // 1: the coupling takes sgn(x_j) (discrete variant), 0: x_j
     float bscale;   // band blocks: power of two undoing the scale of their binary16 encoding (1: none)
     const float *field;   // deformation field h [n] joining the coupling sum (nullptr: none)
+    uint16_t *lr_out = nullptr;   // SNP kernels: binary16 copy of the new x for the long-range gathers
 };
+
+// the new x of state element idx into the long-range copy, when the step keeps one
+__device__ inline void store_lr_copy(const StepArgs &sa, int64_t idx, float x) {
+    if (sa.lr_out) sa.lr_out[idx] = lr_copy_value(x, sa.discrete);
+}
 
 // The coupling sum of row i with the deformation field added: the field enters after the
 // whole sum J x, so every step kernel rounds it identically.
@@ -277,11 +300,11 @@ __device__ inline float ld_val(const uint8_t *__restrict__ p, int64_t e) {
 
 // Partial sums of the long-range lists, one per chunk of at most kHubChunk entries
 // (replica tiles of 16 or 32: several chunks per wave).
-template <int DT, int RT>
+template <int DT, int RT, bool H16>
 __global__ __launch_bounds__(256) void k_hub_partials(
     int64_t n_chunks, int R, const int64_t *__restrict__ cbeg,
     const int64_t *__restrict__ cend, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
-    const float *__restrict__ x_in, float *__restrict__ part, int discrete) {
+    const float *__restrict__ x_in, const uint16_t *__restrict__ h_in, float *__restrict__ part, int discrete) {
     constexpr int RPW = 64 / RT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sub = lane / RT, rr = lane % RT;
@@ -291,7 +314,7 @@ __global__ __launch_bounds__(256) void k_hub_partials(
         float z = 0.f;
 #pragma unroll 4
         for (int64_t e = cbeg[c]; e < cend[c]; ++e)
-            z += ld_val<DT>(l_val, e) * coupling_value(x_in[(int64_t)l_col[e] * R + r], discrete);
+            z += ld_val<DT>(l_val, e) * lr_x<H16>(x_in, h_in, (int64_t)l_col[e] * R + r, discrete);
         part[c * R + r] = z;
     }
 }
@@ -302,11 +325,11 @@ __global__ __launch_bounds__(256) void k_hub_partials(
 // independent of one another and of any further index load.  Each chunk is summed in
 // entry order, as in k_hub_partials.
 constexpr int kLrInFlight = 32;    // x-row gathers a wave keeps in flight (a packet has at most 64)
-template <int DT>
+template <int DT, bool H16>
 __global__ __launch_bounds__(256) void k_lr_packets(
     int64_t n_pk, int R, const int32_t *__restrict__ pk_ptr, const int64_t *__restrict__ cbeg,
     const int64_t *__restrict__ cend, const int32_t *__restrict__ l_col, const uint8_t *__restrict__ l_val,
-    const float *__restrict__ x_in, float *__restrict__ part, int discrete) {
+    const float *__restrict__ x_in, const uint16_t *__restrict__ h_in, float *__restrict__ part, int discrete) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t r = (int64_t)blockIdx.y * 64 + lane;
@@ -331,7 +354,7 @@ __global__ __launch_bounds__(256) void k_lr_packets(
             for (int k = 0; k < kLrInFlight; ++k) {
                 const int32_t jj = j + k < 63 ? j + k : 63;      // lanes past cnt hold column 0
                 vv[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my_val), jj));
-                xv[k] = coupling_value(x_in[(int64_t)__builtin_amdgcn_readlane(my_col, jj) * R + r], discrete);
+                xv[k] = lr_x<H16>(x_in, h_in, (int64_t)__builtin_amdgcn_readlane(my_col, jj) * R + r, discrete);
             }
 #pragma unroll
             for (int k = 0; k < kLrInFlight; ++k) {
@@ -385,6 +408,7 @@ __global__ __launch_bounds__(256) void k_sky_step(
         bsb_update(z, xv, yv, coef, sa);
         y[idx] = yv;
         x_out[idx] = xv;
+        store_lr_copy(sa, idx, xv);
     }
 }
 
@@ -467,6 +491,7 @@ __device__ inline void band_block_finish(int64_t blk, int64_t n, int64_t R, int6
             y[idx] = yv;
             x_out[idx] = xv;
         }
+        store_lr_copy(sa, idx, xv);
     }
 }
 
@@ -599,6 +624,7 @@ __device__ inline void band_block_step_mfma(int64_t blk, int64_t n, int64_t R, i
             bsb_update(zi, xv, yv, coef, sa);
             y[idx] = yv;
             x_out[idx] = xv;
+            store_lr_copy(sa, idx, xv);
         }
     }
 }
@@ -1037,6 +1063,11 @@ static int grid_for(int64_t n, int block = 256, int64_t cap = 65536) {
 }
 
 
+// 16-bit SNP graphs with long-range rows gather x from a binary16 copy (F32 graphs from x)
+static bool lr_copy(const qh_graph *g) {
+    return g->storage == QH_STORE_SKYLINE && g->l_nnz > 0 && g->dtype != QH_F32;
+}
+
 SolvePlan &solve_plan(const qh_graph *gc, int R, hipStream_t st) {
     qh_graph *g = const_cast<qh_graph *>(gc);
     auto it = g->plans.find(R);
@@ -1053,6 +1084,12 @@ SolvePlan &solve_plan(const qh_graph *gc, int R, hipStream_t st) {
     if (!dense16) {
         p->xb.alloc(st_elems);
         p->xb.zero(st);
+        if (lr_copy(g)) {
+            p->la.alloc(st_elems);
+            p->la.zero(st);
+            p->lb.alloc(st_elems);
+            p->lb.zero(st);
+        }
     } else {
         p->ha.alloc(st_elems);
         p->ha.zero(st);
@@ -1108,20 +1145,26 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
     const float *xin = cur ? p.xb.p : p.xa.p;
     float *xout = cur ? p.xa.p : p.xb.p;
     const bool lr = g->l_nnz > 0;
+    // 16-bit graphs with long-range rows: the step also writes a binary16 copy of the new x,
+    // which the next step's long-range gathers read
+    const bool lh = lr && p.la.p != nullptr;
+    StepArgs sl = sa;
+    if (lh) sl.lr_out = cur ? p.la.p : p.lb.p;
+    const uint16_t *lhin = lh ? (cur ? p.lb.p : p.la.p) : nullptr;
     dim3 grid((unsigned)nblk, (unsigned)(R / RT));
-#define QH_HUB(DTV, RTV)                                                                                        \
-    hipLaunchKernelGGL((k_hub_partials<DTV, RTV>), dim3((unsigned)grid_for(g->n_hub_chunks, 4 * (64 / RTV), 4096), \
+#define QH_HUB(DTV, RTV, H16V)                                                                                  \
+    hipLaunchKernelGGL((k_hub_partials<DTV, RTV, H16V>), dim3((unsigned)grid_for(g->n_hub_chunks, 4 * (64 / RTV), 4096), \
                                                         (unsigned)(R / RTV)),                                       \
                        dim3(256), 0, st, g->n_hub_chunks, R, g->hub_chunk_beg.p, g->hub_chunk_end.p, g->l_col.p,   \
-                       g->l_val.p, xin, p.hub_part.p, sa.discrete)
-#define QH_PK(DTV)                                                                                              \
-    hipLaunchKernelGGL((k_lr_packets<DTV>), dim3((unsigned)grid_for(g->n_lr_pk, 4, 1 << 20), (unsigned)(R / 64)),  \
+                       g->l_val.p, xin, lhin, p.hub_part.p, sa.discrete)
+#define QH_PK(DTV, H16V)                                                                                        \
+    hipLaunchKernelGGL((k_lr_packets<DTV, H16V>), dim3((unsigned)grid_for(g->n_lr_pk, 4, 1 << 20), (unsigned)(R / 64)),  \
                        dim3(256), 0, st, g->n_lr_pk, R, g->lr_pk_ptr.p, g->hub_chunk_beg.p, g->hub_chunk_end.p,     \
-                       g->l_col.p, g->l_val.p, xin, p.hub_part.p, sa.discrete)
+                       g->l_col.p, g->l_val.p, xin, lhin, p.hub_part.p, sa.discrete)
 #define QH_SKY(DTV, RTV)                                                                                       \
     hipLaunchKernelGGL((k_sky_step<DTV, RTV>), grid, dim3(256), 0, st, n, R, rows_per_wg, nblk, g->s_off.p,    \
                        g->s_lo.p, g->s_len.p, g->s_val.p, lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, \
-                       xout, p.y.p, sa)
+                       xout, p.y.p, sl)
     // step kernel: band blocks on FMAs (64-replica tiles), band blocks on MFMAs, or per row
     int sk = p.sky_kernel;
     if (sk == kSkyBandFma && !(RT == 64 && g->n_bblk > 0)) sk = kSkyRows;
@@ -1130,7 +1173,7 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
 #define QH_BAND_K(DTV, NTV, FLDV)                                                                                 \
     hipLaunchKernelGGL((k_band_step<DTV, NTV, FLDV>), dim3((unsigned)GB, (unsigned)(R / 64)), dim3(256), 0, st, n, \
                        R, g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                         \
-                       lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sa)
+                       lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sl)
 #define QH_BAND_NT(DTV, NTV)                                            \
     do {                                                                \
         if (sa.field) QH_BAND_K(DTV, NTV, true);                        \
@@ -1144,13 +1187,19 @@ static void launch_step(const qh_graph *g, SolvePlan &p, const StepArgs &sa, int
 #define QH_BANDM(DTV, NBV)                                                                                      \
     hipLaunchKernelGGL((k_band_step_mfma<DTV, NBV>), dim3((unsigned)GB, (unsigned)(R / (NBV * 16))), dim3(256), 0, \
                        st, n, R, g->n_bblk, GB, g->bb_off.p, g->bb_lo.p, g->bb_w.p, g->bb_val.p,                \
-                       lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sa)
+                       lr ? g->row_chunk_ptr.p : nullptr, p.hub_part.p, xin, xout, p.y.p, sl)
 #define QH_LR(DTV)                                                      \
     do {                                                                \
         if (!lr) break;                                                 \
-        if (RT == 16) QH_HUB(DTV, 16);                                  \
-        else if (RT == 32) QH_HUB(DTV, 32);                             \
-        else QH_PK(DTV);                                                \
+        if (lh) {                                                       \
+            if (RT == 16) QH_HUB(DTV, 16, true);                        \
+            else if (RT == 32) QH_HUB(DTV, 32, true);                   \
+            else QH_PK(DTV, true);                                      \
+        } else {                                                        \
+            if (RT == 16) QH_HUB(DTV, 16, false);                       \
+            else if (RT == 32) QH_HUB(DTV, 32, false);                  \
+            else QH_PK(DTV, false);                                     \
+        }                                                               \
     } while (0)
 #define QH_SKY_RT(DTV)                                                  \
     do {                                                                \
@@ -1212,9 +1261,18 @@ static int run_steps(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, cons
     return cur;
 }
 
+// The copies of x that the step kernels read besides x itself, made from xa: the dense
+// paths' 16-bit product copy (ha), or the binary16 copy of the long-range gathers (la).
 static void x_to_h(const qh_graph *g, SolvePlan &p, int64_t n, int R, int discrete, hipStream_t st) {
     const int64_t nR = n * R;
     if (!nR) return;
+    if (x_pingpong(g)) {
+        if (lr_copy(g)) {
+            hipLaunchKernelGGL(k_x_to_lh, dim3(grid_for(nR)), dim3(256), 0, st, nR, p.xa.p, p.la.p, discrete);
+            QH_CHECK_LAUNCH();
+        }
+        return;
+    }
     if (g->dtype == QH_BF16)
         hipLaunchKernelGGL(k_x_to_h<true>, dim3(grid_for(nR)), dim3(256), 0, st, n, R, p.xa.p, p.ha.p, discrete);
     else
@@ -1365,6 +1423,7 @@ static void autotune_sky(const qh_graph *g, SolvePlan &p, const qh_bsb_opts *o, 
             hipLaunchKernelGGL(k_init, dim3(grid_for(n * R)), dim3(256), 0, st, (uint64_t)0x5eed, n, R, p.xa.p,
                                p.y.p);
             QH_CHECK_LAUNCH();
+            x_to_h(g, p, n, R, o->variant == 1, st);
             QH_HIP(hipEventRecord(e0, st));
             run_steps(g, p, o, pump, c0, a0, 0, nt, st);
             QH_HIP(hipEventRecord(e1, st));
@@ -1506,7 +1565,7 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
             hipLaunchKernelGGL(k_copy_state_in, dim3(grid_for(nR)), dim3(256), 0, st, n, R, res->y, p.y.p);
             QH_CHECK_LAUNCH();
         }
-        if (dense16) x_to_h(g, p, n, R, o->variant == 1, st);
+        x_to_h(g, p, n, R, o->variant == 1, st);
     };
     load_state();
     if (ke > kb && n > 0) p.last_plan = persistent ? 2 : 1;
@@ -1537,7 +1596,7 @@ void bsb_solve(const qh_graph *g, const qh_bsb_opts *o, qh_result *res, hipStrea
             }
             readout(view_of(g), p, R, p.xa.p, p.y.p, res, o->greedy != 0, st, ev.last, &ev);
             if (ev.last) break;
-            if (dense16) x_to_h(g, p, n, R, o->variant == 1, st);
+            x_to_h(g, p, n, R, o->variant == 1, st);
             k0 = k1;
         }
         if (res->best_energy) {

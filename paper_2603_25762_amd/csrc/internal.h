@@ -127,6 +127,8 @@ struct SolvePlan {
     int64_t n_pad = 0;
     DevBuf<float> xa, xb, y;        // fp32 state, [n_pad][R]
     DevBuf<uint16_t> ha, hb;        // 16-bit product copies of x (dense f16/bf16/fp8 paths)
+    DevBuf<uint16_t> la, lb;        // binary16 copies of x [n][R] (paired with xa / xb) that the
+                                    // long-range gathers read (16-bit SNP graphs with long-range rows)
     DevBuf<float> pump_lin;         // linear schedule for `steps`
     int pump_steps = 0;
     DevBuf<int8_t> spins;           // [n][R]

@@ -57,16 +57,30 @@ COPY_UNIT = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 COPY_ABS = {"f16": 2.0 ** -25, "bf16": 0.0}
 
 
-def step_with_rounded_copy(J, x, y, p, dt, c0, a0=1.0, fmt=None, walls=True, discrete=False, field=None):
-    """The precision form's step as the dense 16/8-bit kernels compute it, in FP64: the
-    coupling product multiplies the copy of x rounded to ``fmt`` (binary16 or bfloat16, round
-    to nearest even), the update keeps x and y unrounded.  A model of the kernels, kept in
-    the tests: the oracle's step (oracle.bsb_step_dense) is the unrounded definition."""
+def far_mask(n, band_limit):
+    """Entries of the long-range part of a SNP graph built with ``band_limit``: |i - j| above it."""
+    i = np.arange(n)
+    return np.abs(i[:, None] - i[None, :]) > band_limit
+
+
+def step_with_rounded_copy(J, x, y, p, dt, c0, a0=1.0, fmt=None, walls=True, discrete=False, field=None,
+                           lr_band=None):
+    """The precision form's step as the 16/8-bit kernels compute it, in FP64: the coupling
+    product multiplies the copy of x rounded to ``fmt`` (binary16 or bfloat16, round to
+    nearest even; dense storage), or, with ``lr_band`` (16-bit SNP storage built with that
+    band limit), the long-range entries multiply x rounded to binary16 and the band x itself.
+    The update keeps x and y unrounded.  A model of the kernels, kept in the tests: the
+    oracle's step (oracle.bsb_step_dense) is the unrounded definition."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
-    if discrete or fmt is None:
+    if discrete or (fmt is None and lr_band is None):
         return oracle.bsb_step_dense(J, x, y, p, dt, c0, a0, walls=walls, discrete=discrete, field=field)
-    z = np.asarray(J, dtype=np.float64) @ quant.round_to(fmt, x)
+    J = np.asarray(J, dtype=np.float64)
+    if lr_band is not None:
+        far = far_mask(J.shape[0], lr_band)
+        z = np.where(far, 0.0, J) @ x + np.where(far, J, 0.0) @ quant.round_to("f16", x)
+    else:
+        z = J @ quant.round_to(fmt, x)
     if field is not None:
         z = z + np.asarray(field, dtype=np.float64)[:, None]
     y2 = y + (-(a0 - p) * x + c0 * z) * dt

@@ -17,8 +17,8 @@ import oracle
 import paper_2603_25762_amd as qh
 import synth
 from oracle import metrics, quant
-from gpu_helpers import (COPY_ABS, COPY_UNIT, cpu, device_reads, f32, gpu_graph, oracle_graph, snp_abs_terms,
-                         step_bounds, step_with_rounded_copy)
+from gpu_helpers import (COPY_ABS, COPY_UNIT, cpu, device_reads, f32, far_mask, gpu_graph, oracle_graph,
+                         snp_abs_terms, step_bounds, step_with_rounded_copy)
 
 pytestmark = pytest.mark.gpu
 
@@ -160,7 +160,7 @@ def test_skyline_stored_values_bit_exact(dtype):
 # ----------------------------------------------------------------------------- one step
 
 def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, plan=0, discrete=False,
-                   field=False):
+                   field=False, lr_band=None):
     n = J.shape[0]
     rng = np.random.default_rng(rng_seed)
     x0 = f32(rng.uniform(-1.0, 1.0, (n, R)))
@@ -181,9 +181,9 @@ def _one_step_case(g, J, dtype, R, rng_seed, product_format, steps=100, k=37, pl
                  field=None if h is None else torch.tensor(h, dtype=torch.float32, device="cuda"))
     xg, yg = cpu(x).astype(np.float64), cpu(y).astype(np.float64)
     xu, yu = step_with_rounded_copy(J, x0, y0, p, dt, c0, 1.0, product_format, walls=False, discrete=discrete,
-                                    field=h)
+                                    field=h, lr_band=lr_band)
     xo, yo = step_with_rounded_copy(J, x0, y0, p, dt, c0, 1.0, product_format, walls=True, discrete=discrete,
-                                    field=h)
+                                    field=h, lr_band=lr_band)
     if discrete:
         xq = np.ones_like(x0)
     else:
@@ -292,12 +292,13 @@ def test_dense_one_step_field(dtype, plan):
 @pytest.mark.parametrize("plan", [3, 4, 5])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_skyline_one_step_field(dtype, plan):
-    """The field on the SNP step kernels, with long-range rows (chunk partials) present."""
+    """The field on the SNP step kernels, with long-range rows (chunk partials) present (16-bit
+    storage: the long-range entries multiply the binary16 copy of x)."""
     w = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
     g = gpu_graph(w, "snp_llr", dtype, band_limit=100)
     assert g.info()["longrange_nnz"] > 0
     J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
-    _one_step_case(g, J, dtype, 64, 902, None, plan=plan, field=True)
+    _one_step_case(g, J, dtype, 64, 902, None, plan=plan, field=True, lr_band=None if dtype == "f32" else 100)
 
 
 def test_field_solves_match_oracle_plans_and_batches():
@@ -576,11 +577,50 @@ def test_band_mfma_whole_solve_and_tuner(dtype):
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 @pytest.mark.parametrize("R", [32, 64])
 def test_longrange_hub_one_step(dtype, R):
+    """Long-range rows, hub rows among them (chunk partials from the packet kernel for R = 64,
+    per chunk for R = 32); 16-bit storage gathers the binary16 copy of x."""
     w = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
     g = gpu_graph(w, "snp_llr", dtype, band_limit=100)
     assert g.info()["longrange_nnz"] > 0
     J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
-    _one_step_case(g, J, dtype, R, 300 + R, None)
+    _one_step_case(g, J, dtype, R, 300 + R, None, lr_band=None if dtype == "f32" else 100)
+
+
+@pytest.mark.parametrize("plan", [3, 4, 5])
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_longrange_copy_against_unrounded_oracle(dtype, plan):
+    """The binary16 copy of x that 16-bit SNP graphs gather for their long-range entries,
+    bounded against the oracle's unrounded step (stored J, FP64): rounding x_j to binary16
+    moves it by at most 2^-11 |x_j| + 2^-25, so row i's coupling sum moves by at most
+    sum over its long-range j of |J_ij| (2^-11 |x_j| + 2^-25), y by c0 dt times that and x by
+    a0 dt times y's bound, on top of the FP32 step tolerance; band entries take x itself."""
+    w = synth.snp_porec(43, n_snp=2500, n_edges=4000, zipf_s=1.0)
+    g = gpu_graph(w, "snp_llr", dtype, band_limit=100)
+    J = stored_J(oracle_graph(w, "snp_llr").dense(), dtype)
+    n, R, k, steps, dt = J.shape[0], 64, 37, 100, 0.5
+    rng = np.random.default_rng(654)
+    x0 = f32(rng.uniform(-1.0, 1.0, (n, R)))
+    y0 = f32(rng.uniform(-0.6, 0.6, (n, R)))
+    pump = np.linspace(0.0, 1.0, steps).astype(np.float32)
+    c0 = float(np.float32(0.4 / max(1.0, float(np.sqrt((J ** 2).sum() / (n - 1))))))
+    p = float(pump[k])
+    x = torch.tensor(x0, dtype=torch.float32, device="cuda").contiguous()
+    y = torch.tensor(y0, dtype=torch.float32, device="cuda").contiguous()
+    qh.bsb_solve(g, R, steps, dt=dt, c0=c0, pump=torch.tensor(pump, device="cuda"), init=False, x=x, y=y,
+                 step_begin=k, step_end=k + 1, readout=False, plan=plan)
+    xg, yg = cpu(x).astype(np.float64), cpu(y).astype(np.float64)
+    xu, yu = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, walls=False)
+    xo, yo = oracle.bsb_step_dense(J, x0, y0, p, dt, c0, 1.0, walls=True)
+    tol_x, tol_y = step_bounds(np.abs(J) @ np.abs(x0), x0, y0, p, dt, c0)
+    Jfar = np.where(far_mask(n, 100), np.abs(J), 0.0)
+    assert Jfar.sum() > 0
+    copy = c0 * dt * (Jfar @ (COPY_UNIT["f16"] * np.abs(x0) + COPY_ABS["f16"]))
+    tol_y = tol_y + copy
+    tol_x = tol_x + dt * copy
+    ok = np.abs(np.abs(xu) - 1.0) > tol_x        # entries not within the tolerance of a wall
+    assert ok.mean() > 0.9
+    assert np.all(np.abs(yg - yo)[ok] <= tol_y[ok])
+    assert np.all(np.abs(xg - xo)[ok] <= tol_x[ok])
 
 
 @pytest.mark.parametrize("plan", [2, 1])
