@@ -53,6 +53,8 @@ def parse():
                     help="0 auto; batched: 1 per-step, 2 whole-block; read_mhc: 1 per-step, 2 persistent")
     ap.add_argument("--persistent-sync", type=int, default=0, choices=[0, 1, 2])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--build-threads", type=int, default=0,
+                    help="host threads of the batch's graph build (qh_build_graphs; 0 = the library's 8)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the time-to-phase and plain-FP32 measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -222,16 +224,19 @@ def batch_inputs(qh, batch):
     return views
 
 
+BUILD_THREADS = 0
+
+
 def build_batch(qh, batch, dtype=None):
     """The batch's graphs (even blocks read graphs, odd blocks SNP graphs), built together by
-    qh_build_graphs."""
+    qh_build_graphs (BUILD_THREADS host threads; 0 = the library's default)."""
     specs = []
     for i, (w, d) in enumerate(zip(batch.blocks, batch_inputs(qh, batch))):
         kind = "read_signed" if i % 2 == 0 else "snp_llr"
         specs.append(dict(frag_ptr=d["frag_ptr"], snp=d["snp"], allele=d["allele"], phred=d["phred"],
                           init_h1=d["init_h1"], kind=kind, dtype=dtype or w.solve["dtype"],
                           alpha=d["alpha"] if kind == "snp_llr" else None))
-    return qh.build_graphs(specs)
+    return qh.build_graphs(specs, threads=BUILD_THREADS)
 
 
 def batch_gaps(qh, gs, r, batch, ref):
@@ -608,6 +613,8 @@ def main():
         print(f"bench.py drives one GPU; --gpus {a.gpus} is not offered (how the path would shard across GPUs "
               "is described in the design notes only)", file=sys.stderr)
         sys.exit(2)
+    global BUILD_THREADS
+    BUILD_THREADS = a.build_threads
     {"batched": bench_batched, "read_mhc": bench_read_mhc, "snp_chrom": bench_snp,
      "snp_porec": bench_snp}[a.workload](a)
 

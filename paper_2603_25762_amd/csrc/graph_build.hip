@@ -917,6 +917,8 @@ static void pack_dense_storage(qh_graph *g, const int32_t *W, int negate, hipStr
                            g->t_col.p, g->dtype, (const float *)nullptr, g->t_val.p);
         QH_CHECK_LAUNCH();
         QH_HIP(hipStreamSynchronize(st));
+    } else {
+        QH_HIP(hipStreamSynchronize(st));   // the uploads' host vectors go out of scope
     }
 }
 
@@ -1371,6 +1373,7 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
                 }
             }
         }
+        QH_HIP(hipStreamSynchronize(st));   // the uploads' host vectors go out of scope
     }
     QH_HIP(hipStreamSynchronize(st));
 }
