@@ -75,6 +75,47 @@ def test_read_graph_bit_exact(kind, case):
         assert torch.equal(g1.export_rows(0, go.n), g.export_rows(0, go.n))
 
 
+def _oracle_read_row(w, kind, p):
+    """Row p of the oracle's read graph from the oracle run on read p and the reads sharing a
+    SNP with it (an entry (p, q) depends on reads p and q alone), mapped back to all reads."""
+    fp, snp = w.frag_ptr, w.snp
+    owner = np.repeat(np.arange(len(fp) - 1), np.diff(fp))
+    qs = np.unique(owner[np.isin(snp, snp[fp[p]:fp[p + 1]])])
+    lens = np.diff(fp)[qs]
+    sub_fp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    take = np.concatenate([np.arange(fp[q], fp[q + 1]) for q in qs])
+    M = oracle.encode(snp[take], w.allele[take], w.init_h1)
+    go = oracle.read_graph(w.n_snp, sub_fp, snp[take], M, "signed" if kind == "read_signed" else "conflict")
+    i = int(np.searchsorted(qs, p))
+    row = np.zeros(len(fp) - 1)
+    b, e = go.row_ptr[i], go.row_ptr[i + 1]
+    row[qs[go.col[b:e]]] = go.val[b:e]
+    return row
+
+
+@pytest.mark.parametrize("n_reads,kind", [(20000, "read_signed"), (40000, "read_conflict")])
+def test_read_graph_large_fragment_counts(n_reads, kind):
+    """Eqs. (2)-(3) past the row kernel's small-LDS case: 20,000 reads need 80 KB of LDS per
+    row (the large-LDS launch), 40,000 go past its limit to the per-SNP kernel with global
+    atomics.  Sampled rows of the FP64 master equal the oracle's bit for bit (each from the
+    oracle on the reads that share a SNP with the row's read); at 20,000 reads the whole
+    oracle graph also gives the nonzero count and the components."""
+    w = synth.read_small(61, n_snp=4000, n_reads=n_reads, span=(2, 6))
+    g = gpu_graph(w, kind)
+    n = g.info()["n"]
+    assert n == n_reads and g.info()["integer_weights"] == 1
+    rng = np.random.default_rng(5)
+    for r in sorted({0, 1, n // 3, n // 2, n - 2, n - 1, *rng.integers(0, n, 24).tolist()}):
+        assert np.array_equal(cpu(g.export_rows(r, r + 1))[0], _oracle_read_row(w, kind, r)), r
+    if n_reads <= 20000:
+        go = oracle_graph(w, kind)
+        assert g.info()["nnz"] == go.nnz
+        comp, nc = oracle.components(go)
+        assert g.info()["n_comp"] == nc
+        assert np.array_equal(cpu(g.components()), comp)
+    g.free()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16", "fp8"])
 def test_dense_stored_values_bit_exact(dtype):
     w = synth.read_small(9, n_snp=300, n_reads=200, span=(20, 60))
