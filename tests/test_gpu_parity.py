@@ -954,23 +954,34 @@ def test_build_graphs_equals_single_builds(threads):
     and so the last bit, may change from one build to the next).  A malformed block fails
     the whole call with its index, and no graph is returned."""
     blocks = [synth.read_small(70 + b, n_snp=200, n_reads=30 + 25 * b) for b in range(6)] + \
-             [synth.snp_small(80 + b, n_snp=120 + 150 * b) for b in range(6)] + [synth.read_tiny()]
-    kinds = ["read_signed"] * 6 + ["snp_llr"] * 6 + ["read_conflict"]
-    dtypes = ["fp8", "f16", "bf16", "f32", "fp8", "f16", "bf16", "f16", "f32", "bf16", "f16", "f32", "f32"]
+             [synth.snp_small(80 + b, n_snp=120 + 150 * b) for b in range(6)] + [synth.read_tiny()] + \
+             [synth.snp_porec(45, n_snp=2000, n_edges=2500, zipf_s=1.0)]
+    kinds = ["read_signed"] * 6 + ["snp_llr"] * 6 + ["read_conflict", "snp_llr"]
+    dtypes = ["fp8", "f16", "bf16", "f32", "fp8", "f16", "bf16", "f16", "f32", "bf16", "f16", "f32", "f32", "bf16"]
     specs = []
-    for w, k, dt in zip(blocks, kinds, dtypes):
+    for b, (w, k, dt) in enumerate(zip(blocks, kinds, dtypes)):
         d = device_reads(w)
         specs.append(dict(frag_ptr=d["frag_ptr"], snp=d["snp"], allele=d["allele"], phred=d["phred"],
-                          init_h1=d["init_h1"], kind=k, dtype=dt, alpha=d["alpha"], deterministic=True))
+                          init_h1=d["init_h1"], kind=k, dtype=dt, alpha=d["alpha"], deterministic=True,
+                          band_limit=64 if b == 13 else 0))
+    # degenerate graphs among them: one fragment, and none
+    for nf in (1, 0):
+        w = synth.read_small(25, n_snp=50, n_reads=1, span=(5, 10))
+        fp = w.frag_ptr[: nf + 1].copy()
+        specs.append(dict(frag_ptr=qh.to_device(fp), snp=qh.to_device(w.snp[: fp[-1]].copy()),
+                          allele=qh.to_device(w.allele[: fp[-1]].copy()),
+                          phred=qh.to_device(w.phred[: fp[-1]].copy()), init_h1=qh.to_device(w.init_h1)))
     many = qh.build_graphs(specs, threads=threads)
     assert len(many) == len(specs)
+    assert many[13].info()["longrange_nnz"] > 0 and many[-1].info()["n"] == 0 and many[-2].info()["n"] == 1
     for b, (sp, gm) in enumerate(zip(specs, many)):
         g1 = qh.build_graph(**sp)
         assert g1.info() == gm.info(), b
         n = g1.info()["n"]
-        assert torch.equal(g1.export_rows(0, n), gm.export_rows(0, n)), b
-        assert torch.equal(g1.export_rows(0, n, stored=True), gm.export_rows(0, n, stored=True)), b
-        assert torch.equal(g1.components(), gm.components()), b
+        if n:
+            assert torch.equal(g1.export_rows(0, n), gm.export_rows(0, n)), b
+            assert torch.equal(g1.export_rows(0, n, stored=True), gm.export_rows(0, n, stored=True)), b
+            assert torch.equal(g1.components(), gm.components()), b
         g1.free()
     for g in many:
         g.free()
