@@ -227,11 +227,13 @@ def batch_inputs(qh, batch):
 BUILD_THREADS = 0
 
 
-def build_batch(qh, batch, dtype=None):
+def build_batch(qh, batch, dtype=None, inputs=None):
     """The batch's graphs (even blocks read graphs, odd blocks SNP graphs), built together by
-    qh_build_graphs (BUILD_THREADS host threads; 0 = the library's default)."""
+    qh_build_graphs (BUILD_THREADS host threads; 0 = the library's default) from `inputs`
+    (batch_inputs), which are made here when not given."""
     specs = []
-    for i, (w, d) in enumerate(zip(batch.blocks, batch_inputs(qh, batch))):
+    inputs = batch_inputs(qh, batch) if inputs is None else inputs
+    for i, (w, d) in enumerate(zip(batch.blocks, inputs)):
         kind = "read_signed" if i % 2 == 0 else "snp_llr"
         specs.append(dict(frag_ptr=d["frag_ptr"], snp=d["snp"], allele=d["allele"], phred=d["phred"],
                           init_h1=d["init_h1"], kind=kind, dtype=dtype or w.solve["dtype"],
@@ -356,7 +358,9 @@ def bench_batched(a):
         out.update(batch_gaps(qh, gs, r, batch, ref))
         out["oracle_reference"] = "tests/golden/batched_reference.json (stratified 5% subset: 150 blocks)"
     if not a.no_extras:
-        out["time_to_phase_ms"] = round(time_to_phase_batched(qh, batch, R, STEPS, DT, SEED), 1)
+        ttp, parts = time_to_phase_batched(qh, batch, R, STEPS, kw)
+        out["time_to_phase_ms"] = round(ttp, 1)
+        out["time_to_phase_parts_ms"] = parts
         out["fp32_form"] = fp32_form_batched(qh, batch, R, STEPS, DT, SEED, ref, a)
     for g in gs:
         g.free()
@@ -365,26 +369,34 @@ def bench_batched(a):
     print(json.dumps(out), flush=True)
 
 
-def time_to_phase_batched(qh, batch, R, STEPS, DT, SEED):
+def time_to_phase_batched(qh, batch, R, STEPS, kw):
     """Host fragments in -> haplotypes out for the whole batch: H2D of every block's
     fragments (one copy per array kind), the graph builds (qh_build_graphs), the batched
-    solve, the phasing of every block, D2H."""
+    solve with the benchmark's options `kw`, the phasing of every block (qh_phase_batched),
+    D2H."""
     import torch
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gs = build_batch(qh, batch)
-    r = qh.bsb_solve_batched(gs, R, STEPS, dt=DT, seed=SEED)
-    off = r["vertex_offset"]
-    # qh_phase_noalloc: its counters live in the library's static scratch, so the calls (one
-    # stream, in order) need no allocation and no synchronisation each
-    outs = [qh.phase(g, r["best_spins"][int(off[b]):int(off[b + 1])], noalloc=True) for b, g in enumerate(gs)]
-    h1 = torch.cat([o[0] for o in outs]).cpu()
-    blk = torch.cat([o[1] for o in outs]).cpu()
-    ms = (time.perf_counter() - t0) * 1e3
+    t = [time.perf_counter()]
+    inputs = batch_inputs(qh, batch)
+    torch.cuda.synchronize()
+    t.append(time.perf_counter())
+    gs = build_batch(qh, batch, inputs=inputs)
+    t.append(time.perf_counter())
+    r = qh.bsb_solve_batched(gs, R, STEPS, **kw)
+    torch.cuda.synchronize()
+    t.append(time.perf_counter())
+    # every block phased in one call (qh_phase_batched), outputs packed by SNP
+    h1, blk, _ = qh.phase_batched(gs, r["best_spins"])
+    torch.cuda.synchronize()
+    t.append(time.perf_counter())
+    h1 = h1.cpu()
+    blk = blk.cpu()
+    t.append(time.perf_counter())
     del h1, blk
     for g in gs:
         g.free()
-    return ms
+    parts = {k: round((t[i + 1] - t[i]) * 1e3, 1) for i, k in enumerate(("h2d", "build", "solve", "phase", "d2h"))}
+    return (t[-1] - t[0]) * 1e3, parts
 
 
 def fp32_form_batched(qh, batch, R, STEPS, DT, SEED, ref, a):

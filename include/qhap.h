@@ -389,6 +389,17 @@ qh_status qh_phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *
 qh_status qh_phase_noalloc(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block,
                            void *stream);
 
+/* qh_phase of many graphs in one call (Methods, as qh_phase for each), for the blocks of a
+ * batched solve: spins device int8 packed as qh_bsb_solve_batched's best_spins (graph b's
+ * n_b vertices from sum_{c<b} n_c); h1 device int8 and block device int32 packed by SNP
+ * (graph b's n_snp_b SNPs from sum_{c<b} n_snp_c).  Graph b's slices equal qh_phase on graph
+ * b with its slice of spins, bit for bit (labels are each graph's own).  A few launches for
+ * the whole list instead of a few per graph; allocates its tables and counters and
+ * synchronises the stream.  Errors: EINVAL (null argument or graph, n_graphs < 0, a graph
+ * on another device), ENOMEM, EHIP. */
+qh_status qh_phase_batched(const qh_graph *const *graphs, int32_t n_graphs, const int8_t *spins,
+                           int8_t *h1, int32_t *block, void *stream);
+
 /* Eq. 15: J_uv <- -J_uv for every edge whose endpoints disagree in `spins` (device
  * int8 [n]); updates the master and the stored copy in place and recomputes
  * qh_graph_info.total_weight (c0_auto depends on J^2 only and does not change).

@@ -12,7 +12,8 @@ there is no CPU fallback.
 from __future__ import annotations
 
 from ._binding import (  # noqa: F401
-    QhapError, Graph, build_graph, build_graphs, bsb_solve, bsb_solve_batched, phase, flip_crossing, refine,
+    QhapError, Graph, build_graph, build_graphs, bsb_solve, bsb_solve_batched, phase, phase_batched,
+    flip_crossing, refine,
     adaptive_schedule, autotune, load_tuned, energy_trace, refine_adaptive,
     lib_path, load, version, to_device, KIND, STORAGE, DTYPE, Status,
 )

@@ -128,6 +128,7 @@ def load():
                                  ctypes.POINTER(_BatchedResult), P],
         "qh_phase": [P, P, P, P, P],
         "qh_phase_noalloc": [P, P, P, P, P],
+        "qh_phase_batched": [P, ctypes.c_int32, P, P, P, P],
         "qh_flip_crossing": [P, P, P],
         "qh_refine": [P, ctypes.POINTER(_BsbOpts), ctypes.c_int32, ctypes.c_float, ctypes.c_int32, P, P, P,
                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
@@ -183,6 +184,14 @@ class Graph:
     def __init__(self, handle: int, keep=()):
         self._h = ctypes.c_void_p(handle)
         self._keep = keep
+        self._n_snp = None
+
+    @property
+    def n_snp(self) -> int:
+        """SNP count of the graph's inputs (fixed for the graph's life; read once)."""
+        if self._n_snp is None:
+            self._n_snp = int(self.info()["n_snp"])
+        return self._n_snp
 
     @property
     def handle(self):
@@ -468,17 +477,38 @@ def phase(g: Graph, spins: torch.Tensor, n_snp: Optional[int] = None, stream=Non
     may supply the (h1, block) tensors."""
     if spins.dtype != torch.int8:
         raise TypeError("spins must be int8")
-    inf = g.info()
     if n_snp is None:
-        n_snp = inf["n_snp"]
+        n_snp = g.n_snp
+    elif n_snp != g.n_snp:
+        raise ValueError(f"n_snp = {n_snp}, the graph has {g.n_snp} SNPs")
     if out is None:
         h1 = torch.empty(max(n_snp, 1), dtype=torch.int8, device="cuda")
         block = torch.empty(max(n_snp, 1), dtype=torch.int32, device="cuda")
     else:
         h1, block = out
+        if h1.dtype != torch.int8 or block.dtype != torch.int32 or h1.numel() < n_snp or block.numel() < n_snp:
+            raise ValueError(f"out must be int8 and int32 tensors of at least {n_snp} elements")
     fn = load().qh_phase_noalloc if noalloc else load().qh_phase
     _check(fn(g.handle, _ptr(spins), _ptr(h1), _ptr(block), _stream(stream)))
     return h1[:n_snp], block[:n_snp]
+
+
+def phase_batched(graphs: Sequence[Graph], spins: torch.Tensor, stream=None):
+    """qh_phase_batched: every graph of a batched solve phased in one call.  ``spins`` packed as
+    bsb_solve_batched's best_spins; returns (h1, block, snp_offset): graph b's SNPs are
+    h1[snp_offset[b]:snp_offset[b + 1]] (and the same of block)."""
+    if spins.dtype != torch.int8:
+        raise TypeError("spins must be int8")
+    nb = len(graphs)
+    ns = [g.n_snp for g in graphs]
+    so = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    total = int(so[-1])
+    h1 = torch.empty(max(total, 1), dtype=torch.int8, device="cuda")
+    block = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+    if nb:
+        arr = (ctypes.c_void_p * nb)(*[g.handle.value for g in graphs])
+        _check(load().qh_phase_batched(arr, nb, _ptr(spins), _ptr(h1), _ptr(block), _stream(stream)))
+    return h1[:total], block[:total], so
 
 
 def refine_adaptive(g: Graph, *, seed: int = 0, deform: float = 0.0, deform_tries: int = 0,

@@ -368,6 +368,16 @@ qh_status qh_phase_noalloc(const qh_graph *g, const int8_t *spins, int8_t *h1, i
     });
 }
 
+qh_status qh_phase_batched(const qh_graph *const *graphs, int32_t n_graphs, const int8_t *spins, int8_t *h1,
+                           int32_t *block, void *stream) {
+    return guarded([&] {
+        if (n_graphs < 0) fail(QH_EINVAL, "n_graphs < 0");
+        if (n_graphs == 0) return;
+        if (!graphs || !spins || !h1 || !block) fail(QH_EINVAL, "null argument");
+        phase_batched(graphs, n_graphs, spins, h1, block, (hipStream_t)stream);
+    });
+}
+
 qh_status qh_flip_crossing(qh_graph *g, const int8_t *spins, void *stream) {
     return guarded([&] {
         if (!g || !spins) fail(QH_EINVAL, "null argument");

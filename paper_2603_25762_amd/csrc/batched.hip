@@ -94,7 +94,22 @@ void bsb_solve_batched(const qh_graph *const *gs, int nb, const qh_bsb_opts *o, 
 
     // per-block plans: state buffers and readout scratch of the single-graph solve
     std::vector<SolvePlan *> plans(nb);
-    for (int b = 0; b < nb; ++b) plans[b] = &solve_plan(gs[b], R, st);
+    {   // new plans' buffers cleared together, with one kernel
+        std::vector<std::pair<void *, size_t>> zl;
+        DevBuf<uint64_t> zt;
+        begin_plan_zeroing(zl);
+        try {
+            for (int b = 0; b < nb; ++b) plans[b] = &solve_plan(gs[b], R, st);
+        } catch (...) {
+            // the plans made so far stay with their graphs: clear them before failing
+            try {
+                end_plan_zeroing(zl, zt, st);
+            } catch (...) {
+            }
+            throw;
+        }
+        end_plan_zeroing(zl, zt, st);
+    }
     const float *pump = o->pump ? o->pump : linear_pump(*plans[0], o->steps, st);
 
     std::vector<BlockDesc> desc(nb);

@@ -1068,6 +1068,46 @@ static bool lr_copy(const qh_graph *g) {
     return g->storage == QH_STORE_SKYLINE && g->l_nnz > 0 && g->dtype != QH_F32;
 }
 
+// Clearing of new plans' state buffers: one memset each, or, between begin_plan_zeroing
+// and end_plan_zeroing on this thread (the batched solve creating thousands of plans), one
+// kernel over the collected list.
+static thread_local std::vector<std::pair<void *, size_t>> *t_plan_zero = nullptr;
+
+template <class T>
+static void plan_zero(DevBuf<T> &b, hipStream_t st) {
+    if (t_plan_zero) t_plan_zero->push_back({(void *)b.p, b.bytes()});
+    else b.zero(st);
+}
+
+// one workgroup per buffer; the allocator's blocks are 256-byte aligned and the buffers
+// hold 2- or 4-byte elements
+__global__ void k_zero_buffers(const uint64_t *__restrict__ ptr, const uint64_t *__restrict__ bytes) {
+    uint8_t *p = (uint8_t *)ptr[blockIdx.x];
+    const uint64_t nb = bytes[blockIdx.x];
+    const uint64_t n16 = nb / 16;
+    for (uint64_t i = threadIdx.x; i < n16; i += blockDim.x) ((uint4 *)p)[i] = make_uint4(0, 0, 0, 0);
+    for (uint64_t i = n16 * 16 + threadIdx.x; i < nb; i += blockDim.x) p[i] = 0;
+}
+
+void begin_plan_zeroing(std::vector<std::pair<void *, size_t>> &list) { t_plan_zero = &list; }
+
+void end_plan_zeroing(std::vector<std::pair<void *, size_t>> &list, DevBuf<uint64_t> &table, hipStream_t st) {
+    t_plan_zero = nullptr;
+    const size_t m = list.size();
+    if (!m) return;
+    if (m > 0x7fffffffu) fail(QH_EUNSUPPORTED, "too many buffers to clear");
+    std::vector<uint64_t> h(2 * m);
+    for (size_t i = 0; i < m; ++i) {
+        h[i] = (uint64_t)(uintptr_t)list[i].first;
+        h[m + i] = (uint64_t)list[i].second;
+    }
+    table.alloc(2 * m);
+    table.upload(h.data(), 2 * m, st);
+    hipLaunchKernelGGL(k_zero_buffers, dim3((unsigned)m), dim3(256), 0, st, table.p, table.p + m);
+    QH_CHECK_LAUNCH();
+    QH_HIP(hipStreamSynchronize(st));   // the host table goes out of scope
+}
+
 SolvePlan &solve_plan(const qh_graph *gc, int R, hipStream_t st) {
     qh_graph *g = const_cast<qh_graph *>(gc);
     auto it = g->plans.find(R);
@@ -1077,24 +1117,24 @@ SolvePlan &solve_plan(const qh_graph *gc, int R, hipStream_t st) {
     p->n_pad = ceil_div(std::max<int64_t>(g->n, 1), kTile) * kTile;
     size_t st_elems = (size_t)p->n_pad * R;
     p->xa.alloc(st_elems);
-    p->xa.zero(st);
+    plan_zero(p->xa, st);
     p->y.alloc(st_elems);
-    p->y.zero(st);
+    plan_zero(p->y, st);
     bool dense16 = g->storage == QH_STORE_DENSE && g->dtype != QH_F32;
     if (!dense16) {
         p->xb.alloc(st_elems);
-        p->xb.zero(st);
+        plan_zero(p->xb, st);
         if (lr_copy(g)) {
             p->la.alloc(st_elems);
-            p->la.zero(st);
+            plan_zero(p->la, st);
             p->lb.alloc(st_elems);
-            p->lb.zero(st);
+            plan_zero(p->lb, st);
         }
     } else {
         p->ha.alloc(st_elems);
-        p->ha.zero(st);
+        plan_zero(p->ha, st);
         p->hb.alloc(st_elems);
-        p->hb.zero(st);
+        plan_zero(p->hb, st);
     }
     alloc_readout_scratch(*p, g->n, g->n_comp, g->n_chunks, R);
     if (g->n_hub_chunks) p->hub_part.alloc((size_t)g->n_hub_chunks * R);

@@ -313,6 +313,8 @@ void plan_info(const qh_graph *g, int R, qh_plan_info *out);
 // phase.hip
 void phase(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);
 void phase_noalloc(const qh_graph *g, const int8_t *spins, int8_t *h1, int32_t *block, hipStream_t st);
+void phase_batched(const qh_graph *const *gs, int nb, const int8_t *spins, int8_t *h1, int32_t *block,
+                   hipStream_t st);
 void refine(qh_graph *g, const qh_bsb_opts *o, int max_rounds, float deform, int deform_tries, int8_t *h1,
             int32_t *block, int32_t *flips, double *round_cuts, int32_t *rounds_out, int32_t *deformed_out,
             hipStream_t st);
@@ -364,6 +366,10 @@ __device__ inline uint64_t sm64_draw(uint64_t seed, uint64_t k) {
 }
 
 SolvePlan &solve_plan(const qh_graph *g, int R, hipStream_t st);
+// Between these two calls on one thread, new plans' state buffers are collected instead of
+// cleared one by one; the end clears them all with one kernel (and synchronises st).
+void begin_plan_zeroing(std::vector<std::pair<void *, size_t>> &list);
+void end_plan_zeroing(std::vector<std::pair<void *, size_t>> &list, DevBuf<uint64_t> &table, hipStream_t st);
 const float *linear_pump(SolvePlan &p, int steps, hipStream_t st);   // p_k = k / (steps - 1)
 
 // batched.hip

@@ -56,3 +56,12 @@ def test_build_graphs_validates_on_the_host():
     assert lib.qh_build_graphs(1, None, None, None, None, -1, None) == qh.Status.EINVAL
     assert lib.qh_build_graphs(0, None, None, None, None, 0, None) == qh.Status.OK
     assert qh.build_graphs([]) == []
+
+
+def test_phase_batched_validates_on_the_host():
+    """qh_phase_batched rejects a negative graph count and null arrays before any device
+    call; an empty list is a no-op."""
+    lib = qh.load()
+    assert lib.qh_phase_batched(None, -1, None, None, None, None) == qh.Status.EINVAL
+    assert lib.qh_phase_batched(None, 0, None, None, None, None) == qh.Status.OK
+    assert lib.qh_phase_batched(None, 2, None, None, None, None) == qh.Status.EINVAL

@@ -7,6 +7,7 @@ software rounding), one bSB step (<= 1e-5 of the step's own magnitude), the
 FP64 readout (exact for integer weights), phasing (exact), and the final best
 cut of a whole solve (<= 0.1 % below the FP64 oracle, equal switch error).
 """
+import ctypes
 import json
 
 import numpy as np
@@ -793,6 +794,46 @@ def test_phase_parity_exact():
     h1, blk = qh.phase(g, torch.tensor(s, device="cuda"))
     ho, bo = oracle.phase_parity(comp, nc, s, w.init_h1)
     assert np.array_equal(cpu(h1), ho) and np.array_equal(cpu(blk), bo)
+
+
+def test_phase_batched_equals_per_graph_phase():
+    """qh_phase_batched over a list of read and SNP graphs (one and zero fragments, long-range
+    rows, many components among them), with random spins packed as a batched solve packs
+    them: every graph's slice of h1 and block equals qh_phase on that graph, bit for bit; and
+    on the spins of a batched solve, every block's haplotype equals its qh_phase."""
+    batch = synth.batched_blocks(93, n_blocks=40, n_lo=20, n_hi=600)
+    gs = [gpu_graph(w, "read_signed" if i % 2 == 0 else "snp_llr", w.solve["dtype"])
+          for i, w in enumerate(batch.blocks)]
+    gs.append(gpu_graph(synth.read_tiny(), "read_conflict"))
+    gs.append(gpu_graph(synth.snp_porec(45, n_snp=2000, n_edges=2500, zipf_s=1.0), "snp_llr", "bf16",
+                        band_limit=64))
+    for nf in (1, 0):
+        w = synth.read_small(25, n_snp=50, n_reads=1, span=(5, 10))
+        fp = w.frag_ptr[: nf + 1].copy()
+        gs.append(qh.build_graph(qh.to_device(fp), qh.to_device(w.snp[: fp[-1]].copy()),
+                                 qh.to_device(w.allele[: fp[-1]].copy()), qh.to_device(w.phred[: fp[-1]].copy()),
+                                 qh.to_device(w.init_h1)))
+    ns = [g.info()["n"] for g in gs]
+    vo = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    rng = np.random.default_rng(17)
+    spins = torch.tensor(rng.choice(np.array([-1, 1], dtype=np.int8), size=max(int(vo[-1]), 1)), device="cuda")
+    h1, blk, so = qh.phase_batched(gs, spins)
+    assert len(so) == len(gs) + 1 and int(so[-1]) == sum(g.n_snp for g in gs)
+    for b, g in enumerate(gs):
+        sb = spins[int(vo[b]):int(vo[b + 1])] if ns[b] else torch.ones(1, dtype=torch.int8, device="cuda")
+        h1b, blkb = qh.phase(g, sb)
+        assert torch.equal(h1[int(so[b]):int(so[b + 1])], h1b), b
+        assert torch.equal(blk[int(so[b]):int(so[b + 1])], blkb), b
+    # the spins of a batched solve
+    r = qh.bsb_solve_batched(gs[:40], 32, 200, seed=4)
+    h1, blk, so = qh.phase_batched(gs[:40], r["best_spins"])
+    off = r["vertex_offset"]
+    for b, g in enumerate(gs[:40]):
+        h1b, blkb = qh.phase(g, r["best_spins"][int(off[b]):int(off[b + 1])])
+        assert torch.equal(h1[int(so[b]):int(so[b + 1])], h1b) and torch.equal(blk[int(so[b]):int(so[b + 1])], blkb)
+    arr = (ctypes.c_void_p * 2)(gs[0].handle.value, None)       # a null graph in the list
+    rc = qh.load().qh_phase_batched(arr, 2, spins.data_ptr(), h1.data_ptr(), blk.data_ptr(), None)
+    assert rc == qh.Status.EINVAL
 
 
 def test_flip_crossing_matches_oracle():
