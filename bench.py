@@ -428,7 +428,7 @@ def bench_read_mhc(a):
     import paper_2603_25762_amd as qh
     import synth
 
-    dtype = a.dtype or "f16"
+    dtype = a.dtype or "bf16"     # one of the workload's named forms (FP32, BF16, FP8 with row scales)
     R, STEPS, DT = 256, 2000, 0.5
     torch.cuda.set_device(0)
     w = synth.read_mhc()
@@ -499,9 +499,21 @@ def bench_read_mhc(a):
         out.update(oracle_best_cut=ref["best_cut"], cut_gap=(ref["best_cut"] - best_cut) / abs(ref["best_cut"]),
                    oracle_switch_error=ref["switch_error"])
     out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth, w.pos))
+    if ref is not None:
+        out["switch_error_equal"] = out["switch_error"] == ref["switch_error"]
     if not a.no_extras:
         out["time_to_phase_ms"] = round(time_to_phase_single(qh, w, "read_signed", dtype, R, STEPS, DT, seed,
                                                              plan=plan, **kw), 2)
+        # the plain form: J stored in FP32 (the autotuner's plan for it), one whole solve
+        g32 = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="read_signed",
+                             dtype="f32")
+        qh.bsb_solve(g32, R, STEPS, dt=DT, seed=seed, plan=0, readout=False)
+        r32 = qh.bsb_solve(g32, R, STEPS, dt=DT, seed=seed)
+        ms32 = event_ms(lambda: qh.bsb_solve(g32, R, STEPS, dt=DT, seed=seed))
+        cut32 = float(r32["best_cut"].cpu()[0])
+        out["fp32_form"] = dict(value=nnz * R * STEPS / (ms32 * 1e-3), ms_per_solve=round(ms32, 3),
+                                cut_gap=(ref["best_cut"] - cut32) / abs(ref["best_cut"]) if ref else None)
+        g32.free()
     g.free()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_single(w, "read_signed", R, STEPS, DT, seed, STEPS)
@@ -607,6 +619,8 @@ def bench_snp(a):
         out.update(oracle_best_cut=ref["best_cut"], cut_gap=(ref["best_cut"] - best_cut) / abs(ref["best_cut"]),
                    oracle_switch_error=ref["switch_error"])
     out.update(phasing_errors(h1.cpu().numpy(), blk.cpu().numpy(), w.truth, w.pos))
+    if ref is not None:
+        out["switch_error_equal"] = out["switch_error"] == ref["switch_error"]
     if not a.no_extras:
         out["time_to_phase_ms"] = round(time_to_phase_single(qh, w, "snp_llr", dtype, R, STEPS, DT, SEED,
                                                              band_limit=band, plan=plan), 2)
