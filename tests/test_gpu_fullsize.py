@@ -94,14 +94,16 @@ def test_snp_chromosome_full_size(name):
     g.free()
 
 
-def test_read_mhc_full_size():
-    """C2 (8,000 reads, dense FP16 tiles, R = 256, 2,000 steps, autotuned plan)."""
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_read_mhc_full_size(dtype):
+    """C2 (8,000 reads, dense BF16 tiles as the benchmark runs it, and FP16; R = 256, 2,000
+    steps, autotuned plan)."""
     ref = reference("read_mhc")
     w = synth.read_mhc()
     assert synth.workload_hash(w) == ref["hash"], "inputs changed: regenerate the reference"
     d = device_reads(w)
     g = qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="read_signed",
-                       dtype="f16")
+                       dtype=dtype)
     assert g.info()["nnz"] == ref["nnz"]
     r = qh.bsb_solve(g, ref["replicas"], ref["steps"], dt=ref["dt"], seed=ref["seed"])
     cut = float(cpu(r["best_cut"])[0])
