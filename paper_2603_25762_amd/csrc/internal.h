@@ -306,6 +306,7 @@ struct ReadoutDesc {
     int8_t *best_spins;
     double *cuts, *best_cut, *selected_cut;
     int32_t integer;            // 1: integer weights (any summation order is exact)
+    double *gain_acc;           // integer blocks: sum of the greedy pass's applied gains (set by the readout)
 };
 void readout_batched(const std::vector<ReadoutDesc> &descs, int R, bool greedy, hipStream_t st);
 void plan_info(const qh_graph *g, int R, qh_plan_info *out);

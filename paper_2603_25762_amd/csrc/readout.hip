@@ -496,25 +496,21 @@ __device__ inline int slice_of(const int32_t *__restrict__ wg, int nb, int64_t &
 
 // Integer weights: FP64 sums of integers (all below 2^53) are exact in any order, so one
 // wave takes one row and its lanes take the entries, with coalesced loads and a tree sum at
-// the end; the result equals the one-thread-per-row loop of gain_body / cut_rows_body bit
-// for bit (no term is -0 in the gain; in the cut a -0 term leaves a +0 sum +0 either way).
+// the end; the result equals the one-thread-per-row loop of gain_body bit for bit (no term
+// of a gain is -0).
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-// rows [0, n_rows) of a slice, one per wave: a = order ? order[v] : v;
-// out[v] = pre(a) * sum_j -w_j t(s_a, s_j) with t = s_j (gain) or 1 - s_a s_j (cut)
-template <bool GAIN>
-__device__ inline void rows_wave_body(int64_t bx, int64_t gx, int64_t n_rows, const int32_t *__restrict__ order,
-                                      const int64_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                                      const double *__restrict__ val, const int8_t *__restrict__ s,
-                                      double *__restrict__ out) {
+// gains of vertices [0, n) of a slice, one per wave: out[a] = s_a * sum_j -w_j s_j
+__device__ inline void gain_wave_body(int64_t bx, int64_t gx, int64_t n, const int64_t *__restrict__ ptr,
+                                      const int32_t *__restrict__ col, const double *__restrict__ val,
+                                      const int8_t *__restrict__ s, double *__restrict__ out) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int64_t v = bx * 4 + wave; v < n_rows; v += gx * 4) {
-        const int64_t a = order ? order[v] : v;
+    for (int64_t a = bx * 4 + wave; a < n; a += gx * 4) {
         const int sa = s[a];
         const int64_t e1 = ptr[a + 1];
         double acc = 0.0;
@@ -530,12 +526,11 @@ __device__ inline void rows_wave_body(int64_t bx, int64_t gx, int64_t n_rows, co
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 if (e + 64 * k >= e1) break;
-                const int sb = s[c[k]];
-                acc += GAIN ? -w[k] * (double)sb : -w[k] * (1.0 - (double)(sa * sb));
+                acc += -w[k] * (double)s[c[k]];
             }
         }
         acc = wave_sum(acc);
-        if (lane == 0) out[v] = GAIN ? (double)sa * acc : acc;
+        if (lane == 0) out[a] = (double)sa * acc;
     }
 }
 
@@ -553,21 +548,19 @@ __global__ void kb_signs(const ReadoutDesc *tbl, const int32_t *wg, int nb, int 
 __global__ void kb_cut_rows(const ReadoutDesc *tbl, const int32_t *wg, int nb, int R, int final_cut) {
     QH_B(final_cut ? kRows1 : kRowsR);
     if (D.n_comp == 0) return;
-    if (final_cut && D.integer) {
-        rows_wave_body<false>(bx, gx, D.n_ord, D.comp_order, D.m_ptr, D.m_col, D.m_val, D.best_spins, D.rowcut);
-        return;
-    }
+    if (final_cut && D.integer) return;   // (no workgroups are given to it: see kb_totals)
     cut_rows_body(bx, gx, D.n_ord, final_cut ? 1 : R, D.comp_order, D.m_ptr, D.m_col, D.m_val,
                   final_cut ? D.best_spins : D.spins, D.rowcut);
 }
 __global__ void kb_cut_chunks(const ReadoutDesc *tbl, const int32_t *wg, int nb, int R, int final_cut) {
     QH_B(final_cut ? kChunks1 : kChunksR);
-    if (D.n_comp == 0) return;
+    if (D.n_comp == 0 || (final_cut && D.integer)) return;
     cut_chunks_body(bx, gx, D.n_chunks, final_cut ? 1 : R, D.chunk_begin, D.chunk_end, D.rowcut,
                     final_cut ? D.part1 : D.part);
 }
 __global__ void kb_cut_reduce(const ReadoutDesc *tbl, const int32_t *wg, int nb, int R, int final_cut) {
     QH_B(kReduce);
+    if (final_cut && D.integer) return;
     cut_reduce_body(bx, gx, D.n_comp, final_cut ? 1 : R, D.comp_chunk_ptr, final_cut ? D.part1 : D.part,
                     final_cut ? D.cut1 : D.cut_rc);
 }
@@ -579,8 +572,13 @@ __global__ void kb_select(const ReadoutDesc *tbl, const int32_t *wg, int nb, int
 __global__ void kb_totals(const ReadoutDesc *tbl, const int32_t *wg, int nb, int R, int final_cut) {
     QH_B(kOne);
     if (final_cut) {
-        if (D.n_comp) selected_total_body(D.n_comp, D.cut1, nullptr, D.best_cut);
-        else if (threadIdx.x == 0) *D.best_cut = 0.0;
+        if (D.n_comp && D.integer) {   // the selected cut plus the applied gains (kb_apply_flips)
+            if (threadIdx.x == 0) *D.best_cut = *(D.selected_cut ? D.selected_cut : D.best_cut) + *D.gain_acc;
+        } else if (D.n_comp) {
+            selected_total_body(D.n_comp, D.cut1, nullptr, D.best_cut);
+        } else if (threadIdx.x == 0) {
+            *D.best_cut = 0.0;
+        }
         return;
     }
     double *sel = D.selected_cut ? D.selected_cut : D.best_cut;
@@ -600,7 +598,7 @@ __global__ void kb_gain(const ReadoutDesc *tbl, const int32_t *wg, int nb) {
     QH_B(kGain);
     if (D.n_comp == 0) return;
     if (D.integer) {
-        rows_wave_body<true>(bx, gx, D.n, nullptr, D.m_ptr, D.m_col, D.m_val, D.best_spins, D.gain);
+        gain_wave_body(bx, gx, D.n, D.m_ptr, D.m_col, D.m_val, D.best_spins, D.gain);
         return;
     }
     gain_body(bx, gx, D.n, D.m_ptr, D.m_col, D.m_val, D.best_spins, D.gain);
@@ -610,18 +608,38 @@ __global__ void kb_pick(const ReadoutDesc *tbl, const int32_t *wg, int nb, int32
     if (D.n_comp == 0) return;
     pick_body(bx, gx, D.n, D.m_ptr, D.m_col, D.gain, D.eps, nullptr, D.flag, count);
 }
+// Integer blocks also add up the gains they apply: a round flips an independent set, which
+// raises the cut by exactly the sum of its gains, integers that FP64 adds exactly in any
+// order, so the final cut is the selected one plus that sum, as a recount would give it.
 __global__ void kb_apply_flips(const ReadoutDesc *tbl, const int32_t *wg, int nb) {
     QH_B(kVert);
     if (D.n_comp == 0) return;
+    if (D.integer) {
+        __shared__ double part[4];
+        double s = 0.0;
+        for (int64_t a = bx * (int64_t)blockDim.x + threadIdx.x; a < D.n; a += gx * (int64_t)blockDim.x)
+            if (D.flag[a]) s += D.gain[a];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double t = part[0] + part[1] + part[2] + part[3];
+            if (t != 0.0) atomicAdd(D.gain_acc, t);
+        }
+    }
     apply_flips_body(bx, gx, D.n, D.flag, D.best_spins);
 }
 #undef QH_B
 
 // Readout of every block of a batch with one launch per kernel (plus one synchronisation
 // per greedy round for the whole batch).
-void readout_batched(const std::vector<ReadoutDesc> &descs, int R, bool greedy, hipStream_t st) {
-    const int nb = (int)descs.size();
+void readout_batched(const std::vector<ReadoutDesc> &descs_in, int R, bool greedy, hipStream_t st) {
+    const int nb = (int)descs_in.size();
     if (nb == 0) return;
+    DevBuf<double> acc(nb);   // applied greedy gains per block (integer blocks)
+    acc.zero(st);
+    std::vector<ReadoutDesc> descs(descs_in);
+    for (int b = 0; b < nb; ++b) descs[b].gain_acc = acc.p + b;
     // workgroups per block for every index space, as the single-graph launches size them
     std::vector<int32_t> wg((size_t)kSlices * (nb + 1), 0);
     auto fill = [&](int slice, auto work) {
@@ -635,10 +653,11 @@ void readout_batched(const std::vector<ReadoutDesc> &descs, int R, bool greedy, 
     fill(kComp, [&](const ReadoutDesc &d) { return grid_for(d.n_comp); });
     fill(kOne, [&](const ReadoutDesc &) { return 1; });
     fill(kVert, [&](const ReadoutDesc &d) { return grid_for(d.n); });
-    // the integer blocks' R = 1 row sums take one wave per row (four rows per workgroup)
-    fill(kRows1, [&](const ReadoutDesc &d) { return d.integer ? grid_for(d.n_ord, 4) : grid_for(d.n_ord); });
+    // the integer blocks' greedy gains take one wave per row (four rows per workgroup), and
+    // their final cut comes from the applied gains, with no pass over their rows
+    fill(kRows1, [&](const ReadoutDesc &d) { return d.integer ? 0 : grid_for(d.n_ord); });
     fill(kGain, [&](const ReadoutDesc &d) { return d.integer ? grid_for(d.n, 4) : grid_for(d.n); });
-    fill(kChunks1, [&](const ReadoutDesc &d) { return grid_for(d.n_chunks); });
+    fill(kChunks1, [&](const ReadoutDesc &d) { return d.integer ? 0 : grid_for(d.n_chunks); });
     auto total = [&](int slice) { return (unsigned)wg[(size_t)slice * (nb + 1) + nb]; };
     DevBuf<ReadoutDesc> d_tbl(nb);
     DevBuf<int32_t> d_wg(wg.size()), d_cnt(2);
@@ -671,8 +690,8 @@ void readout_batched(const std::vector<ReadoutDesc> &descs, int R, bool greedy, 
             QH_CHECK_LAUNCH();
         }
     }
-    hipLaunchKernelGGL(kb_cut_rows, dim3(total(kRows1)), dim3(256), 0, st, T, W, nb, R, 1);
-    hipLaunchKernelGGL(kb_cut_chunks, dim3(total(kChunks1)), dim3(256), 0, st, T, W, nb, R, 1);
+    if (total(kRows1)) hipLaunchKernelGGL(kb_cut_rows, dim3(total(kRows1)), dim3(256), 0, st, T, W, nb, R, 1);
+    if (total(kChunks1)) hipLaunchKernelGGL(kb_cut_chunks, dim3(total(kChunks1)), dim3(256), 0, st, T, W, nb, R, 1);
     hipLaunchKernelGGL(kb_cut_reduce, dim3(total(kReduce)), dim3(64), 0, st, T, W, nb, R, 1);
     hipLaunchKernelGGL(kb_totals, dim3(total(kOne)), dim3(256), 0, st, T, W, nb, R, 1);
     QH_CHECK_LAUNCH();
