@@ -212,13 +212,15 @@ def batch_inputs(qh, batch):
     """Every block's fragment arrays on the device from one host-to-device copy per array
     kind: the blocks' arrays are views into the concatenation."""
     import numpy as np
+    import torch
     names = ("frag_ptr", "snp", "allele", "phred", "alpha", "init_h1")
     arrs = [w.arrays() for w in batch.blocks]
     views = [dict() for _ in arrs]
     for k in names:
         parts = [np.ascontiguousarray(a[k]) for a in arrs]
         off = np.concatenate([[0], np.cumsum([p.size for p in parts])]).astype(np.int64)
-        dev = qh.to_device(np.concatenate(parts))
+        # staged through a new pinned tensor: the copy to the device then runs at DMA speed
+        dev = torch.from_numpy(np.concatenate(parts)).pin_memory().to("cuda", non_blocking=True)
         for b in range(len(arrs)):
             views[b][k] = dev[int(off[b]):int(off[b + 1])]
     return views
