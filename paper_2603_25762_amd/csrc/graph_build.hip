@@ -41,10 +41,19 @@ __global__ void k_gather_i8(int64_t n, const int64_t *__restrict__ idx, const in
 // ---------------------------------------------------------------------------
 
 // Per fragment: frag_ptr non-decreasing, SNP indices in range and strictly ascending,
-// alleles 0/1.  err[k] = lowest offending fragment + 1 for check k (0 when none).
+// alleles 0/1.  err[k] = lowest offending fragment + 1 for check k (all ones when none);
+// err[4] = frag_ptr[F] (the observation count) and err[5] = frag_ptr[0], so that one copy
+// brings everything back.  With frag_ptr[0] != 0 or a count outside [0, 2^31) nothing else
+// is read (the host reports those).
 __global__ void k_validate_frags(int64_t F, const int64_t *__restrict__ fp, const int32_t *__restrict__ snp,
-                                 const uint8_t *__restrict__ allele, int32_t n_snp, int64_t nobs,
+                                 const uint8_t *__restrict__ allele, int32_t n_snp,
                                  unsigned long long *__restrict__ err) {
+    const int64_t nobs = fp[F], fp0 = fp[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        err[4] = (unsigned long long)nobs;
+        err[5] = (unsigned long long)fp0;
+    }
+    if (fp0 != 0 || nobs < 0 || nobs > INT32_MAX) return;
     for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = fp[f], e = fp[f + 1];
         const unsigned long long tag = (unsigned long long)f + 1;
@@ -927,22 +936,19 @@ static void pack_dense_storage(qh_graph *g, const int32_t *W, int negate, hipStr
 static int64_t validate_fragments(const qh_reads *r, int32_t S, hipStream_t st) {
     const int64_t F = r->n_frag;
     int64_t nobs = 0;
-    if (F > 0) QH_HIP(hipMemcpyAsync(&nobs, r->frag_ptr + F, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    int64_t fp0 = 0;
-    if (F > 0) QH_HIP(hipMemcpyAsync(&fp0, r->frag_ptr, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    QH_HIP(hipStreamSynchronize(st));
-    if (fp0 != 0) fail(QH_EINVAL, "frag_ptr[0] must be 0");
-    if (nobs < 0) fail(QH_EINVAL, "frag_ptr decreases");
-    if (nobs > INT32_MAX) fail(QH_EUNSUPPORTED, "more than 2^31 observations");
     if (F > 0) {
-        DevBuf<unsigned long long> err(4);
+        DevBuf<unsigned long long> err(6);
         QH_HIP(hipMemsetAsync(err.p, 0xFF, 4 * sizeof(unsigned long long), st));
         hipLaunchKernelGGL(k_validate_frags, dim3(grid_for(F)), dim3(256), 0, st, F, r->frag_ptr, r->snp, r->allele,
-                           S, nobs, err.p);
+                           S, err.p);
         QH_CHECK_LAUNCH();
-        unsigned long long eh[4];
+        unsigned long long eh[6];
         QH_HIP(hipMemcpyAsync(eh, err.p, sizeof(eh), hipMemcpyDeviceToHost, st));
         QH_HIP(hipStreamSynchronize(st));
+        nobs = (int64_t)eh[4];
+        if ((int64_t)eh[5] != 0) fail(QH_EINVAL, "frag_ptr[0] must be 0");
+        if (nobs < 0) fail(QH_EINVAL, "frag_ptr decreases");
+        if (nobs > INT32_MAX) fail(QH_EUNSUPPORTED, "more than 2^31 observations");
         if (eh[0] != ~0ull) fail(QH_EINVAL, "frag_ptr decreases at fragment %llu", eh[0] - 1);
         if (eh[1] != ~0ull) fail(QH_EINVAL, "fragment %llu: SNP index out of range", eh[1] - 1);
         if (eh[2] != ~0ull) fail(QH_EINVAL, "fragment %llu: SNP indices not strictly ascending", eh[2] - 1);
@@ -1399,30 +1405,38 @@ static void refresh_total_weight(qh_graph *g, hipStream_t st) {
 }
 
 void finalize_graph(qh_graph *g, hipStream_t st) {
-    // c0 = 0.5 / (sigma sqrt(n)), sigma^2 = sum J^2 / (n (n - 1))
+    // W (as refresh_total_weight), c0 = 0.5 / (sigma sqrt(n)) with sigma^2 = sum J^2 /
+    // (n (n - 1)), and the greedy tolerance of float weights: the partial sums and row sums
+    // of all three come back in one copy
     const int parts = 1024;
-    DevBuf<double> part(parts);
-    refresh_total_weight(g, st);
-    if (g->nnz) {
-        hipLaunchKernelGGL(k_sumsq_partial, dim3(parts), dim3(256), 0, st, g->nnz, g->m_val.p, part.p);
-        QH_CHECK_LAUNCH();
-        auto ph = download(part.p, parts, st);
-        double ss = 0.0;
-        for (double v : ph) ss += v;
-        if (ss > 0.0 && g->n >= 2) {
-            double sigma = std::sqrt(ss / ((double)g->n * (double)(g->n - 1)));
-            g->c0_auto = 0.5 / (sigma * std::sqrt((double)g->n));
+    const int64_t nrs = (!g->integer && g->n) ? g->n : 0;
+    g->total_weight = 0.0;
+    if (g->nnz || nrs) {
+        DevBuf<double> buf(2 * parts + nrs);
+        if (g->nnz) {
+            hipLaunchKernelGGL(k_sum_partial, dim3(parts), dim3(256), 0, st, g->nnz, g->m_val.p, buf.p, 0);
+            hipLaunchKernelGGL(k_sumsq_partial, dim3(parts), dim3(256), 0, st, g->nnz, g->m_val.p, buf.p + parts);
         }
-    }
-    if (!g->integer && g->n) {
-        DevBuf<double> rs(g->n);
-        hipLaunchKernelGGL(k_row_abssum, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, g->m_ptr.p, g->m_val.p,
-                           rs.p);
+        if (nrs)
+            hipLaunchKernelGGL(k_row_abssum, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, g->m_ptr.p, g->m_val.p,
+                               buf.p + 2 * parts);
         QH_CHECK_LAUNCH();
-        auto h = download(rs.p, g->n, st);
-        double m = 0.0;
-        for (double v : h) m = std::max(m, v);
-        g->greedy_eps = 1e-12 * m;
+        auto h = download(buf.p, (size_t)(2 * parts + nrs), st);
+        if (g->nnz) {
+            double sj = 0.0, ss = 0.0;
+            for (int i = 0; i < parts; ++i) sj += h[i];
+            for (int i = 0; i < parts; ++i) ss += h[parts + i];
+            g->total_weight = -0.5 * sj;
+            if (ss > 0.0 && g->n >= 2) {
+                double sigma = std::sqrt(ss / ((double)g->n * (double)(g->n - 1)));
+                g->c0_auto = 0.5 / (sigma * std::sqrt((double)g->n));
+            }
+        }
+        if (nrs) {
+            double m = 0.0;
+            for (int64_t i = 0; i < nrs; ++i) m = std::max(m, h[2 * parts + i]);
+            g->greedy_eps = 1e-12 * m;
+        }
     }
     g->device_bytes = (int64_t)(g->m_ptr.bytes() + g->m_col.bytes() + g->m_val.bytes() + g->comp.bytes() +
                                 g->comp_first.bytes() + g->comp_order.bytes() + g->chunk_comp.bytes() +

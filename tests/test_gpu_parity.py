@@ -1170,6 +1170,12 @@ def test_error_paths():
     with pytest.raises(qh.QhapError) as e:
         qh.build_graph(fp, d["snp"], d["allele"], d["phred"], d["init_h1"])
     assert e.value.status == qh.Status.EINVAL
+    for i, v in ((0, 1), (-1, -1)):                      # frag_ptr[0] != 0; a negative count
+        fp = d["frag_ptr"].clone()
+        fp[i] = v
+        with pytest.raises(qh.QhapError) as e:
+            qh.build_graph(fp, d["snp"], d["allele"], d["phred"], d["init_h1"])
+        assert e.value.status == qh.Status.EINVAL
     n = g.info()["n"]
     x = torch.zeros((n, 16), device="cuda")
     x[3, 2] = float("nan")
