@@ -359,13 +359,16 @@ def bench_batched(a):
     if ref is not None:
         out.update(batch_gaps(qh, gs, r, batch, ref))
         out["oracle_reference"] = "tests/golden/batched_reference.json (stratified 5% subset: 150 blocks)"
+    out["graph_device_bytes"] = int(sum(i["device_bytes"] for i in infos))
+    # the batch is done: its device blocks go back to the library's cache, from which the
+    # next batch's graphs are built, as in a loop over batches
+    for g in gs:
+        g.free()
     if not a.no_extras:
         ttp, parts = time_to_phase_batched(qh, batch, R, STEPS, kw)
         out["time_to_phase_ms"] = round(ttp, 1)
         out["time_to_phase_parts_ms"] = parts
         out["fp32_form"] = fp32_form_batched(qh, batch, R, STEPS, DT, SEED, ref, a)
-    for g in gs:
-        g.free()
     if not a.no_cpu_baseline and ref is not None:
         out["cpu_baseline"] = cpu_baseline_batched(batch, ref)
     print(json.dumps(out), flush=True)

@@ -24,6 +24,9 @@
  *    pass) synchronise the stream themselves and say so.
  *  - The library recycles its device temporaries in stream order: make its calls from
  *    one host thread at a time (qh_build_graphs runs host threads of its own inside).
+ *    Device memory it releases (temporaries, freed graphs) stays cached for its later
+ *    requests, up to a quarter of the device's memory (at most 64 GiB per device);
+ *    qh_release_cached_memory hands it back to the device.
  *  - Spin / momentum state is laid out [n][R] (replica index fastest), FP32.
  *  - Ising convention (Eqs. 4-6): E(s) = -1/2 s^T J s, A = -J, and
  *    cut(s) = 1/4 sum_{a,b} A_ab (1 - s_a s_b).
@@ -451,6 +454,13 @@ typedef struct {
 } qh_schedule;
 
 qh_status qh_adaptive_schedule(int64_t size, qh_schedule *out);
+
+/* Hands every cached idle block of device memory (see Conventions) back to the devices
+ * with hipFree, for callers that need the memory elsewhere (PyTorch's allocator, other
+ * libraries).  Blocks in use are untouched.  released (optional host int64): the bytes
+ * handed back.  Must not run concurrently with another library call.  Errors: none beyond
+ * EHIP. */
+qh_status qh_release_cached_memory(int64_t *released);
 
 const char *qh_last_error(void);
 const char *qh_version(void);

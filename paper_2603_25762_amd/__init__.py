@@ -15,5 +15,5 @@ from ._binding import (  # noqa: F401
     QhapError, Graph, build_graph, build_graphs, bsb_solve, bsb_solve_batched, phase, phase_batched,
     flip_crossing, refine,
     adaptive_schedule, autotune, load_tuned, energy_trace, refine_adaptive,
-    lib_path, load, version, to_device, KIND, STORAGE, DTYPE, Status,
+    lib_path, load, version, release_cached_memory, to_device, KIND, STORAGE, DTYPE, Status,
 )

@@ -137,6 +137,7 @@ def load():
         "qh_autotune": [P, ctypes.POINTER(_BsbOpts), ctypes.POINTER(_BsbOpts), ctypes.POINTER(ctypes.c_float),
                         ctypes.c_char_p, P],
         "qh_adaptive_schedule": [ctypes.c_int64, ctypes.POINTER(_Schedule)],
+        "qh_release_cached_memory": [ctypes.POINTER(ctypes.c_int64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -152,6 +153,13 @@ def load():
 
 def version() -> str:
     return load().qh_version().decode()
+
+
+def release_cached_memory() -> int:
+    """Hands the library's cached idle device blocks back to the device; returns the bytes."""
+    out = ctypes.c_int64(0)
+    _check(load().qh_release_cached_memory(ctypes.byref(out)))
+    return out.value
 
 
 def _check(rc: int):

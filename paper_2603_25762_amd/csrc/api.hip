@@ -195,6 +195,13 @@ qh_status qh_build_graphs(int64_t count, const qh_reads *reads, const qh_snps *s
     });
 }
 
+qh_status qh_release_cached_memory(int64_t *released) {
+    return guarded([&] {
+        const size_t b = release_cached();
+        if (released) *released = (int64_t)b;
+    });
+}
+
 qh_status qh_graph_free(qh_graph *g) {
     return guarded([&] {
         if (!g) return;

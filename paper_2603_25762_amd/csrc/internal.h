@@ -40,6 +40,8 @@ void device_free(void *p);
 // (only once no queued work can still use its blocks).
 void set_pool(uintptr_t tag);
 void merge_pool(int device, uintptr_t tag);
+// hands every cached idle block of every device back with hipFree; returns the bytes released
+size_t release_cached();
 
 // Owning device buffer.
 template <class T>

@@ -7,8 +7,10 @@
 // Reuse is safe because every release happens when no queued work can still use the
 // block: temporaries are released after their stream has been synchronised, a buffer that
 // is reallocated waits for the device first, and graphs (with their solve plans) are freed
-// only after a device synchronisation.  At most kCacheCap bytes per device stay cached;
-// a failed hipMalloc releases the device's cached blocks and tries once more.
+// only after a device synchronisation.  At most a quarter of the device's memory (and no
+// more than kCacheCapMax) stays cached per device, enough for the graphs of a large batch to
+// be recycled into the next one; a failed hipMalloc releases the device's cached blocks and
+// tries once more, and release_cached() hands every cached block back to the device.
 //
 // That argument holds within one stream.  Host threads that work on streams of their own
 // (the many-graph build) therefore get pools of their own: a thread with a pool tag
@@ -16,6 +18,7 @@
 // (which the many-graph build only opens to its threads after a device synchronisation,
 // with its caller waiting), and its pool joins the shared one once its stream has been
 // synchronised.
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -26,11 +29,13 @@ namespace qh {
 
 namespace {
 
-constexpr size_t kCacheCap = (size_t)4 << 30;
+constexpr size_t kCacheCapMax = (size_t)64 << 30;
+constexpr size_t kCacheCapDefault = (size_t)4 << 30;   // until the device's size is known
 
 struct DeviceCache {
     std::map<uintptr_t, std::multimap<size_t, void *>> idle;   // pool tag -> size class -> block
     size_t idle_bytes = 0;
+    size_t cap = 0;                                            // 0: not yet set
 };
 
 thread_local uintptr_t t_pool = 0;   // 0: the shared pool
@@ -65,6 +70,14 @@ void *device_alloc(size_t bytes) {
     const size_t cls = size_class(bytes == 0 ? 1 : bytes);
     std::lock_guard<std::mutex> lk(g_mu);
     DeviceCache &c = g_cache[dev];
+    if (!c.cap) {           // the device is current here
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && total_b)
+            c.cap = std::min(total_b / 4, kCacheCapMax);
+        else
+            (void)hipGetLastError();
+        if (!c.cap) c.cap = kCacheCapDefault;
+    }
     for (uintptr_t tag : {t_pool, (uintptr_t)0}) {
         auto &pool = c.idle[tag];
         auto it = pool.lower_bound(cls);
@@ -99,7 +112,7 @@ void device_free(void *p) {
     const Block b = it->second;
     g_live.erase(it);
     DeviceCache &c = g_cache[b.device];
-    if (c.idle_bytes + b.cls > kCacheCap) {
+    if (c.idle_bytes + b.cls > (c.cap ? c.cap : kCacheCapDefault)) {
         int cur = 0;
         (void)hipGetDevice(&cur);
         if (cur != b.device) (void)hipSetDevice(b.device);
@@ -112,6 +125,21 @@ void device_free(void *p) {
 }
 
 void set_pool(uintptr_t tag) { t_pool = tag; }
+
+size_t release_cached() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    size_t released = 0;
+    int cur = -1;
+    for (auto &kv : g_cache) {
+        if (kv.second.idle.empty()) continue;   // no device call when nothing is cached
+        if (cur < 0) (void)hipGetDevice(&cur);
+        released += kv.second.idle_bytes;
+        if (kv.first != cur) (void)hipSetDevice(kv.first);
+        trim(kv.first);
+    }
+    if (cur >= 0) (void)hipSetDevice(cur);
+    return released;
+}
 
 void merge_pool(int device, uintptr_t tag) {
     if (tag == 0) return;

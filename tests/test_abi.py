@@ -65,3 +65,8 @@ def test_phase_batched_validates_on_the_host():
     assert lib.qh_phase_batched(None, -1, None, None, None, None) == qh.Status.EINVAL
     assert lib.qh_phase_batched(None, 0, None, None, None, None) == qh.Status.OK
     assert lib.qh_phase_batched(None, 2, None, None, None, None) == qh.Status.EINVAL
+
+
+def test_release_cached_memory_without_cached_blocks():
+    """With nothing cached the release makes no device call and reports zero bytes."""
+    assert qh.release_cached_memory() == 0

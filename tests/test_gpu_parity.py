@@ -1410,3 +1410,27 @@ def test_degenerate_graphs():
         assert float(cpu(r["best_cut"])[0]) == 0.0
         h1, blk = qh.phase(g, r["best_spins"] if nf else torch.ones(1, dtype=torch.int8, device="cuda"))
         assert np.all(cpu(h1) == -1)
+
+
+def test_release_cached_memory():
+    """A freed graph's device blocks stay cached (a rebuild reuses them) until
+    qh_release_cached_memory hands them back; a second release finds nothing, and the
+    library allocates afresh afterwards."""
+    w = synth.read_tiny()
+    d = device_reads(w)
+    torch.cuda.synchronize()
+    qh.release_cached_memory()
+
+    def build():
+        return qh.build_graph(d["frag_ptr"], d["snp"], d["allele"], d["phred"], d["init_h1"], kind="read_signed",
+                              dtype="fp8")
+
+    g = build()
+    need = g.info()["device_bytes"]
+    ref = qh.bsb_solve(g, 16, 50, seed=3)["best_cut"].cpu()
+    g.free()
+    assert qh.release_cached_memory() >= need
+    assert qh.release_cached_memory() == 0
+    g = build()
+    assert torch.equal(qh.bsb_solve(g, 16, 50, seed=3)["best_cut"].cpu(), ref)
+    g.free()
