@@ -54,14 +54,21 @@ __global__ void k_validate_frags(int64_t F, const int64_t *__restrict__ fp, cons
         err[5] = (unsigned long long)fp0;
     }
     if (fp0 != 0 || nobs < 0 || nobs > INT32_MAX) return;
-    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < F; f += (int64_t)gridDim.x * blockDim.x) {
+    // one wave per fragment, a lane per observation: the loads of a fragment go out together
+    const int lane = threadIdx.x & 63;
+    const int64_t wpb = blockDim.x >> 6;
+    for (int64_t f = blockIdx.x * wpb + (threadIdx.x >> 6); f < F; f += (int64_t)gridDim.x * wpb) {
         const int64_t b = fp[f], e = fp[f + 1];
         const unsigned long long tag = (unsigned long long)f + 1;
-        if (e < b || b < 0 || e > nobs) { atomicMin(&err[0], tag); continue; }
-        for (int64_t t = b; t < e; ++t) {
+        if (e < b || b < 0 || e > nobs) {
+            if (lane == 0) atomicMin(&err[0], tag);
+            continue;
+        }
+        for (int64_t t = b + lane; t < e; t += 64) {
             const int32_t j = snp[t];
+            const int32_t prev = t > b ? snp[t - 1] : INT32_MIN;
             if (j < 0 || j >= n_snp) atomicMin(&err[1], tag);
-            else if (t > b && j <= snp[t - 1]) atomicMin(&err[2], tag);
+            else if (t > b && j <= prev) atomicMin(&err[2], tag);
             if (allele[t] > 1) atomicMin(&err[3], tag);
         }
     }
@@ -462,64 +469,91 @@ __global__ void k_fixed_to_f64(int64_t n, double *__restrict__ v) {
     }
 }
 
+// kept observations of a fragment whose SNP index, allele code and Phred confidence
+// k_snp_pairs stages in LDS (a longer fragment's later partners come from memory)
+constexpr int kFragLds = 512;
+
 // Eqs. (9), (11)-(13) with the per-fragment factor alpha and the 1/(|S_i|-1)
 // normalisation of Eq. (14).  J = -w, so each pair term enters J with a + sign.
-// One thread per kept observation (fragment f, rank a); it handles the pairs
-// (a, b) with a < b <= a + L of its fragment.  In fixed-point mode a term of magnitude
+// One wave per fragment f and a lane per kept observation (rank a), which handles the
+// pairs (a, b) with a < b <= a + L of the fragment.  In fixed-point mode a term of magnitude
 // 2^20 or more cannot be represented: *clamped is set and the build fails.
-__global__ void k_snp_pairs(int64_t n_kept, const int64_t *__restrict__ kept_obs,
-                            const int32_t *__restrict__ kept_frag, const int64_t *__restrict__ kept_ptr,
-                            const int32_t *__restrict__ snp, const int8_t *__restrict__ M,
-                            const uint8_t *__restrict__ phred, const double *__restrict__ alpha,
-                            const double *__restrict__ qconf, int linkage_k, int32_t band_limit,
-                            const int64_t *__restrict__ s_off, const int32_t *__restrict__ s_lo,
-                            double *__restrict__ s_val64, const int64_t *__restrict__ l_ptr,
-                            const int32_t *__restrict__ l_col, double *__restrict__ l_val64, int fixed,
-                            int32_t *__restrict__ clamped) {
-    for (int64_t kk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; kk < n_kept;
-         kk += (int64_t)gridDim.x * blockDim.x) {
-        int32_t f = kept_frag[kk];
-        int64_t base = kept_ptr[f];
-        int64_t ns = kept_ptr[f + 1] - base;
-        if (ns < 2) continue;
-        int64_t L = (int64_t)linkage_k * (ns - 1) / 10;
-        int64_t a = kk - base;
-        int64_t bmax = a + L < ns - 1 ? a + L : ns - 1;
-        int64_t tu = kept_obs[kk];
-        int32_t u = snp[tu];
-        int Mu = M[tu];
-        double qu = qconf[phred[tu]];
-        double af = alpha ? alpha[f] : 1.0;
-        for (int64_t b = a + 1; b <= bmax; ++b) {
-            int64_t tv = kept_obs[base + b];
-            int32_t v = snp[tv];
-            double qv = qconf[phred[tv]];
-            double p_cis = qu * qv + (1.0 - qu) * (1.0 - qv);
-            double p_trans = qu * (1.0 - qv) + (1.0 - qu) * qv;
-            double sgn = (Mu * (int)M[tv] > 0) ? 1.0 : -1.0;
-            double l = sgn * log10(p_cis / p_trans);
-            double term = af * l / (double)(ns - 1);   // enters J = -w with + sign
-            // fixed = 1: the term as a multiple of 2^-40 (|term| clamped to 2^20), summed with
-            // integer atomics, whose result does not depend on the order of the additions
-            const double tc = term < -0x1p20 ? -0x1p20 : (term > 0x1p20 ? 0x1p20 : term);
-            if (fixed && !(fabs(term) < 0x1p20)) *clamped = 1;
-            const unsigned long long tq = (unsigned long long)(long long)__builtin_rint(tc * 0x1p40);
-            auto add = [&](double *p) {
-                if (fixed) atomicAdd((unsigned long long *)p, tq);
-                else unsafeAtomicAdd(p, term);
-            };
-            if (band_limit == 0 || v - u <= band_limit) {
-                add(&s_val64[s_off[u] + (v - s_lo[u])]);
-                add(&s_val64[s_off[v] + (u - s_lo[v])]);
-            } else {
-                int64_t lo = l_ptr[u], hi = l_ptr[u + 1];
-                while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < v) lo = m + 1; else hi = m; }
-                add(&l_val64[lo]);
-                lo = l_ptr[v]; hi = l_ptr[v + 1];
-                while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < u) lo = m + 1; else hi = m; }
-                add(&l_val64[lo]);
+__global__ __launch_bounds__(256) void k_snp_pairs(int64_t F, const int64_t *__restrict__ kept_obs,
+                                                   const int64_t *__restrict__ kept_ptr,
+                                                   const int32_t *__restrict__ snp, const int8_t *__restrict__ M,
+                                                   const uint8_t *__restrict__ phred,
+                                                   const double *__restrict__ alpha,
+                                                   const double *__restrict__ qconf, int linkage_k,
+                                                   int32_t band_limit, const int64_t *__restrict__ s_off,
+                                                   const int32_t *__restrict__ s_lo, double *__restrict__ s_val64,
+                                                   const int64_t *__restrict__ l_ptr,
+                                                   const int32_t *__restrict__ l_col, double *__restrict__ l_val64,
+                                                   int fixed, int32_t *__restrict__ clamped) {
+    __shared__ double s_q[4][kFragLds];
+    __shared__ int32_t s_u[4][kFragLds];
+    __shared__ int8_t s_m[4][kFragLds];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *sq = s_q[wave];
+    int32_t *su = s_u[wave];
+    int8_t *sm = s_m[wave];
+    for (int64_t f0 = (int64_t)blockIdx.x * 4; f0 < F; f0 += (int64_t)gridDim.x * 4) {
+        const int64_t f = f0 + wave;
+        int64_t base = 0, ns = 0;
+        if (f < F) {
+            base = kept_ptr[f];
+            ns = kept_ptr[f + 1] - base;
+        }
+        if (ns >= 2)
+            for (int64_t a = lane; a < ns && a < kFragLds; a += 64) {
+                const int64_t t = kept_obs[base + a];
+                su[a] = snp[t];
+                sm[a] = M[t];
+                sq[a] = qconf[phred[t]];
+            }
+        __syncthreads();
+        const int64_t L = ns >= 2 ? (int64_t)linkage_k * (ns - 1) / 10 : 0;
+        const double af = (ns >= 2 && alpha) ? alpha[f] : 1.0;
+        for (int64_t a = lane; L >= 1 && a < ns; a += 64) {
+            const bool sa = a < kFragLds;
+            const int64_t ta = sa ? 0 : kept_obs[base + a];
+            const int32_t u = sa ? su[a] : snp[ta];
+            const int Mu = sa ? sm[a] : M[ta];
+            const double qu = sa ? sq[a] : qconf[phred[ta]];
+            const int64_t bmax = a + L < ns - 1 ? a + L : ns - 1;
+            for (int64_t b = a + 1; b <= bmax; ++b) {
+                const bool sb = b < kFragLds;
+                const int64_t tb = sb ? 0 : kept_obs[base + b];
+                const int32_t v = sb ? su[b] : snp[tb];
+                const int Mv = sb ? sm[b] : M[tb];
+                const double qv = sb ? sq[b] : qconf[phred[tb]];
+                const double p_cis = qu * qv + (1.0 - qu) * (1.0 - qv);
+                const double p_trans = qu * (1.0 - qv) + (1.0 - qu) * qv;
+                const double sgn = (Mu * Mv > 0) ? 1.0 : -1.0;
+                const double l = sgn * log10(p_cis / p_trans);
+                const double term = af * l / (double)(ns - 1);   // enters J = -w with + sign
+                // fixed = 1: the term as a multiple of 2^-40 (|term| clamped to 2^20), summed with
+                // integer atomics, whose result does not depend on the order of the additions
+                const double tc = term < -0x1p20 ? -0x1p20 : (term > 0x1p20 ? 0x1p20 : term);
+                if (fixed && !(fabs(term) < 0x1p20)) *clamped = 1;
+                const unsigned long long tq = (unsigned long long)(long long)__builtin_rint(tc * 0x1p40);
+                auto add = [&](double *p) {
+                    if (fixed) atomicAdd((unsigned long long *)p, tq);
+                    else unsafeAtomicAdd(p, term);
+                };
+                if (band_limit == 0 || v - u <= band_limit) {
+                    add(&s_val64[s_off[u] + (v - s_lo[u])]);
+                    add(&s_val64[s_off[v] + (u - s_lo[v])]);
+                } else {
+                    int64_t lo = l_ptr[u], hi = l_ptr[u + 1];
+                    while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < v) lo = m + 1; else hi = m; }
+                    add(&l_val64[lo]);
+                    lo = l_ptr[v]; hi = l_ptr[v + 1];
+                    while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < u) lo = m + 1; else hi = m; }
+                    add(&l_val64[lo]);
+                }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -939,7 +973,7 @@ static int64_t validate_fragments(const qh_reads *r, int32_t S, hipStream_t st) 
     if (F > 0) {
         DevBuf<unsigned long long> err(6);
         QH_HIP(hipMemsetAsync(err.p, 0xFF, 4 * sizeof(unsigned long long), st));
-        hipLaunchKernelGGL(k_validate_frags, dim3(grid_for(F)), dim3(256), 0, st, F, r->frag_ptr, r->snp, r->allele,
+        hipLaunchKernelGGL(k_validate_frags, dim3(grid_for(F, 4)), dim3(256), 0, st, F, r->frag_ptr, r->snp, r->allele,
                            S, err.p);
         QH_CHECK_LAUNCH();
         unsigned long long eh[6];
@@ -1245,8 +1279,8 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
     if (n_kept) {
         DevBuf<int32_t> clamped(1);
         clamped.zero(st);
-        hipLaunchKernelGGL(k_snp_pairs, dim3(grid_for(n_kept, 256, 1 << 20)), dim3(256), 0, st, n_kept,
-                           kept_obs_d.p, kept_frag_d.p, kept_ptr_d.p, r->snp, M.p, r->phred, r->alpha, qconf.p,
+        hipLaunchKernelGGL(k_snp_pairs, dim3(grid_for(F, 4, 1 << 20)), dim3(256), 0, st, F,
+                           kept_obs_d.p, kept_ptr_d.p, r->snp, M.p, r->phred, r->alpha, qconf.p,
                            linkage_k, (int32_t)band_limit, g->s_off.p, g->s_lo.p, s_val64.p, g->l_ptr.p,
                            g->l_col.p, l_val64.p, g->deterministic, clamped.p);
         QH_CHECK_LAUNCH();

@@ -157,6 +157,11 @@ SNP_CASES = {
     "snp_q_low": dict(make=lambda: synth.snp_small(12, n_snp=800, q=(2, 12)), k=10, band=0),
     "porec3000": dict(make=lambda: synth.snp_porec(41, n_snp=3000, n_edges=3000, zipf_s=1.0), k=10,
                       band=100),
+    # eight fragments of 500-1,336 SNPs: longer than the builder's per-wave LDS staging
+    "snp_long_reads": dict(make=lambda: synth.snp_small(13, n_snp=1500, coverage=4.0, read_mean=80000.0,
+                                                        gap_mean=100.0), k=2, band=0),
+    "snp_long_reads_band": dict(make=lambda: synth.snp_small(13, n_snp=1500, coverage=4.0, read_mean=80000.0,
+                                                             gap_mean=100.0), k=2, band=50),
 }
 
 
