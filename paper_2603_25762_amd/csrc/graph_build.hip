@@ -125,6 +125,35 @@ __device__ inline int32_t duf_root(int32_t *p, int32_t x) {
     }
 }
 
+// The same walk through cached parent reads, which may be stale: a stale parent of x is an
+// earlier parent, and every earlier parent is still an ancestor (parents only move towards
+// the root), so the walk ends at a vertex that was a root once; splits still go out as
+// device-coherent stores (plain stores never touch the parent array).
+__device__ inline int32_t duf_root_cached(int32_t *p, int32_t x) {
+    while (true) {
+        const int32_t y = p[x];
+        if (y == x) return x;
+        const int32_t z = p[y];
+        if (z != y) __hip_atomic_store(p + x, z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = y;
+    }
+}
+
+// Joins the trees of x and y: the larger root is hooked under the smaller by
+// compare-and-swap.  The first attempt walks through cached reads; a hook that fails (the
+// walk ended at a vertex that is no longer a root) walks again with device-coherent reads.
+__device__ inline void duf_link(int32_t *p, int32_t x, int32_t y) {
+    bool coherent = false;
+    while (true) {
+        x = coherent ? duf_root(p, x) : duf_root_cached(p, x);
+        y = coherent ? duf_root(p, y) : duf_root_cached(p, y);
+        if (x == y) return;        // both are descendants of that vertex: one tree already
+        if (x < y) { const int32_t t = x; x = y; y = t; }
+        if (atomicCAS(p + x, x, y) == x) return;   // x was a root and now hangs under y
+        coherent = true;
+    }
+}
+
 __global__ void k_uf_init(int64_t n, int32_t *__restrict__ p) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = (int32_t)i;
@@ -137,14 +166,7 @@ __global__ void k_uf_link(int64_t nobs, const int32_t *__restrict__ sorted_snp, 
     for (int64_t q = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nobs;
          q += (int64_t)gridDim.x * blockDim.x) {
         if (sorted_snp[q] != sorted_snp[q - 1]) continue;
-        int32_t a = cov_frag[q - 1], b = cov_frag[q];
-        while (true) {
-            a = duf_root(p, a);
-            b = duf_root(p, b);
-            if (a == b) break;
-            if (a < b) { const int32_t t = a; a = b; b = t; }
-            if (atomicCAS(p + a, a, b) == a) break;   // a was a root and now hangs under b
-        }
+        duf_link(p, cov_frag[q - 1], cov_frag[q]);
     }
 }
 
@@ -205,16 +227,7 @@ __global__ void k_snp_structure(int64_t n_kept, const int64_t *__restrict__ kept
         const int32_t u = snp[kept_obs[kk]];
         const int64_t bmax = a + L < ns - 1 ? a + L : ns - 1;
         if (pass == 0) {
-            if (a > 0) {      // link to the previous kept SNP of the fragment
-                int32_t x = snp[kept_obs[kk - 1]], y = u;
-                while (true) {
-                    x = duf_root(uf, x);
-                    y = duf_root(uf, y);
-                    if (x == y) break;
-                    if (x < y) { const int32_t t = x; x = y; y = t; }
-                    if (atomicCAS(uf + x, x, y) == x) break;
-                }
-            }
+            if (a > 0) duf_link(uf, snp[kept_obs[kk - 1]], u);   // the previous kept SNP of the fragment
             int32_t vmax = -1;
             unsigned long long nlr = 0;
             for (int64_t b = a + 1; b <= bmax; ++b) {
