@@ -219,8 +219,11 @@ def batch_inputs(qh, batch):
     for k in names:
         parts = [np.ascontiguousarray(a[k]) for a in arrs]
         off = np.concatenate([[0], np.cumsum([p.size for p in parts])]).astype(np.int64)
-        # staged through a new pinned tensor: the copy to the device then runs at DMA speed
-        dev = torch.from_numpy(np.concatenate(parts)).pin_memory().to("cuda", non_blocking=True)
+        # the blocks' arrays are packed straight into pinned host memory (one pass over the
+        # host bytes), from which the copy to the device runs at DMA speed
+        host = torch.empty(int(off[-1]), dtype=torch.from_numpy(parts[0][:0]).dtype, pin_memory=True)
+        np.concatenate(parts, out=host.numpy())
+        dev = host.to("cuda", non_blocking=True)
         for b in range(len(arrs)):
             views[b][k] = dev[int(off[b]):int(off[b + 1])]
     return views
