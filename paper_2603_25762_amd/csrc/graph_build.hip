@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <numeric>
 
 #include <rocprim/rocprim.hpp>
@@ -838,6 +840,89 @@ static int grid_for(int64_t n, int block = 256, int64_t cap = 65536) {
     return (int)g;
 }
 
+// Several host arrays into device buffers with one host-to-device copy: the arrays are
+// packed 16-byte aligned behind a table of (destination, offset, bytes), copied in one
+// piece and scattered by one kernel, a workgroup per array.  As with any upload, the
+// stream is synchronised before the object (which owns the packed host copy and the
+// device staging block) goes out of scope.
+struct PackSeg {
+    uint64_t dst, off, bytes;
+};
+constexpr int kPackSegs = 16;
+constexpr size_t kPackTable = kPackSegs * sizeof(PackSeg);   // a multiple of 16
+
+__global__ void k_scatter(const uint8_t *__restrict__ blob) {
+    const PackSeg sg = ((const PackSeg *)blob)[blockIdx.x];
+    const uint8_t *src = blob + kPackTable + sg.off;
+    uint8_t *dst = (uint8_t *)sg.dst;   // device buffers start 256-byte aligned
+    const uint64_t n16 = sg.bytes / 16;
+    for (uint64_t i = threadIdx.x; i < n16; i += blockDim.x) ((uint4 *)dst)[i] = ((const uint4 *)src)[i];
+    for (uint64_t i = n16 * 16 + threadIdx.x; i < sg.bytes; i += blockDim.x) dst[i] = src[i];
+}
+
+class PackedUpload {
+  public:
+    PackedUpload() : blob_(kPackTable, 0) {}
+    PackedUpload(const PackedUpload &) = delete;
+    PackedUpload &operator=(const PackedUpload &) = delete;
+    // a build that fails between the flush and its caller's synchronisation unwinds
+    // through here: wait for the copy before the host and staging blocks are released
+    ~PackedUpload() {
+        if (st_ && std::uncaught_exceptions()) (void)hipStreamSynchronize(st_);
+    }
+    template <class T>
+    void add(DevBuf<T> &dst, const T *src, size_t count) {
+        if (!count) return;
+        if (segs_ == kPackSegs) fail(QH_EHIP, "packed upload: more than %d arrays", kPackSegs);
+        const size_t bytes = count * sizeof(T);
+        const size_t at = (blob_.size() + 15) & ~(size_t)15;
+        blob_.resize(at + bytes);
+        std::memcpy(blob_.data() + at, src, bytes);
+        const PackSeg sg{(uint64_t)(uintptr_t)dst.p, (uint64_t)(at - kPackTable), (uint64_t)bytes};
+        std::memcpy(blob_.data() + segs_ * sizeof(PackSeg), &sg, sizeof(sg));
+        ++segs_;
+    }
+    // queues the copy and the scatter on `st`; once per object
+    void flush(hipStream_t st) {
+        if (!segs_) return;
+        st_ = st;
+        stage_.alloc(blob_.size());
+        QH_HIP(hipMemcpyAsync(stage_.p, blob_.data(), blob_.size(), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_scatter, dim3((unsigned)segs_), dim3(256), 0, st, stage_.p);
+        QH_CHECK_LAUNCH();
+    }
+
+  private:
+    std::vector<uint8_t> blob_;
+    int segs_ = 0;
+    hipStream_t st_ = nullptr;
+    DevBuf<uint8_t> stage_;   // (declared last: released first, after the wait above)
+};
+
+// Eq. (9) per integer Phred score, q = 1 - 10^(-Q/10) for Q = 0..255: one table per device,
+// computed and uploaded once and kept for the life of the process.
+static const double *qconf_table() {
+    static std::mutex mu;
+    static std::map<int, double *> tables;
+    int dev = 0;
+    QH_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    double *&t = tables[dev];
+    if (!t) {
+        double h[256];
+        for (int q = 0; q < 256; ++q) h[q] = 1.0 - std::pow(10.0, -(double)q / 10.0);
+        double *d = nullptr;
+        QH_HIP(hipMalloc(&d, sizeof(h)));
+        if (hipMemcpy(d, h, sizeof(h), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(d);
+            fail(QH_EHIP, "Phred table upload failed");
+        }
+        t = d;
+    }
+    return t;
+}
+
 static int32_t uf_find(std::vector<int32_t> &p, int32_t x) {
     while (p[x] != x) {
         p[x] = p[p[x]];
@@ -866,8 +951,9 @@ static constexpr int kChunkVerts = 32;
 void upload_components(qh_graph *g, const std::vector<int32_t> &comp, int64_t n_comp, hipStream_t st) {
     int64_t n = g->n;
     g->n_comp = n_comp;
+    PackedUpload pu;
     g->comp.alloc(n);
-    g->comp.upload(comp.data(), n, st);
+    pu.add(g->comp, comp.data(), n);
     std::vector<int32_t> first(n_comp, -1);
     std::vector<int64_t> cnt(n_comp + 1, 0);
     for (int64_t i = 0; i < n; ++i)
@@ -894,19 +980,20 @@ void upload_components(qh_graph *g, const std::vector<int32_t> &comp, int64_t n_
     cptr[n_comp] = (int32_t)ccomp.size();
     g->n_chunks = (int64_t)ccomp.size();
     g->comp_first.alloc(n_comp);
-    g->comp_first.upload(first.data(), n_comp, st);
+    pu.add(g->comp_first, first.data(), n_comp);
     g->n_ord = (int64_t)order.size();
     g->comp_order.alloc(order.size());
-    g->comp_order.upload(order.data(), order.size(), st);
+    pu.add(g->comp_order, order.data(), order.size());
     g->chunk_comp.alloc(ccomp.size());
-    g->chunk_comp.upload(ccomp.data(), ccomp.size(), st);
+    pu.add(g->chunk_comp, ccomp.data(), ccomp.size());
     g->chunk_begin.alloc(cbeg.size());
-    g->chunk_begin.upload(cbeg.data(), cbeg.size(), st);
+    pu.add(g->chunk_begin, cbeg.data(), cbeg.size());
     g->chunk_end.alloc(cend.size());
-    g->chunk_end.upload(cend.data(), cend.size(), st);
+    pu.add(g->chunk_end, cend.data(), cend.size());
     g->comp_chunk_ptr.alloc(n_comp + 1);
-    g->comp_chunk_ptr.upload(cptr.data(), n_comp + 1, st);
-    QH_HIP(hipStreamSynchronize(st));  // host vectors go out of scope
+    pu.add(g->comp_chunk_ptr, cptr.data(), n_comp + 1);
+    pu.flush(st);
+    QH_HIP(hipStreamSynchronize(st));  // the packed host copy goes out of scope
 }
 
 
@@ -942,12 +1029,14 @@ static void pack_dense_storage(qh_graph *g, const int32_t *W, int negate, hipStr
     }
     tptr[n_rt] = (int32_t)tcol.size();
     g->n_tiles = (int64_t)tcol.size();
+    PackedUpload pu;
     g->t_ptr.alloc(n_rt + 1);
-    g->t_ptr.upload(tptr.data(), n_rt + 1, st);
+    pu.add(g->t_ptr, tptr.data(), n_rt + 1);
     g->t_col.alloc(tcol.size());
-    g->t_col.upload(tcol.data(), tcol.size(), st);
+    pu.add(g->t_col, tcol.data(), tcol.size());
     DevBuf<int32_t> trow_d(trow.size());
-    trow_d.upload(trow.data(), trow.size(), st);
+    pu.add(trow_d, trow.data(), trow.size());
+    pu.flush(st);
     charge(g, (int64_t)(g->m_ptr.bytes() + g->m_col.bytes() + g->m_val.bytes()),
            std::max<int64_t>(g->n_tiles, 1) * kTileElems * dtype_bytes(g->dtype), "dense tiles");
     g->t_val.alloc((size_t)std::max<int64_t>(g->n_tiles, 1) * kTileElems * dtype_bytes(g->dtype));
@@ -1253,29 +1342,29 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
         pk.push_back((int32_t)cbeg.size());
         g->n_hub_chunks = (int64_t)cbeg.size();
         g->n_lr_pk = (int64_t)pk.size() - 1;
+        PackedUpload pu;
         g->row_chunk_ptr.alloc(n + 1);
-        g->row_chunk_ptr.upload(rptr.data(), n + 1, st);
+        pu.add(g->row_chunk_ptr, rptr.data(), n + 1);
         g->hub_chunk_beg.alloc(cbeg.size());
-        g->hub_chunk_beg.upload(cbeg.data(), cbeg.size(), st);
+        pu.add(g->hub_chunk_beg, cbeg.data(), cbeg.size());
         g->hub_chunk_end.alloc(cend.size());
-        g->hub_chunk_end.upload(cend.data(), cend.size(), st);
+        pu.add(g->hub_chunk_end, cend.data(), cend.size());
         g->lr_pk_ptr.alloc(pk.size());
-        g->lr_pk_ptr.upload(pk.data(), pk.size(), st);
+        pu.add(g->lr_pk_ptr, pk.data(), pk.size());
+        pu.flush(st);
         QH_HIP(hipStreamSynchronize(st));
     }
 
-    // device structure
+    // device structure (the packed copy lives to the end of the build, past its last sync)
+    PackedUpload pu_sky;
     g->s_off.alloc(n);
-    g->s_off.upload(off.data(), n, st);
+    pu_sky.add(g->s_off, off.data(), n);
     g->s_lo.alloc(n);
-    g->s_lo.upload(lo.data(), n, st);
+    pu_sky.add(g->s_lo, lo.data(), n);
     g->s_len.alloc(n);
-    g->s_len.upload(len.data(), n, st);
-    // Eq. (9) per integer Phred score
-    double qconf_h[256];
-    for (int q = 0; q < 256; ++q) qconf_h[q] = 1.0 - std::pow(10.0, -(double)q / 10.0);
-    DevBuf<double> qconf(256);
-    qconf.upload(qconf_h, 256, st);
+    pu_sky.add(g->s_len, len.data(), n);
+    pu_sky.flush(st);
+    const double *qconf = qconf_table();
 
     DevBuf<int8_t> M(nobs);
     if (nobs) {
@@ -1293,7 +1382,7 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
         DevBuf<int32_t> clamped(1);
         clamped.zero(st);
         hipLaunchKernelGGL(k_snp_pairs, dim3(grid_for(F, 4, 1 << 20)), dim3(256), 0, st, F,
-                           kept_obs_d.p, kept_ptr_d.p, r->snp, M.p, r->phred, r->alpha, qconf.p,
+                           kept_obs_d.p, kept_ptr_d.p, r->snp, M.p, r->phred, r->alpha, qconf,
                            linkage_k, (int32_t)band_limit, g->s_off.p, g->s_lo.p, s_val64.p, g->l_ptr.p,
                            g->l_col.p, l_val64.p, g->deterministic, clamped.p);
         QH_CHECK_LAUNCH();
@@ -1385,12 +1474,14 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
         }
         g->n_bblk = nb;
         g->bb_elems = boff[nb];
+        PackedUpload pu;
         g->bb_off.alloc(nb + 1);
-        g->bb_off.upload(boff.data(), nb + 1, st);
+        pu.add(g->bb_off, boff.data(), nb + 1);
         g->bb_lo.alloc(nb);
-        g->bb_lo.upload(blo.data(), nb, st);
+        pu.add(g->bb_lo, blo.data(), nb);
         g->bb_w.alloc(nb);
-        g->bb_w.upload(bw.data(), nb, st);
+        pu.add(g->bb_w, bw.data(), nb);
+        pu.flush(st);
         charge(g, (int64_t)(g->m_ptr.bytes() + g->m_col.bytes() + g->m_val.bytes()),
                std::max<int64_t>(boff[nb], 1) * eb, "band blocks");
         g->bb_val.alloc((size_t)std::max<int64_t>(boff[nb], 1) * eb);
