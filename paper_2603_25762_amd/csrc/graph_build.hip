@@ -484,8 +484,8 @@ __global__ void k_fixed_to_f64(int64_t n, double *__restrict__ v) {
     }
 }
 
-// kept observations of a fragment whose SNP index, allele code and Phred confidence
-// k_snp_pairs stages in LDS (a longer fragment's later partners come from memory)
+// kept observations of a fragment whose SNP index, allele code, Phred confidence and skyline
+// row base k_snp_pairs stages in LDS (a longer fragment's later partners come from memory)
 constexpr int kFragLds = 512;
 
 // Eqs. (9), (11)-(13) with the per-fragment factor alpha and the 1/(|S_i|-1)
@@ -505,10 +505,12 @@ __global__ __launch_bounds__(256) void k_snp_pairs(int64_t F, const int64_t *__r
                                                    const int32_t *__restrict__ l_col, double *__restrict__ l_val64,
                                                    int fixed, int32_t *__restrict__ clamped) {
     __shared__ double s_q[4][kFragLds];
+    __shared__ int64_t s_rb[4][kFragLds];   // skyline row base s_off[u] - s_lo[u] of each SNP
     __shared__ int32_t s_u[4][kFragLds];
     __shared__ int8_t s_m[4][kFragLds];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *sq = s_q[wave];
+    int64_t *srb = s_rb[wave];
     int32_t *su = s_u[wave];
     int8_t *sm = s_m[wave];
     for (int64_t f0 = (int64_t)blockIdx.x * 4; f0 < F; f0 += (int64_t)gridDim.x * 4) {
@@ -521,9 +523,11 @@ __global__ __launch_bounds__(256) void k_snp_pairs(int64_t F, const int64_t *__r
         if (ns >= 2)
             for (int64_t a = lane; a < ns && a < kFragLds; a += 64) {
                 const int64_t t = kept_obs[base + a];
-                su[a] = snp[t];
+                const int32_t u = snp[t];
+                su[a] = u;
                 sm[a] = M[t];
                 sq[a] = qconf[phred[t]];
+                srb[a] = s_off[u] - s_lo[u];
             }
         __syncthreads();
         const int64_t L = ns >= 2 ? (int64_t)linkage_k * (ns - 1) / 10 : 0;
@@ -534,6 +538,7 @@ __global__ __launch_bounds__(256) void k_snp_pairs(int64_t F, const int64_t *__r
             const int32_t u = sa ? su[a] : snp[ta];
             const int Mu = sa ? sm[a] : M[ta];
             const double qu = sa ? sq[a] : qconf[phred[ta]];
+            const int64_t rbu = sa ? srb[a] : s_off[u] - s_lo[u];
             const int64_t bmax = a + L < ns - 1 ? a + L : ns - 1;
             for (int64_t b = a + 1; b <= bmax; ++b) {
                 const bool sb = b < kFragLds;
@@ -556,8 +561,8 @@ __global__ __launch_bounds__(256) void k_snp_pairs(int64_t F, const int64_t *__r
                     else unsafeAtomicAdd(p, term);
                 };
                 if (band_limit == 0 || v - u <= band_limit) {
-                    add(&s_val64[s_off[u] + (v - s_lo[u])]);
-                    add(&s_val64[s_off[v] + (u - s_lo[v])]);
+                    add(&s_val64[rbu + v]);
+                    add(&s_val64[(sb ? srb[b] : s_off[v] - s_lo[v]) + u]);
                 } else {
                     int64_t lo = l_ptr[u], hi = l_ptr[u + 1];
                     while (lo < hi) { int64_t m = (lo + hi) >> 1; if (l_col[m] < v) lo = m + 1; else hi = m; }
