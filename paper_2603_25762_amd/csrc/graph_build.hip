@@ -22,13 +22,24 @@ namespace qh {
 // device kernels
 // ---------------------------------------------------------------------------
 
-// Eq. (1): M = +1 where the observed allele is the one placed on H1, else -1.
+// Eq. (1): M = +1 where the observed allele is the one placed on H1, else -1; the graph's
+// own copy of the initial H1 (S entries) is written on the way.
 __global__ void k_encode(int64_t nobs, const int32_t *__restrict__ snp,
                          const uint8_t *__restrict__ allele, const uint8_t *__restrict__ init_h1,
-                         int8_t *__restrict__ M) {
+                         int8_t *__restrict__ M, int64_t S, uint8_t *__restrict__ h1_copy) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nobs;
          t += (int64_t)gridDim.x * blockDim.x)
         M[t] = (allele[t] == init_h1[snp[t]]) ? 1 : -1;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x)
+        h1_copy[i] = init_h1[i];
+}
+
+// Initial state of the SNP structure pass in one buffer: the long-range pair counter (64-bit,
+// words 0-1), then lo, hi and the union-find parents (n each), every vertex its own.
+__global__ void k_structure_init(int64_t n, int32_t *__restrict__ buf) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * n + 2;
+         i += (int64_t)gridDim.x * blockDim.x)
+        buf[i] = i < 2 ? 0 : (int32_t)((i - 2) % n);
 }
 
 __global__ void k_gather_i8(int64_t n, const int64_t *__restrict__ idx, const int8_t *__restrict__ src,
@@ -255,11 +266,6 @@ __global__ void k_snp_structure(int64_t n_kept, const int64_t *__restrict__ kept
             }
         }
     }
-}
-
-__global__ void k_iota32(int64_t n, int32_t *__restrict__ p) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = (int32_t)i;
 }
 
 // long-range CSR from the sorted, unique directed keys: l_ptr[u] = first key of row u
@@ -1113,10 +1119,11 @@ void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStrea
     g->cov_ptr.alloc(S + 1);
     g->cov_frag.alloc(nobs);
     g->cov_M.alloc(nobs);
+    g->init_h1.alloc(S);
     DevBuf<int32_t> keys_out;   // SNP of every position of the sorted observations
     if (nobs) {
-        hipLaunchKernelGGL(k_encode, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, r->snp, r->allele,
-                           s->init_h1, M.p);
+        hipLaunchKernelGGL(k_encode, dim3(grid_for(std::max<int64_t>(nobs, S))), dim3(256), 0, st, nobs, r->snp,
+                           r->allele, s->init_h1, M.p, (int64_t)S, g->init_h1.p);
         keys_out.alloc(nobs);
         DevBuf<int32_t> obs_frag(nobs), obs_idx(nobs), vals_out(nobs);
         hipLaunchKernelGGL(k_obs_frag, dim3(grid_for(F)), dim3(256), 0, st, F, r->frag_ptr, obs_frag.p, obs_idx.p);
@@ -1156,8 +1163,7 @@ void build_read_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, hipStrea
     int64_t n_comp = label_components(F, parent, comp);
     upload_components(g, comp, n_comp, st);
 
-    g->init_h1.alloc(S);
-    if (S) QH_HIP(hipMemcpyAsync(g->init_h1.p, s->init_h1, S, hipMemcpyDeviceToDevice, st));
+    if (S && !nobs) QH_HIP(hipMemcpyAsync(g->init_h1.p, s->init_h1, S, hipMemcpyDeviceToDevice, st));
 
     // Eqs. (2)-(3) into a dense int32 matrix
     int conflict = g->kind == QH_READ_CONFLICT;
@@ -1245,40 +1251,40 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
     std::vector<int32_t> lo(n), hi(n), parent(n);
     int64_t l_nnz = 0;
     {
-        DevBuf<int32_t> lo_d(n), hi_d(n), uf(n);
-        DevBuf<unsigned long long> lrc(1);
-        lrc.zero(st);
-        if (n) {
-            hipLaunchKernelGGL(k_iota32, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, lo_d.p);
-            hipLaunchKernelGGL(k_iota32, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, hi_d.p);
-            hipLaunchKernelGGL(k_iota32, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, uf.p);
-            QH_CHECK_LAUNCH();
-        }
+        // one buffer (and one copy back): the pair counter, lo, hi and the parents
+        DevBuf<int32_t> sb(3 * (size_t)n + 2);
+        unsigned long long *lrc = (unsigned long long *)sb.p;   // device blocks are 256-byte aligned
+        int32_t *lo_p = sb.p + 2, *hi_p = lo_p + n, *uf_p = hi_p + n;
+        hipLaunchKernelGGL(k_structure_init, dim3(grid_for(3 * (int64_t)n + 2)), dim3(256), 0, st, (int64_t)n,
+                           sb.p);
+        QH_CHECK_LAUNCH();
         if (n_kept) {
             hipLaunchKernelGGL(k_snp_structure, dim3(grid_for(n_kept)), dim3(256), 0, st, n_kept, kept_obs_d.p,
                                kept_frag_d.p, kept_ptr_d.p, r->snp, linkage_k, (int32_t)band_limit, (int64_t)n,
-                               lo_d.p, hi_d.p, uf.p, lrc.p, (uint64_t *)nullptr, 0);
+                               lo_p, hi_p, uf_p, lrc, (uint64_t *)nullptr, 0);
             QH_CHECK_LAUNCH();
         }
         if (n) {
-            hipLaunchKernelGGL(k_uf_flatten, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, uf.p);
+            hipLaunchKernelGGL(k_uf_flatten, dim3(grid_for(n)), dim3(256), 0, st, (int64_t)n, uf_p);
             QH_CHECK_LAUNCH();
         }
-        unsigned long long n_lr_pairs = 0;
-        QH_HIP(hipMemcpyAsync(&n_lr_pairs, lrc.p, sizeof(n_lr_pairs), hipMemcpyDeviceToHost, st));
-        QH_HIP(hipMemcpyAsync(lo.data(), lo_d.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        QH_HIP(hipMemcpyAsync(hi.data(), hi_d.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        QH_HIP(hipMemcpyAsync(parent.data(), uf.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        std::vector<int32_t> sh(3 * (size_t)n + 2);
+        QH_HIP(hipMemcpyAsync(sh.data(), sb.p, sh.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         QH_HIP(hipStreamSynchronize(st));
+        unsigned long long n_lr_pairs = 0;
+        std::memcpy(&n_lr_pairs, sh.data(), sizeof(n_lr_pairs));
+        std::copy(sh.begin() + 2, sh.begin() + 2 + n, lo.begin());
+        std::copy(sh.begin() + 2 + n, sh.begin() + 2 + 2 * (size_t)n, hi.begin());
+        std::copy(sh.begin() + 2 + 2 * (size_t)n, sh.end(), parent.begin());
         // long-range keys u n + v of both directions, sorted and unique
         const int64_t n_dir = 2 * (int64_t)n_lr_pairs;
         g->l_ptr.alloc(n + 1);
         if (n_dir) {
             DevBuf<uint64_t> keys(n_dir), sorted(n_dir), uniq(n_dir);
-            lrc.zero(st);
+            QH_HIP(hipMemsetAsync(lrc, 0, sizeof(unsigned long long), st));
             hipLaunchKernelGGL(k_snp_structure, dim3(grid_for(n_kept)), dim3(256), 0, st, n_kept, kept_obs_d.p,
                                kept_frag_d.p, kept_ptr_d.p, r->snp, linkage_k, (int32_t)band_limit, (int64_t)n,
-                               lo_d.p, hi_d.p, uf.p, lrc.p, keys.p, 1);
+                               lo_p, hi_p, uf_p, lrc, keys.p, 1);
             QH_CHECK_LAUNCH();
             int bits = 1;
             while (bits < 64 && ((uint64_t)1 << bits) < (uint64_t)n * (uint64_t)n) ++bits;
@@ -1372,13 +1378,12 @@ void build_snp_graph(qh_graph *g, const qh_reads *r, const qh_snps *s, int linka
     const double *qconf = qconf_table();
 
     DevBuf<int8_t> M(nobs);
-    if (nobs) {
-        hipLaunchKernelGGL(k_encode, dim3(grid_for(nobs)), dim3(256), 0, st, nobs, r->snp, r->allele,
-                           s->init_h1, M.p);
+    g->init_h1.alloc(n);
+    if (nobs || n) {
+        hipLaunchKernelGGL(k_encode, dim3(grid_for(std::max<int64_t>(nobs, n))), dim3(256), 0, st, nobs, r->snp,
+                           r->allele, s->init_h1, M.p, (int64_t)n, g->init_h1.p);
         QH_CHECK_LAUNCH();
     }
-    g->init_h1.alloc(n);
-    if (n) QH_HIP(hipMemcpyAsync(g->init_h1.p, s->init_h1, n, hipMemcpyDeviceToDevice, st));
 
     DevBuf<double> s_val64(slots), l_val64(l_nnz);
     s_val64.zero(st);
