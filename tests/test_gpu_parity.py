@@ -1438,4 +1438,9 @@ def test_release_cached_memory():
     assert qh.release_cached_memory() == 0
     g = build()
     assert torch.equal(qh.bsb_solve(g, 16, 50, seed=3)["best_cut"].cpu(), ref)
+    # blocks in use stay: a live graph solves the same after another one's blocks are released
+    g2 = build()
+    g2.free()
+    assert qh.release_cached_memory() >= need
+    assert torch.equal(qh.bsb_solve(g, 16, 50, seed=3)["best_cut"].cpu(), ref)
     g.free()
